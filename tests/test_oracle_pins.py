@@ -1,0 +1,355 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: numbers the
+paper prints (tests/golden/), closed forms, invariants of the discrete sum,
+and quadratures written independently of the oracle.
+"""
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle as O
+from closed_forms import (c_k, cheb, load_golden, q_bkw, t_hat, t_tilde, uniform_grid)
+from paper_2105_08806_amd import inputs as I
+
+pytestmark = pytest.mark.filterwarnings("ignore::scipy.integrate.IntegrationWarning")
+
+
+def circle(m):
+    return O.circle_rule(m)
+
+
+def bkw2d_error(N, S, t0=2.0, msig=None):
+    sg, sw = circle(msig or N - 1)
+    p = O.Problem(2, N, S, 0, sphere=sg, sphere_w=sw)
+    c = p.project(I.bkw_f(t0, p.interior_velocities()))
+    q, _, _ = p.collision(c)
+    G, h = uniform_grid(2, 200)
+    e = p.eval(q, G) - q_bkw(t0, G)
+    return np.sqrt(h * h * np.sum(e * e))
+
+
+# ------------------------------------------------------------- basis, nodes
+
+
+@pytest.mark.parametrize("m_v", [5, 12, 33])
+def test_cgl_rule_exactness(m_v):
+    """CGL integrates T_a T_b against (1 - x^2)^-1/2 exactly up to degree 2 m_v - 3."""
+    xi, _, w, _ = O.cgl(m_v, 0, 3.0)
+    for a in range(m_v):
+        for b in range(m_v):
+            if a + b > 2 * m_v - 3:
+                continue
+            val = np.sum(w * cheb(a, xi) * cheb(b, xi))
+            exact = c_k(a) if a == b else 0.0
+            assert abs(val - exact) < 1e-13, (a, b, val)
+
+
+@pytest.mark.parametrize("map_", [0, 1])
+def test_map_is_the_paper_mapping(map_):
+    """v(xi) solves dv/dxi = omega/mu^2 with v(0) = 0, and mu^2 matches eq. (1D_mu_function)."""
+    S = 2.7
+    r = map_
+    xi, v, _, mu2 = O.cgl(17, map_, S)
+    for j in range(1, 16):
+        integral, _ = integrate.quad(lambda x: S / (1 - x * x) ** (1 + r / 2.0), 0.0, xi[j],
+                                     epsabs=1e-13, epsrel=1e-13, limit=200)
+        assert abs(v[j] - integral) < 1e-9 * max(1.0, abs(v[j]))
+        assert abs(mu2[j] - (1 - xi[j] ** 2) ** ((1 + r) / 2) / S) < 1e-15
+    assert v[0] == -np.inf and v[-1] == np.inf
+
+
+@pytest.mark.parametrize("map_", [0, 1])
+def test_biorthogonality_of_oracle_basis(map_):
+    """(T~_k, T^_l) = delta_kl on R (eq. ortho), with T~ taken from the oracle's evaluator."""
+    S, N = 2.0, 6
+    T0 = t_tilde(0, 0.0, S, map_)
+    for k in range(N):
+        coeff = np.zeros((N, N))
+        coeff[k, 0] = 1.0
+
+        def tt(v, k=k, coeff=coeff):
+            return O.eval_expansion(2, N, map_, S, coeff, np.array([[v, 0.0]]))[0] / T0
+
+        for l in range(N):
+            # the integrand decays like mu(xi(v))^2: exp(-|v|/S) for r = 0, v^-2 for r = 1
+            if map_ == 0:
+                val, _ = integrate.quad(lambda v: tt(v) * t_hat(l, v, S, map_), -40 * S, 40 * S,
+                                        epsabs=1e-12, limit=800, points=[0.0])
+            else:
+                val, _ = integrate.quad(
+                    lambda v: tt(v) * t_hat(l, v, S, map_) if abs(v) < 1e100 else 0.0,
+                    -np.inf, np.inf, epsabs=1e-12, limit=800)
+            assert abs(val - (1.0 if k == l else 0.0)) < 1e-8, (k, l, val)
+
+
+@pytest.mark.parametrize("map_", [0, 1])
+def test_projection_inverts_synthesis(map_):
+    """f = mu^4 (T_m - T_{m+2}) vanishes at xi = +-1; its coefficients are
+    sqrt(c_m) e_m - sqrt(c_{m+2}) e_{m+2}, and the interior CGL projection
+    (eq. MultiD_spectral_coef) must return them exactly."""
+    N, S = 9, 3.0
+    sg, sw = circle(4)
+    p = O.Problem(2, N, S, map_, sphere=sg, sphere_w=sw)
+    V = p.interior_velocities()
+    for m1, m2 in [(0, 3), (2, 5), (6, 1)]:
+        c = np.zeros((N, N))
+        for a, sa in ((m1, 1.0), (m1 + 2, -1.0)):
+            for b, sb in ((m2, 1.0), (m2 + 2, -1.0)):
+                if a < N and b < N:
+                    c[a, b] = sa * sb * np.sqrt(c_k(a) * c_k(b))
+        if m1 + 2 >= N or m2 + 2 >= N:
+            continue
+        f = O.eval_expansion(2, N, map_, S, c, V)
+        back = p.project(f)
+        assert np.max(np.abs(back - c)) < 1e-12
+        # the nodal values are the polynomial part P = f / mu^4
+        _, _, _, mu2 = O.cgl(N + 1, map_, S)
+        mu4 = np.outer(mu2[1:-1] ** 2, mu2[1:-1] ** 2)
+        assert np.max(np.abs(p.nodal(c) - f.reshape(N - 1, N - 1) / mu4)) < 1e-11
+
+
+def test_gauss_legendre_and_sphere_rules():
+    x, w = O.gauss_legendre(8)
+    for k in range(16):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs(np.sum(w * x ** k) - exact) < 1e-14
+    s, w = O.sphere_product_rule(8, 8)
+    assert abs(w.sum() - 4 * np.pi) < 1e-13
+    assert np.allclose(np.linalg.norm(s, axis=1), 1.0)
+    # second moments of the unit sphere: 4 pi / 3 on the diagonal
+    M = (s.T * w) @ s
+    assert np.allclose(M, 4 * np.pi / 3 * np.eye(3), atol=1e-13)
+    # antipodal symmetry: -sigma is again a node with the same weight
+    for a in range(len(w)):
+        d = np.linalg.norm(s + s[a], axis=1)
+        b = int(np.argmin(d))
+        assert d[b] < 1e-13 and abs(w[b] - w[a]) < 1e-15
+    s2, w2 = O.circle_rule(16)
+    assert abs(w2.sum() - 2 * np.pi) < 1e-14
+    assert np.allclose((s2.T * w2) @ s2, np.pi * np.eye(2), atol=1e-13)
+
+
+# ------------------------------------------------------ moment functionals
+
+
+def test_moment_functionals_closed_forms():
+    N, S = 12, 3.3
+    m = O.moment_functionals(N, 0, S, 2)
+    for k in range(N):
+        exact = 0.0 if k == 1 else (1 + (-1) ** k) / ((1 - k * k) * S * np.sqrt(c_k(k)))
+        assert abs(m[0, k] - exact) < 1e-13
+    for map_ in (0, 1):
+        m = O.moment_functionals(N, map_, S, 2)
+        for p in range(3):
+            for k in range(N):
+                val, _ = integrate.quad(lambda v: v ** p * t_tilde(k, v, S, map_), -np.inf, np.inf,
+                                        epsabs=1e-13, limit=400)
+                assert abs(m[p, k] - val) < 1e-9 * max(1.0, abs(val)), (map_, p, k, m[p, k], val)
+
+
+def test_moments_of_a_projected_maxwellian():
+    N, S = 24, 3.0
+    sg, sw = circle(4)
+    p = O.Problem(2, N, S, 0, sphere=sg, sphere_w=sw)
+    rho, u, T = 1.3, (0.4, -0.7), 0.8
+    c = p.project(I.maxwellian(p.interior_velocities(), rho, u, T))
+    mom = p.moments(c)
+    exact = [rho, rho * u[0], rho * u[1], rho * (u[0] ** 2 + u[1] ** 2 + 2 * T)]
+    assert np.allclose(mom, exact, atol=1e-7)
+
+
+# -------------------------------------------------------- the collision sum
+
+
+def test_bkw2d_table2_best_errors():
+    """Best L2 error over S at t = 2 (Test 01) reproduces Table 2's Chebyshev-0
+    column within a factor 2 (the S grid of the paper is not stated)."""
+    rows = {int(r[1]): float(r[2]) for r in load_golden("table2_bkw2d_cheb0.txt")}
+    for N, grid in [(9, [2.0, 2.25, 2.5]), (17, [2.75, 3.0, 3.25])]:
+        best = min(bkw2d_error(N, S) for S in grid)
+        assert rows[N] / 2 < best < rows[N] * 2, (N, best, rows[N])
+
+
+def test_bkw2d_spectral_convergence():
+    e = [bkw2d_error(N, 3.0) for N in (9, 13, 17)]
+    assert e[0] > 10 * e[1] > 100 * e[2]
+
+
+def test_bkw3d_convergence_and_table3_scale():
+    """3D BKW at t = 6.5: L-inf error over the 30^3 grid falls spectrally and
+    is already below Table 3's first Chebyshev-0 entry at 9 modes."""
+    t0 = 6.5
+    G, _ = uniform_grid(3, 30)
+    Qb = q_bkw(t0, G)
+    sg, sw = O.sphere_product_rule(4, 8)
+    err = []
+    for N in (7, 9):
+        p = O.Problem(3, N, 2.5, 0, sphere=sg, sphere_w=sw)
+        c = p.project(I.bkw_f(t0, p.interior_velocities()))
+        q, _, _ = p.collision(c)
+        err.append(np.max(np.abs(p.eval(q, G) - Qb)))
+    table3 = float(load_golden("table3_bkw3d_cheb0.txt")[0][3])
+    assert err[1] < err[0] / 10
+    assert err[1] < table3
+
+
+def test_maxwell_moment_derivatives_2d():
+    """d/dt of the printed moment trajectories at t = 0 (Sec. 5.1.2) equals
+    (Q, v_i v_j) and (Q, v_i |v|^2) of the discrete operator."""
+    rows = {r[0]: float(r[1]) for r in load_golden("moments2d_closed_forms.txt")}
+    d = {k: -0.5 * a for k, a in rows.items()}   # d/dt (a e^{-t/2} + b) at t = 0
+    N, S = 25, 4.0
+    sg, sw = circle(24)
+    p = O.Problem(2, N, S, 0, sphere=sg, sphere_w=sw)
+    c = p.project(I.mixture(p.interior_velocities(), I.moments_test_2d()))
+    q, _, _ = p.collision(c)
+    m0, m1, m2, m3 = O.moment_functionals(N, 0, S, 3)
+
+    def mom(a, b):
+        return float(np.einsum("ij,i,j->", q, a, b))
+
+    got = {"P11": mom(m2, m0), "P12": mom(m1, m1), "P22": mom(m0, m2),
+           "q1": mom(m3, m0) + mom(m1, m2), "q2": mom(m2, m1) + mom(m0, m3)}
+    for k in got:
+        assert abs(got[k] - d[k]) < 2e-3 * max(1.0, abs(d[k])), (k, got[k], d[k])
+    # the initial moments themselves: value(0) = a + b
+    ab = {r[0]: float(r[1]) + float(r[2]) for r in load_golden("moments2d_closed_forms.txt")}
+    assert abs(np.einsum("ij,i,j->", c, m2, m0) - ab["P11"]) < 5e-4
+    assert abs(np.einsum("ij,i,j->", c, m1, m1) - ab["P12"]) < 5e-4
+    assert abs(np.einsum("ij,i,j->", c, m0, m2) - ab["P22"]) < 5e-4
+
+
+@pytest.mark.parametrize("map_", [1])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_conservation_algebraic_map(dim, map_):
+    """With r = 1, 1 and |v|^2 lie in the test space (Sec. 3.2 theorem), so the
+    discrete Q has zero mass and energy to rounding; Q+ alone does not."""
+    N = 10 if dim == 2 else 6
+    S = 2.5
+    if dim == 2:
+        sg, sw = circle(8)
+        comps = [(0.6, (0.5, -0.3), 0.7), (0.4, (-0.8, 0.6), 1.2)]
+    else:
+        sg, sw = O.sphere_product_rule(2, 4)
+        comps = [(0.6, (0.5, -0.3, 0.1), 0.7), (0.4, (-0.8, 0.6, 0.2), 1.2)]
+    p = O.Problem(dim, N, S, map_, sphere=sg, sphere_w=sw)
+    c = p.project(I.mixture(p.interior_velocities(), comps))
+    q, qp, _ = p.collision(c)
+    mq, mqp = p.moments(q), p.moments(qp)
+    assert abs(mq[0]) < 1e-13 * abs(mqp[0])
+    assert abs(mq[-1]) < 1e-13 * abs(mqp[-1])
+
+
+def test_maxwell_loss_closed_form():
+    """Maxwell molecules: A_i is the constant (sum_s W_s) b0 rho_h, and by CGL
+    exactness Q-_k = rho_h (f_k - w_0 [P(-1) T_k(-1) + P(1) T_k(1)] / sqrt(c_k))
+    with rho_h = sum_j w_j mu_j^2 P_j the discrete mass."""
+    N, S = 11, 3.0
+    sg, sw = circle(6)
+    p = O.Problem(2, N, S, 0, sphere=sg, sphere_w=sw)   # b0 = 1/(2 pi), sum W = 2 pi
+    c = I.random_coeffs((N, N), seed=5)
+    _, _, qm = p.collision(c)
+    xi, _, w, mu2 = O.cgl(N + 1, 0, S)
+    P = p.nodal(c)
+    rho = np.einsum("ij,i,j->", P, w[1:-1] * mu2[1:-1], w[1:-1] * mu2[1:-1])
+    sc = np.array([np.sqrt(c_k(k)) for k in range(N)])
+    Tm = np.array([(-1.0) ** k for k in range(N)]) / sc
+    Tp = np.ones(N) / sc
+    # 1D projector with endpoints removed, applied per dimension
+    E = np.eye(N) - w[0] * (np.outer(Tm, Tm) + np.outer(Tp, Tp))
+    # interior rule over a tensor product: the dropped set is any endpoint in any dim
+    expect = rho * (E @ c @ E.T)
+    assert np.max(np.abs(qm - expect)) < 1e-13 * np.max(np.abs(qm))
+
+
+def test_parity_symmetry_and_bilinearity():
+    N, S = 10, 2.5
+    sg, sw = circle(8)
+    p = O.Problem(2, N, S, 0, sphere=sg, sphere_w=sw)
+    # even in v1 and symmetric under v1 <-> v2
+    comps = [(0.5, (0.0, 0.0), 0.8), (0.25, (0.9, 0.9), 0.6), (0.25, (-0.9, 0.9), 0.6),
+             ]
+    f = I.mixture(p.interior_velocities(), comps)
+    c = p.project(f)
+    q, _, _ = p.collision(c)
+    scale = np.max(np.abs(q))
+    assert np.max(np.abs(q[1::2, :])) < 1e-14 * scale * 10
+    # bilinearity
+    q2, _, _ = p.collision(1.7 * c)
+    assert np.allclose(q2, 1.7 ** 2 * q, rtol=1e-12, atol=1e-13 * scale)
+    # swap symmetry (M_sigma divisible by 4)
+    comps_s = [(0.5, (0.3, 0.3), 0.8), (0.5, (-0.6, -0.6), 1.1)]
+    cs = p.project(I.mixture(p.interior_velocities(), comps_s))
+    qs, _, _ = p.collision(cs)
+    assert np.max(np.abs(qs - qs.T)) < 1e-13 * np.max(np.abs(qs))
+
+
+def test_equilibrium_maxwellian():
+    """Q(M, M) = 0 for a Maxwellian; the discrete Q falls spectrally with N."""
+    S = 3.0
+    r = []
+    for N in (9, 13, 17):
+        sg, sw = circle(N - 1)
+        p = O.Problem(2, N, S, 0, sphere=sg, sphere_w=sw)
+        c = p.project(I.maxwellian(p.interior_velocities(), 1.0, (0.3, -0.2), 1.0))
+        q, qp, _ = p.collision(c)
+        r.append(np.linalg.norm(q) / np.linalg.norm(qp))
+    assert r[0] > 5 * r[1] > 25 * r[2]
+    assert r[2] < 1e-4
+
+
+def test_q_bkw_weak_form_projection():
+    """Q_k approaches (Q_BKW, T^_k), computed by an independent trapezoid
+    quadrature of the closed form over a wide uniform grid."""
+    t0, S, N = 2.0, 3.25, 25
+    sg, sw = circle(N - 1)
+    p = O.Problem(2, N, S, 0, sphere=sg, sphere_w=sw)
+    c = p.project(I.bkw_f(t0, p.interior_velocities()))
+    q, _, _ = p.collision(c)
+    x = np.linspace(-14.0, 14.0, 1401)
+    h = x[1] - x[0]
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    Qb = q_bkw(t0, np.stack([X, Y], axis=-1))
+    for k1, k2 in [(0, 0), (2, 0), (2, 2), (4, 0), (0, 6)]:
+        val = h * h * np.sum(Qb * np.outer(t_hat(k1, x, S, 0), t_hat(k2, x, S, 0)))
+        assert abs(q[k1, k2] - val) < 1e-6, (k1, k2, q[k1, k2], val)
+
+
+def test_collision_at_matches_full():
+    N, S = 8, 2.0
+    sg, sw = O.sphere_product_rule(2, 4)
+    p = O.Problem(3, N, S, 0, kernel="vhs", b0=0.1, gamma=1.0, sphere=sg, sphere_w=sw)
+    c = I.random_coeffs((N, N, N), seed=3)
+    _, qp, qm = p.collision(c)
+    kidx = np.array([[0, 0, 0], [7, 1, 3], [2, 7, 7], [5, 5, 0]])
+    ap, am = p.collision_at(c, kidx)
+    for r, k in enumerate(kidx):
+        assert abs(ap[r] - qp[tuple(k)]) < 1e-13 * np.max(np.abs(qp))
+        assert abs(am[r] - qm[tuple(k)]) < 1e-13 * np.max(np.abs(qm))
+
+
+def test_rk4_follows_bkw():
+    """RK4 from the projected BKW data at t = 0 to t = 1 (dt = 0.05) stays
+    close to the projection of the exact BKW solution at t = 1."""
+    N, S = 16, 3.0
+    sg, sw = circle(16)
+    p = O.Problem(2, N, S, 0, sphere=sg, sphere_w=sw)
+    V = p.interior_velocities()
+    c0 = p.project(I.bkw_f(0.0, V))
+    c1 = p.rk4(c0, 0.05, 20)
+    exact = p.project(I.bkw_f(1.0, V))
+    assert np.max(np.abs(c1 - exact)) < 1e-3 * np.max(np.abs(exact))
+    assert np.max(np.abs(c1 - exact)) < 0.01 * np.max(np.abs(c0 - exact))
+
+
+def test_cosine_sum_orthogonality():
+    """Points on the CGL angle grid: sum_j w_j cos(k z_j) cos(l z_j) = c_k delta_kl."""
+    m = 12
+    z = np.pi * np.arange(m) / (m - 1)
+    w = np.full(m, np.pi / (m - 1))
+    w[0] = w[-1] = np.pi / (2 * (m - 1))
+    for l in range(5):
+        out = O.cosine_sum(z[:, None], w * np.cos(l * z), 8)
+        ref = np.array([c_k(k) if k == l else 0.0 for k in range(8)])
+        assert np.allclose(out, ref, atol=1e-13)
