@@ -1,0 +1,187 @@
+/*
+ * pgc.h -- C ABI of the MI355X (gfx950) library for the fast Petrov-Galerkin
+ * mapped-Chebyshev collision operator of Hu, Huang, Shen and Yang,
+ * "A fast Petrov-Galerkin spectral method for the multi-dimensional Boltzmann
+ * equation using mapped Chebyshev functions" (arXiv 2105.08806).
+ *
+ * What the library computes
+ * -------------------------
+ * For f_N = sum_k f_k T~_k (eq. fN_Expansion, Sec. 3) the Galerkin
+ * coefficients of the collision operator (eq. Qk_component, Sec. 3)
+ *     Q_k = (Q(f_N, f_N), T^_k) = Q+_k - Q-_k            (eqs. Qplus, Qminus)
+ * discretised with Chebyshev-Gauss-Lobatto rules in xi and eta and a rule on
+ * the unit sphere (Sec. 4.1), and evaluated with the fast algorithm of
+ * Sec. 4.2: the gain through a type-1 non-uniform cosine transform
+ * (eqs. num_fast_k, nufft) -- here one merged transform per evaluation -- and
+ * the loss through its inner kernel sum plus a Chebyshev transform.
+ *
+ * Conventions
+ * -----------
+ *  - N = n_modes is the number of modes per dimension, k_l = 0..N-1 (the
+ *    paper's degree is N-1).  Coefficient tensors are dense, row-major,
+ *    last index fastest: index (k_1*N + k_2)*N + k_3 in 3D.
+ *  - m_v Chebyshev-Gauss-Lobatto nodes per dimension, xi_j = -cos(pi j/(m_v-1)),
+ *    both endpoints included; every velocity sum runs over the m_v - 2
+ *    interior nodes (f_N vanishes at xi = +-1, i.e. v = +-infinity).
+ *    Nodal arrays are n_i^dim, n_i = m_v - 2, row-major.
+ *  - Maps (Sec. 2.1): LOG is r = 0, v = S atanh(xi); ALGEBRAIC is r = 1,
+ *    v = S xi / sqrt(1 - xi^2).
+ *  - Kernels: MAXWELL, B = b0; VHS, B = b0 |v - v_*|^gamma (0 <= gamma <= 1).
+ *
+ * Memory, streams, errors
+ * -----------------------
+ *  - Every array argument named *_dev is a caller-owned DEVICE pointer on the
+ *    current HIP device; *_host arguments are host pointers.
+ *  - Coefficient and Q arrays have the plan's precision: double for
+ *    PGC_PRECISION_FP64, float for PGC_PRECISION_FP32.  State, nodal input
+ *    and moment arrays are always double.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls only
+ *    enqueue work on it and return; no call synchronises the host unless its
+ *    comment says so.  A plan owns all its workspace (allocated in
+ *    pgc_plan_create, freed in pgc_plan_destroy); the calls that take a
+ *    stream allocate nothing.
+ *  - A plan must not be used by two calls that can run concurrently.
+ *  - Every call returns a pgc_status.  On an error return the outputs are
+ *    untouched (for argument errors) or unspecified (device errors).  No C++
+ *    exception crosses this interface.
+ */
+#ifndef PGC_H
+#define PGC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pgc_status {
+    PGC_OK = 0,
+    PGC_ERR_INVALID_ARG = 1,
+    PGC_ERR_UNSUPPORTED = 2,
+    PGC_ERR_OUT_OF_MEMORY = 3,
+    PGC_ERR_DEVICE = 4,
+    PGC_ERR_NUMERIC = 5
+} pgc_status;
+
+enum { PGC_MAP_LOG = 0, PGC_MAP_ALGEBRAIC = 1 };
+enum { PGC_SCALE_DIRECT = 0, PGC_SCALE_FROM_DOMAIN = 1 };
+enum { PGC_KERNEL_MAXWELL = 0, PGC_KERNEL_VHS = 1 };
+enum { PGC_SPHERE_UNIFORM_2D = 0, PGC_SPHERE_PRODUCT_3D = 1, PGC_SPHERE_USER = 2 };
+enum { PGC_PRECISION_FP64 = 0, PGC_PRECISION_FP32 = 1 };
+
+/* Description of one discretised operator.  Fill with pgc_desc_init, then
+ * set what differs.  Tuning fields left at 0 are chosen by the library. */
+typedef struct pgc_plan_desc {
+    int32_t dim;          /* 2 or 3 */
+    int32_t n_modes;      /* N >= 3 (degree >= 2 keeps 1 and |v|^2 in the test space, Sec. 3.2) */
+    int32_t m_v;          /* CGL nodes per dimension incl. endpoints; 0 = n_modes + 1 */
+    int32_t map;          /* PGC_MAP_LOG or PGC_MAP_ALGEBRAIC */
+    int32_t scale_mode;   /* PGC_SCALE_DIRECT: S = scale.  PGC_SCALE_FROM_DOMAIN: S such that
+                             the second and second-to-last nodes map to -scale and +scale
+                             (the adaptive choice of Sec. 5) */
+    double scale;         /* > 0 */
+    int32_t kernel;       /* PGC_KERNEL_MAXWELL or PGC_KERNEL_VHS */
+    double kernel_b0;     /* kernel constant; 0 = 1/|S^{d-1}| (so that int B dsigma = 1 for Maxwell) */
+    double kernel_gamma;  /* VHS exponent in [0, 1] */
+    int32_t sphere;       /* PGC_SPHERE_UNIFORM_2D (theta_s = 2 pi s/n_sigma, W_s = 2 pi/n_sigma),
+                             PGC_SPHERE_PRODUCT_3D (n_theta Gauss-Legendre nodes in cos(theta)
+                             x n_phi uniform phi), or PGC_SPHERE_USER */
+    int32_t n_sigma;      /* UNIFORM_2D and USER: number of directions (even for UNIFORM_2D) */
+    int32_t n_theta;      /* PRODUCT_3D */
+    int32_t n_phi;        /* PRODUCT_3D, even */
+    const double* user_sigma_host;   /* USER: n_sigma x dim unit vectors (copied) */
+    const double* user_weights_host; /* USER: n_sigma positive weights (copied) */
+    int32_t precision;    /* PGC_PRECISION_FP64 or PGC_PRECISION_FP32 */
+    double nufft_tol;     /* requested accuracy of the cosine transform relative to sum |q|;
+                             0 = 1e-13 (FP64) or 1e-7 (FP32) */
+    double upsample;      /* fine-grid upsampling factor sigma_up in [1.5, 4]; 0 = 2 */
+    int32_t kernel_width; /* spreading kernel width W in grid cells (2..16); 0 = from nufft_tol */
+    int32_t slab_planes;  /* fine-grid planes held in LDS per workgroup; 0 = as many as fit */
+    int32_t n_chunks;     /* collision-unit chunks (partial grids); 0 = automatic */
+    int32_t block_threads;/* threads per spreading workgroup (256, 512 or 1024); 0 = automatic */
+} pgc_plan_desc;
+
+typedef struct pgc_plan_s* pgc_plan;
+
+typedef struct pgc_plan_info {
+    int32_t dim, n_modes, m_v, map, kernel, precision;
+    int32_t n_sigma;        /* directions actually used */
+    double scale;           /* the S actually used */
+    int32_t grid_n;         /* periodic fine-grid size n (cells over [0, 2 pi)) */
+    int32_t grid_folded;    /* n/2 + 1 points per dimension over [0, pi] */
+    int32_t kernel_width;   /* W */
+    double kernel_beta;     /* ES shape parameter */
+    double upsample;
+    int32_t slab_planes, n_slabs, n_chunks, block_threads;
+    int64_t n_triples;      /* collision triples per evaluation, n_sigma * n_i^(2 dim) */
+    int64_t workspace_bytes;/* device memory owned by the plan */
+} pgc_plan_info;
+
+/* Human-readable text of a status code (static storage, never NULL). */
+const char* pgc_status_string(pgc_status s);
+
+/* Fill *desc with defaults: 2D, N = 16, LOG map, S = 4, Maxwell, 16 directions,
+ * FP64.  Returns PGC_ERR_INVALID_ARG for NULL. */
+pgc_status pgc_desc_init(pgc_plan_desc* desc);
+
+/* Kernel width W and shape beta that the library would use for a cosine
+ * transform of accuracy tol at upsampling factor upsample (host only, no GPU).
+ * The "exponential of semicircle" kernel exp(beta (sqrt(1 - y^2) - 1)) is the
+ * one of the NUFFT library the paper uses for eq. (nufft). */
+pgc_status pgc_nufft_params(double tol, double upsample, int32_t* width, double* beta);
+
+/* Validate *desc, build every table (nodes, maps, sphere rule, Chebyshev and
+ * cosine-transform matrices, kernel polynomials, moment functionals) in FP64
+ * on the host, upload them and allocate all workspace on the current device.
+ * `stream` orders the uploads; the call synchronises it before returning.
+ * Errors: INVALID_ARG (bad descriptor, odd or non-antipodal sphere rule),
+ * UNSUPPORTED (sizes beyond the kernels' limits), OUT_OF_MEMORY, DEVICE. */
+pgc_status pgc_plan_create(const pgc_plan_desc* desc, void* stream, pgc_plan* plan_out);
+
+/* Free the plan and its workspace (NULL is a no-op).  Synchronises the device. */
+pgc_status pgc_plan_destroy(pgc_plan plan);
+
+/* Copy the plan's resolved parameters into *info (host only). */
+pgc_status pgc_plan_query(pgc_plan plan, pgc_plan_info* info);
+
+/* Host copies of the m_v CGL nodes xi_j, mapped velocities v_j (endpoints
+ * -/+HUGE_VAL) and weights w_j.  Any pointer may be NULL. */
+pgc_status pgc_nodes(pgc_plan plan, double* xi_host, double* v_host, double* w_host);
+
+/* Coefficients of the initial data, eq. (MultiD_spectral_coef) by the
+ * interior CGL rule: f_k = sum_i w_i mu_i^-4 f(v_i) T_k(xi_i)/sqrt(c_k).
+ * f_nodes_dev: n_i^dim doubles (f at the interior nodes); coeffs_dev: N^dim
+ * in the plan's precision. */
+pgc_status pgc_project(pgc_plan plan, const double* f_nodes_dev, void* coeffs_dev, void* stream);
+
+/* The hot path: Q = Q+ - Q- for the coefficients coeffs_dev (N^dim, plan
+ * precision).  q_dev receives Q (N^dim); qplus_dev, if not NULL, receives Q+.
+ * Steps: Chebyshev synthesis of f_N at the nodes (Sec. 4.2), loss field and
+ * loss projection (eq. Qminus), generation of every collision triple and
+ * spreading of its weight onto the folded fine grid (eqs. num_fast_k, nufft),
+ * cosine transform, deconvolution and the final combination. */
+pgc_status pgc_coeffs_to_q(pgc_plan plan, const void* coeffs_dev, void* q_dev, void* qplus_dev,
+                           void* stream);
+
+/* n_steps classical fourth-order Runge-Kutta steps of size dt on
+ * d f_k/dt = Q_k (eq. spectral_ODE), in place on coeffs_dev (N^dim doubles,
+ * whatever the plan precision; FP32 plans round each stage input to float). */
+pgc_status pgc_rk4(pgc_plan plan, double* coeffs_dev, double dt, int32_t n_steps, void* stream);
+
+/* Mass, momentum (dim values) and energy int |v|^2 f_N dv of the expansion
+ * with coefficients coeffs_dev (plan precision), eq. (def_mom), computed in
+ * FP64 from 1D moment functionals: out_dev receives dim + 2 doubles. */
+pgc_status pgc_moments(pgc_plan plan, const void* coeffs_dev, double* out_dev, void* stream);
+
+/* out_dev[r] = sum_k c_k T~_k(v_r) for n velocities v_dev (n x dim doubles);
+ * coeffs_dev in the plan's precision, evaluation in FP64.  Evaluates f_N and
+ * Q_N = sum_k Q_k T~_k (the equivalent form, eq. P_G_method) off the hot path. */
+pgc_status pgc_eval(pgc_plan plan, const void* coeffs_dev, const double* v_dev, int64_t n,
+                    double* out_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PGC_H */

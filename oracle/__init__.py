@@ -173,6 +173,14 @@ class Problem:
                                       _dp(qm)), "collision_at")
         return qp, qm
 
+    def gain_units(self, coeffs, u_lo, u_hi):
+        """Q+ restricted to the collision units [u_lo, u_hi), u = s * n_i^dim + i."""
+        c = np.ascontiguousarray(coeffs, dtype=np.float64)
+        out = np.zeros(self.shape())
+        _check(lib().ora_gain_units(ctypes.byref(self._c), _dp(c), ctypes.c_int64(u_lo),
+                                    ctypes.c_int64(u_hi), _dp(out)), "gain_units")
+        return out
+
     def eval(self, coeffs, v):
         return eval_expansion(self.dim, self.n_modes, self.map, self.S, coeffs, v)
 

@@ -387,13 +387,12 @@ static void loss_field(const ora_problem* p, const ora_tables* t, const ora_node
  * Units (s, i) are split statically over threads; the per-thread partial sums
  * are added in thread order.  With n_k > 0 only the listed k are formed. */
 static void gain_sum(const ora_problem* p, const ora_tables* t, const ora_nodes* nd,
-                     int n_k, const int* kidx, double* out)
+                     int n_k, const int* kidx, int64_t u_lo, int64_t u_hi, double* out)
 {
     int dim = t->dim, N = t->N;
     int64_t nout = n_k > 0 ? n_k : t->Nd;
     int nth = ora_num_threads();
     double* part = (double*)calloc((size_t)nth * nout, sizeof(double));
-    int64_t n_units = (int64_t)p->n_sigma * t->nd;
 #pragma omp parallel
     {
         int tid = 0;
@@ -403,7 +402,7 @@ static void gain_sum(const ora_problem* p, const ora_tables* t, const ora_nodes*
         double* acc = part + (size_t)tid * nout;
         double* a = (double*)malloc(sizeof(double) * 3 * N);
 #pragma omp for schedule(static)
-        for (int64_t u = 0; u < n_units; ++u) {
+        for (int64_t u = u_lo; u < u_hi; ++u) {
             int s = (int)(u / t->nd);
             int64_t i = u % t->nd;
             const double* sg = p->sigma + (size_t)s * dim;
@@ -503,7 +502,7 @@ int ora_collision(const ora_problem* p, const double* coeffs, double* q, double*
     nodes_init(&t, coeffs, &nd);
     double* gp = (double*)malloc(sizeof(double) * t.Nd);
     double* gm = (double*)malloc(sizeof(double) * t.Nd);
-    gain_sum(p, &t, &nd, 0, NULL, gp);
+    gain_sum(p, &t, &nd, 0, NULL, 0, (int64_t)p->n_sigma * t.nd, gp);
     loss_sum(p, &t, &nd, 0, NULL, gm);
     for (int64_t k = 0; k < t.Nd; ++k) {
         if (q) q[k] = gp[k] - gm[k];
@@ -527,8 +526,26 @@ int ora_collision_at(const ora_problem* p, const double* coeffs, int n_k, const 
     tables_init(p, &t);
     ora_nodes nd;
     nodes_init(&t, coeffs, &nd);
-    if (qplus) gain_sum(p, &t, &nd, n_k, kidx, qplus);
+    if (qplus) gain_sum(p, &t, &nd, n_k, kidx, 0, (int64_t)p->n_sigma * t.nd, qplus);
     if (qminus) loss_sum(p, &t, &nd, n_k, kidx, qminus);
+    nodes_free(&nd);
+    tables_free(&t);
+    return 0;
+}
+
+int ora_gain_units(const ora_problem* p, const double* coeffs, int64_t u_lo, int64_t u_hi,
+                   double* qplus)
+{
+    if (check_problem(p) || check_sphere(p)) return -1;
+    ora_tables t;
+    tables_init(p, &t);
+    if (u_lo < 0 || u_hi < u_lo || u_hi > (int64_t)p->n_sigma * t.nd) {
+        tables_free(&t);
+        return -1;
+    }
+    ora_nodes nd;
+    nodes_init(&t, coeffs, &nd);
+    gain_sum(p, &t, &nd, 0, NULL, u_lo, u_hi, qplus);
     nodes_free(&nd);
     tables_free(&t);
     return 0;

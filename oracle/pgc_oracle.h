@@ -61,9 +61,10 @@ int ora_collision(const ora_problem* p, const double* coeffs,
 /* The same sums for n_k selected multi-indices kidx (n_k x dim) only. */
 int ora_collision_at(const ora_problem* p, const double* coeffs, int n_k,
                      const int* kidx, double* qplus, double* qminus);
-/* Gain restricted to the units (s, i) with s in [s_lo, s_hi). */
-int ora_gain_units(const ora_problem* p, const double* coeffs, int s_lo, int s_hi,
-                   int n_k, const int* kidx, double* qplus);
+/* The gain restricted to the collision units u = s * n_i^dim + i with
+ * u_lo <= u < u_hi (all N^dim outputs); the units partition the sum. */
+int ora_gain_units(const ora_problem* p, const double* coeffs, int64_t u_lo, int64_t u_hi,
+                   double* qplus);
 
 /* sum_k c_k T~_k(v) at n velocities v (n x dim). */
 int ora_eval(int dim, int n_modes, int map, double S, const double* coeffs,

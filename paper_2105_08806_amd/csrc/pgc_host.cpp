@@ -1,0 +1,679 @@
+// Host side of the library: descriptor validation, the FP64 plan tables
+// (nodes, maps, sphere rules, Chebyshev and cosine-transform matrices, the
+// spreading kernel and its Fourier transform, moment functionals), device
+// allocation and the extern "C" entry points declared in pgc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <vector>
+
+#include "pgc.h"
+#include "pgc_internal.h"
+
+namespace pgc {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// ---------------------------------------------------------------- small math
+
+// Gauss-Legendre rule on [-1, 1] by Newton iteration on P_n (three-term
+// recurrence), started from the asymptotic node positions.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double t = std::cos(kPi * (4.0 * i + 3.0) / (4.0 * n + 2.0));
+        double pn = 0.0, dpn = 1.0;
+        for (int it = 0; it < 60; ++it) {
+            double p0 = 1.0, p1 = t;
+            for (int k = 1; k < n; ++k) {
+                const double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            pn = (n == 0) ? 1.0 : p1;
+            const double pm = (n == 1) ? 1.0 : p0;
+            dpn = n * (pm - t * pn) / (1.0 - t * t);
+            const double step = pn / dpn;
+            t -= step;
+            if (std::fabs(step) <= 1e-16 * std::fabs(t) + 1e-300) break;
+        }
+        x[n - 1 - i] = t;
+        x[i] = -t;
+        const double wi = 2.0 / ((1.0 - t * t) * dpn * dpn);
+        w[i] = wi;
+        w[n - 1 - i] = wi;
+    }
+}
+
+// exponential of semicircle kernel on [-1, 1]
+double es_kernel(double y, double beta)
+{
+    if (std::fabs(y) >= 1.0) return 0.0;
+    return std::exp(beta * (std::sqrt(1.0 - y * y) - 1.0));
+}
+
+// Accuracy table of the folded cosine transform at upsampling 2, measured on
+// random points against the direct sum (max error over modes / sum |q|),
+// for W = 4..16; entries beyond 13 sit at the FP64 rounding floor.
+const double kErrSigma2[] = {1.3e-5, 1.2e-6, 2.3e-7, 2.3e-8, 1.8e-9, 2.4e-10, 3.2e-11,
+                             3.4e-12, 2.1e-13, 3.3e-14, 2.5e-14, 2.5e-14, 2.5e-14};
+
+double estimated_error(int W, double upsample)
+{
+    if (std::fabs(upsample - 2.0) < 1e-12) return 3.0 * kErrSigma2[W - 4];
+    // exp(-pi W sqrt(1 - 1/sigma)) decay of the ES kernel, with a safety factor
+    return 10.0 * std::exp(-kPi * W * std::sqrt(1.0 - 1.0 / upsample));
+}
+
+double beta_for(int W, double upsample)
+{
+    // beta = 0.98 pi W (1 - 1/(2 sigma)): the shape rule of the ES kernel
+    // (2.30 W at sigma = 2)
+    return 0.98 * kPi * W * (1.0 - 0.5 / upsample);
+}
+
+int width_for(double tol, double upsample)
+{
+    for (int W = 4; W <= kMaxWidth; ++W)
+        if (estimated_error(W, upsample) <= tol) return W;
+    return kMaxWidth;
+}
+
+// Monomial coefficients (in s on [-1, 1]) of the degree terms-1 Chebyshev
+// interpolant of g on the Chebyshev points of the first kind.
+template <class F>
+void cheb_interp_monomial(F g, int terms, double* mono)
+{
+    const int n = terms;
+    std::vector<double> fx(n), cc(n, 0.0);
+    for (int j = 0; j < n; ++j) fx[j] = g(std::cos(kPi * (j + 0.5) / n));
+    for (int k = 0; k < n; ++k) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += fx[j] * std::cos(kPi * k * (j + 0.5) / n);
+        cc[k] = (k == 0 ? 1.0 : 2.0) * s / n;
+    }
+    // sum_k cc_k T_k(s) -> monomials, T_{k+1} = 2 s T_k - T_{k-1}
+    std::vector<double> tm(n, 0.0), t(n, 0.0), tn(n, 0.0);
+    for (int d = 0; d < n; ++d) mono[d] = 0.0;
+    tm[0] = 1.0;
+    mono[0] += cc[0];
+    if (n > 1) {
+        t[1] = 1.0;
+        mono[1] += cc[1];
+    }
+    for (int k = 2; k < n; ++k) {
+        for (int d = 0; d < n; ++d) tn[d] = -tm[d] + (d > 0 ? 2.0 * t[d - 1] : 0.0);
+        for (int d = 0; d < n; ++d) mono[d] += cc[k] * tn[d];
+        tm = t;
+        t = tn;
+    }
+}
+
+// v(xi) for xi = cos(theta') written with the angle, for accuracy near +-1:
+// r = 0: S atanh(cos a) = S ln(cot(a/2)); r = 1: S cos a / sin a.
+double v_of_angle(int map, double S, double a)
+{
+    if (map == 0) return S * std::log(1.0 / std::tan(0.5 * a));
+    return S * std::cos(a) / std::sin(a);
+}
+
+double cheb_norm_sqrt(int k) { return std::sqrt(k == 0 ? kPi : 0.5 * kPi); }
+
+// ---------------------------------------------------------------- validation
+
+pgc_status resolve(const pgc_plan_desc& d, Plan& p)
+{
+    if (d.dim != 2 && d.dim != 3) return PGC_ERR_INVALID_ARG;
+    if (d.n_modes < 3) return PGC_ERR_INVALID_ARG;
+    if (d.map != PGC_MAP_LOG && d.map != PGC_MAP_ALGEBRAIC) return PGC_ERR_INVALID_ARG;
+    if (!(d.scale > 0.0) || !std::isfinite(d.scale)) return PGC_ERR_INVALID_ARG;
+    if (d.scale_mode != PGC_SCALE_DIRECT && d.scale_mode != PGC_SCALE_FROM_DOMAIN)
+        return PGC_ERR_INVALID_ARG;
+    if (d.kernel != PGC_KERNEL_MAXWELL && d.kernel != PGC_KERNEL_VHS) return PGC_ERR_INVALID_ARG;
+    if (d.kernel == PGC_KERNEL_VHS && !(d.kernel_gamma >= 0.0 && d.kernel_gamma <= 1.0))
+        return PGC_ERR_INVALID_ARG;
+    if (d.kernel_b0 < 0.0 || !std::isfinite(d.kernel_b0)) return PGC_ERR_INVALID_ARG;
+    if (d.precision != PGC_PRECISION_FP64 && d.precision != PGC_PRECISION_FP32)
+        return PGC_ERR_INVALID_ARG;
+    if (d.nufft_tol < 0.0 || d.upsample < 0.0) return PGC_ERR_INVALID_ARG;
+    if (d.upsample != 0.0 && (d.upsample < 1.5 || d.upsample > 4.0)) return PGC_ERR_INVALID_ARG;
+    if (d.kernel_width != 0 && (d.kernel_width < 4 || d.kernel_width > kMaxWidth))
+        return PGC_ERR_INVALID_ARG;
+    if (d.slab_planes < 0 || d.n_chunks < 0) return PGC_ERR_INVALID_ARG;
+    if (d.block_threads != 0 && d.block_threads != 256 && d.block_threads != 512 &&
+        d.block_threads != 1024)
+        return PGC_ERR_INVALID_ARG;
+
+    p.dim = d.dim;
+    p.N = d.n_modes;
+    p.m_v = d.m_v == 0 ? d.n_modes + 1 : d.m_v;
+    if (p.m_v < 3) return PGC_ERR_INVALID_ARG;
+    p.ni = p.m_v - 2;
+    p.map = d.map;
+    p.kernel = d.kernel;
+    p.precision = d.precision;
+    p.gamma = d.kernel == PGC_KERNEL_VHS ? d.kernel_gamma : 0.0;
+    p.elt = p.precision == PGC_PRECISION_FP64 ? sizeof(double) : sizeof(float);
+
+    // map scale: direct, or the adaptive choice v(xi_2) = -L, v(xi_{m_v-1}) = L
+    const double a1 = kPi / (p.m_v - 1);  // angle of the second node from the end
+    if (d.scale_mode == PGC_SCALE_DIRECT) p.S = d.scale;
+    else p.S = d.map == PGC_MAP_LOG ? d.scale / std::log(1.0 / std::tan(0.5 * a1))
+                                    : d.scale * std::tan(a1);
+
+    // sphere rule
+    p.sigma.clear();
+    p.sigma_w.clear();
+    if (d.sphere == PGC_SPHERE_UNIFORM_2D) {
+        if (p.dim != 2 || d.n_sigma < 2 || (d.n_sigma & 1)) return PGC_ERR_INVALID_ARG;
+        for (int s = 0; s < d.n_sigma; ++s) {
+            const double th = 2.0 * kPi * s / d.n_sigma;
+            p.sigma.push_back(std::cos(th));
+            p.sigma.push_back(std::sin(th));
+            p.sigma_w.push_back(2.0 * kPi / d.n_sigma);
+        }
+    } else if (d.sphere == PGC_SPHERE_PRODUCT_3D) {
+        if (p.dim != 3 || d.n_theta < 1 || d.n_phi < 2 || (d.n_phi & 1)) return PGC_ERR_INVALID_ARG;
+        std::vector<double> x, w;
+        gauss_legendre(d.n_theta, x, w);
+        for (int a = 0; a < d.n_theta; ++a) {
+            const double st = std::sqrt(std::max(0.0, 1.0 - x[a] * x[a]));
+            for (int b = 0; b < d.n_phi; ++b) {
+                const double ph = 2.0 * kPi * b / d.n_phi;
+                p.sigma.push_back(st * std::cos(ph));
+                p.sigma.push_back(st * std::sin(ph));
+                p.sigma.push_back(x[a]);
+                p.sigma_w.push_back(w[a] * 2.0 * kPi / d.n_phi);
+            }
+        }
+    } else if (d.sphere == PGC_SPHERE_USER) {
+        if (d.n_sigma < 1 || !d.user_sigma_host || !d.user_weights_host) return PGC_ERR_INVALID_ARG;
+        for (int s = 0; s < d.n_sigma; ++s) {
+            double nrm = 0.0;
+            for (int l = 0; l < p.dim; ++l) {
+                const double c = d.user_sigma_host[s * p.dim + l];
+                nrm += c * c;
+                p.sigma.push_back(c);
+            }
+            const double wt = d.user_weights_host[s];
+            if (std::fabs(nrm - 1.0) > 1e-12 || !(wt > 0.0) || !std::isfinite(wt))
+                return PGC_ERR_INVALID_ARG;
+            p.sigma_w.push_back(wt);
+        }
+    } else {
+        return PGC_ERR_INVALID_ARG;
+    }
+    p.n_sigma = (int)p.sigma_w.size();
+    // antipodal symmetry: the discrete energy balance pairs (s, i, j) with
+    // (-s, j, i), so every direction needs its opposite with the same weight
+    for (int s = 0; s < p.n_sigma; ++s) {
+        bool found = false;
+        for (int t = 0; t < p.n_sigma && !found; ++t) {
+            double dist = 0.0;
+            for (int l = 0; l < p.dim; ++l) {
+                const double e = p.sigma[s * p.dim + l] + p.sigma[t * p.dim + l];
+                dist += e * e;
+            }
+            found = dist < 1e-20 && std::fabs(p.sigma_w[s] - p.sigma_w[t]) <= 1e-12 * p.sigma_w[s];
+        }
+        if (!found) return PGC_ERR_INVALID_ARG;
+    }
+    p.wsum = 0.0;
+    for (double w : p.sigma_w) p.wsum += w;
+    const double area = p.dim == 2 ? 2.0 * kPi : 4.0 * kPi;
+    p.b0 = d.kernel_b0 > 0.0 ? d.kernel_b0 : 1.0 / area;
+
+    // spreading kernel and fine grid
+    p.upsample = d.upsample > 0.0 ? d.upsample : 2.0;
+    p.tol = d.nufft_tol > 0.0 ? d.nufft_tol : (p.precision == PGC_PRECISION_FP64 ? 1e-13 : 1e-7);
+    p.W = d.kernel_width > 0 ? d.kernel_width : width_for(p.tol, p.upsample);
+    p.terms = p.W + 2;
+    p.beta = beta_for(p.W, p.upsample);
+    // n >= 2 sigma N, and n/2 >= W so that a footprint folds back at most once
+    // (small N only: a finer grid is merely a larger upsampling factor)
+    p.n = std::max(2 * (int)std::ceil(p.upsample * p.N), 2 * p.W);
+    p.nh = p.n / 2;
+    p.ng = p.nh + 1;
+    p.h = 2.0 * kPi / p.n;
+
+    auto ipow = [](int64_t b, int e) {
+        int64_t r = 1;
+        for (int i = 0; i < e; ++i) r *= b;
+        return r;
+    };
+    p.nid = ipow(p.ni, p.dim);
+    p.Nd = ipow(p.N, p.dim);
+    p.ngd = ipow(p.ng, p.dim);
+    p.n_units = (int64_t)p.n_sigma * p.nid;
+    p.n_triples = p.n_units * p.nid;
+
+    // LDS slabs along the first dimension
+    const int64_t plane_bytes = ipow(p.ng, p.dim - 1) * (int64_t)sizeof(double);  // FP64 cells
+    const int64_t max_planes = kLdsBudget / plane_bytes;
+    if (max_planes < 1) return PGC_ERR_UNSUPPORTED;
+    int planes = d.slab_planes > 0 ? d.slab_planes : (int)std::min<int64_t>(p.ng, max_planes);
+    if (planes > max_planes) return PGC_ERR_UNSUPPORTED;
+    planes = std::min(planes, p.ng);
+    p.n_slabs = (p.ng + planes - 1) / planes;
+    p.slab_planes = (p.ng + p.n_slabs - 1) / p.n_slabs;
+
+    // chunks of collision units: enough workgroups to fill 256 CUs several times
+    int64_t chunks = d.n_chunks > 0 ? d.n_chunks : std::max<int64_t>(1, 2048 / p.n_slabs);
+    chunks = std::min<int64_t>(chunks, p.n_units);
+    const int64_t cap = std::max<int64_t>(1, (int64_t)(1ll << 31) / (p.ngd * (int64_t)sizeof(double)));
+    chunks = std::max<int64_t>(1, std::min(chunks, cap));
+    p.units_per_chunk = (p.n_units + chunks - 1) / chunks;
+    p.n_chunks = (int)((p.n_units + p.units_per_chunk - 1) / p.units_per_chunk);
+    if ((int64_t)p.n_chunks > 2147483647ll) return PGC_ERR_UNSUPPORTED;
+    const int max_threads = p.precision == PGC_PRECISION_FP64 ? 512 : 1024;
+    if (d.block_threads > max_threads) return PGC_ERR_UNSUPPORTED;
+    p.block_threads = d.block_threads > 0 ? d.block_threads : max_threads;
+    return PGC_OK;
+}
+
+// ---------------------------------------------------------------- tables
+
+void build_tables(Plan& p)
+{
+    const int m = p.m_v;
+    p.xi_all.assign(m, 0.0);
+    p.v_all.assign(m, 0.0);
+    p.w_all.assign(m, 0.0);
+    for (int j = 0; j < m; ++j) {
+        // xi_j = -cos(theta_j) = cos(pi - theta_j), theta_j = pi j/(m-1)
+        const double a = kPi * (m - 1 - j) / (m - 1);
+        p.xi_all[j] = (j == 0) ? -1.0 : (j == m - 1 ? 1.0 : std::cos(a));
+        const bool end = (j == 0 || j == m - 1);
+        p.w_all[j] = end ? kPi / (2.0 * (m - 1)) : kPi / (m - 1);
+        p.v_all[j] = end ? (j == 0 ? -HUGE_VAL : HUGE_VAL) : v_of_angle(p.map, p.S, a);
+    }
+    const int ni = p.ni, N = p.N;
+    p.v1.assign(ni, 0.0);
+    p.w1.assign(ni, 0.0);
+    p.mu21.assign(ni, 0.0);
+    p.C.assign((size_t)ni * N, 0.0);
+    p.CT.assign((size_t)N * ni, 0.0);
+    for (int i = 0; i < ni; ++i) {
+        const int j = i + 1;
+        const double a = kPi * (m - 1 - j) / (m - 1);
+        const double sa = std::sin(a);  // sqrt(1 - xi^2)
+        p.v1[i] = p.v_all[j];
+        p.w1[i] = p.w_all[j];
+        p.mu21[i] = (p.map == PGC_MAP_LOG ? sa : sa * sa) / p.S;
+        for (int k = 0; k < N; ++k) {
+            const double tk = std::cos(k * a) / cheb_norm_sqrt(k);  // T_k(cos a) = cos(k a)
+            p.C[(size_t)i * N + k] = tk;
+            p.CT[(size_t)k * ni + i] = tk;
+        }
+    }
+
+    // kernel cells: g_a(s) = psi((a - W/2 + (s+1)/2) 2/W), s in [-1, 1]
+    const int W = p.W, terms = p.terms;
+    p.poly.assign((size_t)terms * W, 0.0);
+    std::vector<double> mono(terms);
+    for (int a = 0; a < W; ++a) {
+        cheb_interp_monomial(
+            [&](double s) { return es_kernel((a - 0.5 * W + 0.5 * (s + 1.0)) * 2.0 / W, p.beta); },
+            terms, mono.data());
+        for (int d = 0; d < terms; ++d) p.poly[(size_t)d * W + a] = mono[d];
+    }
+
+    // Fourier transform of the kernel in z units, psi^(k) = int psi(x/alpha) cos(k x) dx,
+    // alpha = W h / 2, by a 256-point Gauss-Legendre rule in x/alpha
+    std::vector<double> gx, gw;
+    gauss_legendre(256, gx, gw);
+    const double alpha = 0.5 * W * p.h;
+    std::vector<double> psihat(N);
+    for (int k = 0; k < N; ++k) {
+        double s = 0.0;
+        for (size_t q = 0; q < gx.size(); ++q)
+            s += gw[q] * es_kernel(gx[q], p.beta) * std::cos(k * alpha * gx[q]);
+        psihat[k] = alpha * s;
+    }
+    // E[k][m] = cos(k m h) h / (psi^(k) sqrt(c_k)): cosine transform of the folded
+    // grid, deconvolution and the Chebyshev normalisation in one matrix
+    p.E.assign((size_t)N * p.ng, 0.0);
+    for (int k = 0; k < N; ++k)
+        for (int mm = 0; mm < p.ng; ++mm)
+            p.E[(size_t)k * p.ng + mm] = std::cos((double)k * mm * p.h) * p.h /
+                                         (psihat[k] * cheb_norm_sqrt(k));
+
+    // v'_1 window of each slab: a point at grid coordinate x = z/h touches the
+    // folded planes [p0, p1) iff x lies in [p0 - W/2, p1 - 1 + W/2] (reflections
+    // at 0 and pi only add planes nearer the walls); one extra cell of margin.
+    p.slab_vlo.assign(p.n_slabs, 0.0);
+    p.slab_vhi.assign(p.n_slabs, 0.0);
+    for (int b = 0; b < p.n_slabs; ++b) {
+        const int p0 = b * p.slab_planes;
+        const int p1 = std::min(p.ng, p0 + p.slab_planes);
+        const double xlo = p0 - 0.5 * W - 1.0;
+        const double xhi = (p1 - 1) + 0.5 * W + 1.0;
+        const double zlo = xlo * p.h, zhi = xhi * p.h;
+        // z = arccos(xi(v)) decreases in v
+        p.slab_vhi[b] = zlo <= 0.0 ? HUGE_VAL : v_of_angle(p.map, p.S, zlo);
+        p.slab_vlo[b] = zhi >= kPi ? -HUGE_VAL : v_of_angle(p.map, p.S, zhi);
+    }
+
+    // moment functionals m_p[k] = int v^p T~_k(v) dv, p = 0, 1, 2
+    p.mom.assign(3 * (size_t)N, 0.0);
+    const double S = p.S;
+    if (p.map == PGC_MAP_ALGEBRAIC) {
+        // xi = cos a: mu^4 dv = sin(a)^2/S da-type closed forms
+        for (int k = 0; k < N; ++k) {
+            const double sc = cheb_norm_sqrt(k);
+            p.mom[k] = (k == 0 ? kPi / 2 : (k == 2 ? -kPi / 4 : 0.0)) / (S * sc);
+            p.mom[2 * N + k] = S * (k == 0 ? kPi / 2 : (k == 2 ? kPi / 4 : 0.0)) / sc;
+            // int_{-1}^{1} xi T_k(xi) dxi: nonzero for odd k
+            double m1 = 0.0;
+            if (k & 1) {
+                auto int_t = [](int n) { return (n & 1) ? 0.0 : 2.0 / (1.0 - (double)n * n); };
+                m1 = 0.5 * (int_t(k + 1) + int_t(k - 1));
+            }
+            p.mom[N + k] = m1 / sc;
+        }
+    } else {
+        // r = 0: m_p[k] = S^p/(S sqrt c_k) int y^p T_k(tanh y) sech^2 y dy over R,
+        // composite 16-point Gauss-Legendre on [-48, 48] in panels of width 1
+        std::vector<double> px, pw;
+        gauss_legendre(16, px, pw);
+        std::vector<double> acc(3 * (size_t)N, 0.0);
+        for (int panel = -48; panel < 48; ++panel) {
+            for (int q = 0; q < 16; ++q) {
+                const double y = panel + 0.5 + 0.5 * px[q];
+                const double c = std::cosh(y);
+                const double wgt = 0.5 * pw[q] / (c * c);
+                const double ang = std::acos(std::tanh(y));
+                for (int k = 0; k < N; ++k) {
+                    const double t = std::cos(k * ang) * wgt;
+                    acc[k] += t;
+                    acc[N + k] += t * y;
+                    acc[2 * N + k] += t * y * y;
+                }
+            }
+        }
+        for (int k = 0; k < N; ++k) {
+            const double sc = cheb_norm_sqrt(k);
+            p.mom[k] = acc[k] / (S * sc);
+            p.mom[N + k] = acc[N + k] / sc;
+            p.mom[2 * N + k] = S * acc[2 * N + k] / sc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- device memory
+
+hipError_t dev_alloc(Plan& p, void** ptr, size_t bytes)
+{
+    *ptr = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) return e;
+    p.allocations.push_back(*ptr);
+    p.workspace_bytes += (int64_t)bytes;
+    return hipSuccess;
+}
+
+hipError_t upload(Plan& p, void** dst, const std::vector<double>& src, hipStream_t s)
+{
+    hipError_t e = dev_alloc(p, dst, src.size() * p.elt);
+    if (e != hipSuccess || src.empty()) return e;
+    if (p.precision == PGC_PRECISION_FP64)
+        return hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    std::vector<float> f(src.begin(), src.end());
+    e = hipMemcpyAsync(*dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);  // f is about to go out of scope
+}
+
+void free_all(Plan& p)
+{
+    for (void* ptr : p.allocations) (void)hipFree(ptr);
+    p.allocations.clear();
+}
+
+pgc_status from_hip(hipError_t e)
+{
+    if (e == hipSuccess) return PGC_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return PGC_ERR_OUT_OF_MEMORY;
+    return PGC_ERR_DEVICE;
+}
+
+hipError_t allocate(Plan& p, hipStream_t s)
+{
+    hipError_t e;
+#define PGC_TRY(x)               \
+    do {                         \
+        e = (x);                 \
+        if (e != hipSuccess) return e; \
+    } while (0)
+    // the FP64 double-HUGE_VAL windows become +-inf in float as well
+    PGC_TRY(upload(p, &p.dt.v1, p.v1, s));
+    PGC_TRY(upload(p, &p.dt.w1, p.w1, s));
+    PGC_TRY(upload(p, &p.dt.mu21, p.mu21, s));
+    PGC_TRY(upload(p, &p.dt.C, p.C, s));
+    PGC_TRY(upload(p, &p.dt.CT, p.CT, s));
+    PGC_TRY(upload(p, &p.dt.E, p.E, s));
+    PGC_TRY(upload(p, &p.dt.poly, p.poly, s));
+    PGC_TRY(upload(p, &p.dt.sigma, p.sigma, s));
+    PGC_TRY(upload(p, &p.dt.sigma_w, p.sigma_w, s));
+    PGC_TRY(upload(p, &p.dt.slab_vlo, p.slab_vlo, s));
+    PGC_TRY(upload(p, &p.dt.slab_vhi, p.slab_vhi, s));
+
+    const int64_t L = std::max<int64_t>(std::max(p.N, p.ni), p.ng);
+    int64_t t = 1;
+    for (int l = 0; l < p.dim; ++l) t *= L;
+    p.tmp_elems = t;
+    const size_t e8 = p.elt;
+    PGC_TRY(dev_alloc(p, &p.ws.P, p.nid * e8));
+    PGC_TRY(dev_alloc(p, &p.ws.G, p.nid * e8));
+    PGC_TRY(dev_alloc(p, &p.ws.H, p.nid * e8));
+    PGC_TRY(dev_alloc(p, &p.ws.partial, (size_t)p.n_chunks * p.ngd * sizeof(double)));
+    PGC_TRY(dev_alloc(p, &p.ws.grid, p.ngd * e8));
+    PGC_TRY(dev_alloc(p, &p.ws.tmpA, t * e8));
+    PGC_TRY(dev_alloc(p, &p.ws.tmpB, t * e8));
+    PGC_TRY(dev_alloc(p, &p.ws.qminus, p.Nd * e8));
+    PGC_TRY(dev_alloc(p, &p.ws.qplus, p.Nd * e8));
+    PGC_TRY(dev_alloc(p, &p.ws.rk_y, p.Nd * e8));
+    for (int r = 0; r < 4; ++r) PGC_TRY(dev_alloc(p, &p.ws.rk_k[r], p.Nd * e8));
+    void* red = nullptr;
+    PGC_TRY(dev_alloc(p, &red, 64 * sizeof(double)));
+    p.ws.red = static_cast<double*>(red);
+    void* mom = nullptr;
+    PGC_TRY(dev_alloc(p, &mom, p.mom.size() * sizeof(double)));
+    p.ws.mom = static_cast<double*>(mom);
+    PGC_TRY(hipMemcpyAsync(mom, p.mom.data(), p.mom.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    PGC_TRY(hipStreamSynchronize(s));
+#undef PGC_TRY
+    return hipSuccess;
+}
+
+}  // namespace
+}  // namespace pgc
+
+// ==================================================================== C ABI
+
+using pgc::Plan;
+
+struct pgc_plan_s {
+    Plan p;
+};
+
+extern "C" {
+
+const char* pgc_status_string(pgc_status s)
+{
+    switch (s) {
+    case PGC_OK: return "ok";
+    case PGC_ERR_INVALID_ARG: return "invalid argument";
+    case PGC_ERR_UNSUPPORTED: return "unsupported configuration";
+    case PGC_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case PGC_ERR_DEVICE: return "device error";
+    case PGC_ERR_NUMERIC: return "non-finite result";
+    }
+    return "unknown status";
+}
+
+pgc_status pgc_desc_init(pgc_plan_desc* d)
+{
+    if (!d) return PGC_ERR_INVALID_ARG;
+    std::memset(d, 0, sizeof(*d));
+    d->dim = 2;
+    d->n_modes = 16;
+    d->map = PGC_MAP_LOG;
+    d->scale_mode = PGC_SCALE_DIRECT;
+    d->scale = 4.0;
+    d->kernel = PGC_KERNEL_MAXWELL;
+    d->sphere = PGC_SPHERE_UNIFORM_2D;
+    d->n_sigma = 16;
+    d->precision = PGC_PRECISION_FP64;
+    return PGC_OK;
+}
+
+pgc_status pgc_nufft_params(double tol, double upsample, int32_t* width, double* beta)
+{
+    if (!(tol > 0.0) || !(upsample >= 1.5 && upsample <= 4.0)) return PGC_ERR_INVALID_ARG;
+    const int W = pgc::width_for(tol, upsample);
+    if (width) *width = W;
+    if (beta) *beta = pgc::beta_for(W, upsample);
+    return PGC_OK;
+}
+
+pgc_status pgc_plan_create(const pgc_plan_desc* desc, void* stream, pgc_plan* plan_out)
+{
+    if (!desc || !plan_out) return PGC_ERR_INVALID_ARG;
+    *plan_out = nullptr;
+    pgc_plan_s* h = nullptr;
+    try {
+        h = new pgc_plan_s();
+    } catch (const std::bad_alloc&) {
+        return PGC_ERR_OUT_OF_MEMORY;
+    }
+    pgc_status st = pgc::resolve(*desc, h->p);
+    if (st != PGC_OK) {
+        delete h;
+        return st;
+    }
+    try {
+        pgc::build_tables(h->p);
+    } catch (const std::bad_alloc&) {
+        delete h;
+        return PGC_ERR_OUT_OF_MEMORY;
+    }
+    hipError_t e = pgc::allocate(h->p, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        pgc::free_all(h->p);
+        delete h;
+        return pgc::from_hip(e);
+    }
+    *plan_out = h;
+    return PGC_OK;
+}
+
+pgc_status pgc_plan_destroy(pgc_plan plan)
+{
+    if (!plan) return PGC_OK;
+    (void)hipDeviceSynchronize();
+    pgc::free_all(plan->p);
+    delete plan;
+    return PGC_OK;
+}
+
+pgc_status pgc_plan_query(pgc_plan plan, pgc_plan_info* info)
+{
+    if (!plan || !info) return PGC_ERR_INVALID_ARG;
+    const Plan& p = plan->p;
+    std::memset(info, 0, sizeof(*info));
+    info->dim = p.dim;
+    info->n_modes = p.N;
+    info->m_v = p.m_v;
+    info->map = p.map;
+    info->kernel = p.kernel;
+    info->precision = p.precision;
+    info->n_sigma = p.n_sigma;
+    info->scale = p.S;
+    info->grid_n = p.n;
+    info->grid_folded = p.ng;
+    info->kernel_width = p.W;
+    info->kernel_beta = p.beta;
+    info->upsample = p.upsample;
+    info->slab_planes = p.slab_planes;
+    info->n_slabs = p.n_slabs;
+    info->n_chunks = p.n_chunks;
+    info->block_threads = p.block_threads;
+    info->n_triples = p.n_triples;
+    info->workspace_bytes = p.workspace_bytes;
+    return PGC_OK;
+}
+
+pgc_status pgc_nodes(pgc_plan plan, double* xi, double* v, double* w)
+{
+    if (!plan) return PGC_ERR_INVALID_ARG;
+    const Plan& p = plan->p;
+    for (int j = 0; j < p.m_v; ++j) {
+        if (xi) xi[j] = p.xi_all[j];
+        if (v) v[j] = p.v_all[j];
+        if (w) w[j] = p.w_all[j];
+    }
+    return PGC_OK;
+}
+
+pgc_status pgc_project(pgc_plan plan, const double* f_nodes, void* coeffs, void* stream)
+{
+    if (!plan || !f_nodes || !coeffs) return PGC_ERR_INVALID_ARG;
+    return pgc::from_hip(pgc::launch_project(plan->p, f_nodes, coeffs, static_cast<hipStream_t>(stream)));
+}
+
+pgc_status pgc_coeffs_to_q(pgc_plan plan, const void* coeffs, void* q, void* qplus, void* stream)
+{
+    if (!plan || !coeffs || !q) return PGC_ERR_INVALID_ARG;
+    const Plan& p = plan->p;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = pgc::launch_synthesis(p, coeffs, s);
+    if (e == hipSuccess) e = pgc::launch_loss(p, s);
+    if (e == hipSuccess) e = pgc::launch_gain(p, s);
+    if (e == hipSuccess) e = pgc::launch_combine(p, q, qplus, s);
+    return pgc::from_hip(e);
+}
+
+pgc_status pgc_rk4(pgc_plan plan, double* coeffs, double dt, int32_t n_steps, void* stream)
+{
+    if (!plan || !coeffs || n_steps < 0 || !std::isfinite(dt)) return PGC_ERR_INVALID_ARG;
+    const Plan& p = plan->p;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double a[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
+    for (int st = 0; st < n_steps; ++st) {
+        for (int r = 0; r < 4; ++r) {
+            hipError_t e = pgc::launch_rk_stage(p, coeffs, r == 0 ? nullptr : p.ws.rk_k[r - 1], a[r],
+                                                p.ws.rk_y, s);
+            if (e != hipSuccess) return pgc::from_hip(e);
+            pgc_status q = pgc_coeffs_to_q(plan, p.ws.rk_y, p.ws.rk_k[r], nullptr, stream);
+            if (q != PGC_OK) return q;
+        }
+        hipError_t e = pgc::launch_rk_finish(p, coeffs, dt, s);
+        if (e != hipSuccess) return pgc::from_hip(e);
+    }
+    return PGC_OK;
+}
+
+pgc_status pgc_moments(pgc_plan plan, const void* coeffs, double* out, void* stream)
+{
+    if (!plan || !coeffs || !out) return PGC_ERR_INVALID_ARG;
+    return pgc::from_hip(pgc::launch_moments(plan->p, coeffs, out, static_cast<hipStream_t>(stream)));
+}
+
+pgc_status pgc_eval(pgc_plan plan, const void* coeffs, const double* v, int64_t n, double* out,
+                    void* stream)
+{
+    if (!plan || n < 0 || (n > 0 && (!coeffs || !v || !out))) return PGC_ERR_INVALID_ARG;
+    if (n > 2147483647ll) return PGC_ERR_UNSUPPORTED;
+    return pgc::from_hip(pgc::launch_eval(plan->p, coeffs, v, n, out, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

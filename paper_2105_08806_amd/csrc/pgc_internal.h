@@ -1,0 +1,93 @@
+// Internal declarations shared by the host plan code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "pgc.h"
+
+namespace pgc {
+
+constexpr int kMaxWidth = 16;         // largest spreading kernel width W
+constexpr int kMaxPolyTerms = 18;     // Horner terms per kernel cell (degree + 1)
+constexpr int kMaxLdsBytes = 160 * 1024;
+constexpr int kLdsBudget = 155 * 1024;  // slab bytes per workgroup
+
+// Device pointers of one precision (T = float or double).
+struct DeviceTables {
+    void* v1 = nullptr;       // n_i      interior node velocities
+    void* w1 = nullptr;       // n_i      CGL weights
+    void* mu21 = nullptr;     // n_i      mu(xi)^2
+    void* C = nullptr;        // n_i x N  T_k(xi_i)/sqrt(c_k)
+    void* CT = nullptr;       // N x n_i  transpose of C
+    void* E = nullptr;        // N x n_g  cos(k m h) h / (psi^(k) sqrt(c_k))
+    void* poly = nullptr;     // terms x W Horner coefficients of the kernel cells
+    void* sigma = nullptr;    // n_sigma x dim
+    void* sigma_w = nullptr;  // n_sigma
+    void* slab_vlo = nullptr; // n_slabs  v'_1 window of each slab
+    void* slab_vhi = nullptr; // n_slabs
+};
+
+struct Workspace {
+    void* P = nullptr;        // n_i^d  polynomial part at the interior nodes
+    void* G = nullptr;        // n_i^d  w_i g_i = w_i mu_i^2 P_i
+    void* H = nullptr;        // n_i^d  w_i A_i P_i (loss integrand) / projection input
+    void* partial = nullptr;  // n_chunks x n_g^d  per-chunk fine grids (FP64 cells)
+    void* grid = nullptr;     // n_g^d  reduced fine grid
+    void* tmpA = nullptr;     // separable-transform ping-pong buffers
+    void* tmpB = nullptr;
+    void* qminus = nullptr;   // N^d
+    void* qplus = nullptr;    // N^d
+    void* rk_y = nullptr;     // N^d  stage input (plan precision)
+    void* rk_k[4] = {nullptr, nullptr, nullptr, nullptr};
+    double* red = nullptr;    // small FP64 scratch (reductions)
+    double* mom = nullptr;    // 3 x N  moment functionals m_0, m_1, m_2 (FP64)
+    double* eval_tab = nullptr;  // unused placeholder for alignment
+};
+
+struct Plan {
+    // resolved description
+    int dim = 2, N = 0, m_v = 0, ni = 0, map = 0, kernel = 0, precision = 0;
+    double S = 0.0, b0 = 0.0, gamma = 0.0, wsum = 0.0;
+    int n_sigma = 0;
+    std::vector<double> sigma, sigma_w;
+
+    // fine grid and spreading kernel
+    double upsample = 2.0, beta = 0.0, h = 0.0, tol = 0.0;
+    int W = 0, terms = 0, n = 0, nh = 0, ng = 0;
+
+    // gain decomposition
+    int slab_planes = 0, n_slabs = 0, n_chunks = 0, block_threads = 0;
+    int64_t nid = 0, Nd = 0, ngd = 0, n_units = 0, units_per_chunk = 0, n_triples = 0;
+    int64_t tmp_elems = 0;
+
+    // host tables (FP64)
+    std::vector<double> xi_all, v_all, w_all;
+    std::vector<double> v1, w1, mu21, C, CT, E, poly, slab_vlo, slab_vhi, mom;
+
+    size_t elt = 8;
+    DeviceTables dt;
+    Workspace ws;
+    int64_t workspace_bytes = 0;
+    std::vector<void*> allocations;
+};
+
+// ----- launchers (pgc_kernels.hip); all enqueue on `s` and return the launch status
+hipError_t launch_synthesis(const Plan& p, const void* coeffs, hipStream_t s);
+hipError_t launch_loss(const Plan& p, hipStream_t s);
+hipError_t launch_gain(const Plan& p, hipStream_t s);
+hipError_t launch_combine(const Plan& p, void* q, void* qplus, hipStream_t s);
+hipError_t launch_project(const Plan& p, const double* f_nodes, void* coeffs, hipStream_t s);
+hipError_t launch_moments(const Plan& p, const void* coeffs, double* out, hipStream_t s);
+hipError_t launch_eval(const Plan& p, const void* coeffs, const double* v, int64_t n, double* out,
+                       hipStream_t s);
+// y = base + a * k (stage input, plan precision); base is FP64
+hipError_t launch_rk_stage(const Plan& p, const double* base, const void* k, double a, void* y,
+                           hipStream_t s);
+// base += dt/6 (k1 + 2 k2 + 2 k3 + k4)
+hipError_t launch_rk_finish(const Plan& p, double* base, double dt, hipStream_t s);
+hipError_t launch_copy_state(const Plan& p, const double* base, void* y, hipStream_t s);
+
+}  // namespace pgc

@@ -1,0 +1,239 @@
+"""Thin Python binding of the C ABI in include/pgc.h.
+
+Argument marshalling only: every step of the collision path runs in the HIP
+kernels of ``libpgc.so``.  torch tensors supply device memory and the current
+stream; nothing here computes.  If the library is missing the import of this
+module fails loudly -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpgc.so")
+
+MAP_LOG, MAP_ALGEBRAIC = 0, 1
+SCALE_DIRECT, SCALE_FROM_DOMAIN = 0, 1
+KERNEL_MAXWELL, KERNEL_VHS = 0, 1
+SPHERE_UNIFORM_2D, SPHERE_PRODUCT_3D, SPHERE_USER = 0, 1, 2
+FP64, FP32 = 0, 1
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported configuration", 3: "out of device memory",
+          4: "device error", 5: "non-finite result"}
+
+
+class PgcError(RuntimeError):
+    def __init__(self, what, code):
+        super().__init__("%s failed: %s (%d)" % (what, STATUS.get(code, "?"), code))
+        self.code = code
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("n_modes", ctypes.c_int32), ("m_v", ctypes.c_int32),
+        ("map", ctypes.c_int32), ("scale_mode", ctypes.c_int32), ("scale", ctypes.c_double),
+        ("kernel", ctypes.c_int32), ("kernel_b0", ctypes.c_double), ("kernel_gamma", ctypes.c_double),
+        ("sphere", ctypes.c_int32), ("n_sigma", ctypes.c_int32), ("n_theta", ctypes.c_int32),
+        ("n_phi", ctypes.c_int32),
+        ("user_sigma_host", ctypes.POINTER(ctypes.c_double)),
+        ("user_weights_host", ctypes.POINTER(ctypes.c_double)),
+        ("precision", ctypes.c_int32), ("nufft_tol", ctypes.c_double), ("upsample", ctypes.c_double),
+        ("kernel_width", ctypes.c_int32), ("slab_planes", ctypes.c_int32),
+        ("n_chunks", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+    ]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("n_modes", ctypes.c_int32), ("m_v", ctypes.c_int32),
+        ("map", ctypes.c_int32), ("kernel", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("n_sigma", ctypes.c_int32), ("scale", ctypes.c_double), ("grid_n", ctypes.c_int32),
+        ("grid_folded", ctypes.c_int32), ("kernel_width", ctypes.c_int32),
+        ("kernel_beta", ctypes.c_double), ("upsample", ctypes.c_double),
+        ("slab_planes", ctypes.c_int32), ("n_slabs", ctypes.c_int32), ("n_chunks", ctypes.c_int32),
+        ("block_threads", ctypes.c_int32), ("n_triples", ctypes.c_int64),
+        ("workspace_bytes", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpgc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libpgc.so is not built: run python -m paper_2105_08806_amd.build "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.pgc_status_string.restype = ctypes.c_char_p
+        L.pgc_status_string.argtypes = [ctypes.c_int]
+        L.pgc_desc_init.argtypes = [ctypes.POINTER(PlanDesc)]
+        L.pgc_nufft_params.argtypes = [dbl, dbl, ctypes.POINTER(i32), dp]
+        L.pgc_plan_create.argtypes = [ctypes.POINTER(PlanDesc), vp, ctypes.POINTER(vp)]
+        L.pgc_plan_destroy.argtypes = [vp]
+        L.pgc_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+        L.pgc_nodes.argtypes = [vp, dp, dp, dp]
+        L.pgc_project.argtypes = [vp, vp, vp, vp]
+        L.pgc_coeffs_to_q.argtypes = [vp, vp, vp, vp, vp]
+        L.pgc_rk4.argtypes = [vp, vp, dbl, i32, vp]
+        L.pgc_moments.argtypes = [vp, vp, vp, vp]
+        L.pgc_eval.argtypes = [vp, vp, vp, i64, vp, vp]
+        for name in ("pgc_desc_init", "pgc_nufft_params", "pgc_plan_create", "pgc_plan_destroy",
+                     "pgc_plan_query", "pgc_nodes", "pgc_project", "pgc_coeffs_to_q", "pgc_rk4",
+                     "pgc_moments", "pgc_eval"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code, what):
+    if code != 0:
+        raise PgcError(what, code)
+
+
+def nufft_params(tol, upsample=2.0):
+    w = ctypes.c_int32(0)
+    b = ctypes.c_double(0.0)
+    _check(lib().pgc_nufft_params(tol, upsample, ctypes.byref(w), ctypes.byref(b)), "pgc_nufft_params")
+    return w.value, b.value
+
+
+def default_desc() -> PlanDesc:
+    d = PlanDesc()
+    _check(lib().pgc_desc_init(ctypes.byref(d)), "pgc_desc_init")
+    return d
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """One collision operator on the current GPU.
+
+    Keyword arguments are pgc_plan_desc fields (dim, n_modes, scale, map, kernel,
+    kernel_b0, kernel_gamma, sphere, n_sigma, n_theta, n_phi, precision, ...);
+    ``sigma``/``sigma_w`` give a user sphere rule.
+    """
+
+    def __init__(self, sigma=None, sigma_w=None, **fields):
+        import torch
+        self._torch = torch
+        d = default_desc()
+        for k, v in fields.items():
+            if not hasattr(d, k):
+                raise TypeError("unknown plan field %r" % k)
+            setattr(d, k, v)
+        self._keep = []
+        if sigma is not None:
+            s = np.ascontiguousarray(sigma, dtype=np.float64)
+            w = np.ascontiguousarray(sigma_w, dtype=np.float64)
+            self._keep += [s, w]
+            d.sphere = SPHERE_USER
+            d.n_sigma = int(w.size)
+            d.user_sigma_host = s.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            d.user_weights_host = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self.desc = d
+        h = ctypes.c_void_p()
+        _check(lib().pgc_plan_create(ctypes.byref(d), _stream(), ctypes.byref(h)), "pgc_plan_create")
+        self._h = h
+        self.info = PlanInfo()
+        _check(lib().pgc_plan_query(self._h, ctypes.byref(self.info)), "pgc_plan_query")
+        self.dim = self.info.dim
+        self.n_modes = self.info.n_modes
+        self.n_int = self.info.m_v - 2
+        self.dtype = torch.float64 if self.info.precision == FP64 else torch.float32
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pgc_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- shapes
+    def shape(self):
+        return (self.n_modes,) * self.dim
+
+    def node_shape(self):
+        return (self.n_int,) * self.dim
+
+    def _coeffs(self, c):
+        torch = self._torch
+        if not (c.is_cuda and c.dtype == self.dtype and c.is_contiguous() and tuple(c.shape) == self.shape()):
+            raise ValueError("coefficients must be a contiguous %s CUDA tensor of shape %s"
+                             % (self.dtype, self.shape()))
+        return c
+
+    # ---------------------------------------------------------------- calls
+    def nodes(self):
+        m = self.info.m_v
+        xi, v, w = (np.zeros(m) for _ in range(3))
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib().pgc_nodes(self._h, xi.ctypes.data_as(dp), v.ctypes.data_as(dp), w.ctypes.data_as(dp)),
+               "pgc_nodes")
+        return xi, v, w
+
+    def interior_velocities(self):
+        _, v, _ = self.nodes()
+        vi = v[1:-1]
+        g = np.meshgrid(*([vi] * self.dim), indexing="ij")
+        return np.stack([a.ravel() for a in g], axis=1)
+
+    def project(self, f_nodes):
+        torch = self._torch
+        f = torch.as_tensor(f_nodes, dtype=torch.float64).reshape(self.node_shape()).contiguous().cuda()
+        out = torch.empty(self.shape(), dtype=self.dtype, device=f.device)
+        _check(lib().pgc_project(self._h, _ptr(f), _ptr(out), _stream()), "pgc_project")
+        return out
+
+    def coeffs_to_q(self, coeffs, q=None, qplus=None, want_qplus=False):
+        torch = self._torch
+        c = self._coeffs(coeffs)
+        if q is None:
+            q = torch.empty_like(c)
+        if want_qplus and qplus is None:
+            qplus = torch.empty_like(c)
+        _check(lib().pgc_coeffs_to_q(self._h, _ptr(c), _ptr(q), _ptr(qplus) if qplus is not None else None,
+                                     _stream()), "pgc_coeffs_to_q")
+        return (q, qplus) if want_qplus else q
+
+    def rk4(self, coeffs, dt, n_steps):
+        """In place on a float64 CUDA tensor of shape N^dim."""
+        torch = self._torch
+        if not (coeffs.is_cuda and coeffs.dtype == torch.float64 and coeffs.is_contiguous()):
+            raise ValueError("rk4 state must be a contiguous float64 CUDA tensor")
+        _check(lib().pgc_rk4(self._h, _ptr(coeffs), float(dt), int(n_steps), _stream()), "pgc_rk4")
+        return coeffs
+
+    def moments(self, coeffs):
+        torch = self._torch
+        c = self._coeffs(coeffs)
+        out = torch.empty(self.dim + 2, dtype=torch.float64, device=c.device)
+        _check(lib().pgc_moments(self._h, _ptr(c), _ptr(out), _stream()), "pgc_moments")
+        return out
+
+    def eval(self, coeffs, v):
+        torch = self._torch
+        c = self._coeffs(coeffs)
+        vv = torch.as_tensor(v, dtype=torch.float64).reshape(-1, self.dim).contiguous().to(c.device)
+        out = torch.empty(vv.shape[0], dtype=torch.float64, device=c.device)
+        _check(lib().pgc_eval(self._h, _ptr(c), _ptr(vv), int(vv.shape[0]), _ptr(out), _stream()),
+               "pgc_eval")
+        return out

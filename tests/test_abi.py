@@ -1,0 +1,78 @@
+"""The C-ABI library loads and exports every entry point include/pgc.h declares.
+
+CPU only: no call here touches a GPU (only host-only entry points are called).
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "pgc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(pgc_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("pgc_plan_create", "pgc_plan_destroy", "pgc_coeffs_to_q", "pgc_rk4", "pgc_project",
+                 "pgc_moments", "pgc_eval", "pgc_nodes", "pgc_plan_query", "pgc_status_string"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2105_08806_amd import pgc
+    L = pgc.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_host_only_entry_points():
+    from paper_2105_08806_amd import pgc
+    L = pgc.lib()
+    assert L.pgc_status_string(0) == b"ok"
+    assert L.pgc_status_string(1) == b"invalid argument"
+    d = pgc.default_desc()
+    assert d.dim == 2 and d.n_modes == 16 and d.n_sigma == 16 and d.precision == pgc.FP64
+    assert L.pgc_desc_init(None) == 1
+    w64, b64 = pgc.nufft_params(1e-12)
+    w32, b32 = pgc.nufft_params(1e-6)
+    assert 10 <= w64 <= 14 and 5 <= w32 <= 7
+    assert abs(b64 - 0.98 * 3.141592653589793 * w64 * 0.75) < 1e-12
+    with pytest.raises(pgc.PgcError):
+        pgc.nufft_params(-1.0)
+    with pytest.raises(pgc.PgcError):
+        pgc.nufft_params(1e-6, upsample=8.0)
+    # larger upsampling never needs a wider kernel
+    assert pgc.nufft_params(1e-10, 3.0)[0] <= pgc.nufft_params(1e-10, 2.0)[0] + 1
+
+
+def test_null_plan_is_rejected_without_a_device():
+    from paper_2105_08806_amd import pgc
+    L = pgc.lib()
+    assert L.pgc_plan_destroy(None) == 0
+    assert L.pgc_plan_query(None, None) == 1
+    assert L.pgc_coeffs_to_q(None, None, None, None, None) == 1
+    assert L.pgc_rk4(None, None, 0.1, 1, None) == 1
+    out = ctypes.c_void_p()
+    assert L.pgc_plan_create(None, None, ctypes.byref(out)) == 1
+
+
+def test_oracle_and_library_share_no_code():
+    """The oracle sources never include or load the GPU library and vice versa."""
+    osrc = open(os.path.join(ROOT, "oracle", "pgc_oracle.c")).read()
+    opy = open(os.path.join(ROOT, "oracle", "__init__.py")).read()
+    assert "pgc.h" not in osrc and "paper_2105_08806_amd" not in opy
+    csrc = os.path.join(ROOT, "paper_2105_08806_amd", "csrc")
+    for f in os.listdir(csrc):
+        assert "oracle" not in open(os.path.join(csrc, f)).read().lower()
+    for f in ("pgc.py", "build.py", "inputs.py", "__init__.py"):
+        src = open(os.path.join(ROOT, "paper_2105_08806_amd", f)).read()
+        assert "import oracle" not in src and "from oracle" not in src

@@ -1,0 +1,204 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Bars (written here): rel-L2 over all coefficients <= 1e-11 for FP64 plans and
+<= 1e-5 for FP32 plans, element by element on identical seeded inputs.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2105_08806_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-11
+FP32_TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    return torch
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def make_pair(dim, N, S, map_=0, kernel="maxwell", gamma=0.0, b0=None, n_sigma=8, prec=0, m_v=None,
+              n_theta=2, n_phi=4, **tune):
+    from paper_2105_08806_amd import pgc
+    if dim == 2:
+        sg, sw = O.circle_rule(n_sigma)
+        sph = dict(sphere=pgc.SPHERE_UNIFORM_2D, n_sigma=n_sigma)
+    else:
+        sg, sw = O.sphere_product_rule(n_theta, n_phi)
+        sph = dict(sphere=pgc.SPHERE_PRODUCT_3D, n_theta=n_theta, n_phi=n_phi)
+    ora = O.Problem(dim, N, S, map_, m_v=m_v, kernel=kernel, b0=b0, gamma=gamma, sphere=sg, sphere_w=sw)
+    plan = pgc.Plan(dim=dim, n_modes=N, scale=S, map=map_, m_v=m_v or 0,
+                    kernel=pgc.KERNEL_MAXWELL if kernel == "maxwell" else pgc.KERNEL_VHS,
+                    kernel_b0=b0 or 0.0, kernel_gamma=gamma, precision=prec, **sph, **tune)
+    return ora, plan
+
+
+def gpu_q(torch, plan, coeffs):
+    c = torch.tensor(coeffs, dtype=plan.dtype, device="cuda")
+    q, qp = plan.coeffs_to_q(c, want_qplus=True)
+    torch.cuda.synchronize()
+    return q.double().cpu().numpy(), qp.double().cpu().numpy()
+
+
+def check_q(torch, ora, plan, coeffs, tol, label):
+    say("case:", label, plan.info.n_triples, "triples, W =", plan.info.kernel_width,
+        "slabs =", plan.info.n_slabs, "chunks =", plan.info.n_chunks)
+    q, qp = gpu_q(torch, plan, coeffs)
+    q_ref, qp_ref, _ = ora.collision(coeffs)
+    r, rp = rel_l2(q, q_ref), rel_l2(qp, qp_ref)
+    say("  rel-L2 Q = %.3e  Q+ = %.3e" % (r, rp))
+    assert r <= tol, (label, r)
+    assert rp <= tol, (label, rp)
+    return q, q_ref
+
+
+# ----------------------------------------------------------------- tables
+
+
+def test_nodes_match_oracle(torch_cuda):
+    for map_ in (0, 1):
+        ora, plan = make_pair(2, 9, 2.5, map_=map_)
+        xi, v, w = plan.nodes()
+        oxi, ov, ow, _ = O.cgl(ora.m_v, map_, 2.5)
+        assert np.allclose(xi, oxi, rtol=0, atol=1e-15)
+        assert np.allclose(w, ow, rtol=1e-15, atol=0)
+        assert np.allclose(v[1:-1], ov[1:-1], rtol=1e-13, atol=1e-14)
+        assert np.isinf(v[0]) and np.isinf(v[-1])
+        plan.close()
+
+
+# ----------------------------------------------------------------- FP64 parity
+
+
+@pytest.mark.parametrize("map_", [0, 1])
+@pytest.mark.parametrize("kernel", ["maxwell", "vhs"])
+def test_q_parity_2d_fp64(torch_cuda, map_, kernel):
+    ora, plan = make_pair(2, 13, 2.5, map_=map_, kernel=kernel, gamma=1.0 if kernel == "vhs" else 0.0,
+                          b0=1.0 / (2 * np.pi), n_sigma=8)
+    c = I.random_coeffs((13, 13), seed=11 + map_)
+    check_q(torch_cuda, ora, plan, c, FP64_TOL, "2D N=13 map=%d %s random" % (map_, kernel))
+    plan.close()
+
+
+def test_q_parity_2d_bkw_config1(torch_cuda):
+    """2D BKW at t0 = 0, N = 16, S = 4, Maxwell 1/(2 pi), 16 circle directions."""
+    ora, plan = make_pair(2, 16, 4.0, n_sigma=16)
+    c = ora.project(I.bkw_f(0.0, ora.interior_velocities()))
+    check_q(torch_cuda, ora, plan, c, FP64_TOL, "2D BKW N=16")
+    plan.close()
+
+
+@pytest.mark.parametrize("map_", [0, 1])
+def test_q_parity_3d_fp64(torch_cuda, map_):
+    ora, plan = make_pair(3, 8, 2.0, map_=map_, n_theta=2, n_phi=4)
+    comps = [(0.6, (0.4, -0.3, 0.2), 0.8), (0.4, (-0.7, 0.5, -0.1), 1.3)]
+    c = ora.project(I.mixture(ora.interior_velocities(), comps))
+    check_q(torch_cuda, ora, plan, c, FP64_TOL, "3D N=8 map=%d mixture" % map_)
+    plan.close()
+
+
+def test_q_parity_3d_vhs_many_slabs(torch_cuda):
+    """Ragged slabs and chunks: 3 planes per slab, 7 chunks."""
+    ora, plan = make_pair(3, 9, 2.2, kernel="vhs", gamma=1.0, b0=0.3, n_theta=2, n_phi=4,
+                          slab_planes=3, n_chunks=7)
+    assert plan.info.n_slabs > 5
+    c = I.random_coeffs((9, 9, 9), seed=4)
+    check_q(torch_cuda, ora, plan, c, FP64_TOL, "3D N=9 VHS slabs=3")
+    plan.close()
+
+
+def test_q_parity_2d_slabs_and_odd_mv(torch_cuda):
+    ora, plan = make_pair(2, 11, 3.0, m_v=15, n_sigma=6, slab_planes=5, n_chunks=3)
+    c = I.random_coeffs((11, 11), seed=9)
+    check_q(torch_cuda, ora, plan, c, FP64_TOL, "2D N=11 m_v=15 slabs=5")
+    plan.close()
+
+
+def test_minimum_size_and_zero_input(torch_cuda):
+    ora, plan = make_pair(2, 3, 1.5, n_sigma=4)
+    c = I.random_coeffs((3, 3), seed=1)
+    check_q(torch_cuda, ora, plan, c, FP64_TOL, "2D N=3")
+    q, qp = gpu_q(torch_cuda, plan, np.zeros((3, 3)))
+    assert np.all(q == 0) and np.all(qp == 0)
+    plan.close()
+
+
+# ----------------------------------------------------------------- FP32 parity
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_q_parity_fp32(torch_cuda, dim):
+    if dim == 2:
+        ora, plan = make_pair(2, 16, 3.0, n_sigma=16, prec=1)
+        c = ora.project(I.mixture(ora.interior_velocities(), I.two_maxwellians_2d()))
+    else:
+        ora, plan = make_pair(3, 8, 2.0, n_theta=2, n_phi=4, prec=1)
+        c = I.random_coeffs((8, 8, 8), seed=2)
+    check_q(torch_cuda, ora, plan, c.astype(np.float32).astype(np.float64), FP32_TOL,
+            "%dD FP32" % dim)
+    plan.close()
+
+
+# ----------------------------------------------------------------- other entry points
+
+
+def test_project_moments_eval(torch_cuda):
+    import torch
+    for map_ in (0, 1):
+        ora, plan = make_pair(2, 14, 2.5, map_=map_)
+        V = ora.interior_velocities()
+        f = I.mixture(V, [(0.7, (0.3, -0.2), 0.9), (0.3, (-0.5, 0.4), 1.4)])
+        c_ref = ora.project(f)
+        c = plan.project(f)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(c.cpu().numpy() - c_ref)) < 1e-13
+        m = plan.moments(torch.tensor(c_ref, device="cuda"))
+        m_ref = ora.moments(c_ref)
+        assert np.allclose(m.cpu().numpy(), m_ref, rtol=1e-12, atol=1e-13)
+        pts = np.random.default_rng(0).uniform(-5, 5, size=(300, 2))
+        e = plan.eval(torch.tensor(c_ref, device="cuda"), pts)
+        e_ref = ora.eval(c_ref, pts)
+        assert np.allclose(e.cpu().numpy(), e_ref, rtol=1e-12, atol=1e-15)
+        plan.close()
+
+
+def test_rk4_parity(torch_cuda):
+    import torch
+    ora, plan = make_pair(2, 12, 3.0, n_sigma=8)
+    c0 = ora.project(I.bkw_f(0.0, ora.interior_velocities()))
+    ref = ora.rk4(c0, 0.1, 3)
+    state = torch.tensor(c0, dtype=torch.float64, device="cuda")
+    plan.rk4(state, 0.1, 3)
+    torch.cuda.synchronize()
+    assert rel_l2(state.cpu().numpy(), ref) < 1e-12
+    plan.close()
+
+
+def test_invalid_arguments(torch_cuda):
+    from paper_2105_08806_amd import pgc
+    with pytest.raises(pgc.PgcError):
+        pgc.Plan(dim=2, n_modes=8, n_sigma=7)          # odd circle rule
+    with pytest.raises(pgc.PgcError):
+        pgc.Plan(dim=4, n_modes=8)
+    with pytest.raises(pgc.PgcError):
+        pgc.Plan(dim=2, n_modes=2)
+    s = np.array([[1.0, 0.0], [0.0, 1.0]])
+    with pytest.raises(pgc.PgcError):
+        pgc.Plan(dim=2, n_modes=8, sigma=s, sigma_w=np.ones(2))   # not antipodal

@@ -353,3 +353,15 @@ def test_cosine_sum_orthogonality():
         out = O.cosine_sum(z[:, None], w * np.cos(l * z), 8)
         ref = np.array([c_k(k) if k == l else 0.0 for k in range(8)])
         assert np.allclose(out, ref, atol=1e-13)
+
+
+def test_gain_units_partition_the_gain():
+    N, S = 7, 2.0
+    sg, sw = O.sphere_product_rule(2, 2)
+    p = O.Problem(3, N, S, 0, sphere=sg, sphere_w=sw)
+    c = I.random_coeffs((N, N, N), seed=8)
+    _, qp, _ = p.collision(c)
+    n_units = len(sw) * (N - 1) ** 3
+    cut = [0, 5, 117, n_units]
+    parts = sum(p.gain_units(c, a, b) for a, b in zip(cut[:-1], cut[1:]))
+    assert np.max(np.abs(parts - qp)) < 1e-13 * np.max(np.abs(qp))
