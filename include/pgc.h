@@ -100,6 +100,10 @@ typedef struct pgc_plan_desc {
     int32_t slab_planes;  /* fine-grid planes held in LDS per workgroup; 0 = as many as fit */
     int32_t n_chunks;     /* collision-unit chunks (partial grids); 0 = automatic */
     int32_t block_threads;/* threads per spreading workgroup (256, 512 or 1024); 0 = automatic */
+    int32_t gain_mode;    /* spreading scheme: 0 = automatic (binned, falling back to slabs when the
+                             bin index does not fit in device memory), 1 = LDS slabs with one atomic per
+                             contribution, 2 = plan-time bins by footprint corner with register
+                             accumulation (the index holds 8 bytes per merged point) */
 } pgc_plan_desc;
 
 typedef struct pgc_plan_s* pgc_plan;
@@ -115,7 +119,11 @@ typedef struct pgc_plan_info {
     double upsample;
     int32_t slab_planes, n_slabs, n_chunks, block_threads;
     int64_t n_triples;      /* collision triples per evaluation, n_sigma * n_i^(2 dim) */
+    int64_t n_points;       /* distinct transform points after merging the triples that share
+                               v' (exchanging i_l and j_l in any dimension): n_sigma * (n_i (n_i+1)/2)^dim */
     int64_t workspace_bytes;/* device memory owned by the plan */
+    int32_t gain_mode;      /* 1 = slabs, 2 = bins */
+    int64_t n_bin_items;    /* binned mode: work items (runs of one bin) per evaluation */
 } pgc_plan_info;
 
 /* Human-readable text of a status code (static storage, never NULL). */

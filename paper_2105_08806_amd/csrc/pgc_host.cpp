@@ -150,6 +150,7 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
     if (d.block_threads != 0 && d.block_threads != 256 && d.block_threads != 512 &&
         d.block_threads != 1024)
         return PGC_ERR_INVALID_ARG;
+    if (d.gain_mode < 0 || d.gain_mode > 2) return PGC_ERR_INVALID_ARG;
 
     p.dim = d.dim;
     p.N = d.n_modes;
@@ -234,6 +235,12 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
     p.upsample = d.upsample > 0.0 ? d.upsample : 2.0;
     p.tol = d.nufft_tol > 0.0 ? d.nufft_tol : (p.precision == PGC_PRECISION_FP64 ? 1e-13 : 1e-7);
     p.W = d.kernel_width > 0 ? d.kernel_width : width_for(p.tol, p.upsample);
+    p.gain_mode = d.gain_mode == 1 ? kGainSlab : kGainBinned;
+    if (p.gain_mode == kGainBinned && p.W > 14) {
+        if (d.gain_mode == 2) return PGC_ERR_UNSUPPORTED;
+        p.gain_mode = kGainSlab;
+    }
+    p.auto_gain = d.gain_mode == 0;
     p.terms = p.W + 2;
     p.beta = beta_for(p.W, p.upsample);
     // n >= 2 sigma N, and n/2 >= W so that a footprint folds back at most once
@@ -251,8 +258,11 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
     p.nid = ipow(p.ni, p.dim);
     p.Nd = ipow(p.N, p.dim);
     p.ngd = ipow(p.ng, p.dim);
-    p.n_units = (int64_t)p.n_sigma * p.nid;
-    p.n_triples = p.n_units * p.nid;
+    p.np = p.ni * (p.ni + 1) / 2;
+    p.n_triples = (int64_t)p.n_sigma * p.nid * p.nid;
+    p.n_points = (int64_t)p.n_sigma * ipow(p.np, p.dim);
+    // a unit is (a_1, s): the smaller first-dimension node of a pair and a direction
+    p.n_units = (int64_t)p.n_sigma * p.ni;
 
     // LDS slabs along the first dimension
     const int64_t plane_bytes = ipow(p.ng, p.dim - 1) * (int64_t)sizeof(double);  // FP64 cells
@@ -272,7 +282,7 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
     p.units_per_chunk = (p.n_units + chunks - 1) / chunks;
     p.n_chunks = (int)((p.n_units + p.units_per_chunk - 1) / p.units_per_chunk);
     if ((int64_t)p.n_chunks > 2147483647ll) return PGC_ERR_UNSUPPORTED;
-    const int max_threads = p.precision == PGC_PRECISION_FP64 ? 512 : 1024;
+    const int max_threads = p.precision == PGC_PRECISION_FP64 ? 256 : 1024;
     if (d.block_threads > max_threads) return PGC_ERR_UNSUPPORTED;
     p.block_threads = d.block_threads > 0 ? d.block_threads : max_threads;
     return PGC_OK;
@@ -445,6 +455,77 @@ pgc_status from_hip(hipError_t e)
     return PGC_ERR_DEVICE;
 }
 
+// Sort the merged points by the base cell of their footprint: count per bin on
+// the device, prefix sums and the work-item list on the host, then scatter the
+// point ids.  Temporaries are freed before returning.
+hipError_t build_bins(Plan& p, hipStream_t s)
+{
+    BinIndex& B = p.bins;
+    B.nb = p.nh + 2;
+    B.off = p.W / 2;
+    int64_t nbins = 1;
+    for (int l = 0; l < p.dim; ++l) nbins *= B.nb;
+    unsigned int* count = nullptr;
+    unsigned long long* cursor = nullptr;
+    hipError_t e = hipMalloc(&count, nbins * sizeof(unsigned int));
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(count, 0, nbins * sizeof(unsigned int), s);
+    if (e == hipSuccess) e = launch_bin_build(p, count, nullptr, nullptr, 0, s);
+    std::vector<unsigned int> hc(nbins);
+    if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), count, nbins * sizeof(unsigned int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(count);
+    if (e != hipSuccess) return e;
+
+    std::vector<unsigned long long> begin(nbins);
+    unsigned long long total = 0;
+    for (int64_t b = 0; b < nbins; ++b) {
+        begin[b] = total;
+        total += hc[b];
+    }
+    if ((int64_t)total != p.n_points) return hipErrorUnknown;  // every merged point has one bin
+
+    struct Item {
+        int bin;
+        long long begin;
+        int count;
+    };
+    std::vector<Item> items;
+    for (int64_t b = 0; b < nbins; ++b)
+        for (unsigned int o = 0; o < hc[b]; o += kBinChunk)
+            items.push_back({(int)b, (long long)(begin[b] + o), (int)std::min<unsigned int>(kBinChunk, hc[b] - o)});
+    // full runs first: the long items start early and the short ones fill the tail
+    std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.count > y.count; });
+    B.n_items = (int64_t)items.size();
+    std::vector<int> ib(items.size()), ic(items.size());
+    std::vector<long long> ibeg(items.size());
+    for (size_t k = 0; k < items.size(); ++k) {
+        ib[k] = items[k].bin;
+        ibeg[k] = items[k].begin;
+        ic[k] = items[k].count;
+    }
+    void* d = nullptr;
+    if ((e = dev_alloc(p, &d, std::max<size_t>(1, total) * sizeof(unsigned long long))) != hipSuccess) return e;
+    B.ids = static_cast<unsigned long long*>(d);
+    if ((e = dev_alloc(p, &d, std::max<size_t>(1, ib.size()) * sizeof(int))) != hipSuccess) return e;
+    B.item_bin = static_cast<int*>(d);
+    if ((e = dev_alloc(p, &d, std::max<size_t>(1, ibeg.size()) * sizeof(long long))) != hipSuccess) return e;
+    B.item_begin = static_cast<long long*>(d);
+    if ((e = dev_alloc(p, &d, std::max<size_t>(1, ic.size()) * sizeof(int))) != hipSuccess) return e;
+    B.item_count = static_cast<int*>(d);
+    if (!items.empty()) {
+        if ((e = hipMemcpyAsync(B.item_bin, ib.data(), ib.size() * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(B.item_begin, ibeg.data(), ibeg.size() * sizeof(long long), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(B.item_count, ic.data(), ic.size() * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+    }
+    if ((e = hipMalloc(&cursor, nbins * sizeof(unsigned long long))) != hipSuccess) return e;
+    e = hipMemcpyAsync(cursor, begin.data(), nbins * sizeof(unsigned long long), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_bin_build(p, nullptr, cursor, B.ids, 1, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(cursor);
+    return e;
+}
+
 hipError_t allocate(Plan& p, hipStream_t s)
 {
     hipError_t e;
@@ -474,7 +555,34 @@ hipError_t allocate(Plan& p, hipStream_t s)
     PGC_TRY(dev_alloc(p, &p.ws.P, p.nid * e8));
     PGC_TRY(dev_alloc(p, &p.ws.G, p.nid * e8));
     PGC_TRY(dev_alloc(p, &p.ws.H, p.nid * e8));
-    PGC_TRY(dev_alloc(p, &p.ws.partial, (size_t)p.n_chunks * p.ngd * sizeof(double)));
+    {
+        int64_t nsym = 1;
+        for (int l = 0; l < p.dim; ++l) nsym *= p.np;
+        PGC_TRY(dev_alloc(p, &p.ws.sym, nsym * e8));
+        std::vector<int> pa(p.np), pb(p.np), base(p.ni);
+        int q = 0;
+        for (int a = 0; a < p.ni; ++a) {
+            base[a] = q;
+            for (int b = a; b < p.ni; ++b, ++q) {
+                pa[q] = a;
+                pb[q] = b;
+            }
+        }
+        void* d = nullptr;
+        PGC_TRY(dev_alloc(p, &d, pa.size() * sizeof(int)));
+        p.dt.pair_a = static_cast<int*>(d);
+        PGC_TRY(dev_alloc(p, &d, pb.size() * sizeof(int)));
+        p.dt.pair_b = static_cast<int*>(d);
+        PGC_TRY(dev_alloc(p, &d, base.size() * sizeof(int)));
+        p.dt.pair_base = static_cast<int*>(d);
+        PGC_TRY(hipMemcpyAsync(p.dt.pair_a, pa.data(), pa.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        PGC_TRY(hipMemcpyAsync(p.dt.pair_b, pb.data(), pb.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        PGC_TRY(hipMemcpyAsync(p.dt.pair_base, base.data(), base.size() * sizeof(int),
+                               hipMemcpyHostToDevice, s));
+        PGC_TRY(hipStreamSynchronize(s));
+    }
+    if (p.gain_mode == kGainSlab)
+        PGC_TRY(dev_alloc(p, &p.ws.partial, (size_t)p.n_chunks * p.ngd * sizeof(double)));
     PGC_TRY(dev_alloc(p, &p.ws.grid, p.ngd * e8));
     PGC_TRY(dev_alloc(p, &p.ws.tmpA, t * e8));
     PGC_TRY(dev_alloc(p, &p.ws.tmpB, t * e8));
@@ -490,6 +598,21 @@ hipError_t allocate(Plan& p, hipStream_t s)
     p.ws.mom = static_cast<double*>(mom);
     PGC_TRY(hipMemcpyAsync(mom, p.mom.data(), p.mom.size() * sizeof(double), hipMemcpyHostToDevice, s));
     PGC_TRY(hipStreamSynchronize(s));
+    if (p.gain_mode == kGainBinned) {
+        void* g64 = nullptr;
+        PGC_TRY(dev_alloc(p, &g64, p.ngd * sizeof(double)));
+        p.ws.grid64 = static_cast<double*>(g64);
+        e = build_bins(p, s);
+        if (e == hipErrorOutOfMemory && p.auto_gain) {
+            // the bin index does not fit: fall back to LDS slabs
+            (void)hipGetLastError();
+            p.gain_mode = kGainSlab;
+            p.bins = BinIndex();
+            PGC_TRY(dev_alloc(p, &p.ws.partial, (size_t)p.n_chunks * p.ngd * sizeof(double)));
+        } else if (e != hipSuccess) {
+            return e;
+        }
+    }
 #undef PGC_TRY
     return hipSuccess;
 }
@@ -608,6 +731,9 @@ pgc_status pgc_plan_query(pgc_plan plan, pgc_plan_info* info)
     info->n_chunks = p.n_chunks;
     info->block_threads = p.block_threads;
     info->n_triples = p.n_triples;
+    info->n_points = p.n_points;
+    info->gain_mode = p.gain_mode;
+    info->n_bin_items = p.bins.n_items;
     info->workspace_bytes = p.workspace_bytes;
     return PGC_OK;
 }

@@ -28,11 +28,30 @@ struct DeviceTables {
     void* sigma_w = nullptr;  // n_sigma
     void* slab_vlo = nullptr; // n_slabs  v'_1 window of each slab
     void* slab_vhi = nullptr; // n_slabs
+    int* pair_a = nullptr;    // np  unordered node pairs (a <= b) per dimension
+    int* pair_b = nullptr;    // np
+    int* pair_base = nullptr; // n_i  index of the pair (a, a)
 };
+
+constexpr int kGainSlab = 1;    // LDS slabs, per-point atomics
+constexpr int kGainBinned = 2;  // plan-time bins by base cell, register accumulation
+
+// Merged points sorted by the base cell of their footprint (built at plan time).
+struct BinIndex {
+    int nb = 0;                 // bins per dimension
+    int off = 0;                // bin index = t0 + off
+    int64_t n_items = 0;        // work items (runs of at most kBinChunk ids of one bin)
+    int* item_bin = nullptr;
+    long long* item_begin = nullptr;
+    int* item_count = nullptr;
+    unsigned long long* ids = nullptr;  // n_points packed point ids, grouped by bin
+};
+constexpr int kBinChunk = 8192;
 
 struct Workspace {
     void* P = nullptr;        // n_i^d  polynomial part at the interior nodes
     void* G = nullptr;        // n_i^d  w_i g_i = w_i mu_i^2 P_i
+    void* sym = nullptr;      // np^d   orbit sums of G_i G_j over exchanged node pairs
     void* H = nullptr;        // n_i^d  w_i A_i P_i (loss integrand) / projection input
     void* partial = nullptr;  // n_chunks x n_g^d  per-chunk fine grids (FP64 cells)
     void* grid = nullptr;     // n_g^d  reduced fine grid
@@ -43,6 +62,7 @@ struct Workspace {
     void* rk_y = nullptr;     // N^d  stage input (plan precision)
     void* rk_k[4] = {nullptr, nullptr, nullptr, nullptr};
     double* red = nullptr;    // small FP64 scratch (reductions)
+    double* grid64 = nullptr; // n_g^d FP64 grid of the binned gain
     double* mom = nullptr;    // 3 x N  moment functionals m_0, m_1, m_2 (FP64)
     double* eval_tab = nullptr;  // unused placeholder for alignment
 };
@@ -60,7 +80,9 @@ struct Plan {
 
     // gain decomposition
     int slab_planes = 0, n_slabs = 0, n_chunks = 0, block_threads = 0;
+    int np = 0;  // unordered node pairs per dimension, n_i (n_i + 1) / 2
     int64_t nid = 0, Nd = 0, ngd = 0, n_units = 0, units_per_chunk = 0, n_triples = 0;
+    int64_t n_points = 0;  // merged points per evaluation, n_sigma * np^d
     int64_t tmp_elems = 0;
 
     // host tables (FP64)
@@ -68,6 +90,9 @@ struct Plan {
     std::vector<double> v1, w1, mu21, C, CT, E, poly, slab_vlo, slab_vhi, mom;
 
     size_t elt = 8;
+    int gain_mode = kGainBinned;
+    bool auto_gain = true;
+    BinIndex bins;
     DeviceTables dt;
     Workspace ws;
     int64_t workspace_bytes = 0;
@@ -79,6 +104,10 @@ hipError_t launch_synthesis(const Plan& p, const void* coeffs, hipStream_t s);
 hipError_t launch_loss(const Plan& p, hipStream_t s);
 hipError_t launch_gain(const Plan& p, hipStream_t s);
 hipError_t launch_combine(const Plan& p, void* q, void* qplus, hipStream_t s);
+// plan time: mode 0 counts points per bin into `count`, mode 1 scatters ids
+// through the per-bin cursors
+hipError_t launch_bin_build(const Plan& p, unsigned int* count, unsigned long long* cursor,
+                            unsigned long long* ids, int mode, hipStream_t s);
 hipError_t launch_project(const Plan& p, const double* f_nodes, void* coeffs, hipStream_t s);
 hipError_t launch_moments(const Plan& p, const void* coeffs, double* out, hipStream_t s);
 hipError_t launch_eval(const Plan& p, const void* coeffs, const double* v, int64_t n, double* out,

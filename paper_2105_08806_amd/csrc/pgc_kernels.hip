@@ -14,6 +14,7 @@
 //   combine     Q = Q+ - Q-
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -201,10 +202,58 @@ __global__ void __launch_bounds__(256) loss_h_vhs(const T* __restrict__ P, const
 
 // ------------------------------------------------------------------ gain
 
+// Pair orbits.  v' = (v_i + v_j)/2 + |v_i - v_j| sigma/2 does not change when
+// i_l and j_l are exchanged in any dimension l (each component of v_i + v_j
+// and of (v_i - v_j)^2 is symmetric), so the 2^d triples (s, i, j) of one
+// orbit share one point z.  The merged point carries the orbit sum
+//   Sym(a, b) = sum over the distinct (i', j') of the orbit of G_i' G_j'
+// for per-dimension unordered pairs a_l <= b_l.  Pairs are numbered
+// p(a, b) = a n_i - a (a - 1)/2 + (b - a), so b runs contiguously for fixed a.
+// Sym is stored [p_2][p_3][p_1] (3D) or [p_2][p_1] (2D): p_1 fastest.
+template <typename T, int DIM>
+__global__ void pair_orbit_sums(const T* __restrict__ G, T* __restrict__ sym,
+                                const int* __restrict__ pair_a, const int* __restrict__ pair_b,
+                                int ni, int np, int64_t n_total)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n_total) return;
+    int pr[DIM];  // pair index per dimension, pr[0] = p_1
+    {
+        int64_t r = e;
+        pr[0] = (int)(r % np);
+        r /= np;
+        for (int l = DIM - 1; l >= 1; --l) {
+            pr[l] = (int)(r % np);
+            r /= np;
+        }
+    }
+    int a[DIM], b[DIM];
+    double c = 1.0;
+    for (int l = 0; l < DIM; ++l) {
+        a[l] = pair_a[pr[l]];
+        b[l] = pair_b[pr[l]];
+        if (a[l] == b[l]) c *= 0.5;  // both orders of an equal pair are one triple
+    }
+    double acc = 0.0;
+    for (int eps = 0; eps < (1 << DIM); ++eps) {
+        int64_t x = 0, y = 0;
+        for (int l = 0; l < DIM; ++l) {
+            const bool sw = (eps >> l) & 1;
+            x = x * ni + (sw ? b[l] : a[l]);
+            y = y * ni + (sw ? a[l] : b[l]);
+        }
+        acc += (double)G[x] * (double)G[y];
+    }
+    sym[e] = (T)(c * acc);
+}
+
 template <typename T>
 struct GainParams {
     const T* v1;        // n_i interior node velocities
-    const T* G;         // n_i^d  w_j g_j
+    const T* sym;       // np^d orbit sums, p_1 fastest
+    const int* pair_a;  // np  smaller node of each pair
+    const int* pair_b;  // np  larger node
+    const int* pair_base;  // n_i  index of the pair (a, a)
     const T* sigma;     // n_sigma x d
     const T* sigma_w;   // n_sigma
     const T* poly;      // terms x W
@@ -212,8 +261,8 @@ struct GainParams {
     const T* slab_vhi;
     double* partial;    // n_chunks x n_g^d
     T S, inv_S, h_inv, b0, gamma;
-    int map, vhs, ni, ng, nh, slab_planes;
-    int64_t nid, ngd, n_units, units_per_chunk;
+    int map, vhs, ni, np, ng, nh, slab_planes, n_sigma;
+    int64_t ngd, n_units, units_per_chunk;
 };
 
 // post-collision coordinate in the transform variable and the factor mu^-2:
@@ -254,105 +303,165 @@ __device__ __forceinline__ void lds_add(double* addr, double v)
     __hip_atomic_fetch_add(addr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// One workgroup = (chunk of collision units, slab of fine-grid planes along
-// the first dimension).  The slab lives in LDS; every unit (s, i) of the chunk
-// is split into pencils j = (j_1, j_rest) with j_1 running.  Along a pencil
-// the first component of v' = (v_i + v_j)/2 + |v_i - v_j| sigma/2 is
-// non-decreasing in v_{j,1} (its derivative is (1 - sigma_1 cos)/2 >= 0), so
-// the points that reach the slab form one contiguous j_1 range, found by a
-// binary search against the slab's v'-window.
 // FP64 points need about 2x the registers of FP32 ones: 512 threads keep
 // 256 VGPRs per lane available without spilling.
 template <typename T>
-constexpr int spread_max_threads() { return sizeof(T) == 8 ? 512 : 1024; }
+constexpr int spread_max_threads() { return sizeof(T) == 8 ? 256 : 1024; }
 
+// wave-uniform copy of lane p's value (p is uniform)
+__device__ __forceinline__ int lane_get(int x, int p) { return __builtin_amdgcn_readlane(x, p); }
+__device__ __forceinline__ float lane_get(float x, int p)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), p));
+}
+__device__ __forceinline__ double lane_get(double x, int p)
+{
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), p);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), p);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename T, int TERMS>
+__device__ __forceinline__ T horner(const T* c, T s)
+{
+    T v = c[TERMS - 1];
+#pragma unroll
+    for (int d = TERMS - 2; d >= 0; --d) v = fma(v, s, c[d]);
+    return v;
+}
+
+// One workgroup = (chunk of units, slab of fine-grid planes along the first
+// dimension); the slab lives in LDS.  A unit is (a_1, s): the smaller node of
+// the first-dimension pair and a direction.  A pencil fixes the pairs of the
+// other dimensions; along it b_1 runs from a_1 to n_i - 1.  The first
+// component of v' is non-decreasing in v_{b_1} (its derivative is
+// (1 - sigma_1 cos)/2 >= 0), so the points reaching the slab form one
+// contiguous b_1 range, found by a binary search against the slab window.
+//
+// Generation is per lane (each lane walks its own pencil); spreading is per
+// wave: the lanes own the cells of one footprint -- (b, c) with a loop over
+// the first-dimension offset a in 3D, (a, b) in 2D -- and the wave spreads the
+// points of all its lanes one after the other.  Each lane evaluates the
+// kernel cells it owns by Horner from the point's offsets; the point's data
+// reaches the lanes through readlane.  The LDS atomics of one instruction then
+// touch W consecutive cells per row, and the slab test on the first dimension
+// is a scalar branch.
 template <typename T, int DIM, int W>
 __global__ void __launch_bounds__(spread_max_threads<T>()) gain_spread(GainParams<T> P)
 {
     constexpr int TERMS = W + 2;
+    constexpr int NPASS = (W * W + 63) / 64;
     extern __shared__ unsigned char lds_raw[];
     double* slab = reinterpret_cast<double*>(lds_raw);
 
-    const int b = blockIdx.y;
+    const int blk = blockIdx.y;
     const int64_t c = blockIdx.x;
-    const int p0 = b * P.slab_planes;
+    const int p0 = blk * P.slab_planes;
     const int p1 = min(P.ng, p0 + P.slab_planes);
     const int plane = (DIM == 2) ? P.ng : P.ng * P.ng;
     const int slab_elems = (p1 - p0) * plane;
     for (int e = threadIdx.x; e < slab_elems; e += blockDim.x) slab[e] = 0;
     __syncthreads();
 
-    const T vlo = P.slab_vlo[b];
-    const T vhi = P.slab_vhi[b];
+    const T vlo = P.slab_vlo[blk];
+    const T vhi = P.slab_vhi[blk];
     const int ni = P.ni;
-    const int npencil = (DIM == 2) ? ni : ni * ni;
+    const int np = P.np;
+    const int npencil = (DIM == 2) ? np : np * np;
     const int64_t u0 = c * P.units_per_chunk;
     const int64_t u1 = min(P.n_units, u0 + P.units_per_chunk);
-    const int64_t n_items = (u1 - u0) * npencil;
-    const T half = (T)0.5;
-
-    // Lanes of a wave take consecutive units of the same pencil: their points
-    // land far apart on the grid.  (Consecutive pencils of one unit can map
-    // onto the same cells -- e.g. v'_2 = max(v_i2, v_j2) for sigma = e_2 --
-    // and then every lane's LDS atomic hits one address.)
     const int64_t n_u = u1 - u0;
-    for (int64_t item = threadIdx.x; item < n_items; item += blockDim.x) {
-        const int64_t u = u0 + item % n_u;
-        const int pencil = (int)(item / n_u);
-        const int s = (int)(u / P.nid);
-        const int64_t i = u % P.nid;
-        const T cu = P.sigma_w[s] * P.G[i] * P.b0;
-        if (cu == (T)0) continue;
+    const int64_t n_items = n_u * npencil;
+    const T half = (T)0.5;
+    const int lane = threadIdx.x & 63;
 
-        T vi[DIM], sg[DIM], vr[DIM];
-        {
-            int64_t r = i;
-            for (int l = DIM - 1; l >= 0; --l) {
-                vi[l] = P.v1[r % ni];
-                r /= ni;
+    // cells owned by this lane in each pass, and their kernel polynomials
+    int own_x[NPASS], own_y[NPASS];
+    bool own_ok[NPASS];
+    T cx[NPASS][TERMS], cy[NPASS][TERMS];
+#pragma unroll
+    for (int r = 0; r < NPASS; ++r) {
+        const int e = lane + 64 * r;
+        own_ok[r] = e < W * W;
+        own_x[r] = own_ok[r] ? e / W : 0;
+        own_y[r] = own_ok[r] ? e % W : 0;
+#pragma unroll
+        for (int d = 0; d < TERMS; ++d) {
+            cx[r][d] = P.poly[d * W + own_x[r]];
+            cy[r][d] = P.poly[d * W + own_y[r]];
+        }
+    }
+
+    // generation state of this lane
+    int64_t item = threadIdx.x;
+    bool have = false;
+    int b1 = 0;
+    T va1 = 0, r2 = 0, cs = 0;
+    T sg[DIM], cen[DIM];
+    const T* symrow = P.sym;
+
+    while (true) {
+        bool valid = false;
+        T q = 0, sfr[DIM];
+        int t0[DIM];
+        for (int l = 0; l < DIM; ++l) {
+            sfr[l] = 0;
+            t0[l] = 0;
+        }
+        while (item < n_items) {
+            if (!have) {
+                const int64_t u = u0 + item % n_u;
+                const int pencil = (int)(item / n_u);
+                const int a1 = (int)(u / P.n_sigma);
+                const int s = (int)(u % P.n_sigma);
+                cs = P.sigma_w[s] * P.b0;
+                for (int l = 0; l < DIM; ++l) sg[l] = P.sigma[s * DIM + l];
+                va1 = P.v1[a1];
+                const int pa = (DIM == 2) ? pencil : pencil / np;
+                const T x = P.v1[P.pair_a[pa]], y = P.v1[P.pair_b[pa]];
+                cen[1] = (x + y) * half;
+                r2 = (x - y) * (x - y);
+                if constexpr (DIM == 3) {
+                    const int pb = pencil % np;
+                    const T x2 = P.v1[P.pair_a[pb]], y2 = P.v1[P.pair_b[pb]];
+                    cen[2] = (x2 + y2) * half;
+                    r2 += (x2 - y2) * (x2 - y2);
+                }
+                symrow = P.sym + (int64_t)pencil * np + P.pair_base[a1] - a1;  // index by b_1
+                int lo = a1, hi = ni;  // first b_1 whose v'_1 reaches the slab window
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const T vb = P.v1[mid];
+                    const T d = va1 - vb;
+                    const T v1p = (va1 + vb) * half + sqrt(d * d + r2) * sg[0] * half;
+                    if (v1p < vlo) lo = mid + 1;
+                    else hi = mid;
+                }
+                b1 = lo;
+                have = true;
             }
-        }
-        for (int l = 0; l < DIM; ++l) sg[l] = P.sigma[s * DIM + l];
-        T r2 = 0;
-        if constexpr (DIM == 2) {
-            vr[1] = P.v1[pencil];
-            const T d = vi[1] - vr[1];
-            r2 = d * d;
-        } else {
-            vr[1] = P.v1[pencil / ni];
-            vr[2] = P.v1[pencil % ni];
-            const T d1 = vi[1] - vr[1], d2 = vi[2] - vr[2];
-            r2 = d1 * d1 + d2 * d2;
-        }
-
-        // first j_1 whose v'_1 reaches the slab window
-        int lo = 0, hi = ni;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            const T vj = P.v1[mid];
-            const T d = vi[0] - vj;
-            const T un = sqrt(d * d + r2);
-            const T v1p = (vi[0] + vj) * half + un * sg[0] * half;
-            if (v1p < vlo) lo = mid + 1;
-            else hi = mid;
-        }
-
-        for (int j1 = lo; j1 < ni; ++j1) {
-            const T vj = P.v1[j1];
-            const T d = vi[0] - vj;
+            if (b1 >= ni) {
+                have = false;
+                item += blockDim.x;
+                continue;
+            }
+            const T vb = P.v1[b1];
+            const T d = va1 - vb;
             const T un = sqrt(d * d + r2);
             T vp[DIM];
-            vp[0] = (vi[0] + vj) * half + un * sg[0] * half;
-            if (vp[0] > vhi) break;
-            const int64_t j = (int64_t)j1 * npencil + pencil;
-            const T gj = P.G[j];
-            if (gj == (T)0) continue;
-            T q = cu * gj;
+            vp[0] = (va1 + vb) * half + un * sg[0] * half;
+            if (vp[0] > vhi) {
+                have = false;
+                item += blockDim.x;
+                continue;
+            }
+            const T sy = symrow[b1];
+            ++b1;
+            if (sy == (T)0) continue;
+            q = cs * sy;
             if (P.vhs) q *= (P.gamma == (T)1) ? un : (un > (T)0 ? pow(un, P.gamma) : (T)(P.gamma == (T)0));
-            for (int l = 1; l < DIM; ++l) vp[l] = (vi[l] + vr[l]) * half + un * sg[l] * half;
-
-            int t0[DIM];
-            T ker[DIM][W];
+            for (int l = 1; l < DIM; ++l) vp[l] = cen[l] + un * sg[l] * half;
 #pragma unroll
             for (int l = 0; l < DIM; ++l) {
                 T z, m2;
@@ -361,39 +470,53 @@ __global__ void __launch_bounds__(spread_max_threads<T>()) gain_spread(GainParam
                 const T xs = z * P.h_inv - (T)(0.5 * W);
                 const T tf = ceil(xs);
                 t0[l] = (int)tf;
-                kernel_cells<T, W, TERMS>(P.poly, (T)2 * (tf - xs) - (T)1, ker[l]);
+                sfr[l] = (T)2 * (tf - xs) - (T)1;
             }
+            valid = true;
+            break;
+        }
 
-            int idx1[W];
-#pragma unroll
-            for (int a = 0; a < W; ++a) idx1[a] = fold_index(t0[1] + a, P.nh);
+        const unsigned long long mask = __ballot(valid);
+        if (mask == 0ull) break;
+
+        // first-dimension kernel cells of this lane's point (3D: shared by the wave)
+        T k1[W];
+        if constexpr (DIM == 3) kernel_cells<T, W, TERMS>(P.poly, sfr[0], k1);
+
+        unsigned long long rem = mask;
+        while (rem) {
+            const int p = __builtin_ctzll(rem);
+            rem &= rem - 1ull;
+            const T qp = lane_get(q, p);
+            const int ta = lane_get(t0[0], p);
+            const int tb = lane_get(t0[1], p);
+            const T sa = lane_get(sfr[0], p);
+            const T sb = lane_get(sfr[1], p);
             if constexpr (DIM == 2) {
 #pragma unroll
-                for (int a = 0; a < W; ++a) {
-                    const int m0 = fold_index(t0[0] + a, P.nh);
-                    if (m0 < p0 || m0 >= p1) continue;
-                    const T qa = q * ker[0][a];
-                    double* row = slab + (m0 - p0) * plane;
-#pragma unroll
-                    for (int bb = 0; bb < W; ++bb) lds_add(row + idx1[bb], (double)(qa * ker[1][bb]));
+                for (int r = 0; r < NPASS; ++r) {
+                    const int m0 = fold_index(ta + own_x[r], P.nh);
+                    if (own_ok[r] && m0 >= p0 && m0 < p1) {
+                        const T val = qp * horner<T, TERMS>(cx[r], sa) * horner<T, TERMS>(cy[r], sb);
+                        lds_add(slab + (m0 - p0) * plane + fold_index(tb + own_y[r], P.nh), (double)val);
+                    }
                 }
             } else {
-                int idx2[W];
+                const int tc = lane_get(t0[2], p);
+                const T sc = lane_get(sfr[2], p);
+                T k1p[W];
 #pragma unroll
-                for (int a = 0; a < W; ++a) idx2[a] = fold_index(t0[DIM - 1] + a, P.nh);
+                for (int a = 0; a < W; ++a) k1p[a] = lane_get(k1[a], p);
 #pragma unroll
-                for (int a = 0; a < W; ++a) {
-                    const int m0 = fold_index(t0[0] + a, P.nh);
-                    if (m0 < p0 || m0 >= p1) continue;
-                    const T qa = q * ker[0][a];
-                    double* pl = slab + (m0 - p0) * plane;
+                for (int r = 0; r < NPASS; ++r) {
+                    if (!own_ok[r]) continue;
+                    const T val = qp * horner<T, TERMS>(cx[r], sb) * horner<T, TERMS>(cy[r], sc);
+                    double* cell = slab + fold_index(tb + own_x[r], P.nh) * P.ng +
+                                   fold_index(tc + own_y[r], P.nh) - (int64_t)p0 * plane;
 #pragma unroll
-                    for (int bb = 0; bb < W; ++bb) {
-                        const T qab = qa * ker[1][bb];
-                        double* row = pl + idx1[bb] * P.ng;
-#pragma unroll
-                        for (int cc = 0; cc < W; ++cc)
-                            lds_add(row + idx2[cc], (double)(qab * ker[DIM - 1][cc]));
+                    for (int a = 0; a < W; ++a) {
+                        const int m0 = fold_index(ta + a, P.nh);
+                        if (m0 >= p0 && m0 < p1) lds_add(cell + m0 * plane, (double)(val * k1p[a]));
                     }
                 }
             }
@@ -402,6 +525,270 @@ __global__ void __launch_bounds__(spread_max_threads<T>()) gain_spread(GainParam
     __syncthreads();
     double* dst = P.partial + c * P.ngd + (int64_t)p0 * plane;
     for (int e = threadIdx.x; e < slab_elems; e += blockDim.x) dst[e] = slab[e];
+}
+
+// ------------------------------------------------------------------ binned gain
+//
+// The positions of the merged points depend on the plan only (not on f), so the
+// plan sorts them once by the base cell of their spreading footprint (the
+// corner t0 = ceil(z/h - W/2) in every dimension).  One evaluation then walks
+// the bins: a wave regenerates 64 points of one bin, stages their kernel
+// vectors in LDS and accumulates the bin's W^d footprint in registers, one
+// lane per footprint column, before a single flush of W^d global FP64 atomics.
+//
+// Point ids pack (b_1, a_1, s, p_2, p_3) as b1 | a1 << 8 | s << 16 | p2 << 26 | p3 << 42.
+
+__device__ __forceinline__ unsigned long long pack_id(int s, int a1, int b1, int p2, int p3)
+{
+    return (unsigned long long)b1 | ((unsigned long long)a1 << 8) | ((unsigned long long)s << 16) |
+           ((unsigned long long)p2 << 26) | ((unsigned long long)p3 << 42);
+}
+
+// geometry of one merged point: weight without the orbit sum, and z/h - W/2
+template <typename T, int DIM>
+__device__ __forceinline__ void point_geometry(const GainParams<T>& P, int s, int a1, int b1, int p2,
+                                               int p3, T halfW, T& q, T* xs, int64_t& sym_idx)
+{
+    const T half = (T)0.5;
+    const T va = P.v1[a1], vb = P.v1[b1];
+    const T d = va - vb;
+    T cen[DIM], r2;
+    {
+        const T x = P.v1[P.pair_a[p2]], y = P.v1[P.pair_b[p2]];
+        cen[1] = (x + y) * half;
+        r2 = (x - y) * (x - y);
+    }
+    if constexpr (DIM == 3) {
+        const T x = P.v1[P.pair_a[p3]], y = P.v1[P.pair_b[p3]];
+        cen[2] = (x + y) * half;
+        r2 += (x - y) * (x - y);
+    }
+    const T un = sqrt(d * d + r2);
+    T vp[DIM];
+    vp[0] = (va + vb) * half + un * P.sigma[s * DIM] * half;
+    for (int l = 1; l < DIM; ++l) vp[l] = cen[l] + un * P.sigma[s * DIM + l] * half;
+    q = P.sigma_w[s] * P.b0;
+    if (P.vhs) q *= (P.gamma == (T)1) ? un : (un > (T)0 ? pow(un, P.gamma) : (T)(P.gamma == (T)0));
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) {
+        T z, m2;
+        map_point(vp[l], P, z, m2);
+        q *= m2;
+        xs[l] = z * P.h_inv - halfW;
+    }
+    const int64_t p1 = P.pair_base[a1] + (b1 - a1);
+    sym_idx = (DIM == 2) ? (int64_t)p2 * P.np + p1 : ((int64_t)p2 * P.np + p3) * P.np + p1;
+}
+
+struct BinGeo {
+    int nb;      // bins per dimension
+    int off;     // bin index = t0 + off
+    int W;
+    int64_t n_items;  // (s, a_1, pencil) generation items
+};
+
+template <typename T, int DIM>
+__device__ __forceinline__ int64_t point_bin(const T* xs, const BinGeo& B)
+{
+    int64_t bin = 0;
+    for (int l = 0; l < DIM; ++l) {
+        int t = (int)ceil(xs[l]) + B.off;
+        t = t < 0 ? 0 : (t >= B.nb ? B.nb - 1 : t);
+        bin = bin * B.nb + t;
+    }
+    return bin;
+}
+
+// plan time: MODE 0 counts the points of every bin, MODE 1 scatters their ids
+template <typename T, int DIM, int MODE>
+__global__ void __launch_bounds__(256) bin_points(GainParams<T> P, BinGeo B,
+                                                  unsigned int* __restrict__ count,
+                                                  unsigned long long* __restrict__ cursor,
+                                                  unsigned long long* __restrict__ ids)
+{
+    const int np = P.np;
+    const int npencil = (DIM == 2) ? np : np * np;
+    const T halfW = (T)(0.5 * B.W);
+    for (int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; item < B.n_items;
+         item += (int64_t)gridDim.x * blockDim.x) {
+        const int pencil = (int)(item % npencil);
+        const int64_t us = item / npencil;
+        const int s = (int)(us % P.n_sigma);
+        const int a1 = (int)(us / P.n_sigma);
+        const int p2 = (DIM == 2) ? pencil : pencil / np;
+        const int p3 = (DIM == 2) ? 0 : pencil % np;
+        for (int b1 = a1; b1 < P.ni; ++b1) {
+            T q, xs[DIM];
+            int64_t si;
+            point_geometry<T, DIM>(P, s, a1, b1, p2, p3, halfW, q, xs, si);
+            const int64_t bin = point_bin<T, DIM>(xs, B);
+            if constexpr (MODE == 0) {
+                atomicAdd(count + bin, 1u);
+            } else {
+                const unsigned long long slot = atomicAdd(cursor + bin, 1ull);
+                ids[slot] = pack_id(s, a1, b1, p2, p3);
+            }
+        }
+    }
+}
+
+struct BinItems {
+    const int* bin;              // bin of each work item
+    const long long* begin;      // first id of the item
+    const int* count;            // ids in the item (<= 64 * batches)
+    const unsigned long long* ids;
+    double* grid;                // n_g^d FP64 accumulation grid
+    BinGeo geo;
+};
+
+// One wave per work item (a run of ids of one bin).  LP lanes serve one point:
+// in 3D lane e <-> footprint column (b, c) = (e / W, e % W) with the W cells
+// along the first dimension in registers; in 2D lane e <-> b.  G = 64 / LP
+// points are processed per step; NPASS > 1 when W^2 > 64.
+template <typename T, int DIM, int W>
+__global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
+{
+    constexpr int TERMS = W + 2;
+    constexpr int CELLS = (DIM == 2) ? W : W * W;          // lanes per point, all passes
+    constexpr int LP = CELLS <= 64 ? CELLS : 64;
+    constexpr int G = CELLS <= 64 ? 64 / CELLS : 1;
+    constexpr int NPASS = (CELLS + 63) / 64;
+    constexpr int STRIDE = 1 + DIM * W;                      // staged values per point
+    __shared__ T stage[64 * STRIDE];
+    __shared__ double red[(G > 1) ? 64 * W : 1];
+
+    const int lane = threadIdx.x;
+    const int item = blockIdx.x;
+    const int bin = BI.bin[item];
+    const long long first = BI.begin[item];
+    const int n = BI.count[item];
+    const T halfW = (T)(0.5 * W);
+
+    // base cell of the bin
+    int t0[DIM];
+    {
+        int r = bin;
+        for (int l = DIM - 1; l >= 0; --l) {
+            t0[l] = r % BI.geo.nb - BI.geo.off;
+            r /= BI.geo.nb;
+        }
+    }
+    const int g = lane / LP;
+    const int e0 = lane % LP;
+    const bool lane_on = g < G;
+
+    double acc64[NPASS][W];
+    T acc[NPASS][W];
+#pragma unroll
+    for (int r = 0; r < NPASS; ++r)
+#pragma unroll
+        for (int a = 0; a < W; ++a) acc64[r][a] = 0.0;
+
+    for (int base = 0; base < n; base += 64) {
+        const int nv = min(64, n - base);
+        // regenerate one point per lane and stage q and its kernel vectors
+        {
+            T* st = stage + lane * STRIDE;
+            if (lane < nv) {
+                const unsigned long long id = BI.ids[first + base + lane];
+                const int b1 = (int)(id & 0xffull), a1 = (int)((id >> 8) & 0xffull);
+                const int s = (int)((id >> 16) & 0x3ffull);
+                const int p2 = (int)((id >> 26) & 0xffffull), p3 = (int)((id >> 42) & 0xffffull);
+                T q, xs[DIM];
+                int64_t si;
+                point_geometry<T, DIM>(P, s, a1, b1, p2, p3, halfW, q, xs, si);
+                st[0] = q * P.sym[si];
+#pragma unroll
+                for (int l = 0; l < DIM; ++l) {
+                    T k[W];
+                    // offset relative to the bin's corner: s = 2 (t0 - xs) - 1
+                    kernel_cells<T, W, TERMS>(P.poly, (T)2 * ((T)t0[l] - xs[l]) - (T)1, k);
+#pragma unroll
+                    for (int a = 0; a < W; ++a) st[1 + l * W + a] = k[a];
+                }
+            } else {
+                st[0] = (T)0;
+#pragma unroll
+                for (int a = 0; a < DIM * W; ++a) st[1 + a] = (T)0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NPASS; ++r)
+#pragma unroll
+            for (int a = 0; a < W; ++a) acc[r][a] = (T)0;
+        const int steps = (nv + G - 1) / G;
+        for (int st_i = 0; st_i < steps; ++st_i) {
+            const int pnt = st_i * G + g;
+            if (lane_on && pnt < nv) {
+                const T* sp = stage + pnt * STRIDE;
+                const T qp = sp[0];
+                T k1[W];
+#pragma unroll
+                for (int a = 0; a < W; ++a) k1[a] = sp[1 + a];
+#pragma unroll
+                for (int r = 0; r < NPASS; ++r) {
+                    const int e = e0 + 64 * r;
+                    if (e < CELLS) {
+                        T t;
+                        if constexpr (DIM == 2) t = qp * sp[1 + W + e];
+                        else t = qp * sp[1 + W + e / W] * sp[1 + 2 * W + e % W];
+#pragma unroll
+                        for (int a = 0; a < W; ++a) acc[r][a] = fma(t, k1[a], acc[r][a]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NPASS; ++r)
+#pragma unroll
+            for (int a = 0; a < W; ++a) acc64[r][a] += (double)acc[r][a];
+        __syncthreads();
+    }
+
+    // groups of lanes that served different points hold partial sums of the same cells
+    if constexpr (G > 1) {
+        if (lane_on && g > 0) {
+#pragma unroll
+            for (int a = 0; a < W; ++a) red[((g - 1) * LP + e0) * W + a] = acc64[0][a];
+        }
+        __syncthreads();
+        if (g == 0) {
+            for (int gg = 1; gg < G; ++gg)
+#pragma unroll
+                for (int a = 0; a < W; ++a) acc64[0][a] += red[((gg - 1) * LP + e0) * W + a];
+        }
+    }
+    if (g != 0) return;
+#pragma unroll
+    for (int r = 0; r < NPASS; ++r) {
+        const int e = e0 + 64 * r;
+        if (e >= CELLS) continue;
+        int64_t rest;
+        if constexpr (DIM == 2) rest = fold_index(t0[1] + e, P.nh);
+        else rest = (int64_t)fold_index(t0[1] + e / W, P.nh) * P.ng + fold_index(t0[2] + e % W, P.nh);
+        const int64_t plane = (DIM == 2) ? P.ng : (int64_t)P.ng * P.ng;
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            const double v = acc64[r][a];
+            if (v != 0.0)
+                __hip_atomic_fetch_add(BI.grid + fold_index(t0[0] + a, P.nh) * plane + rest, v,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+__global__ void fill_zero(double* __restrict__ x, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.0;
+}
+
+template <typename T>
+__global__ void grid_convert(const double* __restrict__ g, T* __restrict__ out, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (T)g[i];
 }
 
 // grid[m] = sum_c partial[c][m], FP64 accumulation in chunk order
@@ -662,11 +1049,14 @@ hipError_t spread_dispatch(const Plan& p, const GainParams<T>& gp, hipStream_t s
 }
 
 template <typename T>
-hipError_t gain_t(const Plan& p, hipStream_t s)
+GainParams<T> gain_params(const Plan& p)
 {
     GainParams<T> gp;
     gp.v1 = static_cast<const T*>(p.dt.v1);
-    gp.G = static_cast<const T*>(p.ws.G);
+    gp.sym = static_cast<const T*>(p.ws.sym);
+    gp.pair_a = p.dt.pair_a;
+    gp.pair_b = p.dt.pair_b;
+    gp.pair_base = p.dt.pair_base;
     gp.sigma = static_cast<const T*>(p.dt.sigma);
     gp.sigma_w = static_cast<const T*>(p.dt.sigma_w);
     gp.poly = static_cast<const T*>(p.dt.poly);
@@ -681,18 +1071,114 @@ hipError_t gain_t(const Plan& p, hipStream_t s)
     gp.map = p.map;
     gp.vhs = p.kernel == PGC_KERNEL_VHS;
     gp.ni = p.ni;
+    gp.np = p.np;
     gp.ng = p.ng;
     gp.nh = p.nh;
     gp.slab_planes = p.slab_planes;
-    gp.nid = p.nid;
+    gp.n_sigma = p.n_sigma;
     gp.ngd = p.ngd;
     gp.n_units = p.n_units;
     gp.units_per_chunk = p.units_per_chunk;
-    hipError_t e = (p.dim == 2) ? spread_dispatch<T, 2>(p, gp, s) : spread_dispatch<T, 3>(p, gp, s);
+    return gp;
+}
+
+template <typename T, int DIM, int W>
+hipError_t binned_launch(const Plan& p, const GainParams<T>& gp, const BinItems& bi, hipStream_t s)
+{
+    if (p.bins.n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL((gain_binned<T, DIM, W>), dim3((unsigned)p.bins.n_items), dim3(64), 0, s, gp, bi);
+    return hipGetLastError();
+}
+
+template <typename T, int DIM>
+hipError_t binned_dispatch(const Plan& p, const GainParams<T>& gp, const BinItems& bi, hipStream_t s)
+{
+    switch (p.W) {
+#define PGC_B_CASE(w) \
+    case w: return binned_launch<T, DIM, w>(p, gp, bi, s);
+        PGC_B_CASE(4)
+        PGC_B_CASE(5)
+        PGC_B_CASE(6)
+        PGC_B_CASE(7)
+        PGC_B_CASE(8)
+        PGC_B_CASE(9)
+        PGC_B_CASE(10)
+        PGC_B_CASE(11)
+        PGC_B_CASE(12)
+        PGC_B_CASE(13)
+        PGC_B_CASE(14)
+#undef PGC_B_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// plan time: count and scatter the merged points into their bins
+template <typename T>
+hipError_t bin_build_t(const Plan& p, unsigned int* count, unsigned long long* cursor,
+                       unsigned long long* ids, int mode, hipStream_t s)
+{
+    const GainParams<T> gp = gain_params<T>(p);
+    BinGeo bg;
+    bg.nb = p.bins.nb;
+    bg.off = p.bins.off;
+    bg.W = p.W;
+    const int64_t npencil = p.dim == 2 ? p.np : (int64_t)p.np * p.np;
+    bg.n_items = (int64_t)p.n_sigma * p.ni * npencil;
+    const int64_t want = (bg.n_items + 255) / 256;
+    const unsigned blocks = (unsigned)std::min<int64_t>(want, 65536);
+    if (p.dim == 2) {
+        if (mode == 0)
+            hipLaunchKernelGGL((bin_points<T, 2, 0>), dim3(blocks), dim3(256), 0, s, gp, bg, count, cursor, ids);
+        else
+            hipLaunchKernelGGL((bin_points<T, 2, 1>), dim3(blocks), dim3(256), 0, s, gp, bg, count, cursor, ids);
+    } else {
+        if (mode == 0)
+            hipLaunchKernelGGL((bin_points<T, 3, 0>), dim3(blocks), dim3(256), 0, s, gp, bg, count, cursor, ids);
+        else
+            hipLaunchKernelGGL((bin_points<T, 3, 1>), dim3(blocks), dim3(256), 0, s, gp, bg, count, cursor, ids);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gain_t(const Plan& p, hipStream_t s)
+{
+    const int64_t n_sym = p.dim == 2 ? (int64_t)p.np * p.np : (int64_t)p.np * p.np * p.np;
+    if (p.dim == 2)
+        hipLaunchKernelGGL((pair_orbit_sums<T, 2>), dim3(blocks_for(n_sym, 256)), dim3(256), 0, s,
+                           static_cast<const T*>(p.ws.G), static_cast<T*>(p.ws.sym), p.dt.pair_a,
+                           p.dt.pair_b, p.ni, p.np, n_sym);
+    else
+        hipLaunchKernelGGL((pair_orbit_sums<T, 3>), dim3(blocks_for(n_sym, 256)), dim3(256), 0, s,
+                           static_cast<const T*>(p.ws.G), static_cast<T*>(p.ws.sym), p.dt.pair_a,
+                           p.dt.pair_b, p.ni, p.np, n_sym);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_partials<T>, dim3(blocks_for(p.ngd, 256)), dim3(256), 0, s,
-                       static_cast<const double*>(p.ws.partial), static_cast<T*>(p.ws.grid), p.ngd,
-                       p.n_chunks);
+
+    const GainParams<T> gp = gain_params<T>(p);
+    if (p.gain_mode == kGainBinned) {
+        hipLaunchKernelGGL(fill_zero, dim3(blocks_for(p.ngd, 256)), dim3(256), 0, s, p.ws.grid64, p.ngd);
+        BinItems bi;
+        bi.bin = p.bins.item_bin;
+        bi.begin = p.bins.item_begin;
+        bi.count = p.bins.item_count;
+        bi.ids = p.bins.ids;
+        bi.grid = p.ws.grid64;
+        bi.geo.nb = p.bins.nb;
+        bi.geo.off = p.bins.off;
+        bi.geo.W = p.W;
+        bi.geo.n_items = 0;
+        e = (p.dim == 2) ? binned_dispatch<T, 2>(p, gp, bi, s) : binned_dispatch<T, 3>(p, gp, bi, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(grid_convert<T>, dim3(blocks_for(p.ngd, 256)), dim3(256), 0, s,
+                           p.ws.grid64, static_cast<T*>(p.ws.grid), p.ngd);
+    } else {
+        e = (p.dim == 2) ? spread_dispatch<T, 2>(p, gp, s) : spread_dispatch<T, 3>(p, gp, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(reduce_partials<T>, dim3(blocks_for(p.ngd, 256)), dim3(256), 0, s,
+                           static_cast<const double*>(p.ws.partial), static_cast<T*>(p.ws.grid), p.ngd,
+                           p.n_chunks);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return separable<T>(p, static_cast<const T*>(p.ws.grid), static_cast<T*>(p.ws.qplus),
@@ -738,6 +1224,13 @@ hipError_t launch_loss(const Plan& p, hipStream_t s)
 hipError_t launch_gain(const Plan& p, hipStream_t s)
 {
     return p.precision == PGC_PRECISION_FP64 ? gain_t<double>(p, s) : gain_t<float>(p, s);
+}
+
+hipError_t launch_bin_build(const Plan& p, unsigned int* count, unsigned long long* cursor,
+                            unsigned long long* ids, int mode, hipStream_t s)
+{
+    return p.precision == PGC_PRECISION_FP64 ? bin_build_t<double>(p, count, cursor, ids, mode, s)
+                                             : bin_build_t<float>(p, count, cursor, ids, mode, s);
 }
 
 hipError_t launch_combine(const Plan& p, void* q, void* qplus, hipStream_t s)

@@ -20,6 +20,7 @@ SCALE_DIRECT, SCALE_FROM_DOMAIN = 0, 1
 KERNEL_MAXWELL, KERNEL_VHS = 0, 1
 SPHERE_UNIFORM_2D, SPHERE_PRODUCT_3D, SPHERE_USER = 0, 1, 2
 FP64, FP32 = 0, 1
+GAIN_AUTO, GAIN_SLAB, GAIN_BINNED = 0, 1, 2
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported configuration", 3: "out of device memory",
           4: "device error", 5: "non-finite result"}
@@ -43,6 +44,7 @@ class PlanDesc(ctypes.Structure):
         ("precision", ctypes.c_int32), ("nufft_tol", ctypes.c_double), ("upsample", ctypes.c_double),
         ("kernel_width", ctypes.c_int32), ("slab_planes", ctypes.c_int32),
         ("n_chunks", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+        ("gain_mode", ctypes.c_int32),
     ]
 
 
@@ -55,7 +57,8 @@ class PlanInfo(ctypes.Structure):
         ("kernel_beta", ctypes.c_double), ("upsample", ctypes.c_double),
         ("slab_planes", ctypes.c_int32), ("n_slabs", ctypes.c_int32), ("n_chunks", ctypes.c_int32),
         ("block_threads", ctypes.c_int32), ("n_triples", ctypes.c_int64),
-        ("workspace_bytes", ctypes.c_int64),
+        ("n_points", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+        ("gain_mode", ctypes.c_int32), ("n_bin_items", ctypes.c_int64),
     ]
 
 

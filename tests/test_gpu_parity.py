@@ -58,8 +58,9 @@ def gpu_q(torch, plan, coeffs):
 
 
 def check_q(torch, ora, plan, coeffs, tol, label):
-    say("case:", label, plan.info.n_triples, "triples, W =", plan.info.kernel_width,
-        "slabs =", plan.info.n_slabs, "chunks =", plan.info.n_chunks)
+    say("case:", label, plan.info.n_triples, "triples,", plan.info.n_points, "points, W =",
+        plan.info.kernel_width, "mode =", plan.info.gain_mode, "slabs =", plan.info.n_slabs,
+        "bin items =", plan.info.n_bin_items)
     q, qp = gpu_q(torch, plan, coeffs)
     q_ref, qp_ref, _ = ora.collision(coeffs)
     r, rp = rel_l2(q, q_ref), rel_l2(qp, qp_ref)
@@ -202,3 +203,23 @@ def test_invalid_arguments(torch_cuda):
     s = np.array([[1.0, 0.0], [0.0, 1.0]])
     with pytest.raises(pgc.PgcError):
         pgc.Plan(dim=2, n_modes=8, sigma=s, sigma_w=np.ones(2))   # not antipodal
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_q_parity_both_gain_modes(torch_cuda, dim, prec):
+    """The LDS-slab scheme and the binned scheme give the same Q within the bar."""
+    from paper_2105_08806_amd import pgc
+    N = 12 if dim == 2 else 8
+    shape = (N,) * dim
+    c = I.random_coeffs(shape, seed=21 + dim)
+    tol = FP64_TOL if prec == 0 else FP32_TOL
+    for mode in (pgc.GAIN_SLAB, pgc.GAIN_BINNED):
+        if dim == 2:
+            ora, plan = make_pair(2, N, 2.5, n_sigma=8, prec=prec, gain_mode=mode)
+        else:
+            ora, plan = make_pair(3, N, 2.0, n_theta=2, n_phi=4, prec=prec, gain_mode=mode)
+        assert plan.info.gain_mode == mode
+        check_q(torch_cuda, ora, plan, c.astype(np.float32).astype(np.float64) if prec else c, tol,
+                "%dD mode=%d prec=%d" % (dim, mode, prec))
+        plan.close()
