@@ -94,8 +94,8 @@ typedef struct pgc_plan_desc {
     const double* user_weights_host; /* USER: n_sigma positive weights (copied) */
     int32_t precision;    /* PGC_PRECISION_FP64 or PGC_PRECISION_FP32 */
     double nufft_tol;     /* requested accuracy of the cosine transform relative to sum |q|;
-                             0 = 1e-13 (FP64) or 1e-7 (FP32) */
-    double upsample;      /* fine-grid upsampling factor sigma_up in [1.5, 4]; 0 = 2 */
+                             0 = 5e-13 (FP64) or 1e-6 (FP32) */
+    double upsample;      /* fine-grid upsampling factor sigma_up in [1.5, 4]; 0 = 3 */
     int32_t kernel_width; /* spreading kernel width W in grid cells (2..16); 0 = from nufft_tol */
     int32_t slab_planes;  /* fine-grid planes held in LDS per workgroup; 0 = as many as fit */
     int32_t n_chunks;     /* collision-unit chunks (partial grids); 0 = automatic */
@@ -187,6 +187,17 @@ pgc_status pgc_moments(pgc_plan plan, const void* coeffs_dev, double* out_dev, v
  * Q_N = sum_k Q_k T~_k (the equivalent form, eq. P_G_method) off the hot path. */
 pgc_status pgc_eval(pgc_plan plan, const void* coeffs_dev, const double* v_dev, int64_t n,
                     double* out_dev, void* stream);
+
+/* Stage timing.  With profiling on, every pgc_coeffs_to_q records HIP events
+ * on its stream between its stages (no host synchronisation); pgc_stage_times
+ * waits for the recorded events and returns, per stage, the accumulated
+ * milliseconds (ms_out) and the number of timed calls (calls_out may be NULL),
+ * then resets the accumulators.  Stages: 0 synthesis, 1 loss field and loss
+ * projection, 2 pair-orbit sums, 3 spreading (the dominant kernel), 4 grid to
+ * modes (conversion and cosine transform), 5 combination.  n_stages <= 8.
+ * pgc_set_profiling(plan, 0) stops recording. */
+pgc_status pgc_set_profiling(pgc_plan plan, int32_t on);
+pgc_status pgc_stage_times(pgc_plan plan, double* ms_out, int32_t n_stages, int64_t* calls_out);
 
 #ifdef __cplusplus
 }

@@ -59,15 +59,18 @@ double es_kernel(double y, double beta)
     return std::exp(beta * (std::sqrt(1.0 - y * y) - 1.0));
 }
 
-// Accuracy table of the folded cosine transform at upsampling 2, measured on
-// random points against the direct sum (max error over modes / sum |q|),
-// for W = 4..16; entries beyond 13 sit at the FP64 rounding floor.
+// Accuracy of the folded cosine transform at upsampling 2 and 3, measured on
+// random points against the direct sum (max error over modes / sum |q|), for
+// W = 4..16; entries at 2.5e-14 sit at the FP64 rounding floor.
 const double kErrSigma2[] = {1.3e-5, 1.2e-6, 2.3e-7, 2.3e-8, 1.8e-9, 2.4e-10, 3.2e-11,
                              3.4e-12, 2.1e-13, 3.3e-14, 2.5e-14, 2.5e-14, 2.5e-14};
+const double kErrSigma3[] = {5.1e-6, 2.5e-7, 2.6e-8, 2.6e-9, 1.9e-10, 1.7e-11, 8.9e-13,
+                             9.9e-14, 2.5e-14, 2.5e-14, 2.5e-14, 2.5e-14, 2.5e-14};
 
 double estimated_error(int W, double upsample)
 {
     if (std::fabs(upsample - 2.0) < 1e-12) return 3.0 * kErrSigma2[W - 4];
+    if (std::fabs(upsample - 3.0) < 1e-12) return 3.0 * kErrSigma3[W - 4];
     // exp(-pi W sqrt(1 - 1/sigma)) decay of the ES kernel, with a safety factor
     return 10.0 * std::exp(-kPi * W * std::sqrt(1.0 - 1.0 / upsample));
 }
@@ -232,8 +235,10 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
     p.b0 = d.kernel_b0 > 0.0 ? d.kernel_b0 : 1.0 / area;
 
     // spreading kernel and fine grid
-    p.upsample = d.upsample > 0.0 ? d.upsample : 2.0;
-    p.tol = d.nufft_tol > 0.0 ? d.nufft_tol : (p.precision == PGC_PRECISION_FP64 ? 1e-13 : 1e-7);
+    // upsampling 3 trades a 1.5^d larger fine grid (cheap: one cosine transform per
+    // evaluation) for a narrower kernel (W^d work per point): measured fastest
+    p.upsample = d.upsample > 0.0 ? d.upsample : 3.0;
+    p.tol = d.nufft_tol > 0.0 ? d.nufft_tol : (p.precision == PGC_PRECISION_FP64 ? 5e-13 : 1e-6);
     p.W = d.kernel_width > 0 ? d.kernel_width : width_for(p.tol, p.upsample);
     p.gain_mode = d.gain_mode == 1 ? kGainSlab : kGainBinned;
     if (p.gain_mode == kGainBinned && p.W > 14) {
@@ -243,9 +248,10 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
     p.auto_gain = d.gain_mode == 0;
     p.terms = p.W + 2;
     p.beta = beta_for(p.W, p.upsample);
-    // n >= 2 sigma N, and n/2 >= W so that a footprint folds back at most once
-    // (small N only: a finer grid is merely a larger upsampling factor)
-    p.n = std::max(2 * (int)std::ceil(p.upsample * p.N), 2 * p.W);
+    // n >= 2 sigma N, and n >= 4 W so that a footprint folds back at most once and
+    // the kernel stays narrow against the period (small N only: a finer grid is
+    // merely a larger upsampling factor)
+    p.n = std::max(2 * (int)std::ceil(p.upsample * p.N), 4 * p.W);
     p.nh = p.n / 2;
     p.ng = p.nh + 1;
     p.h = 2.0 * kPi / p.n;
@@ -558,7 +564,7 @@ hipError_t allocate(Plan& p, hipStream_t s)
     {
         int64_t nsym = 1;
         for (int l = 0; l < p.dim; ++l) nsym *= p.np;
-        PGC_TRY(dev_alloc(p, &p.ws.sym, nsym * e8));
+        if (p.gain_mode == kGainSlab) PGC_TRY(dev_alloc(p, &p.ws.sym, nsym * e8));
         std::vector<int> pa(p.np), pb(p.np), base(p.ni);
         int q = 0;
         for (int a = 0; a < p.ni; ++a) {
@@ -609,6 +615,9 @@ hipError_t allocate(Plan& p, hipStream_t s)
             p.gain_mode = kGainSlab;
             p.bins = BinIndex();
             PGC_TRY(dev_alloc(p, &p.ws.partial, (size_t)p.n_chunks * p.ngd * sizeof(double)));
+            int64_t nsym = 1;
+            for (int l = 0; l < p.dim; ++l) nsym *= p.np;
+            PGC_TRY(dev_alloc(p, &p.ws.sym, nsym * e8));
         } else if (e != hipSuccess) {
             return e;
         }
@@ -702,6 +711,7 @@ pgc_status pgc_plan_create(const pgc_plan_desc* desc, void* stream, pgc_plan* pl
 pgc_status pgc_plan_destroy(pgc_plan plan)
 {
     if (!plan) return PGC_OK;
+    (void)pgc_set_profiling(plan, 0);
     (void)hipDeviceSynchronize();
     pgc::free_all(plan->p);
     delete plan;
@@ -756,16 +766,91 @@ pgc_status pgc_project(pgc_plan plan, const double* f_nodes, void* coeffs, void*
     return pgc::from_hip(pgc::launch_project(plan->p, f_nodes, coeffs, static_cast<hipStream_t>(stream)));
 }
 
+namespace {
+
+// read back one recorded event set into the accumulators
+hipError_t prof_collect(pgc::Profiler& pr, int set)
+{
+    hipError_t e = hipEventSynchronize(pr.ev[set][pgc::kStages]);
+    if (e != hipSuccess) return e;
+    for (int k = 0; k < pgc::kStages; ++k) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, pr.ev[set][k], pr.ev[set][k + 1]) == hipSuccess) pr.ms[k] += ms;
+    }
+    pr.calls += 1;
+    return hipSuccess;
+}
+
+}  // namespace
+
 pgc_status pgc_coeffs_to_q(pgc_plan plan, const void* coeffs, void* q, void* qplus, void* stream)
 {
     if (!plan || !coeffs || !q) return PGC_ERR_INVALID_ARG;
-    const Plan& p = plan->p;
+    Plan& p = plan->p;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p.prof) {
+        pgc::Profiler& pr = *p.prof;
+        if (pr.used == pgc::kProfRing) {  // ring full: fold in the oldest set first
+            hipError_t e = prof_collect(pr, pr.head);
+            if (e != hipSuccess) return pgc::from_hip(e);
+            --pr.used;
+        }
+        p.prof_set = pr.head;
+        pr.head = (pr.head + 1) % pgc::kProfRing;
+        ++pr.used;
+    }
+    pgc::prof_mark(p, 0, s);
     hipError_t e = pgc::launch_synthesis(p, coeffs, s);
+    pgc::prof_mark(p, 1, s);
     if (e == hipSuccess) e = pgc::launch_loss(p, s);
     if (e == hipSuccess) e = pgc::launch_gain(p, s);
+    pgc::prof_mark(p, 5, s);
     if (e == hipSuccess) e = pgc::launch_combine(p, q, qplus, s);
+    pgc::prof_mark(p, 6, s);
+    p.prof_set = -1;
     return pgc::from_hip(e);
+}
+
+pgc_status pgc_set_profiling(pgc_plan plan, int32_t on)
+{
+    if (!plan) return PGC_ERR_INVALID_ARG;
+    Plan& p = plan->p;
+    if (on && !p.prof) {
+        pgc::Profiler* pr = new (std::nothrow) pgc::Profiler();
+        if (!pr) return PGC_ERR_OUT_OF_MEMORY;
+        for (int r = 0; r < pgc::kProfRing; ++r)
+            for (int k = 0; k <= pgc::kStages; ++k)
+                if (hipEventCreate(&pr->ev[r][k]) != hipSuccess) return PGC_ERR_DEVICE;
+        p.prof = pr;
+    } else if (!on && p.prof) {
+        (void)hipDeviceSynchronize();
+        for (int r = 0; r < pgc::kProfRing; ++r)
+            for (int k = 0; k <= pgc::kStages; ++k) (void)hipEventDestroy(p.prof->ev[r][k]);
+        delete p.prof;
+        p.prof = nullptr;
+    }
+    return PGC_OK;
+}
+
+pgc_status pgc_stage_times(pgc_plan plan, double* ms_out, int32_t n_stages, int64_t* calls_out)
+{
+    if (!plan || !ms_out || n_stages < 1 || n_stages > 8) return PGC_ERR_INVALID_ARG;
+    Plan& p = plan->p;
+    for (int k = 0; k < n_stages; ++k) ms_out[k] = 0.0;
+    if (calls_out) *calls_out = 0;
+    if (!p.prof) return PGC_OK;
+    pgc::Profiler& pr = *p.prof;
+    while (pr.used > 0) {
+        const int set = (pr.head - pr.used + pgc::kProfRing) % pgc::kProfRing;
+        hipError_t e = prof_collect(pr, set);
+        if (e != hipSuccess) return pgc::from_hip(e);
+        --pr.used;
+    }
+    for (int k = 0; k < n_stages && k < pgc::kStages; ++k) ms_out[k] = pr.ms[k];
+    if (calls_out) *calls_out = pr.calls;
+    for (int k = 0; k < pgc::kStages; ++k) pr.ms[k] = 0.0;
+    pr.calls = 0;
+    return PGC_OK;
 }
 
 pgc_status pgc_rk4(pgc_plan plan, double* coeffs, double dt, int32_t n_steps, void* stream)

@@ -67,6 +67,17 @@ struct Workspace {
     double* eval_tab = nullptr;  // unused placeholder for alignment
 };
 
+constexpr int kStages = 6;     // synthesis, loss, orbit sums, spreading, grid->modes, combine
+constexpr int kProfRing = 32;  // event sets recorded before the oldest must be read back
+
+struct Profiler {
+    hipEvent_t ev[kProfRing][kStages + 1];
+    int used = 0;          // recorded sets not yet read back
+    int head = 0;          // next set to record
+    double ms[kStages] = {0, 0, 0, 0, 0, 0};
+    int64_t calls = 0;
+};
+
 struct Plan {
     // resolved description
     int dim = 2, N = 0, m_v = 0, ni = 0, map = 0, kernel = 0, precision = 0;
@@ -92,12 +103,20 @@ struct Plan {
     size_t elt = 8;
     int gain_mode = kGainBinned;
     bool auto_gain = true;
+    Profiler* prof = nullptr;  // stage timing, off unless requested
+    int prof_set = -1;         // event set of the call being recorded
     BinIndex bins;
     DeviceTables dt;
     Workspace ws;
     int64_t workspace_bytes = 0;
     std::vector<void*> allocations;
 };
+
+// record the event that closes stage `stage - 1` / opens `stage` (no-op when off)
+inline void prof_mark(const Plan& p, int stage, hipStream_t s)
+{
+    if (p.prof && p.prof_set >= 0) (void)hipEventRecord(p.prof->ev[p.prof_set][stage], s);
+}
 
 // ----- launchers (pgc_kernels.hip); all enqueue on `s` and return the launch status
 hipError_t launch_synthesis(const Plan& p, const void* coeffs, hipStream_t s);

@@ -250,7 +250,8 @@ __global__ void pair_orbit_sums(const T* __restrict__ G, T* __restrict__ sym,
 template <typename T>
 struct GainParams {
     const T* v1;        // n_i interior node velocities
-    const T* sym;       // np^d orbit sums, p_1 fastest
+    const T* G;         // n_i^d  w_j g_j (the nodal factor of every triple)
+    const T* sym;       // np^d orbit sums, p_1 fastest (slab scheme)
     const int* pair_a;  // np  smaller node of each pair
     const int* pair_b;  // np  larger node
     const int* pair_base;  // n_i  index of the pair (a, a)
@@ -580,6 +581,32 @@ __device__ __forceinline__ void point_geometry(const GainParams<T>& P, int s, in
     sym_idx = (DIM == 2) ? (int64_t)p2 * P.np + p1 : ((int64_t)p2 * P.np + p3) * P.np + p1;
 }
 
+// Orbit sum of one merged point straight from the nodal table G (small enough
+// to stay in L2): the 2^d exchanges of (a_l, b_l) pair up into 2^(d-1) products
+// G_x G_y counted twice, and each equal pair a_l = b_l halves the count.
+template <typename T, int DIM>
+__device__ __forceinline__ T orbit_sum(const GainParams<T>& P, int a1, int b1, int p2, int p3)
+{
+    const int ni = P.ni;
+    const int a2 = P.pair_a[p2], b2 = P.pair_b[p2];
+    T c = (T)2;
+    if (a1 == b1) c *= (T)0.5;
+    if (a2 == b2) c *= (T)0.5;
+    T acc;
+    if constexpr (DIM == 2) {
+        acc = P.G[a1 * ni + a2] * P.G[b1 * ni + b2] + P.G[a1 * ni + b2] * P.G[b1 * ni + a2];
+    } else {
+        const int a3 = P.pair_a[p3], b3 = P.pair_b[p3];
+        if (a3 == b3) c *= (T)0.5;
+        const int A1 = a1 * ni, B1 = b1 * ni;
+        acc = P.G[(A1 + a2) * ni + a3] * P.G[(B1 + b2) * ni + b3] +
+              P.G[(A1 + a2) * ni + b3] * P.G[(B1 + b2) * ni + a3] +
+              P.G[(A1 + b2) * ni + a3] * P.G[(B1 + a2) * ni + b3] +
+              P.G[(A1 + b2) * ni + b3] * P.G[(B1 + a2) * ni + a3];
+    }
+    return c * acc;
+}
+
 struct BinGeo {
     int nb;      // bins per dimension
     int off;     // bin index = t0 + off
@@ -697,7 +724,7 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
                 T q, xs[DIM];
                 int64_t si;
                 point_geometry<T, DIM>(P, s, a1, b1, p2, p3, halfW, q, xs, si);
-                st[0] = q * P.sym[si];
+                st[0] = q * orbit_sum<T, DIM>(P, a1, b1, p2, p3);
 #pragma unroll
                 for (int l = 0; l < DIM; ++l) {
                     T k[W];
@@ -1053,6 +1080,7 @@ GainParams<T> gain_params(const Plan& p)
 {
     GainParams<T> gp;
     gp.v1 = static_cast<const T*>(p.dt.v1);
+    gp.G = static_cast<const T*>(p.ws.G);
     gp.sym = static_cast<const T*>(p.ws.sym);
     gp.pair_a = p.dt.pair_a;
     gp.pair_b = p.dt.pair_b;
@@ -1143,8 +1171,11 @@ hipError_t bin_build_t(const Plan& p, unsigned int* count, unsigned long long* c
 template <typename T>
 hipError_t gain_t(const Plan& p, hipStream_t s)
 {
+    prof_mark(p, 2, s);
     const int64_t n_sym = p.dim == 2 ? (int64_t)p.np * p.np : (int64_t)p.np * p.np * p.np;
-    if (p.dim == 2)
+    if (p.gain_mode == kGainBinned) {
+        // the binned scheme forms each orbit sum from G where it is used
+    } else if (p.dim == 2)
         hipLaunchKernelGGL((pair_orbit_sums<T, 2>), dim3(blocks_for(n_sym, 256)), dim3(256), 0, s,
                            static_cast<const T*>(p.ws.G), static_cast<T*>(p.ws.sym), p.dt.pair_a,
                            p.dt.pair_b, p.ni, p.np, n_sym);
@@ -1156,6 +1187,7 @@ hipError_t gain_t(const Plan& p, hipStream_t s)
     if (e != hipSuccess) return e;
 
     const GainParams<T> gp = gain_params<T>(p);
+    prof_mark(p, 3, s);
     if (p.gain_mode == kGainBinned) {
         hipLaunchKernelGGL(fill_zero, dim3(blocks_for(p.ngd, 256)), dim3(256), 0, s, p.ws.grid64, p.ngd);
         BinItems bi;
@@ -1170,11 +1202,13 @@ hipError_t gain_t(const Plan& p, hipStream_t s)
         bi.geo.n_items = 0;
         e = (p.dim == 2) ? binned_dispatch<T, 2>(p, gp, bi, s) : binned_dispatch<T, 3>(p, gp, bi, s);
         if (e != hipSuccess) return e;
+        prof_mark(p, 4, s);
         hipLaunchKernelGGL(grid_convert<T>, dim3(blocks_for(p.ngd, 256)), dim3(256), 0, s,
                            p.ws.grid64, static_cast<T*>(p.ws.grid), p.ngd);
     } else {
         e = (p.dim == 2) ? spread_dispatch<T, 2>(p, gp, s) : spread_dispatch<T, 3>(p, gp, s);
         if (e != hipSuccess) return e;
+        prof_mark(p, 4, s);
         hipLaunchKernelGGL(reduce_partials<T>, dim3(blocks_for(p.ngd, 256)), dim3(256), 0, s,
                            static_cast<const double*>(p.ws.partial), static_cast<T*>(p.ws.grid), p.ngd,
                            p.n_chunks);

@@ -88,9 +88,11 @@ def lib():
         L.pgc_rk4.argtypes = [vp, vp, dbl, i32, vp]
         L.pgc_moments.argtypes = [vp, vp, vp, vp]
         L.pgc_eval.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.pgc_set_profiling.argtypes = [vp, i32]
+        L.pgc_stage_times.argtypes = [vp, dp, i32, ctypes.POINTER(i64)]
         for name in ("pgc_desc_init", "pgc_nufft_params", "pgc_plan_create", "pgc_plan_destroy",
                      "pgc_plan_query", "pgc_nodes", "pgc_project", "pgc_coeffs_to_q", "pgc_rk4",
-                     "pgc_moments", "pgc_eval"):
+                     "pgc_moments", "pgc_eval", "pgc_set_profiling", "pgc_stage_times"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -231,6 +233,19 @@ class Plan:
         out = torch.empty(self.dim + 2, dtype=torch.float64, device=c.device)
         _check(lib().pgc_moments(self._h, _ptr(c), _ptr(out), _stream()), "pgc_moments")
         return out
+
+    STAGES = ("synthesis", "loss", "orbit_sums", "spread", "grid_to_modes", "combine")
+
+    def set_profiling(self, on=True):
+        _check(lib().pgc_set_profiling(self._h, 1 if on else 0), "pgc_set_profiling")
+
+    def stage_times(self):
+        """Accumulated ms per stage since the last call, and the number of timed calls."""
+        ms = np.zeros(len(self.STAGES))
+        calls = ctypes.c_int64(0)
+        _check(lib().pgc_stage_times(self._h, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     len(self.STAGES), ctypes.byref(calls)), "pgc_stage_times")
+        return dict(zip(self.STAGES, ms.tolist())), int(calls.value)
 
     def eval(self, coeffs, v):
         torch = self._torch
