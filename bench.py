@@ -117,6 +117,33 @@ def cpu_baseline(inputs, budget_s=15.0):
                       "%.1f s, scaled to one full evaluation (%.0f s)" % (k, n_units, dt, per_eval)}
 
 
+def bkw_curve(torch, pgc, inputs, np, steps=20):
+    """3D BKW: RK4 from t = 6.5 with dt = 0.1 for `steps` steps in FP64 and FP32.
+    Prints, per step, the rel-L2 distance of each state from the projection of
+    the exact BKW solution at that time, and of the FP32 state from the FP64
+    one (one JSON object per step)."""
+    plans, states = {}, {}
+    for prec in (pgc.FP64, pgc.FP32):
+        plans[prec] = make_plan(pgc, prec)
+        states[prec] = plans[prec].project(inputs.bkw_f(T0, plans[prec].interior_velocities())).double()
+    V = plans[pgc.FP64].interior_velocities()
+    for k in range(1, steps + 1):
+        for prec in (pgc.FP64, pgc.FP32):
+            plans[prec].rk4(states[prec], DT, 1)
+        t = T0 + k * DT
+        exact = plans[pgc.FP64].project(inputs.bkw_f(t, V)).cpu().numpy()
+        s64 = states[pgc.FP64].cpu().numpy()
+        s32 = states[pgc.FP32].cpu().numpy()
+        nx = np.linalg.norm(exact)
+        print(json.dumps({"step": k, "t": round(t, 6),
+                          "fp64_vs_exact": float(np.linalg.norm(s64 - exact) / nx),
+                          "fp32_vs_exact": float(np.linalg.norm(s32 - exact) / nx),
+                          "fp32_vs_fp64": float(np.linalg.norm(s32 - s64) / np.linalg.norm(s64))}),
+              flush=True)
+    for p in plans.values():
+        p.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,9 +151,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp32-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=["bench", "profile", "copy"], default="bench",
+    ap.add_argument("--mode", choices=["bench", "profile", "copy", "bkw"], default="bench",
                     help="profile: two evaluations per precision (for rocprofv3); "
-                         "copy: a 1 GiB device copy (calibrates the HBM byte counters)")
+                         "copy: a 1 GiB device copy (calibrates the HBM byte counters); "
+                         "bkw: the 20-step RK4 BKW error curve in FP64 and FP32")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d"
@@ -144,6 +172,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log("copied 1 GiB 3 times")
+        return
+    if args.mode == "bkw":
+        bkw_curve(torch, pgc, inputs, np)
         return
     if args.mode == "profile":
         for prec in (pgc.FP64, pgc.FP32):

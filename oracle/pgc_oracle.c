@@ -56,6 +56,20 @@ static double inv_mu2_of_v(int map, double S, double v)
     return (S * S + v * v) / S;
 }
 
+/* zeta = xi(v') and mu(zeta)^-2 together; for r = 0 both come from one
+ * exponential, e = exp(v/S): tanh = (e - 1/e)/(e + 1/e), S cosh = S (e + 1/e)/2. */
+static void test_point(int map, double S, double v, double* zeta, double* m2)
+{
+    if (map == 0) {
+        double e = exp(v / S), ei = 1.0 / e;
+        *zeta = (e - ei) / (e + ei);
+        *m2 = 0.5 * S * (e + ei);
+    } else {
+        *zeta = map_xi(map, S, v);
+        *m2 = inv_mu2_of_v(map, S, v);
+    }
+}
+
 /* mu(xi(v))^4 written in v, the weight of the trial functions T~_k. */
 static double mu4_of_v(int map, double S, double v)
 {
@@ -67,20 +81,19 @@ static double mu4_of_v(int map, double S, double v)
     return S * S / (d * d);
 }
 
-/* T_k(x)/sqrt(c_k) for k = 0..n-1 by the three-term recurrence of Sec. 2.1. */
+/* T_k(x)/sqrt(c_k) for k = 0..n-1 by the three-term recurrence of Sec. 2.1
+ * (1/sqrt(c_k) is 1/sqrt(pi) for k = 0 and sqrt(2/pi) otherwise). */
 static void cheb_scaled(double x, int n, double* out)
 {
+    const double r0 = 1.0 / sqrt(cheb_norm(0)), r1 = 1.0 / sqrt(cheb_norm(1));
     double tm = 1.0, t = x;
-    for (int k = 0; k < n; ++k) {
-        double tk;
-        if (k == 0) tk = 1.0;
-        else if (k == 1) tk = x;
-        else {
-            tk = 2.0 * x * t - tm;
-            tm = t;
-            t = tk;
-        }
-        out[k] = tk / sqrt(cheb_norm(k));
+    if (n > 0) out[0] = r0;
+    if (n > 1) out[1] = x * r1;
+    for (int k = 2; k < n; ++k) {
+        const double tk = 2.0 * x * t - tm;
+        tm = t;
+        t = tk;
+        out[k] = tk * r1;
     }
 }
 
@@ -418,8 +431,8 @@ static void gain_sum(const ora_problem* p, const ora_tables* t, const ora_nodes*
                 if (wt == 0.0) continue;
                 for (int l = 0; l < dim; ++l) {
                     double vp = 0.5 * (vi[l] + vj[l]) + 0.5 * un * sg[l];
-                    double zeta = map_xi(p->map, p->S, vp);
-                    double m2 = inv_mu2_of_v(p->map, p->S, vp);
+                    double zeta, m2;
+                    test_point(p->map, p->S, vp, &zeta, &m2);
                     double* al = a + l * N;
                     cheb_scaled(zeta, N, al);
                     for (int k = 0; k < N; ++k) al[k] *= m2;
