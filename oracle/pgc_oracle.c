@@ -392,27 +392,45 @@ static void loss_field(const ora_problem* p, const ora_tables* t, const ora_node
     }
 }
 
+/* Compensated accumulation (Ogita, Rump and Oishi, "Accurate sum and dot
+ * product", SIAM J. Sci. Comput. 26 (2005), algorithm Sum2): the rounding error
+ * of each addition s + x is recovered exactly by Knuth's TwoSum and collected
+ * in c, so s + c carries the sum as if it were formed in twice the working
+ * precision.  The gain of one coefficient adds up to n_sigma * n_i^(2 dim)
+ * terms (5e8 for a 2D 64-mode problem), whose plain sequential sum would lose
+ * about 1e-11 relative: more than the error of the method being checked. */
+static inline void sum2_add(double* s, double* c, double x)
+{
+    const double t = *s + x;
+    const double bp = t - *s;
+    *c += (*s - (t - bp)) + (x - bp);
+    *s = t;
+}
+
 /* The gain, eq. (Qplus) with (Qplus1), (FF) and (num_fast_k) before any fast
  * transform: for every triple (s, i, j)
  *   v' = (v_i + v_j)/2 + |v_i - v_j| sigma_s / 2,
  *   weight = W_s w_i g_i w_j g_j B(|v_i - v_j|),
  *   Q+_k += weight * T^_k(v'),  T^_k(v') = prod_l mu(zeta_l)^-2 T_{k_l}(zeta_l)/sqrt(c_{k_l}).
- * Units (s, i) are split statically over threads; the per-thread partial sums
- * are added in thread order.  With n_k > 0 only the listed k are formed. */
+ * Units (s, i) are split statically over threads; every addition is
+ * compensated (sum2_add) and the per-thread partial sums are added in thread
+ * order.  With n_k > 0 only the listed k are formed. */
 static void gain_sum(const ora_problem* p, const ora_tables* t, const ora_nodes* nd,
                      int n_k, const int* kidx, int64_t u_lo, int64_t u_hi, double* out)
 {
     int dim = t->dim, N = t->N;
     int64_t nout = n_k > 0 ? n_k : t->Nd;
     int nth = ora_num_threads();
-    double* part = (double*)calloc((size_t)nth * nout, sizeof(double));
+    /* per thread: nout running sums followed by nout compensations */
+    double* part = (double*)calloc((size_t)nth * 2 * nout, sizeof(double));
 #pragma omp parallel
     {
         int tid = 0;
 #ifdef _OPENMP
         tid = omp_get_thread_num();
 #endif
-        double* acc = part + (size_t)tid * nout;
+        double* acc = part + (size_t)tid * 2 * nout;
+        double* cmp = acc + nout;
         double* a = (double*)malloc(sizeof(double) * 3 * N);
 #pragma omp for schedule(static)
         for (int64_t u = u_lo; u < u_hi; ++u) {
@@ -441,13 +459,14 @@ static void gain_sum(const ora_problem* p, const ora_tables* t, const ora_nodes*
                     for (int r = 0; r < n_k; ++r) {
                         double b = wt;
                         for (int l = 0; l < dim; ++l) b *= a[l * N + kidx[r * dim + l]];
-                        acc[r] += b;
+                        sum2_add(&acc[r], &cmp[r], b);
                     }
                 } else if (dim == 2) {
                     for (int k1 = 0; k1 < N; ++k1) {
                         double b1 = wt * a[k1];
                         double* row = acc + (size_t)k1 * N;
-                        for (int k2 = 0; k2 < N; ++k2) row[k2] += b1 * a[N + k2];
+                        double* rowc = cmp + (size_t)k1 * N;
+                        for (int k2 = 0; k2 < N; ++k2) sum2_add(&row[k2], &rowc[k2], b1 * a[N + k2]);
                     }
                 } else {
                     for (int k1 = 0; k1 < N; ++k1) {
@@ -455,7 +474,9 @@ static void gain_sum(const ora_problem* p, const ora_tables* t, const ora_nodes*
                         for (int k2 = 0; k2 < N; ++k2) {
                             double b2 = b1 * a[N + k2];
                             double* row = acc + ((size_t)k1 * N + k2) * N;
-                            for (int k3 = 0; k3 < N; ++k3) row[k3] += b2 * a[2 * N + k3];
+                            double* rowc = cmp + ((size_t)k1 * N + k2) * N;
+                            for (int k3 = 0; k3 < N; ++k3)
+                                sum2_add(&row[k3], &rowc[k3], b2 * a[2 * N + k3]);
                         }
                     }
                 }
@@ -464,9 +485,12 @@ static void gain_sum(const ora_problem* p, const ora_tables* t, const ora_nodes*
         free(a);
     }
     for (int64_t k = 0; k < nout; ++k) {
-        double s = 0.0;
-        for (int th = 0; th < nth; ++th) s += part[(size_t)th * nout + k];
-        out[k] = s;
+        double s = 0.0, c = 0.0;
+        for (int th = 0; th < nth; ++th) {
+            sum2_add(&s, &c, part[(size_t)th * 2 * nout + k]);
+            c += part[(size_t)th * 2 * nout + nout + k];
+        }
+        out[k] = s + c;
     }
     free(part);
 }
