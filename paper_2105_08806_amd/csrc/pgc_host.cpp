@@ -436,6 +436,17 @@ hipError_t dev_alloc(Plan& p, void** ptr, size_t bytes)
     return hipSuccess;
 }
 
+// FP64 tables (the dense transforms use them for both plan precisions)
+hipError_t upload64(Plan& p, double** dst, const std::vector<double>& src, hipStream_t s)
+{
+    void* d = nullptr;
+    hipError_t e = dev_alloc(p, &d, src.size() * sizeof(double));
+    *dst = static_cast<double*>(d);
+    if (e != hipSuccess || src.empty()) return e;
+    return hipMemcpyAsync(d, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, s);
+}
+
+// tables of the gain kernels, in the plan precision
 hipError_t upload(Plan& p, void** dst, const std::vector<double>& src, hipStream_t s)
 {
     hipError_t e = dev_alloc(p, dst, src.size() * p.elt);
@@ -541,12 +552,17 @@ hipError_t allocate(Plan& p, hipStream_t s)
         if (e != hipSuccess) return e; \
     } while (0)
     // the FP64 double-HUGE_VAL windows become +-inf in float as well
+    const bool fp64 = p.precision == PGC_PRECISION_FP64;
     PGC_TRY(upload(p, &p.dt.v1, p.v1, s));
-    PGC_TRY(upload(p, &p.dt.w1, p.w1, s));
-    PGC_TRY(upload(p, &p.dt.mu21, p.mu21, s));
-    PGC_TRY(upload(p, &p.dt.C, p.C, s));
-    PGC_TRY(upload(p, &p.dt.CT, p.CT, s));
-    PGC_TRY(upload(p, &p.dt.E, p.E, s));
+    if (fp64)
+        p.dt.v1d = static_cast<double*>(p.dt.v1);
+    else
+        PGC_TRY(upload64(p, &p.dt.v1d, p.v1, s));
+    PGC_TRY(upload64(p, &p.dt.w1, p.w1, s));
+    PGC_TRY(upload64(p, &p.dt.mu21, p.mu21, s));
+    PGC_TRY(upload64(p, &p.dt.C, p.C, s));
+    PGC_TRY(upload64(p, &p.dt.CT, p.CT, s));
+    PGC_TRY(upload64(p, &p.dt.E, p.E, s));
     PGC_TRY(upload(p, &p.dt.poly, p.poly, s));
     PGC_TRY(upload(p, &p.dt.sigma, p.sigma, s));
     PGC_TRY(upload(p, &p.dt.sigma_w, p.sigma_w, s));
@@ -558,9 +574,20 @@ hipError_t allocate(Plan& p, hipStream_t s)
     for (int l = 0; l < p.dim; ++l) t *= L;
     p.tmp_elems = t;
     const size_t e8 = p.elt;
-    PGC_TRY(dev_alloc(p, &p.ws.P, p.nid * e8));
-    PGC_TRY(dev_alloc(p, &p.ws.G, p.nid * e8));
-    PGC_TRY(dev_alloc(p, &p.ws.H, p.nid * e8));
+    auto alloc64 = [&p](double** dst, int64_t n) {
+        void* d = nullptr;
+        hipError_t r = dev_alloc(p, &d, (size_t)n * sizeof(double));
+        *dst = static_cast<double*>(d);
+        return r;
+    };
+    PGC_TRY(alloc64(&p.ws.P, p.nid));
+    PGC_TRY(alloc64(&p.ws.G, p.nid));
+    if (fp64)
+        p.ws.Gg = p.ws.G;
+    else
+        PGC_TRY(dev_alloc(p, &p.ws.Gg, p.nid * e8));
+    PGC_TRY(alloc64(&p.ws.H, p.nid));
+    PGC_TRY(alloc64(&p.ws.cin, p.Nd));
     {
         int64_t nsym = 1;
         for (int l = 0; l < p.dim; ++l) nsym *= p.np;
@@ -589,11 +616,11 @@ hipError_t allocate(Plan& p, hipStream_t s)
     }
     if (p.gain_mode == kGainSlab)
         PGC_TRY(dev_alloc(p, &p.ws.partial, (size_t)p.n_chunks * p.ngd * sizeof(double)));
-    PGC_TRY(dev_alloc(p, &p.ws.grid, p.ngd * e8));
-    PGC_TRY(dev_alloc(p, &p.ws.tmpA, t * e8));
-    PGC_TRY(dev_alloc(p, &p.ws.tmpB, t * e8));
-    PGC_TRY(dev_alloc(p, &p.ws.qminus, p.Nd * e8));
-    PGC_TRY(dev_alloc(p, &p.ws.qplus, p.Nd * e8));
+    PGC_TRY(alloc64(&p.ws.grid, p.gain_mode == kGainSlab ? p.ngd : 1));
+    PGC_TRY(alloc64(&p.ws.tmpA, t));
+    PGC_TRY(alloc64(&p.ws.tmpB, t));
+    PGC_TRY(alloc64(&p.ws.qminus, p.Nd));
+    PGC_TRY(alloc64(&p.ws.qplus, p.Nd));
     PGC_TRY(dev_alloc(p, &p.ws.rk_y, p.Nd * e8));
     for (int r = 0; r < 4; ++r) PGC_TRY(dev_alloc(p, &p.ws.rk_k[r], p.Nd * e8));
     void* red = nullptr;
@@ -615,6 +642,7 @@ hipError_t allocate(Plan& p, hipStream_t s)
             p.gain_mode = kGainSlab;
             p.bins = BinIndex();
             PGC_TRY(dev_alloc(p, &p.ws.partial, (size_t)p.n_chunks * p.ngd * sizeof(double)));
+            PGC_TRY(alloc64(&p.ws.grid, p.ngd));
             int64_t nsym = 1;
             for (int l = 0; l < p.dim; ++l) nsym *= p.np;
             PGC_TRY(dev_alloc(p, &p.ws.sym, nsym * e8));

@@ -15,14 +15,18 @@ constexpr int kMaxPolyTerms = 18;     // Horner terms per kernel cell (degree + 
 constexpr int kMaxLdsBytes = 160 * 1024;
 constexpr int kLdsBudget = 155 * 1024;  // slab bytes per workgroup
 
-// Device pointers of one precision (T = float or double).
+// Device tables.  The dense transforms (synthesis, loss, grid -> modes,
+// projection) run in FP64 for both plan precisions, so their tables are FP64;
+// the tables read by point generation and spreading are in the plan precision
+// (T = float or double).
 struct DeviceTables {
-    void* v1 = nullptr;       // n_i      interior node velocities
-    void* w1 = nullptr;       // n_i      CGL weights
-    void* mu21 = nullptr;     // n_i      mu(xi)^2
-    void* C = nullptr;        // n_i x N  T_k(xi_i)/sqrt(c_k)
-    void* CT = nullptr;       // N x n_i  transpose of C
-    void* E = nullptr;        // N x n_g  cos(k m h) h / (psi^(k) sqrt(c_k))
+    void* v1 = nullptr;       // n_i      interior node velocities (plan precision)
+    double* v1d = nullptr;    // n_i      the same in FP64 (aliases v1 for FP64 plans)
+    double* w1 = nullptr;     // n_i      CGL weights
+    double* mu21 = nullptr;   // n_i      mu(xi)^2
+    double* C = nullptr;      // n_i x N  T_k(xi_i)/sqrt(c_k)
+    double* CT = nullptr;     // N x n_i  transpose of C
+    double* E = nullptr;      // N x n_g  cos(k m h) h / (psi^(k) sqrt(c_k))
     void* poly = nullptr;     // terms x W Horner coefficients of the kernel cells
     void* sigma = nullptr;    // n_sigma x dim
     void* sigma_w = nullptr;  // n_sigma
@@ -48,23 +52,25 @@ struct BinIndex {
 };
 constexpr int kBinChunk = 8192;
 
+// Buffers marked FP64 are FP64 for both plan precisions.
 struct Workspace {
-    void* P = nullptr;        // n_i^d  polynomial part at the interior nodes
-    void* G = nullptr;        // n_i^d  w_i g_i = w_i mu_i^2 P_i
+    double* cin = nullptr;    // N^d    FP64 copy of FP32 input coefficients
+    double* P = nullptr;      // n_i^d  polynomial part at the interior nodes (FP64)
+    double* G = nullptr;      // n_i^d  w_i g_i = w_i mu_i^2 P_i (FP64)
+    void* Gg = nullptr;       // n_i^d  G in the plan precision, read by the gain (aliases G for FP64)
     void* sym = nullptr;      // np^d   orbit sums of G_i G_j over exchanged node pairs
-    void* H = nullptr;        // n_i^d  w_i A_i P_i (loss integrand) / projection input
+    double* H = nullptr;      // n_i^d  w_i A_i P_i (loss integrand) / projection input (FP64)
     void* partial = nullptr;  // n_chunks x n_g^d  per-chunk fine grids (FP64 cells)
-    void* grid = nullptr;     // n_g^d  reduced fine grid
-    void* tmpA = nullptr;     // separable-transform ping-pong buffers
-    void* tmpB = nullptr;
-    void* qminus = nullptr;   // N^d
-    void* qplus = nullptr;    // N^d
+    double* grid = nullptr;   // n_g^d  reduced fine grid of the slab scheme (FP64)
+    double* tmpA = nullptr;   // separable-transform ping-pong buffers (FP64)
+    double* tmpB = nullptr;
+    double* qminus = nullptr; // N^d (FP64)
+    double* qplus = nullptr;  // N^d (FP64)
     void* rk_y = nullptr;     // N^d  stage input (plan precision)
     void* rk_k[4] = {nullptr, nullptr, nullptr, nullptr};
     double* red = nullptr;    // small FP64 scratch (reductions)
     double* grid64 = nullptr; // n_g^d FP64 grid of the binned gain
     double* mom = nullptr;    // 3 x N  moment functionals m_0, m_1, m_2 (FP64)
-    double* eval_tab = nullptr;  // unused placeholder for alignment
 };
 
 constexpr int kStages = 6;     // synthesis, loss, orbit sums, spreading, grid->modes, combine

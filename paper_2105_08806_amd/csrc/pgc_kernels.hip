@@ -54,16 +54,16 @@ __global__ void __launch_bounds__(256) sep_apply(const T* __restrict__ in, T* __
     out[idx] = acc;
 }
 
-// apply the K x L matrix M along every axis of a dim-dimensional L^dim tensor
-template <typename T>
-hipError_t separable(const Plan& p, const T* in, T* out, const T* M, int K, int L, hipStream_t s)
+// apply the K x L matrix M along every axis of a dim-dimensional L^dim tensor (FP64)
+hipError_t separable(const Plan& p, const double* in, double* out, const double* M, int K, int L,
+                     hipStream_t s)
 {
     int64_t dims[3] = {L, L, L};
-    const T* src = in;
-    T* bufs[2] = {static_cast<T*>(p.ws.tmpA), static_cast<T*>(p.ws.tmpB)};
+    const double* src = in;
+    double* bufs[2] = {p.ws.tmpA, p.ws.tmpB};
     int pp = 0;
     for (int ax = p.dim - 1; ax >= 0; --ax) {
-        T* dst = (ax == 0) ? out : bufs[pp];
+        double* dst = (ax == 0) ? out : bufs[pp];
         pp ^= 1;
         int64_t A = 1, B = 1;
         for (int l = 0; l < ax; ++l) A *= dims[l];
@@ -71,8 +71,8 @@ hipError_t separable(const Plan& p, const T* in, T* out, const T* M, int K, int 
         const int64_t total = A * K * B;
         const int threads = 256;
         const int64_t blocks = (total + threads - 1) / threads;
-        hipLaunchKernelGGL(sep_apply<T>, dim3((unsigned)blocks), dim3(threads), 0, s, src, dst, M, A,
-                           L, B, K);
+        hipLaunchKernelGGL(sep_apply<double>, dim3((unsigned)blocks), dim3(threads), 0, s, src, dst, M,
+                           A, L, B, K);
         dims[ax] = K;
         src = dst;
     }
@@ -94,16 +94,34 @@ __device__ __forceinline__ void node_weights(int64_t f, int dim, int ni, const T
     }
 }
 
-// G_i = w_i mu_i^2 P_i  (the weighted f_N / mu^2 of the gain and loss integrals)
+// G_i = w_i mu_i^2 P_i  (the weighted f_N / mu^2 of the gain and loss integrals),
+// in FP64 and, when Gg is given, rounded once to the precision of the gain
 template <typename T>
-__global__ void make_weighted(const T* __restrict__ P, T* __restrict__ G, const T* __restrict__ w1,
-                              const T* __restrict__ mu21, int dim, int ni, int64_t nid)
+__global__ void make_weighted(const double* __restrict__ P, double* __restrict__ G,
+                              T* __restrict__ Gg, const double* __restrict__ w1,
+                              const double* __restrict__ mu21, int dim, int ni, int64_t nid)
 {
     const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (f >= nid) return;
-    T w, mu2;
+    double w, mu2;
     node_weights(f, dim, ni, w1, mu21, w, mu2);
-    G[f] = w * mu2 * P[f];
+    const double g = w * mu2 * P[f];
+    G[f] = g;
+    if (Gg) Gg[f] = (T)g;
+}
+
+template <typename T>
+__global__ void widen(const T* __restrict__ x, double* __restrict__ y, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (double)x[i];
+}
+
+template <typename T>
+__global__ void narrow(const double* __restrict__ x, T* __restrict__ y, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (T)x[i];
 }
 
 // ------------------------------------------------------------------ loss
@@ -811,49 +829,41 @@ __global__ void fill_zero(double* __restrict__ x, int64_t n)
     if (i < n) x[i] = 0.0;
 }
 
-template <typename T>
-__global__ void grid_convert(const double* __restrict__ g, T* __restrict__ out, int64_t n)
-{
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) out[i] = (T)g[i];
-}
-
 // grid[m] = sum_c partial[c][m], FP64 accumulation in chunk order
-template <typename T>
-__global__ void reduce_partials(const double* __restrict__ partial, T* __restrict__ grid,
+__global__ void reduce_partials(const double* __restrict__ partial, double* __restrict__ grid,
                                 int64_t ngd, int n_chunks)
 {
     const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (m >= ngd) return;
     double acc = 0.0;
-    for (int c = 0; c < n_chunks; ++c) acc += (double)partial[(int64_t)c * ngd + m];
-    grid[m] = (T)acc;
+    for (int c = 0; c < n_chunks; ++c) acc += partial[(int64_t)c * ngd + m];
+    grid[m] = acc;
 }
 
+// Q = Q+ - Q- formed in FP64, rounded once to the output precision
 template <typename T>
-__global__ void combine_kernel(const T* __restrict__ qp, const T* __restrict__ qm, T* __restrict__ q,
-                               T* __restrict__ qplus_out, int64_t n)
+__global__ void combine_kernel(const double* __restrict__ qp, const double* __restrict__ qm,
+                               T* __restrict__ q, T* __restrict__ qplus_out, int64_t n)
 {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const T a = qp[k];
-    q[k] = a - qm[k];
-    if (qplus_out) qplus_out[k] = a;
+    const double a = qp[k];
+    q[k] = (T)(a - qm[k]);
+    if (qplus_out) qplus_out[k] = (T)a;
 }
 
 // ------------------------------------------------------------------ projection
 
 // H_i = w_i mu_i^-4 f(v_i)  (eq. MultiD_spectral_coef on the interior CGL nodes)
-template <typename T>
-__global__ void project_weight(const double* __restrict__ f, T* __restrict__ H,
-                               const T* __restrict__ w1, const T* __restrict__ mu21, int dim, int ni,
-                               int64_t nid)
+__global__ void project_weight(const double* __restrict__ f, double* __restrict__ H,
+                               const double* __restrict__ w1, const double* __restrict__ mu21,
+                               int dim, int ni, int64_t nid)
 {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= nid) return;
-    T w, mu2;
+    double w, mu2;
     node_weights(r, dim, ni, w1, mu21, w, mu2);
-    H[r] = (T)(f[r] * (double)w / ((double)mu2 * (double)mu2));
+    H[r] = f[r] * w / (mu2 * mu2);
 }
 
 // ------------------------------------------------------------------ moments
@@ -991,47 +1001,45 @@ inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + thre
 
 // ------------------------------------------------------------------ typed drivers
 
+// a1: P = C^{(x)d} f and G = w mu^2 P, in FP64 (FP32 inputs are widened first)
 template <typename T>
 hipError_t synthesis_t(const Plan& p, const void* coeffs, hipStream_t s)
 {
-    hipError_t e = separable<T>(p, static_cast<const T*>(coeffs), static_cast<T*>(p.ws.P),
-                                static_cast<const T*>(p.dt.C), p.ni, p.N, s);
+    const double* c64 = static_cast<const double*>(coeffs);
+    if (p.precision != PGC_PRECISION_FP64) {
+        hipLaunchKernelGGL(widen<T>, dim3(blocks_for(p.Nd, 256)), dim3(256), 0, s,
+                           static_cast<const T*>(coeffs), p.ws.cin, p.Nd);
+        c64 = p.ws.cin;
+    }
+    hipError_t e = separable(p, c64, p.ws.P, p.dt.C, p.ni, p.N, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(make_weighted<T>, dim3(blocks_for(p.nid, 256)), dim3(256), 0, s,
-                       static_cast<const T*>(p.ws.P), static_cast<T*>(p.ws.G),
-                       static_cast<const T*>(p.dt.w1), static_cast<const T*>(p.dt.mu21), p.dim, p.ni,
-                       p.nid);
+    T* gg = p.precision == PGC_PRECISION_FP64 ? nullptr : static_cast<T*>(p.ws.Gg);
+    hipLaunchKernelGGL(make_weighted<T>, dim3(blocks_for(p.nid, 256)), dim3(256), 0, s, p.ws.P,
+                       p.ws.G, gg, p.dt.w1, p.dt.mu21, p.dim, p.ni, p.nid);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t loss_t(const Plan& p, hipStream_t s)
+// a2 + a3: the loss field and its projection, FP64 for both plan precisions
+hipError_t loss_fp64(const Plan& p, hipStream_t s)
 {
     const double scale = p.wsum * p.b0;
     if (p.kernel == PGC_KERNEL_MAXWELL) {
-        hipLaunchKernelGGL(sum_kernel<T>, dim3(1), dim3(kRedThreads), 0, s,
-                           static_cast<const T*>(p.ws.G), p.nid, p.ws.red);
-        hipLaunchKernelGGL(loss_h_maxwell<T>, dim3(blocks_for(p.nid, 256)), dim3(256), 0, s,
-                           static_cast<const T*>(p.ws.P), static_cast<T*>(p.ws.H),
-                           static_cast<const T*>(p.dt.w1), static_cast<const T*>(p.dt.mu21),
-                           p.ws.red, scale, p.dim, p.ni, p.nid);
+        hipLaunchKernelGGL(sum_kernel<double>, dim3(1), dim3(kRedThreads), 0, s, p.ws.G, p.nid,
+                           p.ws.red);
+        hipLaunchKernelGGL(loss_h_maxwell<double>, dim3(blocks_for(p.nid, 256)), dim3(256), 0, s,
+                           p.ws.P, p.ws.H, p.dt.w1, p.dt.mu21, p.ws.red, scale, p.dim, p.ni, p.nid);
     } else if (p.dim == 2) {
-        hipLaunchKernelGGL((loss_h_vhs<T, 2>), dim3(blocks_for(p.nid, 256)), dim3(256), 0, s,
-                           static_cast<const T*>(p.ws.P), static_cast<const T*>(p.ws.G),
-                           static_cast<T*>(p.ws.H), static_cast<const T*>(p.dt.v1),
-                           static_cast<const T*>(p.dt.w1), static_cast<const T*>(p.dt.mu21), scale,
-                           (T)p.gamma, p.ni, p.nid);
+        hipLaunchKernelGGL((loss_h_vhs<double, 2>), dim3(blocks_for(p.nid, 256)), dim3(256), 0, s,
+                           p.ws.P, p.ws.G, p.ws.H, p.dt.v1d, p.dt.w1, p.dt.mu21, scale, p.gamma,
+                           p.ni, p.nid);
     } else {
-        hipLaunchKernelGGL((loss_h_vhs<T, 3>), dim3(blocks_for(p.nid, 256)), dim3(256), 0, s,
-                           static_cast<const T*>(p.ws.P), static_cast<const T*>(p.ws.G),
-                           static_cast<T*>(p.ws.H), static_cast<const T*>(p.dt.v1),
-                           static_cast<const T*>(p.dt.w1), static_cast<const T*>(p.dt.mu21), scale,
-                           (T)p.gamma, p.ni, p.nid);
+        hipLaunchKernelGGL((loss_h_vhs<double, 3>), dim3(blocks_for(p.nid, 256)), dim3(256), 0, s,
+                           p.ws.P, p.ws.G, p.ws.H, p.dt.v1d, p.dt.w1, p.dt.mu21, scale, p.gamma,
+                           p.ni, p.nid);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return separable<T>(p, static_cast<const T*>(p.ws.H), static_cast<T*>(p.ws.qminus),
-                        static_cast<const T*>(p.dt.CT), p.N, p.ni, s);
+    return separable(p, p.ws.H, p.ws.qminus, p.dt.CT, p.N, p.ni, s);
 }
 
 template <typename T, int DIM, int W>
@@ -1080,7 +1088,7 @@ GainParams<T> gain_params(const Plan& p)
 {
     GainParams<T> gp;
     gp.v1 = static_cast<const T*>(p.dt.v1);
-    gp.G = static_cast<const T*>(p.ws.G);
+    gp.G = static_cast<const T*>(p.ws.Gg);
     gp.sym = static_cast<const T*>(p.ws.sym);
     gp.pair_a = p.dt.pair_a;
     gp.pair_b = p.dt.pair_b;
@@ -1177,11 +1185,11 @@ hipError_t gain_t(const Plan& p, hipStream_t s)
         // the binned scheme forms each orbit sum from G where it is used
     } else if (p.dim == 2)
         hipLaunchKernelGGL((pair_orbit_sums<T, 2>), dim3(blocks_for(n_sym, 256)), dim3(256), 0, s,
-                           static_cast<const T*>(p.ws.G), static_cast<T*>(p.ws.sym), p.dt.pair_a,
+                           static_cast<const T*>(p.ws.Gg), static_cast<T*>(p.ws.sym), p.dt.pair_a,
                            p.dt.pair_b, p.ni, p.np, n_sym);
     else
         hipLaunchKernelGGL((pair_orbit_sums<T, 3>), dim3(blocks_for(n_sym, 256)), dim3(256), 0, s,
-                           static_cast<const T*>(p.ws.G), static_cast<T*>(p.ws.sym), p.dt.pair_a,
+                           static_cast<const T*>(p.ws.Gg), static_cast<T*>(p.ws.sym), p.dt.pair_a,
                            p.dt.pair_b, p.ni, p.np, n_sym);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1203,41 +1211,43 @@ hipError_t gain_t(const Plan& p, hipStream_t s)
         e = (p.dim == 2) ? binned_dispatch<T, 2>(p, gp, bi, s) : binned_dispatch<T, 3>(p, gp, bi, s);
         if (e != hipSuccess) return e;
         prof_mark(p, 4, s);
-        hipLaunchKernelGGL(grid_convert<T>, dim3(blocks_for(p.ngd, 256)), dim3(256), 0, s,
-                           p.ws.grid64, static_cast<T*>(p.ws.grid), p.ngd);
+        e = separable(p, p.ws.grid64, p.ws.qplus, p.dt.E, p.N, p.ng, s);
     } else {
         e = (p.dim == 2) ? spread_dispatch<T, 2>(p, gp, s) : spread_dispatch<T, 3>(p, gp, s);
         if (e != hipSuccess) return e;
         prof_mark(p, 4, s);
-        hipLaunchKernelGGL(reduce_partials<T>, dim3(blocks_for(p.ngd, 256)), dim3(256), 0, s,
-                           static_cast<const double*>(p.ws.partial), static_cast<T*>(p.ws.grid), p.ngd,
-                           p.n_chunks);
+        hipLaunchKernelGGL(reduce_partials, dim3(blocks_for(p.ngd, 256)), dim3(256), 0, s,
+                           static_cast<const double*>(p.ws.partial), p.ws.grid, p.ngd, p.n_chunks);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = separable(p, p.ws.grid, p.ws.qplus, p.dt.E, p.N, p.ng, s);
     }
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return separable<T>(p, static_cast<const T*>(p.ws.grid), static_cast<T*>(p.ws.qplus),
-                        static_cast<const T*>(p.dt.E), p.N, p.ng, s);
+    return e;
 }
 
 template <typename T>
 hipError_t combine_t(const Plan& p, void* q, void* qplus, hipStream_t s)
 {
-    hipLaunchKernelGGL(combine_kernel<T>, dim3(blocks_for(p.Nd, 256)), dim3(256), 0, s,
-                       static_cast<const T*>(p.ws.qplus), static_cast<const T*>(p.ws.qminus),
-                       static_cast<T*>(q), static_cast<T*>(qplus), p.Nd);
+    hipLaunchKernelGGL(combine_kernel<T>, dim3(blocks_for(p.Nd, 256)), dim3(256), 0, s, p.ws.qplus,
+                       p.ws.qminus, static_cast<T*>(q), static_cast<T*>(qplus), p.Nd);
     return hipGetLastError();
 }
 
+// the projection in FP64; FP32 plans round the coefficients once at the end
 template <typename T>
 hipError_t project_t(const Plan& p, const double* f, void* coeffs, hipStream_t s)
 {
-    hipLaunchKernelGGL(project_weight<T>, dim3(blocks_for(p.nid, 256)), dim3(256), 0, s, f,
-                       static_cast<T*>(p.ws.H), static_cast<const T*>(p.dt.w1),
-                       static_cast<const T*>(p.dt.mu21), p.dim, p.ni, p.nid);
+    hipLaunchKernelGGL(project_weight, dim3(blocks_for(p.nid, 256)), dim3(256), 0, s, f, p.ws.H,
+                       p.dt.w1, p.dt.mu21, p.dim, p.ni, p.nid);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return separable<T>(p, static_cast<const T*>(p.ws.H), static_cast<T*>(coeffs),
-                        static_cast<const T*>(p.dt.CT), p.N, p.ni, s);
+    if (p.precision == PGC_PRECISION_FP64)
+        return separable(p, p.ws.H, static_cast<double*>(coeffs), p.dt.CT, p.N, p.ni, s);
+    e = separable(p, p.ws.H, p.ws.cin, p.dt.CT, p.N, p.ni, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(narrow<T>, dim3(blocks_for(p.Nd, 256)), dim3(256), 0, s, p.ws.cin,
+                       static_cast<T*>(coeffs), p.Nd);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -1250,10 +1260,7 @@ hipError_t launch_synthesis(const Plan& p, const void* coeffs, hipStream_t s)
                                              : synthesis_t<float>(p, coeffs, s);
 }
 
-hipError_t launch_loss(const Plan& p, hipStream_t s)
-{
-    return p.precision == PGC_PRECISION_FP64 ? loss_t<double>(p, s) : loss_t<float>(p, s);
-}
+hipError_t launch_loss(const Plan& p, hipStream_t s) { return loss_fp64(p, s); }
 
 hipError_t launch_gain(const Plan& p, hipStream_t s)
 {

@@ -44,7 +44,7 @@ def rel(a, b):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_2d_n64_vhs_sampled(torch_cuda, prec):
-    """BASELINE config 2: 2D, 64 modes, S=6, VHS gamma=1, 32 directions, two
+    """The 2D VHS workload: 64 modes, S=6, VHS gamma=1, 32 directions, two
     Maxwellians at +-(1.5, 0) with seeded temperatures."""
     torch = torch_cuda
     from paper_2105_08806_amd import pgc
@@ -68,14 +68,17 @@ def test_2d_n64_vhs_sampled(torch_cuda, prec):
     say("  sampled rel-L2 Q = %.3e, Q+ = %.3e" % (r_q, r_qp))
     bar = 1e-11 if prec == 0 else 1e-5
     assert r_q <= bar and r_qp <= bar
-    # the data are even in v_2: odd k_2 coefficients vanish at any size
-    assert np.max(np.abs(q[:, 1::2])) <= (1e-13 if prec == 0 else 1e-6) * np.max(np.abs(q))
+    # the data are even in v_2: odd k_2 coefficients vanish at any size, up to
+    # the transform tolerance (5e-13 FP64, 1e-6 FP32) relative to the largest Q
+    odd = np.max(np.abs(q[:, 1::2])) / np.max(np.abs(q))
+    say("  odd k_2 coefficients / max |Q| = %.2e" % odd)
+    assert odd <= (1e-12 if prec == 0 else 2e-6)
     plan.close()
 
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_3d_n32_direction_subset_sampled(torch_cuda, prec):
-    """BASELINE config 3 geometry (3D, 32 modes, S=5, Maxwell 1/(4 pi), BKW at
+    """The 3D BKW workload geometry (3D, 32 modes, S=5, Maxwell 1/(4 pi), BKW at
     t=6.5) restricted to one antipodal pair of the 64-point rule, so the oracle
     can afford sampled outputs; the kernels and index are those of the full
     workload."""
@@ -126,11 +129,17 @@ def test_3d_n32_full_rule_properties(torch_cuda):
         plan.close()
     q64 = out[0][0]
     scale = np.max(np.abs(q64))
+    # odd coefficients and the (k_1, k_2) asymmetry vanish up to the transform
+    # tolerance (5e-13) relative to the largest Q
     for ax in range(3):
         sl = [slice(None)] * 3
         sl[ax] = slice(1, None, 2)
-        assert np.max(np.abs(q64[tuple(sl)])) <= 1e-13 * scale
-    assert np.max(np.abs(q64 - q64.transpose(1, 0, 2))) <= 1e-13 * scale
+        odd = np.max(np.abs(q64[tuple(sl)])) / scale
+        say("  odd k_%d coefficients / max |Q| = %.2e" % (ax + 1, odd))
+        assert odd <= 1e-12
+    asym = np.max(np.abs(q64 - q64.transpose(1, 0, 2))) / scale
+    say("  (k_1, k_2) asymmetry / max |Q| = %.2e" % asym)
+    assert asym <= 1e-12
     r32 = rel(out[1][0], q64)
     say("  3D N=32 FP32 vs FP64 rel-L2 %.3e" % r32)
     assert r32 <= 1e-5
@@ -155,9 +164,9 @@ def test_3d_n32_algebraic_map_conserves(torch_cuda):
 
 
 def test_rk4_2d_bkw_config1(torch_cuda):
-    """BASELINE config 1: 2D BKW at t0 = 0, 16 modes, S = 4, 16 directions, RK4
+    """The 2D BKW workload: t0 = 0, 16 modes, S = 4, 16 directions, RK4
     to t = 1 with dt = 0.05: matches the oracle's RK4 and follows the exact BKW
-    solution."""
+    solution as closely as the oracle's own RK4 does."""
     torch = torch_cuda
     from paper_2105_08806_amd import pgc
     N, S = 16, 4.0
@@ -173,14 +182,17 @@ def test_rk4_2d_bkw_config1(torch_cuda):
     got = st.cpu().numpy()
     r = rel(got, ref)
     exact = ora.project(I.bkw_f(1.0, V))
-    say("  RK4 2D BKW: rel-L2 vs oracle RK4 %.3e, vs exact BKW %.3e" % (r, rel(got, exact)))
+    e_gpu, e_ora = rel(got, exact), rel(ref, exact)
+    say("  RK4 2D BKW: rel-L2 vs oracle RK4 %.3e; vs exact BKW %.3e (oracle %.3e, start %.3e)"
+        % (r, e_gpu, e_ora, rel(c0, exact)))
     assert r <= 1e-10
-    assert np.max(np.abs(got - exact)) < 0.05 * np.max(np.abs(c0 - exact))
+    assert abs(e_gpu - e_ora) <= 1e-9 * max(e_ora, 1e-300)
+    assert e_gpu < rel(c0, exact)
     plan.close()
 
 
 def test_rk4_3d_bkw_fp64_fp32_short(torch_cuda):
-    """BASELINE config 3 dynamics, three RK4 steps (dt = 0.1 from t = 6.5): the
+    """The 3D BKW workload dynamics, three RK4 steps (dt = 0.1 from t = 6.5): the
     FP64 state follows the projected exact BKW solution, and FP32 stays within
     1e-5 of FP64 (the 20-step error curve is in bench.py --mode bkw)."""
     torch = torch_cuda
