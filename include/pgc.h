@@ -199,6 +199,71 @@ pgc_status pgc_eval(pgc_plan plan, const void* coeffs_dev, const double* v_dev, 
 pgc_status pgc_set_profiling(pgc_plan plan, int32_t on);
 pgc_status pgc_stage_times(pgc_plan plan, double* ms_out, int32_t n_stages, int64_t* calls_out);
 
+/* ------------------------------------------------------------------------
+ * Batches: one evaluation of Q for each of many velocity cells (for example
+ * the spatial cells of a kinetic solver), with mixed N.  Every cell applies
+ * the discretisation of `base` with its own n_modes.  The cells that share an
+ * N share one internal plan (tables and plan-time bin index); the gain of all
+ * cells runs as one persistent launch over (bin run, group of cells) work
+ * units, so the geometry of a merged point is generated once for every group
+ * of cells that reads it.  Supported: dim = 2, precision FP32 (the gain in
+ * FP32 with FP64 fine grids, the dense stages in FP64, as for FP32 plans),
+ * at most 8 distinct N, 3 <= N <= 255, kernel widths 4..8.
+ *
+ * Packed layout: the coefficients of cell c are the dense N_c^2 block that
+ * starts at element offsets[c] of the packed array (float).  The packed Q
+ * array uses the same offsets.  Passing offsets_dev = NULL selects the dense
+ * packing in cell order (offsets[c] = sum of N_b^2 over b < c, returned by
+ * pgc_batch_offsets).  offsets_dev is a device array of n_cells int64.
+ * ------------------------------------------------------------------------ */
+typedef struct pgc_batch_s* pgc_batch;
+
+typedef struct pgc_batch_info {
+    int32_t n_cells;
+    int32_t n_groups;           /* distinct N */
+    int32_t group_n_modes[8];   /* N of each group, descending */
+    int32_t group_cells[8];     /* cells in each group */
+    int64_t coeffs_total;       /* length of the dense packing, sum of N_c^2 */
+    int32_t kernel_width;       /* W of the spreading kernel (the same for every N) */
+    int32_t cells_per_wave;     /* C: cells a gain work unit serves (1, 2, 4 or 8) */
+    int32_t waves;              /* persistent 64-lane workgroups of the gain launch */
+    int64_t n_units;            /* gain work units per evaluation */
+    int64_t n_points;           /* merged transform points over all cells */
+    int64_t workspace_bytes;    /* device memory owned by the batch and its plans */
+    double tuned_ms[4];         /* autotuner: gain time for C = 1, 2, 4, 8 (0 = not tried) */
+    int32_t has_graph;          /* a captured graph is ready for pgc_batch_graph_launch */
+} pgc_batch_info;
+
+/* Build a batch of n_cells cells; n_modes_host[c] is the N of cell c.
+ * With autotune != 0 the call times the gain for every supported C on the
+ * device (a few evaluations of the gain) and keeps the fastest; otherwise
+ * C = 1.  `stream` orders the set-up work, which the call synchronises.
+ * Errors: INVALID_ARG, UNSUPPORTED (dim != 2, precision != FP32, more than 8
+ * distinct N, a kernel width outside 4..8), OUT_OF_MEMORY, DEVICE. */
+pgc_status pgc_batch_create(const pgc_plan_desc* base, int32_t n_cells, const int32_t* n_modes_host,
+                            int32_t autotune, void* stream, pgc_batch* batch_out);
+/* Free the batch (NULL is a no-op).  Synchronises the device. */
+pgc_status pgc_batch_destroy(pgc_batch batch);
+pgc_status pgc_batch_query(pgc_batch batch, pgc_batch_info* info);
+/* The n_cells offsets of the dense packing (host array). */
+pgc_status pgc_batch_offsets(pgc_batch batch, int64_t* offsets_host);
+/* Force C cells per work unit (1, 2, 4 or 8, subject to C W^2 <= 200), or re-run
+ * the autotuner.  Both drop a captured graph and synchronise `stream`. */
+pgc_status pgc_batch_set_tile(pgc_batch batch, int32_t cells_per_wave, void* stream);
+pgc_status pgc_batch_autotune(pgc_batch batch, void* stream);
+/* Q of every cell: packed_q_dev receives Q_c at offsets[c] (float).  Stream
+ * ordered, allocates nothing.  The input and output ranges must not overlap. */
+pgc_status pgc_batch_coeffs_to_q(pgc_batch batch, const void* packed_coeffs_dev, const int64_t* offsets_dev,
+                                 void* packed_q_dev, void* stream);
+/* Record the same evaluation, for these three device pointers, into a HIP
+ * graph owned by the batch (replacing any earlier one); `stream` is
+ * synchronised first and nothing runs.  pgc_batch_graph_launch replays it on
+ * `stream` (INVALID_ARG when no graph is ready).  The graph reads the pointers
+ * captured, so the caller refills the same input buffer between replays. */
+pgc_status pgc_batch_capture(pgc_batch batch, const void* packed_coeffs_dev, const int64_t* offsets_dev,
+                             void* packed_q_dev, void* stream);
+pgc_status pgc_batch_graph_launch(pgc_batch batch, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

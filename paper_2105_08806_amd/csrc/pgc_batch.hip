@@ -1,0 +1,691 @@
+// Batched evaluation of Q for many velocity cells with mixed N (2D, FP32 gain).
+//
+// A kinetic solver calls the collision operator once per spatial cell; the
+// cells of one batch may use different numbers of modes.  The positions of the
+// merged transform points (and so their bins, kernel values and fine-grid
+// footprints) depend only on the discretisation of a cell, not on its f, so
+// every cell with the same N shares one plan: its node tables, its sphere rule
+// and its plan-time bin index.  Only the orbit-sum weight of a point differs
+// between cells.  One work unit of the gain is (bin run, group of C cells of
+// one N): each lane regenerates points of the run once, forms C orbit sums and
+// accumulates C private W x W footprint tiles in registers; a single
+// persistent launch pulls the units of every N group from one counter, the
+// longest runs first.  The dense stages (synthesis, loss, grid to modes) are
+// batched contractions over the cells of each group, in FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "pgc_device.h"
+#include "pgc_internal.h"
+
+namespace pgc {
+namespace {
+
+constexpr int kMaxGroups = 8;
+
+// per-N group, as the persistent gain kernel reads it
+struct GroupDev {
+    GainParams<float> gp;
+    const int* item_bin;
+    const long long* item_begin;
+    const int* item_count;
+    const unsigned long long* ids;
+    const float* Gg;     // n_cells x nid, G of every cell rounded to FP32
+    double* grid;        // n_cells x ngd FP64 fine grids
+    int nb, off, n_cells, ncg;  // ncg = cell groups of C cells
+    int64_t nid, ngd, unit_begin;
+};
+
+__device__ __forceinline__ unsigned long long lane0(unsigned long long x)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(x & 0xffffffffull), 0);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(x >> 32), 0);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Persistent gain over every group: one 64-lane wave per workgroup takes units
+// u = atomicAdd(counter) until the counter passes n_units (every wave reaches
+// that exit).  Unit u of group g covers bin run (u - begin_g) / ncg_g and cells
+// C ((u - begin_g) % ncg_g) .. + C - 1 of the group.
+template <int W, int C>
+__global__ void __launch_bounds__(64) gain_batched(const GroupDev* __restrict__ groups, int n_groups,
+                                                   unsigned long long n_units,
+                                                   unsigned long long* __restrict__ counter)
+{
+    constexpr int TERMS = W + 2;
+    constexpr int CELLS = W * W;
+    constexpr int NOUT = C * CELLS;
+    constexpr int RS = 65;  // row stride of the reduction buffer (no bank conflicts)
+    __shared__ float red[NOUT * RS];
+    const int lane = threadIdx.x;
+    const double halfW = 0.5 * W;
+
+    for (;;) {
+        unsigned long long u = 0;
+        if (lane == 0) u = atomicAdd(counter, 1ull);
+        u = lane0(u);
+        if (u >= n_units) break;
+        int g = 0;
+        while (g + 1 < n_groups && (long long)u >= groups[g + 1].unit_begin) ++g;
+        const GroupDev& D = groups[g];
+        const long long local = (long long)u - D.unit_begin;
+        const int item = (int)(local / D.ncg);
+        const int c0 = (int)(local % D.ncg) * C;
+        const int nc = min(C, D.n_cells - c0);
+        const int bin = D.item_bin[item];
+        const long long first = D.item_begin[item];
+        const int n = D.item_count[item];
+        const int t0x = bin / D.nb - D.off;
+        const int t0y = bin % D.nb - D.off;
+
+        float acc[C][CELLS];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int e = 0; e < CELLS; ++e) acc[c][e] = 0.f;
+
+        for (int i = lane; i < n; i += 64) {
+            const unsigned long long id = D.ids[first + i];
+            const int b1 = (int)(id & 0xffull), a1 = (int)((id >> 8) & 0xffull);
+            const int s = (int)((id >> 16) & 0x3ffull);
+            const int p2 = (int)((id >> 26) & 0xffffull);
+            float q;
+            double xs[2];
+            int64_t si;
+            point_geometry<float, 2>(D.gp, s, a1, b1, p2, 0, halfW, q, xs, si);
+            float kx[W], ky[W];
+            kernel_cells64<float, W, TERMS>(D.gp.poly64, 2.0 * ((double)t0x - xs[0]) - 1.0, kx);
+            kernel_cells64<float, W, TERMS>(D.gp.poly64, 2.0 * ((double)t0y - xs[1]) - 1.0, ky);
+            int ix[2], iy[2];
+            q *= orbit_terms<float, 2>(D.gp, a1, b1, p2, 0, ix, iy);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                float w = 0.f;
+                if (c < nc) {
+                    const float* Gc = D.Gg + (int64_t)(c0 + c) * D.nid;
+                    w = q * fmaf(Gc[ix[0]], Gc[iy[0]], Gc[ix[1]] * Gc[iy[1]]);
+                }
+#pragma unroll
+                for (int a = 0; a < W; ++a) {
+                    const float t = w * kx[a];
+#pragma unroll
+                    for (int b = 0; b < W; ++b) acc[c][a * W + b] = fmaf(t, ky[b], acc[c][a * W + b]);
+                }
+            }
+        }
+
+        // sum the 64 private tiles (FP64) and flush one atomic per footprint cell
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int e = 0; e < CELLS; ++e) red[(c * CELLS + e) * RS + lane] = acc[c][e];
+        __syncthreads();
+        for (int o = lane; o < nc * CELLS; o += 64) {
+            const float* r = red + o * RS;
+            double v = 0.0;
+            for (int l = 0; l < 64; ++l) v += (double)r[l];
+            if (v != 0.0) {
+                const int c = o / CELLS, e = o % CELLS;
+                double* grid = D.grid + (int64_t)(c0 + c) * D.ngd;
+                const int64_t cell = (int64_t)fold_index(t0x + e / W, D.gp.nh) * D.gp.ng +
+                                     fold_index(t0y + e % W, D.gp.nh);
+                __hip_atomic_fetch_add(grid + cell, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void reset_counter(unsigned long long* __restrict__ counter)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0ull;
+}
+
+__global__ void fill_zero64(double* __restrict__ x, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.0;
+}
+
+__global__ void fill_one32(float* __restrict__ x, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 1.f;
+}
+
+// cin[c][k] = packed[offsets[cells[c]] + k] (widened to FP64)
+__global__ void batch_gather(const float* __restrict__ packed, const int64_t* __restrict__ offsets,
+                             const int* __restrict__ cells, int64_t Nd, int64_t n_total,
+                             double* __restrict__ cin)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_total) return;
+    const int64_t c = i / Nd;
+    cin[i] = (double)packed[offsets[cells[c]] + (i - c * Nd)];
+}
+
+// packed_q[offsets[cells[c]] + k] = Q+ - Q- (FP64, rounded once)
+__global__ void batch_scatter(const double* __restrict__ qp, const double* __restrict__ qm,
+                              const int64_t* __restrict__ offsets, const int* __restrict__ cells,
+                              int64_t Nd, int64_t n_total, float* __restrict__ packed_q)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_total) return;
+    const int64_t c = i / Nd;
+    packed_q[offsets[cells[c]] + (i - c * Nd)] = (float)(qp[i] - qm[i]);
+}
+
+inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// the cells-per-wave values the gain kernel is built for, by kernel width
+bool tile_supported(int W, int C)
+{
+    if (W < 4 || W > 8) return false;
+    if (C != 1 && C != 2 && C != 4 && C != 8) return false;
+    return C * W * W <= 200;
+}
+
+template <int W, int C>
+hipError_t gain_launch_wc(const GroupDev* groups, int n_groups, unsigned long long n_units,
+                          unsigned long long* counter, int waves, hipStream_t s)
+{
+    if constexpr (C * W * W <= 200) {
+        hipLaunchKernelGGL((gain_batched<W, C>), dim3(waves), dim3(64), 0, s, groups, n_groups, n_units,
+                           counter);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int W>
+hipError_t gain_launch_w(int C, const GroupDev* groups, int n_groups, unsigned long long n_units,
+                         unsigned long long* counter, int waves, hipStream_t s)
+{
+    switch (C) {
+    case 1: return gain_launch_wc<W, 1>(groups, n_groups, n_units, counter, waves, s);
+    case 2: return gain_launch_wc<W, 2>(groups, n_groups, n_units, counter, waves, s);
+    case 4: return gain_launch_wc<W, 4>(groups, n_groups, n_units, counter, waves, s);
+    case 8: return gain_launch_wc<W, 8>(groups, n_groups, n_units, counter, waves, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t gain_launch(int W, int C, const GroupDev* groups, int n_groups, unsigned long long n_units,
+                       unsigned long long* counter, int waves, hipStream_t s)
+{
+    switch (W) {
+    case 4: return gain_launch_w<4>(C, groups, n_groups, n_units, counter, waves, s);
+    case 5: return gain_launch_w<5>(C, groups, n_groups, n_units, counter, waves, s);
+    case 6: return gain_launch_w<6>(C, groups, n_groups, n_units, counter, waves, s);
+    case 7: return gain_launch_w<7>(C, groups, n_groups, n_units, counter, waves, s);
+    case 8: return gain_launch_w<8>(C, groups, n_groups, n_units, counter, waves, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// resident 64-lane workgroups of the gain kernel on the whole device
+template <int W, int C>
+int resident_waves_wc()
+{
+    if constexpr (C * W * W <= 200) {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gain_batched<W, C>, 64, 0) != hipSuccess)
+            return 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        return std::max(1, per_cu) * std::max(1, cus);
+    } else {
+        return 0;
+    }
+}
+
+template <int W>
+int resident_waves_w(int C)
+{
+    switch (C) {
+    case 1: return resident_waves_wc<W, 1>();
+    case 2: return resident_waves_wc<W, 2>();
+    case 4: return resident_waves_wc<W, 4>();
+    case 8: return resident_waves_wc<W, 8>();
+    default: return 0;
+    }
+}
+
+int resident_waves(int W, int C)
+{
+    switch (W) {
+    case 4: return resident_waves_w<4>(C);
+    case 5: return resident_waves_w<5>(C);
+    case 6: return resident_waves_w<6>(C);
+    case 7: return resident_waves_w<7>(C);
+    case 8: return resident_waves_w<8>(C);
+    default: return 0;
+    }
+}
+
+GainParams<float> group_gain_params(const Plan& p)
+{
+    GainParams<float> gp;
+    std::memset(&gp, 0, sizeof(gp));
+    gp.v1 = static_cast<const float*>(p.dt.v1);
+    gp.pair_a = p.dt.pair_a;
+    gp.pair_b = p.dt.pair_b;
+    gp.pair_base = p.dt.pair_base;
+    gp.sigma = static_cast<const float*>(p.dt.sigma);
+    gp.wfac = static_cast<const float*>(p.dt.wfac);
+    gp.poly = static_cast<const float*>(p.dt.poly);
+    gp.S = (float)p.S;
+    gp.inv_S = (float)(1.0 / p.S);
+    gp.inv_S64 = 1.0 / p.S;
+    gp.h_inv = (float)(1.0 / p.h);
+    gp.h_inv64 = 1.0 / p.h;
+    gp.poly64 = p.dt.poly64;
+    gp.b0 = (float)p.b0;
+    gp.gamma = (float)p.gamma;
+    gp.map = p.map;
+    gp.vhs = p.kernel == PGC_KERNEL_VHS;
+    gp.ni = p.ni;
+    gp.np = p.np;
+    gp.ng = p.ng;
+    gp.nh = p.nh;
+    gp.n_sigma = p.n_sigma;
+    gp.ngd = p.ngd;
+    return gp;
+}
+
+}  // namespace
+}  // namespace pgc
+
+using pgc::Plan;
+
+struct BatchGroup {
+    pgc_plan plan = nullptr;  // the shared discretisation of every cell with this N
+    int N = 0;
+    std::vector<int> cells;   // batch indices of the group's cells
+    int* cells_dev = nullptr;
+    double* cin = nullptr;    // n_cells x N^d FP64 coefficients
+    double* grid = nullptr;   // n_cells x n_g^d
+    pgc::DenseBufs b;
+};
+
+struct pgc_batch_s {
+    int n_cells = 0, W = 0;
+    std::vector<int> cell_modes;
+    std::vector<int64_t> offsets;  // dense packing, cell order
+    int64_t total = 0;
+    int64_t* offsets_dev = nullptr;
+    std::vector<BatchGroup> groups;
+    pgc::GroupDev* groups_dev = nullptr;
+    unsigned long long* counter = nullptr;
+    int C = 0, waves = 0;
+    unsigned long long n_units = 0;
+    int64_t n_points = 0;
+    double tuned_ms[4] = {0, 0, 0, 0};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<void*> allocations;
+    int64_t workspace_bytes = 0;
+};
+
+namespace {
+
+hipError_t batch_alloc(pgc_batch_s& b, void** ptr, size_t bytes)
+{
+    *ptr = nullptr;
+    hipError_t e = hipMalloc(ptr, std::max<size_t>(bytes, 16));
+    if (e != hipSuccess) return e;
+    b.allocations.push_back(*ptr);
+    b.workspace_bytes += (int64_t)bytes;
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t batch_alloc_n(pgc_batch_s& b, T** ptr, int64_t n)
+{
+    void* v = nullptr;
+    hipError_t e = batch_alloc(b, &v, (size_t)n * sizeof(T));
+    *ptr = static_cast<T*>(v);
+    return e;
+}
+
+void batch_free(pgc_batch_s* b)
+{
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (void* p : b->allocations) (void)hipFree(p);
+    for (BatchGroup& g : b->groups) (void)pgc_plan_destroy(g.plan);
+    delete b;
+}
+
+void drop_graph(pgc_batch_s& b)
+{
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+}
+
+// lay out the work units for C cells per wave and upload the group table
+hipError_t set_units(pgc_batch_s& b, int C, hipStream_t s)
+{
+    std::vector<pgc::GroupDev> gd(b.groups.size());
+    unsigned long long begin = 0;
+    for (size_t g = 0; g < b.groups.size(); ++g) {
+        const BatchGroup& G = b.groups[g];
+        const Plan& p = G.plan->p;
+        pgc::GroupDev& d = gd[g];
+        std::memset(&d, 0, sizeof(d));
+        d.gp = pgc::group_gain_params(p);
+        d.item_bin = p.bins.item_bin;
+        d.item_begin = p.bins.item_begin;
+        d.item_count = p.bins.item_count;
+        d.ids = p.bins.ids;
+        d.Gg = static_cast<const float*>(G.b.Gg);
+        d.grid = G.grid;
+        d.nb = p.bins.nb;
+        d.off = p.bins.off;
+        d.n_cells = (int)G.cells.size();
+        d.ncg = (d.n_cells + C - 1) / C;
+        d.nid = p.nid;
+        d.ngd = p.ngd;
+        d.unit_begin = (int64_t)begin;
+        begin += (unsigned long long)p.bins.n_items * (unsigned long long)d.ncg;
+    }
+    hipError_t e = hipMemcpyAsync(b.groups_dev, gd.data(), gd.size() * sizeof(pgc::GroupDev),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    b.C = C;
+    b.n_units = begin;
+    b.waves = pgc::resident_waves(b.W, C);
+    return b.waves > 0 ? hipSuccess : hipErrorInvalidValue;
+}
+
+hipError_t enqueue_gain(const pgc_batch_s& b, hipStream_t s)
+{
+    for (const BatchGroup& G : b.groups) {
+        const Plan& p = G.plan->p;
+        const int64_t n = (int64_t)G.cells.size() * p.ngd;
+        hipLaunchKernelGGL(pgc::fill_zero64, dim3(pgc::nblocks(n, 256)), dim3(256), 0, s, G.grid, n);
+    }
+    hipLaunchKernelGGL(pgc::reset_counter, dim3(1), dim3(64), 0, s, b.counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return pgc::gain_launch(b.W, b.C, b.groups_dev, (int)b.groups.size(), b.n_units, b.counter, b.waves, s);
+}
+
+// every stage of one batched evaluation, stream-ordered, no allocation
+hipError_t enqueue_all(const pgc_batch_s& b, const float* packed, const int64_t* offsets, float* packed_q,
+                       hipStream_t s)
+{
+    hipError_t e;
+    for (const BatchGroup& G : b.groups) {
+        const Plan& p = G.plan->p;
+        const int nb = (int)G.cells.size();
+        const int64_t n = (int64_t)nb * p.Nd;
+        hipLaunchKernelGGL(pgc::batch_gather, dim3(pgc::nblocks(n, 256)), dim3(256), 0, s, packed, offsets,
+                           G.cells_dev, p.Nd, n, G.cin);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = pgc::launch_dense_synthesis(p, G.cin, nb, G.b, s)) != hipSuccess) return e;
+        if ((e = pgc::launch_dense_loss(p, nb, G.b, s)) != hipSuccess) return e;
+    }
+    if ((e = enqueue_gain(b, s)) != hipSuccess) return e;
+    for (const BatchGroup& G : b.groups) {
+        const Plan& p = G.plan->p;
+        const int nb = (int)G.cells.size();
+        const int64_t n = (int64_t)nb * p.Nd;
+        if ((e = pgc::launch_dense_grid_to_modes(p, G.grid, nb, G.b, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(pgc::batch_scatter, dim3(pgc::nblocks(n, 256)), dim3(256), 0, s, G.b.qplus,
+                           G.b.qminus, offsets, G.cells_dev, p.Nd, n, packed_q);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// time the gain for every supported C on G = 1 and keep the fastest
+hipError_t autotune(pgc_batch_s& b, hipStream_t s)
+{
+    for (const BatchGroup& G : b.groups) {
+        const int64_t n = (int64_t)G.cells.size() * G.plan->p.nid;
+        hipLaunchKernelGGL(pgc::fill_one32, dim3(pgc::nblocks(n, 256)), dim3(256), 0, s,
+                           static_cast<float*>(G.b.Gg), n);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipEvent_t t0, t1;
+    if ((e = hipEventCreate(&t0)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&t1)) != hipSuccess) {
+        (void)hipEventDestroy(t0);
+        return e;
+    }
+    const int cands[4] = {1, 2, 4, 8};
+    int best = 0;
+    double best_ms = 0.0;
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+        b.tuned_ms[k] = 0.0;
+        if (!pgc::tile_supported(b.W, cands[k])) continue;
+        if ((e = set_units(b, cands[k], s)) != hipSuccess) break;
+        if ((e = enqueue_gain(b, s)) != hipSuccess) break;  // warm-up
+        if ((e = hipEventRecord(t0, s)) != hipSuccess) break;
+        if ((e = enqueue_gain(b, s)) != hipSuccess) break;
+        if ((e = hipEventRecord(t1, s)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(t1)) != hipSuccess) break;
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+        b.tuned_ms[k] = ms;
+        if (best == 0 || ms < best_ms) {
+            best = cands[k];
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (e != hipSuccess) return e;
+    if (best == 0) return hipErrorInvalidValue;
+    return set_units(b, best, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+pgc_status pgc_batch_create(const pgc_plan_desc* base, int32_t n_cells, const int32_t* n_modes_host,
+                            int32_t autotune_on, void* stream, pgc_batch* out)
+{
+    if (!base || !n_modes_host || !out || n_cells <= 0) return PGC_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (base->dim != 2 || base->precision != PGC_PRECISION_FP32) return PGC_ERR_UNSUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    pgc_batch_s* b = nullptr;
+    try {
+        b = new pgc_batch_s();
+        b->n_cells = n_cells;
+        b->cell_modes.assign(n_modes_host, n_modes_host + n_cells);
+        std::map<int, std::vector<int>, std::greater<int>> by_n;  // largest N first
+        for (int c = 0; c < n_cells; ++c) {
+            const int N = n_modes_host[c];
+            if (N < 3 || N > 255) {
+                delete b;
+                return PGC_ERR_INVALID_ARG;
+            }
+            by_n[N].push_back(c);
+            b->offsets.push_back(b->total);
+            b->total += (int64_t)N * N;
+        }
+        if (by_n.size() > (size_t)pgc::kMaxGroups) {
+            delete b;
+            return PGC_ERR_UNSUPPORTED;
+        }
+        for (auto& kv : by_n) {
+            BatchGroup g;
+            g.N = kv.first;
+            g.cells = kv.second;
+            b->groups.push_back(g);
+        }
+    } catch (const std::bad_alloc&) {
+        delete b;
+        return PGC_ERR_OUT_OF_MEMORY;
+    }
+
+    pgc_status st = PGC_OK;
+    hipError_t e = hipSuccess;
+    for (BatchGroup& g : b->groups) {
+        pgc_plan_desc d = *base;
+        d.n_modes = g.N;
+        d.m_v = 0;
+        d.gain_mode = pgc::kGainBinned;
+        st = pgc_plan_create(&d, stream, &g.plan);
+        if (st != PGC_OK) break;
+        const Plan& p = g.plan->p;
+        if (b->W == 0) b->W = p.W;
+        if (p.W != b->W || !pgc::tile_supported(p.W, 1) || p.gain_mode != pgc::kGainBinned) {
+            st = PGC_ERR_UNSUPPORTED;
+            break;
+        }
+        b->n_points += p.n_points * (int64_t)g.cells.size();
+        const int64_t nb = (int64_t)g.cells.size();
+        const int64_t L = std::max<int64_t>(std::max(p.N, p.ni), p.ng);
+        const int64_t t = L * L;
+        if ((e = batch_alloc_n(*b, &g.cells_dev, nb)) != hipSuccess) break;
+        if ((e = batch_alloc_n(*b, &g.cin, nb * p.Nd)) != hipSuccess) break;
+        if ((e = batch_alloc_n(*b, &g.b.P, nb * p.nid)) != hipSuccess) break;
+        if ((e = batch_alloc_n(*b, &g.b.G, nb * p.nid)) != hipSuccess) break;
+        float* gg = nullptr;
+        if ((e = batch_alloc_n(*b, &gg, nb * p.nid)) != hipSuccess) break;
+        g.b.Gg = gg;
+        if ((e = batch_alloc_n(*b, &g.b.H, nb * p.nid)) != hipSuccess) break;
+        if ((e = batch_alloc_n(*b, &g.b.qminus, nb * p.Nd)) != hipSuccess) break;
+        if ((e = batch_alloc_n(*b, &g.b.qplus, nb * p.Nd)) != hipSuccess) break;
+        if ((e = batch_alloc_n(*b, &g.b.tmpA, nb * t)) != hipSuccess) break;
+        if ((e = batch_alloc_n(*b, &g.b.tmpB, nb * t)) != hipSuccess) break;
+        if ((e = batch_alloc_n(*b, &g.b.red, nb)) != hipSuccess) break;
+        if ((e = batch_alloc_n(*b, &g.grid, nb * p.ngd)) != hipSuccess) break;
+        if ((e = hipMemcpyAsync(g.cells_dev, g.cells.data(), nb * sizeof(int), hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+            break;
+    }
+    if (st == PGC_OK && e == hipSuccess) {
+        if ((e = batch_alloc_n(*b, &b->offsets_dev, b->n_cells)) == hipSuccess &&
+            (e = hipMemcpyAsync(b->offsets_dev, b->offsets.data(), b->n_cells * sizeof(int64_t),
+                                hipMemcpyHostToDevice, s)) == hipSuccess &&
+            (e = batch_alloc_n(*b, &b->groups_dev, (int64_t)b->groups.size())) == hipSuccess &&
+            (e = batch_alloc_n(*b, &b->counter, 1)) == hipSuccess) {
+            e = autotune_on ? autotune(*b, s) : set_units(*b, 1, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        }
+    }
+    if (st == PGC_OK && e != hipSuccess) st = pgc::status_of(e);
+    if (st != PGC_OK) {
+        batch_free(b);
+        return st;
+    }
+    *out = b;
+    return PGC_OK;
+}
+
+pgc_status pgc_batch_destroy(pgc_batch batch)
+{
+    batch_free(batch);
+    return PGC_OK;
+}
+
+pgc_status pgc_batch_query(pgc_batch b, pgc_batch_info* info)
+{
+    if (!b || !info) return PGC_ERR_INVALID_ARG;
+    std::memset(info, 0, sizeof(*info));
+    info->n_cells = b->n_cells;
+    info->n_groups = (int32_t)b->groups.size();
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+        info->group_n_modes[g] = b->groups[g].N;
+        info->group_cells[g] = (int32_t)b->groups[g].cells.size();
+    }
+    info->coeffs_total = b->total;
+    info->kernel_width = b->W;
+    info->cells_per_wave = b->C;
+    info->waves = b->waves;
+    info->n_units = (int64_t)b->n_units;
+    info->n_points = b->n_points;
+    info->workspace_bytes = b->workspace_bytes;
+    for (const BatchGroup& g : b->groups) info->workspace_bytes += g.plan->p.workspace_bytes;
+    for (int k = 0; k < 4; ++k) info->tuned_ms[k] = b->tuned_ms[k];
+    info->has_graph = b->exec != nullptr;
+    return PGC_OK;
+}
+
+pgc_status pgc_batch_offsets(pgc_batch b, int64_t* offsets_host)
+{
+    if (!b || !offsets_host) return PGC_ERR_INVALID_ARG;
+    std::copy(b->offsets.begin(), b->offsets.end(), offsets_host);
+    return PGC_OK;
+}
+
+pgc_status pgc_batch_set_tile(pgc_batch b, int32_t cells_per_wave, void* stream)
+{
+    if (!b) return PGC_ERR_INVALID_ARG;
+    if (!pgc::tile_supported(b->W, cells_per_wave)) return PGC_ERR_UNSUPPORTED;
+    drop_graph(*b);
+    return pgc::status_of(set_units(*b, cells_per_wave, static_cast<hipStream_t>(stream)));
+}
+
+pgc_status pgc_batch_autotune(pgc_batch b, void* stream)
+{
+    if (!b) return PGC_ERR_INVALID_ARG;
+    drop_graph(*b);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = autotune(*b, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return pgc::status_of(e);
+}
+
+pgc_status pgc_batch_coeffs_to_q(pgc_batch b, const void* packed_coeffs_dev, const int64_t* offsets_dev,
+                                 void* packed_q_dev, void* stream)
+{
+    if (!b || !packed_coeffs_dev || !packed_q_dev) return PGC_ERR_INVALID_ARG;
+    const int64_t* off = offsets_dev ? offsets_dev : b->offsets_dev;
+    return pgc::status_of(enqueue_all(*b, static_cast<const float*>(packed_coeffs_dev), off,
+                                      static_cast<float*>(packed_q_dev), static_cast<hipStream_t>(stream)));
+}
+
+pgc_status pgc_batch_capture(pgc_batch b, const void* packed_coeffs_dev, const int64_t* offsets_dev,
+                             void* packed_q_dev, void* stream)
+{
+    if (!b || !packed_coeffs_dev || !packed_q_dev) return PGC_ERR_INVALID_ARG;
+    const int64_t* off = offsets_dev ? offsets_dev : b->offsets_dev;
+    drop_graph(*b);
+    hipStream_t user = static_cast<hipStream_t>(stream);
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamSynchronize(user);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return pgc::status_of(e);
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t ee = enqueue_all(*b, static_cast<const float*>(packed_coeffs_dev), off,
+                                    static_cast<float*>(packed_q_dev), cs);
+        e = hipStreamEndCapture(cs, &b->graph);
+        if (ee != hipSuccess) e = ee;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        drop_graph(*b);
+        return pgc::status_of(e);
+    }
+    return PGC_OK;
+}
+
+pgc_status pgc_batch_graph_launch(pgc_batch b, void* stream)
+{
+    if (!b || !b->exec) return PGC_ERR_INVALID_ARG;
+    return pgc::status_of(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

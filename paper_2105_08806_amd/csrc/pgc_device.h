@@ -1,0 +1,212 @@
+// Device-side pieces shared by the gain kernels of single plans and of
+// batches: fine-grid folding, the per-point geometry of a merged collision
+// point, its kernel values, its orbit sum and its bin.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pgc {
+namespace {
+
+__device__ __forceinline__ int fold_index(int t, int nh)
+{
+    // reflection of an unfolded grid index into [0, nh]: the images -z and
+    // 2 pi - z of a point z in [0, pi] land on -t and 2 nh - t.
+    return t < 0 ? -t : (t > nh ? 2 * nh - t : t);
+}
+
+template <typename T>
+struct GainParams {
+    const T* v1;        // n_i interior node velocities
+    const T* G;         // n_i^d  w_j g_j (the nodal factor of every triple)
+    const T* sym;       // np^d orbit sums, p_1 fastest (slab scheme)
+    const int* pair_a;  // np  smaller node of each pair
+    const int* pair_b;  // np  larger node
+    const int* pair_base;  // n_i  index of the pair (a, a)
+    const T* sigma;     // n_sigma x d
+    const T* wfac;      // n_sigma  W_s b0 S^d, formed in FP64 and rounded once
+    const T* poly;      // terms x W  (slab scheme)
+    const double* poly64;  // terms x W  the same coefficients in FP64 (binned schemes)
+    const T* slab_vlo;  // n_slabs
+    const T* slab_vhi;
+    double* partial;    // n_chunks x n_g^d
+    T S, inv_S, h_inv, b0, gamma;
+    double inv_S64, h_inv64;  // 1/S and 1/h in FP64
+    int map, vhs, ni, np, ng, nh, slab_planes, n_sigma;
+    int64_t ngd, n_units, units_per_chunk;
+};
+
+// post-collision coordinate in the transform variable and the factor mu^-2 / S
+// (the constant S of every dimension sits in the direction weight wfac):
+//   r = 0: zeta = tanh(t), z = arccos zeta = 2 atan(exp(-t)), mu^-2 / S = cosh(t)
+//   r = 1: zeta = t/sqrt(1+t^2), z = atan2(1, t),             mu^-2 / S = 1 + t^2
+// with t = v/S.  Evaluated in FP64 for both precisions: the FP32 exp and atan
+// of the device library carry a small bias that moves every point the same
+// way, which left a floor of about 4e-7 (relative) in an FP32 gain, while
+// these few FP64 operations per point cost little next to the spreading.
+template <typename T>
+__device__ __forceinline__ void map_point(T v, const GainParams<T>& P, double& z, T& m2)
+{
+    const double t = (double)v * P.inv_S64;
+    if (P.map == 0) {
+        const double e = exp(-t);
+        z = 2.0 * atan(e);
+        m2 = (T)(0.5 * (e + 1.0 / e));
+    } else {
+        z = atan2(1.0, t);
+        m2 = (T)fma(t, t, 1.0);
+    }
+}
+
+// values of the W kernel cells at offset s in [-1, 1): Horner in s
+template <typename T, int W, int TERMS>
+__device__ __forceinline__ void kernel_cells(const T* __restrict__ poly, T s, T* out)
+{
+#pragma unroll
+    for (int a = 0; a < W; ++a) out[a] = poly[(TERMS - 1) * W + a];
+#pragma unroll
+    for (int d = TERMS - 2; d >= 0; --d) {
+#pragma unroll
+        for (int a = 0; a < W; ++a) out[a] = fma(out[a], s, poly[d * W + a]);
+    }
+}
+
+// The same kernel values from the FP64 coefficients, evaluated in FP64 and
+// rounded once to T.  The monomial coefficients of the cells are several
+// times larger than the kernel values, so FP32 coefficients and an FP32 Horner
+// sweep would leave a systematic error of a few 1e-7 in every kernel value,
+// which the deconvolution by the exact kernel transform does not undo.  A
+// gfx950 lane issues an FP64 FMA at the rate of an FP32 one.
+template <typename T, int W, int TERMS>
+__device__ __forceinline__ void kernel_cells64(const double* __restrict__ poly, double s, T* out)
+{
+    double v[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) v[a] = poly[(TERMS - 1) * W + a];
+#pragma unroll
+    for (int d = TERMS - 2; d >= 0; --d) {
+#pragma unroll
+        for (int a = 0; a < W; ++a) v[a] = fma(v[a], s, poly[d * W + a]);
+    }
+#pragma unroll
+    for (int a = 0; a < W; ++a) out[a] = (T)v[a];
+}
+
+// Merged point ids pack (b_1, a_1, s, p_2, p_3) as
+// b1 | a1 << 8 | s << 16 | p2 << 26 | p3 << 42.
+__device__ __forceinline__ unsigned long long pack_id(int s, int a1, int b1, int p2, int p3)
+{
+    return (unsigned long long)b1 | ((unsigned long long)a1 << 8) | ((unsigned long long)s << 16) |
+           ((unsigned long long)p2 << 26) | ((unsigned long long)p3 << 42);
+}
+
+// geometry of one merged point: weight without the orbit sum, and z/h - W/2
+// (in FP64 from z, so that bins and kernel offsets agree for both precisions)
+template <typename T, int DIM>
+__device__ __forceinline__ void point_geometry(const GainParams<T>& P, int s, int a1, int b1, int p2,
+                                               int p3, double halfW, T& q, double* xs,
+                                               int64_t& sym_idx)
+{
+    const T half = (T)0.5;
+    const T va = P.v1[a1], vb = P.v1[b1];
+    const T d = va - vb;
+    T cen[DIM], r2;
+    {
+        const T x = P.v1[P.pair_a[p2]], y = P.v1[P.pair_b[p2]];
+        cen[1] = (x + y) * half;
+        r2 = (x - y) * (x - y);
+    }
+    if constexpr (DIM == 3) {
+        const T x = P.v1[P.pair_a[p3]], y = P.v1[P.pair_b[p3]];
+        cen[2] = (x + y) * half;
+        r2 += (x - y) * (x - y);
+    }
+    const T un = sqrt(d * d + r2);
+    T vp[DIM];
+    vp[0] = (va + vb) * half + un * P.sigma[s * DIM] * half;
+    for (int l = 1; l < DIM; ++l) vp[l] = cen[l] + un * P.sigma[s * DIM + l] * half;
+    q = P.wfac[s];
+    if (P.vhs) q *= (P.gamma == (T)1) ? un : (un > (T)0 ? pow(un, P.gamma) : (T)(P.gamma == (T)0));
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) {
+        double z;
+        T m2;
+        map_point(vp[l], P, z, m2);
+        q *= m2;
+        xs[l] = z * P.h_inv64 - halfW;
+    }
+    const int64_t p1 = P.pair_base[a1] + (b1 - a1);
+    sym_idx = (DIM == 2) ? (int64_t)p2 * P.np + p1 : ((int64_t)p2 * P.np + p3) * P.np + p1;
+}
+
+// The 2^(d-1) products G_x G_y of the orbit of one merged point: the 2^d
+// exchanges of (a_l, b_l) pair up into products counted twice, and each equal
+// pair a_l = b_l halves the count.  Writes the flat node indices of the
+// products and returns the multiplicity c.
+template <typename T, int DIM>
+__device__ __forceinline__ T orbit_terms(const GainParams<T>& P, int a1, int b1, int p2, int p3,
+                                         int* ix, int* iy)
+{
+    const int ni = P.ni;
+    const int a2 = P.pair_a[p2], b2 = P.pair_b[p2];
+    T c = (T)2;
+    if (a1 == b1) c *= (T)0.5;
+    if (a2 == b2) c *= (T)0.5;
+    if constexpr (DIM == 2) {
+        ix[0] = a1 * ni + a2;
+        iy[0] = b1 * ni + b2;
+        ix[1] = a1 * ni + b2;
+        iy[1] = b1 * ni + a2;
+    } else {
+        const int a3 = P.pair_a[p3], b3 = P.pair_b[p3];
+        if (a3 == b3) c *= (T)0.5;
+        const int A1 = a1 * ni, B1 = b1 * ni;
+        ix[0] = (A1 + a2) * ni + a3;
+        iy[0] = (B1 + b2) * ni + b3;
+        ix[1] = (A1 + a2) * ni + b3;
+        iy[1] = (B1 + b2) * ni + a3;
+        ix[2] = (A1 + b2) * ni + a3;
+        iy[2] = (B1 + a2) * ni + b3;
+        ix[3] = (A1 + b2) * ni + b3;
+        iy[3] = (B1 + a2) * ni + a3;
+    }
+    return c;
+}
+
+// Orbit sum of one merged point straight from the nodal table G (small enough
+// to stay in L2).
+template <typename T, int DIM>
+__device__ __forceinline__ T orbit_sum(const GainParams<T>& P, int a1, int b1, int p2, int p3)
+{
+    constexpr int NT = 1 << (DIM - 1);
+    int ix[NT], iy[NT];
+    const T c = orbit_terms<T, DIM>(P, a1, b1, p2, p3, ix, iy);
+    T acc = P.G[ix[0]] * P.G[iy[0]];
+#pragma unroll
+    for (int t = 1; t < NT; ++t) acc = fma(P.G[ix[t]], P.G[iy[t]], acc);
+    return c * acc;
+}
+
+struct BinGeo {
+    int nb;      // bins per dimension
+    int off;     // bin index = t0 + off
+    int W;
+    int64_t n_items;  // (s, a_1, pencil) generation items
+};
+
+template <int DIM>
+__device__ __forceinline__ int64_t point_bin(const double* xs, const BinGeo& B)
+{
+    int64_t bin = 0;
+    for (int l = 0; l < DIM; ++l) {
+        int t = (int)ceil(xs[l]) + B.off;
+        t = t < 0 ? 0 : (t >= B.nb ? B.nb - 1 : t);
+        bin = bin * B.nb + t;
+    }
+    return bin;
+}
+
+}  // namespace
+}  // namespace pgc

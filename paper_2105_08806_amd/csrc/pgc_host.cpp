@@ -465,12 +465,7 @@ void free_all(Plan& p)
     p.allocations.clear();
 }
 
-pgc_status from_hip(hipError_t e)
-{
-    if (e == hipSuccess) return PGC_OK;
-    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return PGC_ERR_OUT_OF_MEMORY;
-    return PGC_ERR_DEVICE;
-}
+pgc_status from_hip(hipError_t e) { return status_of(e); }
 
 // Sort the merged points by the base cell of their footprint: count per bin on
 // the device, prefix sums and the work-item list on the host, then scatter the
@@ -564,8 +559,18 @@ hipError_t allocate(Plan& p, hipStream_t s)
     PGC_TRY(upload64(p, &p.dt.CT, p.CT, s));
     PGC_TRY(upload64(p, &p.dt.E, p.E, s));
     PGC_TRY(upload(p, &p.dt.poly, p.poly, s));
+    if (fp64)
+        p.dt.poly64 = static_cast<double*>(p.dt.poly);
+    else
+        PGC_TRY(upload64(p, &p.dt.poly64, p.poly, s));
     PGC_TRY(upload(p, &p.dt.sigma, p.sigma, s));
-    PGC_TRY(upload(p, &p.dt.sigma_w, p.sigma_w, s));
+    {
+        // W_s b0 S^d: the constant factors of every point's weight, one rounding in FP32
+        p.wfac.resize(p.sigma_w.size());
+        const double sd = std::pow(p.S, p.dim);
+        for (size_t i = 0; i < p.wfac.size(); ++i) p.wfac[i] = p.sigma_w[i] * p.b0 * sd;
+        PGC_TRY(upload(p, &p.dt.wfac, p.wfac, s));
+    }
     PGC_TRY(upload(p, &p.dt.slab_vlo, p.slab_vlo, s));
     PGC_TRY(upload(p, &p.dt.slab_vhi, p.slab_vhi, s));
 
@@ -660,10 +665,6 @@ hipError_t allocate(Plan& p, hipStream_t s)
 // ==================================================================== C ABI
 
 using pgc::Plan;
-
-struct pgc_plan_s {
-    Plan p;
-};
 
 extern "C" {
 

@@ -28,8 +28,9 @@ struct DeviceTables {
     double* CT = nullptr;     // N x n_i  transpose of C
     double* E = nullptr;      // N x n_g  cos(k m h) h / (psi^(k) sqrt(c_k))
     void* poly = nullptr;     // terms x W Horner coefficients of the kernel cells
+    double* poly64 = nullptr; // the same in FP64 (aliases poly for FP64 plans)
     void* sigma = nullptr;    // n_sigma x dim
-    void* sigma_w = nullptr;  // n_sigma
+    void* wfac = nullptr;     // n_sigma  W_s b0 S^d (direction weight, kernel constant, map scale)
     void* slab_vlo = nullptr; // n_slabs  v'_1 window of each slab
     void* slab_vhi = nullptr; // n_slabs
     int* pair_a = nullptr;    // np  unordered node pairs (a <= b) per dimension
@@ -89,7 +90,7 @@ struct Plan {
     int dim = 2, N = 0, m_v = 0, ni = 0, map = 0, kernel = 0, precision = 0;
     double S = 0.0, b0 = 0.0, gamma = 0.0, wsum = 0.0;
     int n_sigma = 0;
-    std::vector<double> sigma, sigma_w;
+    std::vector<double> sigma, sigma_w, wfac;
 
     // fine grid and spreading kernel
     double upsample = 2.0, beta = 0.0, h = 0.0, tol = 0.0;
@@ -118,6 +119,20 @@ struct Plan {
     std::vector<void*> allocations;
 };
 
+// Buffers of the dense (FP64) stages for nb cells, each nb times the size of
+// the corresponding single-cell Workspace buffer.
+struct DenseBufs {
+    double* P = nullptr;
+    double* G = nullptr;
+    void* Gg = nullptr;       // plan precision; NULL when the gain reads G itself (FP64)
+    double* H = nullptr;
+    double* qminus = nullptr;
+    double* qplus = nullptr;
+    double* tmpA = nullptr;   // nb * max(N, n_i, n_g)^d each
+    double* tmpB = nullptr;
+    double* red = nullptr;    // nb
+};
+
 // record the event that closes stage `stage - 1` / opens `stage` (no-op when off)
 inline void prof_mark(const Plan& p, int stage, hipStream_t s)
 {
@@ -129,6 +144,12 @@ hipError_t launch_synthesis(const Plan& p, const void* coeffs, hipStream_t s);
 hipError_t launch_loss(const Plan& p, hipStream_t s);
 hipError_t launch_gain(const Plan& p, hipStream_t s);
 hipError_t launch_combine(const Plan& p, void* q, void* qplus, hipStream_t s);
+// the dense stages for nb cells of one plan's size (batches)
+hipError_t launch_dense_synthesis(const Plan& p, const double* c64, int nb, const DenseBufs& b,
+                                  hipStream_t s);
+hipError_t launch_dense_loss(const Plan& p, int nb, const DenseBufs& b, hipStream_t s);
+hipError_t launch_dense_grid_to_modes(const Plan& p, const double* grid, int nb, const DenseBufs& b,
+                                      hipStream_t s);
 // plan time: mode 0 counts points per bin into `count`, mode 1 scatters ids
 // through the per-bin cursors
 hipError_t launch_bin_build(const Plan& p, unsigned int* count, unsigned long long* cursor,
@@ -144,4 +165,17 @@ hipError_t launch_rk_stage(const Plan& p, const double* base, const void* k, dou
 hipError_t launch_rk_finish(const Plan& p, double* base, double dt, hipStream_t s);
 hipError_t launch_copy_state(const Plan& p, const double* base, void* y, hipStream_t s);
 
+// status of a HIP error code
+inline pgc_status status_of(hipError_t e)
+{
+    if (e == hipSuccess) return PGC_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return PGC_ERR_OUT_OF_MEMORY;
+    return PGC_ERR_DEVICE;
+}
+
 }  // namespace pgc
+
+// the opaque plan handle of the C ABI
+struct pgc_plan_s {
+    pgc::Plan p;
+};

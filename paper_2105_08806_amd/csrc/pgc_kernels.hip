@@ -18,19 +18,13 @@
 #include <cmath>
 #include <cstdint>
 
+#include "pgc_device.h"
 #include "pgc_internal.h"
 
 namespace pgc {
 namespace {
 
 constexpr int kRedThreads = 1024;
-
-__device__ __forceinline__ int fold_index(int t, int nh)
-{
-    // reflection of an unfolded grid index into [0, nh]: the images -z and
-    // 2 pi - z of a point z in [0, pi] land on -t and 2 nh - t.
-    return t < 0 ? -t : (t > nh ? 2 * nh - t : t);
-}
 
 // ------------------------------------------------------------------ transforms
 
@@ -54,18 +48,19 @@ __global__ void __launch_bounds__(256) sep_apply(const T* __restrict__ in, T* __
     out[idx] = acc;
 }
 
-// apply the K x L matrix M along every axis of a dim-dimensional L^dim tensor (FP64)
+// apply the K x L matrix M along every axis of nb consecutive dim-dimensional
+// L^dim tensors (FP64); tmpA and tmpB hold nb * max(K, L)^dim values each
 hipError_t separable(const Plan& p, const double* in, double* out, const double* M, int K, int L,
-                     hipStream_t s)
+                     int nb, double* tmpA, double* tmpB, hipStream_t s)
 {
     int64_t dims[3] = {L, L, L};
     const double* src = in;
-    double* bufs[2] = {p.ws.tmpA, p.ws.tmpB};
+    double* bufs[2] = {tmpA, tmpB};
     int pp = 0;
     for (int ax = p.dim - 1; ax >= 0; --ax) {
         double* dst = (ax == 0) ? out : bufs[pp];
         pp ^= 1;
-        int64_t A = 1, B = 1;
+        int64_t A = nb, B = 1;
         for (int l = 0; l < ax; ++l) A *= dims[l];
         for (int l = ax + 1; l < p.dim; ++l) B *= dims[l];
         const int64_t total = A * K * B;
@@ -99,12 +94,13 @@ __device__ __forceinline__ void node_weights(int64_t f, int dim, int ni, const T
 template <typename T>
 __global__ void make_weighted(const double* __restrict__ P, double* __restrict__ G,
                               T* __restrict__ Gg, const double* __restrict__ w1,
-                              const double* __restrict__ mu21, int dim, int ni, int64_t nid)
+                              const double* __restrict__ mu21, int dim, int ni, int64_t nid,
+                              int64_t n_total)
 {
-    const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (f >= nid) return;
+    const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;  // over n_cells * nid
+    if (f >= n_total) return;
     double w, mu2;
-    node_weights(f, dim, ni, w1, mu21, w, mu2);
+    node_weights(f % nid, dim, ni, w1, mu21, w, mu2);
     const double g = w * mu2 * P[f];
     G[f] = g;
     if (Gg) Gg[f] = (T)g;
@@ -126,53 +122,56 @@ __global__ void narrow(const double* __restrict__ x, T* __restrict__ y, int64_t 
 
 // ------------------------------------------------------------------ loss
 
-// red[0] = sum_j G_j  (Maxwell molecules: the inner integral of eq. Qminus is
-// a single number; FP64 accumulation, fixed order within one workgroup)
-template <typename T>
-__global__ void __launch_bounds__(kRedThreads) sum_kernel(const T* __restrict__ G, int64_t n,
+// red[c] = sum_j G_j of cell c = blockIdx.x (Maxwell molecules: the inner
+// integral of eq. Qminus is a single number; fixed order within one workgroup)
+__global__ void __launch_bounds__(kRedThreads) sum_kernel(const double* __restrict__ G, int64_t n,
                                                           double* __restrict__ red)
 {
     __shared__ double sh[kRedThreads / 64];
+    const double* g = G + blockIdx.x * n;
     double acc = 0.0;
-    for (int64_t f = threadIdx.x; f < n; f += blockDim.x) acc += (double)G[f];
+    for (int64_t f = threadIdx.x; f < n; f += blockDim.x) acc += g[f];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
-        red[0] = t;
+        red[blockIdx.x] = t;
     }
 }
 
-// H_i = w_i A P_i with A = (sum_s W_s) b0 sum_j G_j
-template <typename T>
-__global__ void loss_h_maxwell(const T* __restrict__ P, T* __restrict__ H, const T* __restrict__ w1,
-                               const T* __restrict__ mu21, const double* __restrict__ red,
-                               double scale, int dim, int ni, int64_t nid)
+// H_i = w_i A P_i with A = (sum_s W_s) b0 sum_j G_j, over n_cells * nid nodes
+__global__ void loss_h_maxwell(const double* __restrict__ P, double* __restrict__ H,
+                               const double* __restrict__ w1, const double* __restrict__ mu21,
+                               const double* __restrict__ red, double scale, int dim, int ni,
+                               int64_t nid, int64_t n_total)
 {
     const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (f >= nid) return;
-    T w, mu2;
-    node_weights(f, dim, ni, w1, mu21, w, mu2);
-    const T A = (T)(scale * red[0]);
-    H[f] = w * A * P[f];
+    if (f >= n_total) return;
+    double w, mu2;
+    node_weights(f % nid, dim, ni, w1, mu21, w, mu2);
+    H[f] = w * (scale * red[f / nid]) * P[f];
 }
 
-// VHS: A_i = (sum_s W_s) b0 sum_j G_j |v_i - v_j|^gamma, one thread per node i,
-// the j sweep staged through LDS in tiles.
-template <typename T, int DIM>
-__global__ void __launch_bounds__(256) loss_h_vhs(const T* __restrict__ P, const T* __restrict__ G,
-                                                  T* __restrict__ H, const T* __restrict__ v1,
-                                                  const T* __restrict__ w1,
-                                                  const T* __restrict__ mu21, double scale,
-                                                  T gamma, int ni, int64_t nid)
+// VHS: A_i = (sum_s W_s) b0 sum_j G_j |v_i - v_j|^gamma, one thread per node i
+// of cell blockIdx.y, the j sweep staged through LDS in tiles.
+template <int DIM>
+__global__ void __launch_bounds__(256) loss_h_vhs(const double* __restrict__ P,
+                                                  const double* __restrict__ G,
+                                                  double* __restrict__ H,
+                                                  const double* __restrict__ v1,
+                                                  const double* __restrict__ w1,
+                                                  const double* __restrict__ mu21, double scale,
+                                                  double gamma, int ni, int64_t nid)
 {
     constexpr int kTile = 256;
-    __shared__ T sv[kTile][DIM];
-    __shared__ T sg[kTile];
+    __shared__ double sv[kTile][DIM];
+    __shared__ double sg[kTile];
+    const int64_t cell = blockIdx.y;
+    const double* Gc = G + cell * nid;
     const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    T vi[DIM];
+    double vi[DIM];
     {
         int64_t r = f < nid ? f : 0;
         for (int l = DIM - 1; l >= 0; --l) {
@@ -180,7 +179,7 @@ __global__ void __launch_bounds__(256) loss_h_vhs(const T* __restrict__ P, const
             r /= ni;
         }
     }
-    T acc = 0;
+    double acc = 0;
     for (int64_t j0 = 0; j0 < nid; j0 += kTile) {
         __syncthreads();
         const int64_t j = j0 + threadIdx.x;
@@ -191,7 +190,7 @@ __global__ void __launch_bounds__(256) loss_h_vhs(const T* __restrict__ P, const
                     sv[threadIdx.x][l] = v1[r % ni];
                     r /= ni;
                 }
-                sg[threadIdx.x] = G[j];
+                sg[threadIdx.x] = Gc[j];
             } else {
                 for (int l = 0; l < DIM; ++l) sv[threadIdx.x][l] = 0;
                 sg[threadIdx.x] = 0;
@@ -200,22 +199,22 @@ __global__ void __launch_bounds__(256) loss_h_vhs(const T* __restrict__ P, const
         __syncthreads();
         const int cnt = (int)((nid - j0) < kTile ? (nid - j0) : kTile);
         for (int t = 0; t < cnt; ++t) {
-            T u2 = 0;
+            double u2 = 0;
             for (int l = 0; l < DIM; ++l) {
-                const T d = vi[l] - sv[t][l];
+                const double d = vi[l] - sv[t][l];
                 u2 += d * d;
             }
-            T b;
-            if (gamma == (T)1) b = sqrt(u2);
-            else if (gamma == (T)0) b = 1;
-            else b = u2 > 0 ? pow(u2, (T)0.5 * gamma) : (T)0;
+            double b;
+            if (gamma == 1.0) b = sqrt(u2);
+            else if (gamma == 0.0) b = 1;
+            else b = u2 > 0 ? pow(u2, 0.5 * gamma) : 0.0;
             acc = fma(sg[t], b, acc);
         }
     }
     if (f >= nid) return;
-    T w, mu2;
+    double w, mu2;
     node_weights(f, DIM, ni, w1, mu21, w, mu2);
-    H[f] = w * (T)scale * acc * P[f];
+    H[cell * nid + f] = w * scale * acc * P[cell * nid + f];
 }
 
 // ------------------------------------------------------------------ gain
@@ -263,54 +262,6 @@ __global__ void pair_orbit_sums(const T* __restrict__ G, T* __restrict__ sym,
         acc += (double)G[x] * (double)G[y];
     }
     sym[e] = (T)(c * acc);
-}
-
-template <typename T>
-struct GainParams {
-    const T* v1;        // n_i interior node velocities
-    const T* G;         // n_i^d  w_j g_j (the nodal factor of every triple)
-    const T* sym;       // np^d orbit sums, p_1 fastest (slab scheme)
-    const int* pair_a;  // np  smaller node of each pair
-    const int* pair_b;  // np  larger node
-    const int* pair_base;  // n_i  index of the pair (a, a)
-    const T* sigma;     // n_sigma x d
-    const T* sigma_w;   // n_sigma
-    const T* poly;      // terms x W
-    const T* slab_vlo;  // n_slabs
-    const T* slab_vhi;
-    double* partial;    // n_chunks x n_g^d
-    T S, inv_S, h_inv, b0, gamma;
-    int map, vhs, ni, np, ng, nh, slab_planes, n_sigma;
-    int64_t ngd, n_units, units_per_chunk;
-};
-
-// post-collision coordinate in the transform variable and the factor mu^-2:
-//   r = 0: zeta = tanh(v/S), z = arccos zeta = 2 atan(exp(-v/S)), mu^-2 = S cosh(v/S)
-//   r = 1: zeta = v/sqrt(S^2+v^2), z = atan2(S, v),              mu^-2 = (S^2+v^2)/S
-template <typename T>
-__device__ __forceinline__ void map_point(T v, const GainParams<T>& P, T& z, T& m2)
-{
-    if (P.map == 0) {
-        const T e = exp(-v * P.inv_S);
-        z = (T)2 * atan(e);
-        m2 = (T)0.5 * P.S * (e + (T)1 / e);
-    } else {
-        z = atan2(P.S, v);
-        m2 = (P.S * P.S + v * v) * P.inv_S;
-    }
-}
-
-// values of the W kernel cells at offset s in [-1, 1): Horner in s
-template <typename T, int W, int TERMS>
-__device__ __forceinline__ void kernel_cells(const T* __restrict__ poly, T s, T* out)
-{
-#pragma unroll
-    for (int a = 0; a < W; ++a) out[a] = poly[(TERMS - 1) * W + a];
-#pragma unroll
-    for (int d = TERMS - 2; d >= 0; --d) {
-#pragma unroll
-        for (int a = 0; a < W; ++a) out[a] = fma(out[a], s, poly[d * W + a]);
-    }
 }
 
 // The fine grid accumulates in FP64 for both precisions: on gfx950 the LDS
@@ -434,7 +385,7 @@ __global__ void __launch_bounds__(spread_max_threads<T>()) gain_spread(GainParam
                 const int pencil = (int)(item / n_u);
                 const int a1 = (int)(u / P.n_sigma);
                 const int s = (int)(u % P.n_sigma);
-                cs = P.sigma_w[s] * P.b0;
+                cs = P.wfac[s];
                 for (int l = 0; l < DIM; ++l) sg[l] = P.sigma[s * DIM + l];
                 va1 = P.v1[a1];
                 const int pa = (DIM == 2) ? pencil : pencil / np;
@@ -483,13 +434,14 @@ __global__ void __launch_bounds__(spread_max_threads<T>()) gain_spread(GainParam
             for (int l = 1; l < DIM; ++l) vp[l] = cen[l] + un * sg[l] * half;
 #pragma unroll
             for (int l = 0; l < DIM; ++l) {
-                T z, m2;
+                double z;
+                T m2;
                 map_point(vp[l], P, z, m2);
                 q *= m2;
-                const T xs = z * P.h_inv - (T)(0.5 * W);
-                const T tf = ceil(xs);
+                const double xs = z * P.h_inv64 - 0.5 * W;
+                const double tf = ceil(xs);
                 t0[l] = (int)tf;
-                sfr[l] = (T)2 * (tf - xs) - (T)1;
+                sfr[l] = (T)(2.0 * (tf - xs) - 1.0);
             }
             valid = true;
             break;
@@ -554,95 +506,6 @@ __global__ void __launch_bounds__(spread_max_threads<T>()) gain_spread(GainParam
 // the bins: a wave regenerates 64 points of one bin, stages their kernel
 // vectors in LDS and accumulates the bin's W^d footprint in registers, one
 // lane per footprint column, before a single flush of W^d global FP64 atomics.
-//
-// Point ids pack (b_1, a_1, s, p_2, p_3) as b1 | a1 << 8 | s << 16 | p2 << 26 | p3 << 42.
-
-__device__ __forceinline__ unsigned long long pack_id(int s, int a1, int b1, int p2, int p3)
-{
-    return (unsigned long long)b1 | ((unsigned long long)a1 << 8) | ((unsigned long long)s << 16) |
-           ((unsigned long long)p2 << 26) | ((unsigned long long)p3 << 42);
-}
-
-// geometry of one merged point: weight without the orbit sum, and z/h - W/2
-template <typename T, int DIM>
-__device__ __forceinline__ void point_geometry(const GainParams<T>& P, int s, int a1, int b1, int p2,
-                                               int p3, T halfW, T& q, T* xs, int64_t& sym_idx)
-{
-    const T half = (T)0.5;
-    const T va = P.v1[a1], vb = P.v1[b1];
-    const T d = va - vb;
-    T cen[DIM], r2;
-    {
-        const T x = P.v1[P.pair_a[p2]], y = P.v1[P.pair_b[p2]];
-        cen[1] = (x + y) * half;
-        r2 = (x - y) * (x - y);
-    }
-    if constexpr (DIM == 3) {
-        const T x = P.v1[P.pair_a[p3]], y = P.v1[P.pair_b[p3]];
-        cen[2] = (x + y) * half;
-        r2 += (x - y) * (x - y);
-    }
-    const T un = sqrt(d * d + r2);
-    T vp[DIM];
-    vp[0] = (va + vb) * half + un * P.sigma[s * DIM] * half;
-    for (int l = 1; l < DIM; ++l) vp[l] = cen[l] + un * P.sigma[s * DIM + l] * half;
-    q = P.sigma_w[s] * P.b0;
-    if (P.vhs) q *= (P.gamma == (T)1) ? un : (un > (T)0 ? pow(un, P.gamma) : (T)(P.gamma == (T)0));
-#pragma unroll
-    for (int l = 0; l < DIM; ++l) {
-        T z, m2;
-        map_point(vp[l], P, z, m2);
-        q *= m2;
-        xs[l] = z * P.h_inv - halfW;
-    }
-    const int64_t p1 = P.pair_base[a1] + (b1 - a1);
-    sym_idx = (DIM == 2) ? (int64_t)p2 * P.np + p1 : ((int64_t)p2 * P.np + p3) * P.np + p1;
-}
-
-// Orbit sum of one merged point straight from the nodal table G (small enough
-// to stay in L2): the 2^d exchanges of (a_l, b_l) pair up into 2^(d-1) products
-// G_x G_y counted twice, and each equal pair a_l = b_l halves the count.
-template <typename T, int DIM>
-__device__ __forceinline__ T orbit_sum(const GainParams<T>& P, int a1, int b1, int p2, int p3)
-{
-    const int ni = P.ni;
-    const int a2 = P.pair_a[p2], b2 = P.pair_b[p2];
-    T c = (T)2;
-    if (a1 == b1) c *= (T)0.5;
-    if (a2 == b2) c *= (T)0.5;
-    T acc;
-    if constexpr (DIM == 2) {
-        acc = P.G[a1 * ni + a2] * P.G[b1 * ni + b2] + P.G[a1 * ni + b2] * P.G[b1 * ni + a2];
-    } else {
-        const int a3 = P.pair_a[p3], b3 = P.pair_b[p3];
-        if (a3 == b3) c *= (T)0.5;
-        const int A1 = a1 * ni, B1 = b1 * ni;
-        acc = P.G[(A1 + a2) * ni + a3] * P.G[(B1 + b2) * ni + b3] +
-              P.G[(A1 + a2) * ni + b3] * P.G[(B1 + b2) * ni + a3] +
-              P.G[(A1 + b2) * ni + a3] * P.G[(B1 + a2) * ni + b3] +
-              P.G[(A1 + b2) * ni + b3] * P.G[(B1 + a2) * ni + a3];
-    }
-    return c * acc;
-}
-
-struct BinGeo {
-    int nb;      // bins per dimension
-    int off;     // bin index = t0 + off
-    int W;
-    int64_t n_items;  // (s, a_1, pencil) generation items
-};
-
-template <typename T, int DIM>
-__device__ __forceinline__ int64_t point_bin(const T* xs, const BinGeo& B)
-{
-    int64_t bin = 0;
-    for (int l = 0; l < DIM; ++l) {
-        int t = (int)ceil(xs[l]) + B.off;
-        t = t < 0 ? 0 : (t >= B.nb ? B.nb - 1 : t);
-        bin = bin * B.nb + t;
-    }
-    return bin;
-}
 
 // plan time: MODE 0 counts the points of every bin, MODE 1 scatters their ids
 template <typename T, int DIM, int MODE>
@@ -653,7 +516,7 @@ __global__ void __launch_bounds__(256) bin_points(GainParams<T> P, BinGeo B,
 {
     const int np = P.np;
     const int npencil = (DIM == 2) ? np : np * np;
-    const T halfW = (T)(0.5 * B.W);
+    const double halfW = 0.5 * B.W;
     for (int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; item < B.n_items;
          item += (int64_t)gridDim.x * blockDim.x) {
         const int pencil = (int)(item % npencil);
@@ -663,10 +526,11 @@ __global__ void __launch_bounds__(256) bin_points(GainParams<T> P, BinGeo B,
         const int p2 = (DIM == 2) ? pencil : pencil / np;
         const int p3 = (DIM == 2) ? 0 : pencil % np;
         for (int b1 = a1; b1 < P.ni; ++b1) {
-            T q, xs[DIM];
+            T q;
+            double xs[DIM];
             int64_t si;
             point_geometry<T, DIM>(P, s, a1, b1, p2, p3, halfW, q, xs, si);
-            const int64_t bin = point_bin<T, DIM>(xs, B);
+            const int64_t bin = point_bin<DIM>(xs, B);
             if constexpr (MODE == 0) {
                 atomicAdd(count + bin, 1u);
             } else {
@@ -707,7 +571,7 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
     const int bin = BI.bin[item];
     const long long first = BI.begin[item];
     const int n = BI.count[item];
-    const T halfW = (T)(0.5 * W);
+    const double halfW = 0.5 * W;
 
     // base cell of the bin
     int t0[DIM];
@@ -739,7 +603,8 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
                 const int b1 = (int)(id & 0xffull), a1 = (int)((id >> 8) & 0xffull);
                 const int s = (int)((id >> 16) & 0x3ffull);
                 const int p2 = (int)((id >> 26) & 0xffffull), p3 = (int)((id >> 42) & 0xffffull);
-                T q, xs[DIM];
+                T q;
+                double xs[DIM];
                 int64_t si;
                 point_geometry<T, DIM>(P, s, a1, b1, p2, p3, halfW, q, xs, si);
                 st[0] = q * orbit_sum<T, DIM>(P, a1, b1, p2, p3);
@@ -747,7 +612,7 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
                 for (int l = 0; l < DIM; ++l) {
                     T k[W];
                     // offset relative to the bin's corner: s = 2 (t0 - xs) - 1
-                    kernel_cells<T, W, TERMS>(P.poly, (T)2 * ((T)t0[l] - xs[l]) - (T)1, k);
+                    kernel_cells64<T, W, TERMS>(P.poly64, 2.0 * ((double)t0[l] - xs[l]) - 1.0, k);
 #pragma unroll
                     for (int a = 0; a < W; ++a) st[1 + l * W + a] = k[a];
                 }
@@ -999,9 +864,37 @@ __global__ void rk_finish_kernel(double* __restrict__ base, const T* __restrict_
 
 inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
+DenseBufs plan_bufs(const Plan& p)
+{
+    DenseBufs b;
+    b.P = p.ws.P;
+    b.G = p.ws.G;
+    b.Gg = p.ws.Gg;
+    b.H = p.ws.H;
+    b.qminus = p.ws.qminus;
+    b.qplus = p.ws.qplus;
+    b.tmpA = p.ws.tmpA;
+    b.tmpB = p.ws.tmpB;
+    b.red = p.ws.red;
+    return b;
+}
+
 // ------------------------------------------------------------------ typed drivers
 
-// a1: P = C^{(x)d} f and G = w mu^2 P, in FP64 (FP32 inputs are widened first)
+// a1 for nb cells: P = C^{(x)d} f and G = w mu^2 P in FP64 from FP64
+// coefficients c64 (nb * N^d); Gg (plan precision) receives G rounded once
+template <typename T>
+hipError_t dense_synthesis_t(const Plan& p, const double* c64, int nb, const DenseBufs& b,
+                             hipStream_t s)
+{
+    hipError_t e = separable(p, c64, b.P, p.dt.C, p.ni, p.N, nb, b.tmpA, b.tmpB, s);
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)nb * p.nid;
+    hipLaunchKernelGGL(make_weighted<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, b.P, b.G,
+                       static_cast<T*>(b.Gg), p.dt.w1, p.dt.mu21, p.dim, p.ni, p.nid, n);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t synthesis_t(const Plan& p, const void* coeffs, hipStream_t s)
 {
@@ -1011,35 +904,30 @@ hipError_t synthesis_t(const Plan& p, const void* coeffs, hipStream_t s)
                            static_cast<const T*>(coeffs), p.ws.cin, p.Nd);
         c64 = p.ws.cin;
     }
-    hipError_t e = separable(p, c64, p.ws.P, p.dt.C, p.ni, p.N, s);
-    if (e != hipSuccess) return e;
-    T* gg = p.precision == PGC_PRECISION_FP64 ? nullptr : static_cast<T*>(p.ws.Gg);
-    hipLaunchKernelGGL(make_weighted<T>, dim3(blocks_for(p.nid, 256)), dim3(256), 0, s, p.ws.P,
-                       p.ws.G, gg, p.dt.w1, p.dt.mu21, p.dim, p.ni, p.nid);
-    return hipGetLastError();
+    DenseBufs b = plan_bufs(p);
+    if (p.precision == PGC_PRECISION_FP64) b.Gg = nullptr;  // G itself is read by the gain
+    return dense_synthesis_t<T>(p, c64, 1, b, s);
 }
 
-// a2 + a3: the loss field and its projection, FP64 for both plan precisions
-hipError_t loss_fp64(const Plan& p, hipStream_t s)
+// a2 + a3 for nb cells: the loss field and its projection Q- (FP64)
+hipError_t dense_loss(const Plan& p, int nb, const DenseBufs& b, hipStream_t s)
 {
     const double scale = p.wsum * p.b0;
     if (p.kernel == PGC_KERNEL_MAXWELL) {
-        hipLaunchKernelGGL(sum_kernel<double>, dim3(1), dim3(kRedThreads), 0, s, p.ws.G, p.nid,
-                           p.ws.red);
-        hipLaunchKernelGGL(loss_h_maxwell<double>, dim3(blocks_for(p.nid, 256)), dim3(256), 0, s,
-                           p.ws.P, p.ws.H, p.dt.w1, p.dt.mu21, p.ws.red, scale, p.dim, p.ni, p.nid);
+        const int64_t n = (int64_t)nb * p.nid;
+        hipLaunchKernelGGL(sum_kernel, dim3(nb), dim3(kRedThreads), 0, s, b.G, p.nid, b.red);
+        hipLaunchKernelGGL(loss_h_maxwell, dim3(blocks_for(n, 256)), dim3(256), 0, s, b.P, b.H,
+                           p.dt.w1, p.dt.mu21, b.red, scale, p.dim, p.ni, p.nid, n);
     } else if (p.dim == 2) {
-        hipLaunchKernelGGL((loss_h_vhs<double, 2>), dim3(blocks_for(p.nid, 256)), dim3(256), 0, s,
-                           p.ws.P, p.ws.G, p.ws.H, p.dt.v1d, p.dt.w1, p.dt.mu21, scale, p.gamma,
-                           p.ni, p.nid);
+        hipLaunchKernelGGL(loss_h_vhs<2>, dim3(blocks_for(p.nid, 256), nb), dim3(256), 0, s, b.P, b.G,
+                           b.H, p.dt.v1d, p.dt.w1, p.dt.mu21, scale, p.gamma, p.ni, p.nid);
     } else {
-        hipLaunchKernelGGL((loss_h_vhs<double, 3>), dim3(blocks_for(p.nid, 256)), dim3(256), 0, s,
-                           p.ws.P, p.ws.G, p.ws.H, p.dt.v1d, p.dt.w1, p.dt.mu21, scale, p.gamma,
-                           p.ni, p.nid);
+        hipLaunchKernelGGL(loss_h_vhs<3>, dim3(blocks_for(p.nid, 256), nb), dim3(256), 0, s, b.P, b.G,
+                           b.H, p.dt.v1d, p.dt.w1, p.dt.mu21, scale, p.gamma, p.ni, p.nid);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return separable(p, p.ws.H, p.ws.qminus, p.dt.CT, p.N, p.ni, s);
+    return separable(p, b.H, b.qminus, p.dt.CT, p.N, p.ni, nb, b.tmpA, b.tmpB, s);
 }
 
 template <typename T, int DIM, int W>
@@ -1094,14 +982,17 @@ GainParams<T> gain_params(const Plan& p)
     gp.pair_b = p.dt.pair_b;
     gp.pair_base = p.dt.pair_base;
     gp.sigma = static_cast<const T*>(p.dt.sigma);
-    gp.sigma_w = static_cast<const T*>(p.dt.sigma_w);
+    gp.wfac = static_cast<const T*>(p.dt.wfac);
     gp.poly = static_cast<const T*>(p.dt.poly);
     gp.slab_vlo = static_cast<const T*>(p.dt.slab_vlo);
     gp.slab_vhi = static_cast<const T*>(p.dt.slab_vhi);
     gp.partial = static_cast<double*>(p.ws.partial);
     gp.S = (T)p.S;
     gp.inv_S = (T)(1.0 / p.S);
+    gp.inv_S64 = 1.0 / p.S;
     gp.h_inv = (T)(1.0 / p.h);
+    gp.h_inv64 = 1.0 / p.h;
+    gp.poly64 = p.dt.poly64;
     gp.b0 = (T)p.b0;
     gp.gamma = (T)p.gamma;
     gp.map = p.map;
@@ -1211,7 +1102,7 @@ hipError_t gain_t(const Plan& p, hipStream_t s)
         e = (p.dim == 2) ? binned_dispatch<T, 2>(p, gp, bi, s) : binned_dispatch<T, 3>(p, gp, bi, s);
         if (e != hipSuccess) return e;
         prof_mark(p, 4, s);
-        e = separable(p, p.ws.grid64, p.ws.qplus, p.dt.E, p.N, p.ng, s);
+        e = separable(p, p.ws.grid64, p.ws.qplus, p.dt.E, p.N, p.ng, 1, p.ws.tmpA, p.ws.tmpB, s);
     } else {
         e = (p.dim == 2) ? spread_dispatch<T, 2>(p, gp, s) : spread_dispatch<T, 3>(p, gp, s);
         if (e != hipSuccess) return e;
@@ -1220,7 +1111,7 @@ hipError_t gain_t(const Plan& p, hipStream_t s)
                            static_cast<const double*>(p.ws.partial), p.ws.grid, p.ngd, p.n_chunks);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = separable(p, p.ws.grid, p.ws.qplus, p.dt.E, p.N, p.ng, s);
+        e = separable(p, p.ws.grid, p.ws.qplus, p.dt.E, p.N, p.ng, 1, p.ws.tmpA, p.ws.tmpB, s);
     }
     return e;
 }
@@ -1242,8 +1133,9 @@ hipError_t project_t(const Plan& p, const double* f, void* coeffs, hipStream_t s
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (p.precision == PGC_PRECISION_FP64)
-        return separable(p, p.ws.H, static_cast<double*>(coeffs), p.dt.CT, p.N, p.ni, s);
-    e = separable(p, p.ws.H, p.ws.cin, p.dt.CT, p.N, p.ni, s);
+        return separable(p, p.ws.H, static_cast<double*>(coeffs), p.dt.CT, p.N, p.ni, 1, p.ws.tmpA,
+                         p.ws.tmpB, s);
+    e = separable(p, p.ws.H, p.ws.cin, p.dt.CT, p.N, p.ni, 1, p.ws.tmpA, p.ws.tmpB, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(narrow<T>, dim3(blocks_for(p.Nd, 256)), dim3(256), 0, s, p.ws.cin,
                        static_cast<T*>(coeffs), p.Nd);
@@ -1260,7 +1152,25 @@ hipError_t launch_synthesis(const Plan& p, const void* coeffs, hipStream_t s)
                                              : synthesis_t<float>(p, coeffs, s);
 }
 
-hipError_t launch_loss(const Plan& p, hipStream_t s) { return loss_fp64(p, s); }
+hipError_t launch_loss(const Plan& p, hipStream_t s) { return dense_loss(p, 1, plan_bufs(p), s); }
+
+hipError_t launch_dense_synthesis(const Plan& p, const double* c64, int nb, const DenseBufs& b,
+                                  hipStream_t s)
+{
+    return p.precision == PGC_PRECISION_FP64 ? dense_synthesis_t<double>(p, c64, nb, b, s)
+                                             : dense_synthesis_t<float>(p, c64, nb, b, s);
+}
+
+hipError_t launch_dense_loss(const Plan& p, int nb, const DenseBufs& b, hipStream_t s)
+{
+    return dense_loss(p, nb, b, s);
+}
+
+hipError_t launch_dense_grid_to_modes(const Plan& p, const double* grid, int nb, const DenseBufs& b,
+                                      hipStream_t s)
+{
+    return separable(p, grid, b.qplus, p.dt.E, p.N, p.ng, nb, b.tmpA, b.tmpB, s);
+}
 
 hipError_t launch_gain(const Plan& p, hipStream_t s)
 {

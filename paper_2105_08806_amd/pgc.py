@@ -62,6 +62,17 @@ class PlanInfo(ctypes.Structure):
     ]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_cells", ctypes.c_int32), ("n_groups", ctypes.c_int32),
+        ("group_n_modes", ctypes.c_int32 * 8), ("group_cells", ctypes.c_int32 * 8),
+        ("coeffs_total", ctypes.c_int64), ("kernel_width", ctypes.c_int32),
+        ("cells_per_wave", ctypes.c_int32), ("waves", ctypes.c_int32), ("n_units", ctypes.c_int64),
+        ("n_points", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+        ("tuned_ms", ctypes.c_double * 4), ("has_graph", ctypes.c_int32),
+    ]
+
+
 _lib = None
 
 
@@ -90,9 +101,22 @@ def lib():
         L.pgc_eval.argtypes = [vp, vp, vp, i64, vp, vp]
         L.pgc_set_profiling.argtypes = [vp, i32]
         L.pgc_stage_times.argtypes = [vp, dp, i32, ctypes.POINTER(i64)]
+        L.pgc_batch_create.argtypes = [ctypes.POINTER(PlanDesc), i32, ctypes.POINTER(i32), i32, vp,
+                                       ctypes.POINTER(vp)]
+        L.pgc_batch_destroy.argtypes = [vp]
+        L.pgc_batch_query.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+        L.pgc_batch_offsets.argtypes = [vp, ctypes.POINTER(i64)]
+        L.pgc_batch_set_tile.argtypes = [vp, i32, vp]
+        L.pgc_batch_autotune.argtypes = [vp, vp]
+        L.pgc_batch_coeffs_to_q.argtypes = [vp, vp, vp, vp, vp]
+        L.pgc_batch_capture.argtypes = [vp, vp, vp, vp, vp]
+        L.pgc_batch_graph_launch.argtypes = [vp, vp]
         for name in ("pgc_desc_init", "pgc_nufft_params", "pgc_plan_create", "pgc_plan_destroy",
                      "pgc_plan_query", "pgc_nodes", "pgc_project", "pgc_coeffs_to_q", "pgc_rk4",
-                     "pgc_moments", "pgc_eval", "pgc_set_profiling", "pgc_stage_times"):
+                     "pgc_moments", "pgc_eval", "pgc_set_profiling", "pgc_stage_times",
+                     "pgc_batch_create", "pgc_batch_destroy", "pgc_batch_query", "pgc_batch_offsets",
+                     "pgc_batch_set_tile", "pgc_batch_autotune", "pgc_batch_coeffs_to_q",
+                     "pgc_batch_capture", "pgc_batch_graph_launch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -125,6 +149,23 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _desc_from(fields, sigma=None, sigma_w=None, keep=None):
+    d = default_desc()
+    for k, v in fields.items():
+        if not hasattr(d, k):
+            raise TypeError("unknown plan field %r" % k)
+        setattr(d, k, v)
+    if sigma is not None:
+        s = np.ascontiguousarray(sigma, dtype=np.float64)
+        w = np.ascontiguousarray(sigma_w, dtype=np.float64)
+        keep += [s, w]
+        d.sphere = SPHERE_USER
+        d.n_sigma = int(w.size)
+        d.user_sigma_host = s.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.user_weights_host = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return d
+
+
 class Plan:
     """One collision operator on the current GPU.
 
@@ -136,20 +177,8 @@ class Plan:
     def __init__(self, sigma=None, sigma_w=None, **fields):
         import torch
         self._torch = torch
-        d = default_desc()
-        for k, v in fields.items():
-            if not hasattr(d, k):
-                raise TypeError("unknown plan field %r" % k)
-            setattr(d, k, v)
         self._keep = []
-        if sigma is not None:
-            s = np.ascontiguousarray(sigma, dtype=np.float64)
-            w = np.ascontiguousarray(sigma_w, dtype=np.float64)
-            self._keep += [s, w]
-            d.sphere = SPHERE_USER
-            d.n_sigma = int(w.size)
-            d.user_sigma_host = s.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-            d.user_weights_host = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d = _desc_from(fields, sigma, sigma_w, self._keep)
         self.desc = d
         h = ctypes.c_void_p()
         _check(lib().pgc_plan_create(ctypes.byref(d), _stream(), ctypes.byref(h)), "pgc_plan_create")
@@ -255,3 +284,98 @@ class Plan:
         _check(lib().pgc_eval(self._h, _ptr(c), _ptr(vv), int(vv.shape[0]), _ptr(out), _stream()),
                "pgc_eval")
         return out
+
+
+class Batch:
+    """Q for many 2D velocity cells with mixed N in one batched evaluation (FP32).
+
+    ``n_modes`` lists the N of every cell; keyword arguments are the shared
+    pgc_plan_desc fields (precision defaults to FP32, the only one supported).
+    Packed arrays hold the cells' N^2 coefficient blocks at ``offsets``.
+    """
+
+    def __init__(self, n_modes, autotune=True, sigma=None, sigma_w=None, **fields):
+        import torch
+        self._torch = torch
+        fields.setdefault("dim", 2)
+        fields.setdefault("precision", FP32)
+        self._keep = []
+        d = _desc_from(fields, sigma, sigma_w, self._keep)
+        self.desc = d
+        nm = np.ascontiguousarray(n_modes, dtype=np.int32)
+        self.n_modes = nm.copy()
+        h = ctypes.c_void_p()
+        _check(lib().pgc_batch_create(ctypes.byref(d), int(nm.size),
+                                      nm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      1 if autotune else 0, _stream(), ctypes.byref(h)), "pgc_batch_create")
+        self._h = h
+        self.refresh_info()
+        off = np.zeros(nm.size, dtype=np.int64)
+        _check(lib().pgc_batch_offsets(self._h, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+               "pgc_batch_offsets")
+        self.offsets = off
+        self.total = int(self.info.coeffs_total)
+
+    def refresh_info(self):
+        self.info = BatchInfo()
+        _check(lib().pgc_batch_query(self._h, ctypes.byref(self.info)), "pgc_batch_query")
+        return self.info
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pgc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _packed(self, x, name):
+        torch = self._torch
+        if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.dim() == 1):
+            raise ValueError("%s must be a contiguous 1-D float32 CUDA tensor" % name)
+        return x
+
+    def pack(self, blocks):
+        """Dense packing of a list of per-cell N^2 arrays (host) into one CUDA tensor."""
+        torch = self._torch
+        flat = np.concatenate([np.asarray(b, dtype=np.float32).reshape(-1) for b in blocks])
+        if flat.size != self.total:
+            raise ValueError("blocks hold %d values, the batch packs %d" % (flat.size, self.total))
+        return torch.tensor(flat, device="cuda")
+
+    def unpack(self, packed):
+        """Per-cell N x N float64 host arrays of a dense packed tensor."""
+        x = packed.double().cpu().numpy()
+        return [x[o:o + n * n].reshape(n, n) for o, n in zip(self.offsets, self.n_modes)]
+
+    def set_tile(self, cells_per_wave):
+        _check(lib().pgc_batch_set_tile(self._h, int(cells_per_wave), _stream()), "pgc_batch_set_tile")
+        self.refresh_info()
+
+    def autotune(self):
+        _check(lib().pgc_batch_autotune(self._h, _stream()), "pgc_batch_autotune")
+        self.refresh_info()
+
+    def coeffs_to_q(self, packed, q=None, offsets=None):
+        torch = self._torch
+        c = self._packed(packed, "packed coefficients")
+        if q is None:
+            q = torch.empty_like(c)
+        self._packed(q, "packed q")
+        _check(lib().pgc_batch_coeffs_to_q(self._h, _ptr(c), _ptr(offsets) if offsets is not None else None,
+                                           _ptr(q), _stream()), "pgc_batch_coeffs_to_q")
+        return q
+
+    def capture(self, packed, q, offsets=None):
+        self._packed(packed, "packed coefficients")
+        self._packed(q, "packed q")
+        _check(lib().pgc_batch_capture(self._h, _ptr(packed), _ptr(offsets) if offsets is not None else None,
+                                       _ptr(q), _stream()), "pgc_batch_capture")
+        self._graph_io = (packed, q, offsets)  # the graph reads these buffers
+        self.refresh_info()
+
+    def graph_launch(self):
+        _check(lib().pgc_batch_graph_launch(self._h, _stream()), "pgc_batch_graph_launch")

@@ -76,3 +76,26 @@ def test_oracle_and_library_share_no_code():
     for f in ("pgc.py", "build.py", "inputs.py", "__init__.py"):
         src = open(os.path.join(ROOT, "paper_2105_08806_amd", f)).read()
         assert "import oracle" not in src and "from oracle" not in src
+
+
+def test_batch_argument_errors_without_a_device():
+    """Batch entry points reject bad arguments before any device work."""
+    from paper_2105_08806_amd import pgc
+    L = pgc.lib()
+    assert L.pgc_batch_destroy(None) == 0
+    info = pgc.BatchInfo()
+    assert L.pgc_batch_query(None, ctypes.byref(info)) == 1
+    assert L.pgc_batch_graph_launch(None, None) == 1
+    assert L.pgc_batch_coeffs_to_q(None, None, None, None, None) == 1
+    d = pgc.default_desc()
+    d.precision = pgc.FP32
+    modes = (ctypes.c_int32 * 3)(8, 8, 10)
+    h = ctypes.c_void_p()
+    assert L.pgc_batch_create(ctypes.byref(d), 0, modes, 0, None, ctypes.byref(h)) == 1
+    assert L.pgc_batch_create(ctypes.byref(d), 3, None, 0, None, ctypes.byref(h)) == 1
+    d3 = pgc.default_desc()
+    d3.dim, d3.precision = 3, pgc.FP32
+    assert L.pgc_batch_create(ctypes.byref(d3), 3, modes, 0, None, ctypes.byref(h)) == 2
+    d64 = pgc.default_desc()   # FP64 batches are not built
+    assert L.pgc_batch_create(ctypes.byref(d64), 3, modes, 0, None, ctypes.byref(h)) == 2
+    assert not h.value
