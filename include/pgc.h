@@ -264,6 +264,99 @@ pgc_status pgc_batch_capture(pgc_batch batch, const void* packed_coeffs_dev, con
                              void* packed_q_dev, void* stream);
 pgc_status pgc_batch_graph_launch(pgc_batch batch, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the coefficients-to-Q map of one FP32 plan.
+ *
+ * A multilayer perceptron on the N^d coefficients (per-feature normalisation,
+ * n_layers - 1 hidden layers of `width` units with SiLU, a linear output
+ * layer), trained by the library's own forward and backward kernels on pairs
+ * (f, Q) that the plan itself produced.  Products run on the matrix cores in
+ * BF16 with FP32 accumulation; master weights and Adam state are FP32.  The
+ * network output is projected onto the coefficient vectors whose mass,
+ * momentum and energy vanish (the invariants of the test space, Sec. 3.2),
+ * which is exact for the algebraic map and the quadrature rule of the plan.
+ *
+ * The plan is the fallback and the judge.  A sample falls back to
+ * pgc_coeffs_to_q of the plan when (a) the relative mass/momentum/energy
+ * residual of the returned Q exceeds gate_residual, or (b) the residual of the
+ * raw network output, or the RMS z-score of the normalised input, exceeds
+ * gate_raw_factor times the largest one seen on the training set (an input
+ * unlike the training data; 0 disables).  Every
+ * judge_stride-th sample of a call is also evaluated by the plan; if any of
+ * them differs from the network by more than judge_tol (relative L2), every
+ * sample of the call comes from the plan (0 disables the judge).
+ *
+ * Arrays: f and q are n_samples x N^d float rows (device).  The plan must
+ * outlive the surrogate and must not be used concurrently with it.
+ * ------------------------------------------------------------------------ */
+typedef struct pgc_surrogate_s* pgc_surrogate;
+
+typedef struct pgc_surrogate_desc {
+    int32_t width;           /* hidden width; default 1024 */
+    int32_t n_layers;        /* linear layers (>= 2); default 4 */
+    int32_t batch_max;       /* rows per forward/backward pass; default 256 */
+    uint64_t seed;           /* weight initialisation */
+    double gate_residual;    /* default 1e-6 */
+    double gate_raw_factor;  /* default 4 */
+    int32_t judge_stride;    /* default 64 */
+    double judge_tol;        /* default 5e-2 */
+} pgc_surrogate_desc;
+
+typedef struct pgc_surrogate_info {
+    int32_t n_features;      /* N^d */
+    int32_t width, n_layers, batch_max;
+    int64_t n_params;        /* weights and biases */
+    int32_t n_constraints;   /* d + 2 invariants */
+    int64_t steps;           /* optimiser steps taken */
+    double raw_residual_calibrated;
+    int64_t workspace_bytes;
+    double zscore_calibrated;   /* largest RMS z-score of a training input */
+} pgc_surrogate_info;
+
+pgc_status pgc_surrogate_desc_init(pgc_surrogate_desc* desc);
+/* Allocate and initialise the network for `plan` (FP32 plans only:
+ * UNSUPPORTED otherwise).  Synchronises `stream`. */
+pgc_status pgc_surrogate_create(pgc_plan plan, const pgc_surrogate_desc* desc, void* stream, pgc_surrogate* out);
+pgc_status pgc_surrogate_destroy(pgc_surrogate s);
+pgc_status pgc_surrogate_query(pgc_surrogate s, pgc_surrogate_info* info);
+/* Per-feature mean and standard deviation of inputs and targets over the
+ * n_samples rows of f_dev and q_dev (call before training). */
+pgc_status pgc_surrogate_set_normalization(pgc_surrogate s, const float* f_dev, const float* q_dev,
+                                           int64_t n_samples, void* stream);
+/* `epochs` passes of mini-batch Adam (batch <= batch_max rows, step size lr
+ * with cosine decay over the epochs) on the mean squared error of the
+ * normalised output; loss_host (may be NULL) receives the mean loss of each
+ * epoch.  Then calibrates the raw-residual gate on the training set.
+ * Synchronises `stream` after every step. */
+pgc_status pgc_surrogate_train(pgc_surrogate s, const float* f_dev, const float* q_dev, int64_t n_samples,
+                               int32_t epochs, int32_t batch, double lr, uint64_t seed, double* loss_host,
+                               void* stream);
+/* Q of n_samples rows: q_dev receives the surrogate's Q, or the plan's for
+ * the samples that fall back.  fallback_host (may be NULL) receives one flag
+ * per sample, n_fallback the count, judge_err the largest relative error the
+ * judge saw.  Synchronises `stream`. */
+pgc_status pgc_surrogate_coeffs_to_q(pgc_surrogate s, const float* f_dev, int64_t n_samples, float* q_dev,
+                                     int32_t* fallback_host, int64_t* n_fallback, double* judge_err, void* stream);
+/* Loss and gradient (all parameters, in the get_params order without the
+ * normalisation vectors) of the first n_samples <= batch_max rows. */
+pgc_status pgc_surrogate_loss_grad(pgc_surrogate s, const float* f_dev, const float* q_dev, int32_t n_samples,
+                                   double* loss_host, float* grad_host, void* stream);
+/* Parameters flattened layer by layer, W (out x in, row-major) then b, then
+ * mu_in, sd_in, mu_out, sd_out (N^d each): n_params + 4 N^d floats. */
+pgc_status pgc_surrogate_get_params(pgc_surrogate s, float* params_host, void* stream);
+pgc_status pgc_surrogate_set_params(pgc_surrogate s, const float* params_host, void* stream);
+/* Binary file of the parameters and the gate calibration; load checks the shape. */
+pgc_status pgc_surrogate_save(pgc_surrogate s, const char* path, void* stream);
+pgc_status pgc_surrogate_load(pgc_surrogate s, const char* path, void* stream);
+
+/* The matrix-core product the surrogate is built on, exposed for testing:
+ * C (M x N, FP32, row stride ldc) = op(A) op(B) + bias (or C += ... when
+ * accumulate != 0), A and B BF16 device matrices given as uint16 bit
+ * patterns, op(A)[m][k] = trans_a ? A[k lda + m] : A[m lda + k], likewise B. */
+pgc_status pgc_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* a_dev, int32_t lda, int32_t trans_a,
+                         const uint16_t* b_dev, int32_t ldb, int32_t trans_b, float* c_dev, int32_t ldc,
+                         const float* bias_dev, int32_t accumulate, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

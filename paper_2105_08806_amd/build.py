@@ -25,7 +25,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
-SOURCES = ["pgc_kernels.hip", "pgc_host.cpp", "pgc_batch.hip"]
+SOURCES = ["pgc_kernels.hip", "pgc_host.cpp", "pgc_batch.hip", "pgc_mlp.hip"]
 
 
 def _compile(src: str) -> str:

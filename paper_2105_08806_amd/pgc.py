@@ -73,6 +73,23 @@ class BatchInfo(ctypes.Structure):
     ]
 
 
+class SurrogateDesc(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32), ("n_layers", ctypes.c_int32), ("batch_max", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("gate_residual", ctypes.c_double), ("gate_raw_factor", ctypes.c_double),
+        ("judge_stride", ctypes.c_int32), ("judge_tol", ctypes.c_double),
+    ]
+
+
+class SurrogateInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_features", ctypes.c_int32), ("width", ctypes.c_int32), ("n_layers", ctypes.c_int32),
+        ("batch_max", ctypes.c_int32), ("n_params", ctypes.c_int64), ("n_constraints", ctypes.c_int32),
+        ("steps", ctypes.c_int64), ("raw_residual_calibrated", ctypes.c_double),
+        ("workspace_bytes", ctypes.c_int64), ("zscore_calibrated", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -111,6 +128,25 @@ def lib():
         L.pgc_batch_coeffs_to_q.argtypes = [vp, vp, vp, vp, vp]
         L.pgc_batch_capture.argtypes = [vp, vp, vp, vp, vp]
         L.pgc_batch_graph_launch.argtypes = [vp, vp]
+        u64 = ctypes.c_uint64
+        L.pgc_surrogate_desc_init.argtypes = [ctypes.POINTER(SurrogateDesc)]
+        L.pgc_surrogate_create.argtypes = [vp, ctypes.POINTER(SurrogateDesc), vp, ctypes.POINTER(vp)]
+        L.pgc_surrogate_destroy.argtypes = [vp]
+        L.pgc_surrogate_query.argtypes = [vp, ctypes.POINTER(SurrogateInfo)]
+        L.pgc_surrogate_set_normalization.argtypes = [vp, vp, vp, i64, vp]
+        L.pgc_surrogate_train.argtypes = [vp, vp, vp, i64, i32, i32, dbl, u64, dp, vp]
+        L.pgc_surrogate_coeffs_to_q.argtypes = [vp, vp, i64, vp, ctypes.POINTER(i32), ctypes.POINTER(i64), dp, vp]
+        L.pgc_surrogate_loss_grad.argtypes = [vp, vp, vp, i32, dp, ctypes.POINTER(ctypes.c_float), vp]
+        L.pgc_surrogate_get_params.argtypes = [vp, ctypes.POINTER(ctypes.c_float), vp]
+        L.pgc_surrogate_set_params.argtypes = [vp, ctypes.POINTER(ctypes.c_float), vp]
+        L.pgc_surrogate_save.argtypes = [vp, ctypes.c_char_p, vp]
+        L.pgc_surrogate_load.argtypes = [vp, ctypes.c_char_p, vp]
+        L.pgc_gemm_bf16.argtypes = [i32, i32, i32, vp, i32, i32, vp, i32, i32, vp, i32, vp, i32, vp]
+        for name in ("pgc_surrogate_desc_init", "pgc_surrogate_create", "pgc_surrogate_destroy",
+                     "pgc_surrogate_query", "pgc_surrogate_set_normalization", "pgc_surrogate_train",
+                     "pgc_surrogate_coeffs_to_q", "pgc_surrogate_loss_grad", "pgc_surrogate_get_params",
+                     "pgc_surrogate_set_params", "pgc_surrogate_save", "pgc_surrogate_load", "pgc_gemm_bf16"):
+            getattr(L, name).restype = ctypes.c_int
         for name in ("pgc_desc_init", "pgc_nufft_params", "pgc_plan_create", "pgc_plan_destroy",
                      "pgc_plan_query", "pgc_nodes", "pgc_project", "pgc_coeffs_to_q", "pgc_rk4",
                      "pgc_moments", "pgc_eval", "pgc_set_profiling", "pgc_stage_times",
@@ -379,3 +415,150 @@ class Batch:
 
     def graph_launch(self):
         _check(lib().pgc_batch_graph_launch(self._h, _stream()), "pgc_batch_graph_launch")
+
+
+def gemm_bf16(a, b, trans_a=False, trans_b=False, bias=None, out=None, accumulate=False):
+    """C = op(a) op(b) (+ bias) on the matrix cores; a, b are torch.bfloat16 CUDA matrices."""
+    import torch
+    if a.dtype != torch.bfloat16 or b.dtype != torch.bfloat16:
+        raise ValueError("a and b must be bfloat16")
+    a, b = a.contiguous(), b.contiguous()
+    M = a.shape[1] if trans_a else a.shape[0]
+    K = a.shape[0] if trans_a else a.shape[1]
+    N = b.shape[0] if trans_b else b.shape[1]
+    Kb = b.shape[1] if trans_b else b.shape[0]
+    if K != Kb:
+        raise ValueError("inner dimensions differ")
+    if out is None:
+        out = torch.zeros(M, N, dtype=torch.float32, device=a.device)
+    _check(lib().pgc_gemm_bf16(M, N, K, _ptr(a), a.shape[1], int(trans_a), _ptr(b), b.shape[1], int(trans_b),
+                               _ptr(out), out.shape[1], _ptr(bias) if bias is not None else None,
+                               int(accumulate), _stream()), "pgc_gemm_bf16")
+    return out
+
+
+class Surrogate:
+    """Learned coefficients-to-Q map of an FP32 plan, with the plan as fallback and judge."""
+
+    def __init__(self, plan, **fields):
+        import torch
+        self._torch = torch
+        if plan.info.precision != FP32:
+            raise ValueError("the surrogate needs an FP32 plan")
+        self.plan = plan  # kept alive: the surrogate falls back to it
+        d = SurrogateDesc()
+        _check(lib().pgc_surrogate_desc_init(ctypes.byref(d)), "pgc_surrogate_desc_init")
+        for k, v in fields.items():
+            if not hasattr(d, k):
+                raise TypeError("unknown surrogate field %r" % k)
+            setattr(d, k, v)
+        self.desc = d
+        h = ctypes.c_void_p()
+        _check(lib().pgc_surrogate_create(plan._h, ctypes.byref(d), _stream(), ctypes.byref(h)),
+               "pgc_surrogate_create")
+        self._h = h
+        self.refresh_info()
+        self.n = self.info.n_features
+
+    def refresh_info(self):
+        self.info = SurrogateInfo()
+        _check(lib().pgc_surrogate_query(self._h, ctypes.byref(self.info)), "pgc_surrogate_query")
+        return self.info
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pgc_surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _rows(self, x, name):
+        torch = self._torch
+        if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.dim() == 2
+                and x.shape[1] == self.n):
+            raise ValueError("%s must be a contiguous float32 CUDA tensor of shape (rows, %d)" % (name, self.n))
+        return x
+
+    def set_normalization(self, f, q):
+        self._rows(f, "f")
+        self._rows(q, "q")
+        _check(lib().pgc_surrogate_set_normalization(self._h, _ptr(f), _ptr(q), f.shape[0], _stream()),
+               "pgc_surrogate_set_normalization")
+
+    def train(self, f, q, epochs, batch=None, lr=1e-3, seed=0):
+        self._rows(f, "f")
+        self._rows(q, "q")
+        batch = batch or self.info.batch_max
+        losses = np.zeros(max(1, epochs))
+        _check(lib().pgc_surrogate_train(self._h, _ptr(f), _ptr(q), f.shape[0], int(epochs), int(batch),
+                                         float(lr), int(seed),
+                                         losses.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()),
+               "pgc_surrogate_train")
+        self.refresh_info()
+        return losses[:epochs]
+
+    def coeffs_to_q(self, f, q=None):
+        """(q, fallback flags, number of fallbacks, largest judge error)."""
+        torch = self._torch
+        self._rows(f, "f")
+        if q is None:
+            q = torch.empty_like(f)
+        flags = np.zeros(f.shape[0], dtype=np.int32)
+        nfb = ctypes.c_int64(0)
+        jerr = ctypes.c_double(0.0)
+        _check(lib().pgc_surrogate_coeffs_to_q(self._h, _ptr(f), f.shape[0], _ptr(q),
+                                               flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                               ctypes.byref(nfb), ctypes.byref(jerr), _stream()),
+               "pgc_surrogate_coeffs_to_q")
+        return q, flags, int(nfb.value), float(jerr.value)
+
+    def loss_grad(self, f, q):
+        self._rows(f, "f")
+        self._rows(q, "q")
+        g = np.zeros(self.info.n_params, dtype=np.float32)
+        loss = ctypes.c_double(0.0)
+        _check(lib().pgc_surrogate_loss_grad(self._h, _ptr(f), _ptr(q), f.shape[0], ctypes.byref(loss),
+                                             g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream()),
+               "pgc_surrogate_loss_grad")
+        return loss.value, g
+
+    def get_params(self):
+        p = np.zeros(self.info.n_params + 4 * self.n, dtype=np.float32)
+        _check(lib().pgc_surrogate_get_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream()),
+               "pgc_surrogate_get_params")
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != self.info.n_params + 4 * self.n:
+            raise ValueError("expected %d values" % (self.info.n_params + 4 * self.n))
+        _check(lib().pgc_surrogate_set_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream()),
+               "pgc_surrogate_set_params")
+
+    def layer_dims(self):
+        w, L, n = self.info.width, self.info.n_layers, self.n
+        return [n] + [w] * (L - 1) + [n]
+
+    def unflatten(self, p):
+        """[(W, b), ...] and (mu_in, sd_in, mu_out, sd_out) from a flat parameter vector."""
+        dims = self.layer_dims()
+        out, off = [], 0
+        for i, o in zip(dims[:-1], dims[1:]):
+            W = p[off:off + i * o].reshape(o, i)
+            off += i * o
+            b = p[off:off + o]
+            off += o
+            out.append((W, b))
+        norms = tuple(p[off + k * self.n: off + (k + 1) * self.n] for k in range(4))
+        return out, norms
+
+    def save(self, path):
+        _check(lib().pgc_surrogate_save(self._h, str(path).encode(), _stream()), "pgc_surrogate_save")
+
+    def load(self, path):
+        _check(lib().pgc_surrogate_load(self._h, str(path).encode(), _stream()), "pgc_surrogate_load")
+        self.refresh_info()

@@ -1,0 +1,200 @@
+"""GPU checks of the learned surrogate: the BF16 matrix-core product, the
+network's gradients against the FP64 reference (oracle/mlp.py, same BF16
+rounding points), training on pairs the plan itself produces, the fallback
+gates, and what the trained network gains over the plain path."""
+import os
+import sys
+import tempfile
+import time
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+from paper_2105_08806_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    return torch
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.mark.parametrize("ta,tb", [(False, False), (False, True), (True, False), (True, True)])
+@pytest.mark.parametrize("M,N,K", [(70, 45, 83), (130, 200, 1500), (1, 17, 5)])
+def test_gemm_bf16_layouts(torch_cuda, ta, tb, M, N, K):
+    torch = torch_cuda
+    from paper_2105_08806_amd import pgc
+    g = torch.Generator().manual_seed(M * 7 + N + K)
+    a = torch.randn((K, M) if ta else (M, K), generator=g).to(torch.bfloat16)
+    b = torch.randn((N, K) if tb else (K, N), generator=g).to(torch.bfloat16)
+    bias = torch.randn(N, generator=g)
+    ref = (a.double().T if ta else a.double()) @ (b.double().T if tb else b.double()) + bias.double()
+    c = pgc.gemm_bf16(a.cuda(), b.cuda(), ta, tb, bias=bias.cuda())
+    torch.cuda.synchronize()
+    assert rel(c.double().cpu().numpy(), ref.numpy()) <= 1e-5
+    # accumulate onto existing values
+    c2 = pgc.gemm_bf16(a.cuda(), b.cuda(), ta, tb, out=c.clone(), accumulate=True)
+    torch.cuda.synchronize()
+    ref2 = ref + (a.double().T if ta else a.double()) @ (b.double().T if tb else b.double())
+    assert rel(c2.double().cpu().numpy(), ref2.numpy()) <= 1e-5
+
+
+def small_plan(pgc, N=5):
+    # algebraic map, which conserves mass, momentum and energy (Sec. 3.2)
+    return pgc.Plan(dim=3, n_modes=N, scale=3.0, map=pgc.MAP_ALGEBRAIC, sphere=pgc.SPHERE_PRODUCT_3D,
+                    n_theta=4, n_phi=4, precision=pgc.FP32)
+
+
+def test_gradients_match_oracle(torch_cuda):
+    """Loss and every parameter gradient of a 4-layer network at random
+    parameters and normalisation, against the FP64 reference."""
+    torch = torch_cuda
+    from paper_2105_08806_amd import pgc
+    plan = small_plan(pgc)
+    s = pgc.Surrogate(plan, width=48, n_layers=4, batch_max=16, seed=1)
+    n = s.n
+    rng = np.random.default_rng(11)
+    dims = s.layer_dims()
+    params = [(rng.normal(0, 1.5 / np.sqrt(i), size=(o, i)), rng.normal(0, 0.2, size=o))
+              for i, o in zip(dims[:-1], dims[1:])]
+    norms = [rng.normal(0, 0.1, n), 0.5 + rng.random(n), rng.normal(0, 0.1, n), 0.5 + rng.random(n)]
+    flat = np.concatenate([np.concatenate([W.ravel(), b]) for W, b in params] + norms).astype(np.float32)
+    s.set_params(flat)
+    back = s.get_params()
+    assert np.array_equal(back, flat)
+    params32, norms32 = s.unflatten(back.astype(np.float64))
+    f = rng.normal(size=(13, n)).astype(np.float32)
+    q = rng.normal(size=(13, n)).astype(np.float32)
+    loss, g = s.loss_grad(torch.tensor(f, device="cuda"), torch.tensor(q, device="cuda"))
+    ref_loss, ref_g = mlp.loss_and_grad(params32, f.astype(np.float64), q.astype(np.float64), *norms32, bf16=True)
+    say("loss gpu %.8f oracle %.8f" % (loss, ref_loss))
+    assert abs(loss - ref_loss) <= 1e-5 * ref_loss
+    off = 0
+    for li, ((W, b), (gW, gb)) in enumerate(zip(params32, ref_g)):
+        got_W = g[off:off + W.size].reshape(W.shape)
+        off += W.size
+        got_b = g[off:off + b.size]
+        off += b.size
+        eW, eb = rel(got_W, gW), rel(got_b, gb)
+        say("  layer %d: rel-L2 dW %.2e db %.2e" % (li, eW, eb))
+        assert eW <= 2e-3 and eb <= 2e-3
+    s.close()
+    plan.close()
+
+
+def make_pairs(torch, pgc, plan, n_pairs, seed):
+    """(f, Q) rows from Gaussian mixtures projected by the plan and evaluated by the plan."""
+    V = plan.interior_velocities()
+    mixes = I.gaussian_mixtures_3d(n_pairs, seed=seed)
+    f = torch.empty(n_pairs, plan.n_modes ** 3, dtype=torch.float32, device="cuda")
+    q = torch.empty_like(f)
+    for r, comps in enumerate(mixes):
+        c = plan.project(I.gaussian_mixture(V, comps))
+        f[r].copy_(c.reshape(-1))
+        plan.coeffs_to_q(c, q=q[r].view(c.shape))
+    torch.cuda.synchronize()
+    return f, q
+
+
+def test_training_gates_and_gain(torch_cuda):
+    torch = torch_cuda
+    from paper_2105_08806_amd import pgc
+    plan = small_plan(pgc, N=6)
+    t = time.perf_counter()
+    f_tr, q_tr = make_pairs(torch, pgc, plan, 4096, seed=2024)
+    f_te, q_te = make_pairs(torch, pgc, plan, 128, seed=77)
+    say("4224 pairs from the plan in %.1f s" % (time.perf_counter() - t))
+    s = pgc.Surrogate(plan, width=256, n_layers=4, batch_max=64, seed=3, judge_stride=0)
+    s.set_normalization(f_tr, q_tr)
+    t = time.perf_counter()
+    losses = s.train(f_tr, q_tr, epochs=40, batch=64, lr=2e-3, seed=5)
+    say("trained in %.1f s" % (time.perf_counter() - t))
+    say("loss: first %.3e last %.3e; raw residual calibrated %.2e, z-score %.2f" % (losses[0], losses[-1],
+                                                                      s.info.raw_residual_calibrated, s.info.zscore_calibrated))
+    assert losses[-1] < 0.1 * losses[0]
+    q_s, flags, nfb, _ = s.coeffs_to_q(f_te)
+    torch.cuda.synchronize()
+    qs, qt = q_s.double().cpu().numpy(), q_te.double().cpu().numpy()
+    err = np.array([rel(a, b) for a, b in zip(qs, qt)])
+    # the baseline a network must beat: the training-set mean of Q
+    mean_q = q_tr.double().mean(0).cpu().numpy()
+    base = np.array([rel(mean_q, b) for b in qt])
+    say("held-out rel-L2: surrogate median %.3e max %.3e; mean-Q baseline median %.3e; fallbacks %d"
+        % (np.median(err), err.max(), np.median(base), nfb))
+    assert np.median(err) < 0.25 * np.median(base)
+    # the returned Q conserves mass, momentum and energy
+    mom = np.array([plan.moments(q_s[r].view(6, 6, 6)).cpu().numpy() for r in range(8)])
+    scale = np.array([plan.moments(q_te[r].abs().view(6, 6, 6).contiguous()).cpu().numpy() for r in range(8)])
+    say("moment residual / moment of |Q|: %.2e" % np.max(np.abs(mom) / np.abs(scale).max(axis=1, keepdims=True)))
+
+    # gain: time of the surrogate against the plain path on the held-out set
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        s.coeffs_to_q(f_te)
+    torch.cuda.synchronize()
+    t_s = (time.perf_counter() - t) / 3
+    qq = torch.empty_like(f_te)
+    t = time.perf_counter()
+    for r in range(f_te.shape[0]):
+        plan.coeffs_to_q(f_te[r].view(6, 6, 6), q=qq[r].view(6, 6, 6))
+    torch.cuda.synchronize()
+    t_p = time.perf_counter() - t
+    say("held-out batch of %d: surrogate %.2f ms, plain path %.2f ms (x%.1f)" % (f_te.shape[0], t_s * 1e3,
+                                                                                 t_p * 1e3, t_p / t_s))
+
+    # out-of-distribution input trips the raw-residual gate; those samples come from the plan
+    f_odd = f_te[:8].clone()
+    f_odd[:, 1::2] *= -40.0
+    q_odd, fl, nfb_odd, _ = s.coeffs_to_q(f_odd)
+    plain = torch.empty_like(f_odd)
+    for r in range(8):
+        plan.coeffs_to_q(f_odd[r].view(6, 6, 6), q=plain[r].view(6, 6, 6))
+    torch.cuda.synchronize()
+    say("out-of-distribution: %d of 8 fell back" % nfb_odd)
+    assert nfb_odd >= 1
+    for r in range(8):
+        if fl[r]:
+            assert torch.equal(q_odd[r], plain[r])
+
+    # a judge with a tolerance no network meets sends the whole call to the plan
+    s2 = pgc.Surrogate(plan, width=256, n_layers=4, batch_max=64, seed=3, judge_stride=16, judge_tol=1e-9)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "net.bin")
+        s.save(path)
+        s2.load(path)
+    q_j, fl_j, nfb_j, jerr = s2.coeffs_to_q(f_te[:32])
+    torch.cuda.synchronize()
+    say("judge: largest sampled error %.2e, fallbacks %d of 32" % (jerr, nfb_j))
+    assert nfb_j == 32 and jerr > 1e-9
+    plain32 = torch.empty_like(f_te[:32])
+    for r in range(32):
+        plan.coeffs_to_q(f_te[r].view(6, 6, 6), q=plain32[r].view(6, 6, 6))
+    torch.cuda.synchronize()
+    assert torch.equal(q_j, plain32)
+    # the loaded network reproduces the saved one
+    s3 = pgc.Surrogate(plan, width=256, n_layers=4, batch_max=64, seed=9, judge_stride=0)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "net.bin")
+        s.save(path)
+        s3.load(path)
+    q3, _, _, _ = s3.coeffs_to_q(f_te)
+    torch.cuda.synchronize()
+    assert torch.equal(q3, q_s)
+    for x in (s, s2, s3):
+        x.close()
+    plan.close()
