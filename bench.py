@@ -117,6 +117,174 @@ def cpu_baseline(inputs, budget_s=15.0):
                       "%.1f s, scaled to one full evaluation (%.0f s)" % (k, n_units, dt, per_eval)}
 
 
+def batched_variant(torch, pgc, inputs, np, n_cells, reps):
+    """The batched workload: n_cells 2D velocity cells, N drawn from {32, 48, 64},
+    S = 6, Maxwell, 32 directions, each cell a Maxwellian with a 5% Hermite
+    perturbation; one batched evaluation per step, replayed from a HIP graph.
+    Near equilibrium Q is 1-5% of Q+, so the transform tolerance is 1e-8
+    (kernel width 7).  Accuracy: sampled cells against the FP64 single-cell
+    path; the plain FP64 time of the whole batch is estimated from timed cells
+    of every N."""
+    S, M, tol = 6.0, 32, 1e-8
+    cells = inputs.cell_maxwellians_2d(n_cells, seed=8806)
+    t0 = time.time()
+    plans = {N: pgc.Plan(dim=2, n_modes=N, scale=S, n_sigma=M, precision=pgc.FP64) for N in (32, 48, 64)}
+    V = {N: plans[N].interior_velocities() for N in plans}
+    coeffs = [plans[c["N"]].project(inputs.perturbed_maxwellian_2d(V[c["N"]], c)) for c in cells]
+    packed = torch.cat([c.float().reshape(-1) for c in coeffs])
+    b = pgc.Batch([c["N"] for c in cells], scale=S, n_sigma=M, nufft_tol=tol)
+    q = torch.empty_like(packed)
+    b.capture(packed, q)
+    b.graph_launch()
+    torch.cuda.synchronize()
+    log("batched: %d cells ready in %.1f s: W=%d, C=%d (tuned ms %s), %d units, %.3e points" % (
+        n_cells, time.time() - t0, b.info.kernel_width, b.info.cells_per_wave,
+        [round(x, 1) for x in b.info.tuned_ms], b.info.n_units, b.info.n_points))
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for r in range(reps):
+        b.graph_launch()
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    log("batched: %.1f ms per evaluation of %d cells" % (ms, n_cells))
+    qs = b.unpack(q)
+    errs, t_cell = [], {}
+    for N in (32, 48, 64):
+        picks = [i for i, c in enumerate(cells) if c["N"] == N][:3]
+        for i in picks:
+            ref = plans[N].coeffs_to_q(coeffs[i].float().double().contiguous())
+            torch.cuda.synchronize()
+            t = time.time()
+            for _ in range(2):
+                plans[N].coeffs_to_q(coeffs[i])
+            torch.cuda.synchronize()
+            t_cell.setdefault(N, []).append((time.time() - t) / 2)
+            errs.append(float(np.linalg.norm(qs[i] - ref.cpu().numpy()) / np.linalg.norm(ref.cpu().numpy())))
+    counts = {N: sum(1 for c in cells if c["N"] == N) for N in (32, 48, 64)}
+    fp64_s = sum(counts[N] * min(t_cell[N]) for N in counts)
+    out = {"value": n_cells / (ms / 1e3), "unit": "cell Q-evals/s", "ms_per_eval": ms,
+           "workload": "2D batch of %d cells, N from {32,48,64} (%s), S=6, Maxwell, 32 directions, "
+                       "perturbed Maxwellians, FP32 gain (W=%d), graph replay" % (
+                           n_cells, counts, b.info.kernel_width),
+           "rel_l2_vs_fp64_path_max": max(errs), "cells_checked": len(errs),
+           "plain_fp64_est_s_per_batch": fp64_s, "speedup_vs_plain_fp64": fp64_s / (ms / 1e3),
+           "cells_per_wave": b.info.cells_per_wave, "points_per_s": b.info.n_points / (ms / 1e3)}
+    b.close()
+    for p in plans.values():
+        p.close()
+    return out
+
+
+def symmetric_copies(torch, f, N):
+    """The 16 images of coefficient rows under the symmetries of the 8 x 8
+    product rule: v_l -> -v_l (c_k -> (-1)^k_l c_k) and v_1 <-> v_2."""
+    x = f.view(-1, N, N, N)
+    sign = (1.0 - 2.0 * (torch.arange(N, device=f.device) % 2)).to(f.dtype)
+    out = []
+    for swap in (False, True):
+        y = x.transpose(1, 2) if swap else x
+        for m in range(8):
+            z = y
+            if m & 1:
+                z = z * sign.view(1, N, 1, 1)
+            if m & 2:
+                z = z * sign.view(1, 1, N, 1)
+            if m & 4:
+                z = z * sign.view(1, 1, 1, N)
+            out.append(z.reshape(-1, N ** 3))
+    return torch.cat(out).contiguous()
+
+
+def surrogate_variant(torch, pgc, inputs, np, n_pairs, epochs):
+    """The learned surrogate: 3D, N = 24, algebraic map, S = 5, Maxwell, the
+    8 x 8 product rule; a 4-layer MLP of width 1024 (BF16 matrix cores) trained
+    on n_pairs pairs from the FP32 plan on mixtures of 2-4 anisotropic
+    Gaussians, each pair used with its 16 exact symmetric images.  Reports the
+    held-out error against the plain path, the fallback count under the gates
+    and the judge, and the throughput of both."""
+    N = 24
+    t0 = time.time()
+    plan = pgc.Plan(dim=3, n_modes=N, scale=5.0, map=pgc.MAP_ALGEBRAIC, sphere=pgc.SPHERE_PRODUCT_3D,
+                    n_theta=8, n_phi=8, precision=pgc.FP32)
+    V = plan.interior_velocities()
+
+    def pairs(n, seed):
+        f = torch.empty(n, N ** 3, dtype=torch.float32, device="cuda")
+        q = torch.empty_like(f)
+        for r, comps in enumerate(inputs.gaussian_mixtures_3d(n, seed=seed)):
+            c = plan.project(inputs.gaussian_mixture(V, comps))
+            f[r].copy_(c.reshape(-1))
+            plan.coeffs_to_q(c, q=q[r].view(N, N, N))
+            if r % 512 == 511:
+                torch.cuda.synchronize()
+                log("  surrogate: %d pairs" % (r + 1))
+        torch.cuda.synchronize()
+        return f, q
+
+    f_tr, q_tr = pairs(n_pairs, 2024)
+    f_te, q_te = pairs(128, 77)
+    t_gen = time.time() - t0
+    fa, qa = symmetric_copies(torch, f_tr, N), symmetric_copies(torch, q_tr, N)
+    s = pgc.Surrogate(plan, width=1024, n_layers=4, batch_max=256, seed=3)
+    s.set_normalization(fa, qa)
+    t = time.time()
+    losses = s.train(fa, qa, epochs=epochs, batch=256, lr=1e-3, seed=5)
+    torch.cuda.synchronize()
+    t_train = time.time() - t
+    log("surrogate: %d pairs (x16 images) in %.1f s, %d epochs in %.1f s, loss %.3e -> %.3e" % (
+        n_pairs, t_gen, epochs, t_train, losses[0], losses[-1]))
+    # accuracy of the network alone (judge and gates off) on held-out pairs
+    raw = pgc.Surrogate(plan, width=1024, n_layers=4, batch_max=256, seed=3, judge_stride=0,
+                        gate_raw_factor=0.0, gate_residual=1.0)
+    raw.set_params(s.get_params())
+    q_net, _, _, _ = raw.coeffs_to_q(f_te)
+    torch.cuda.synchronize()
+    err = [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in
+           zip(q_net.double().cpu().numpy(), q_te.double().cpu().numpy())]
+    # the surrogate as deployed: gates and judge on
+    torch.cuda.synchronize()
+    t = time.time()
+    q_dep, flags, nfb, jerr = s.coeffs_to_q(f_te)
+    torch.cuda.synchronize()
+    t_dep = time.time() - t
+    t = time.time()
+    for _ in range(3):
+        raw.coeffs_to_q(f_te)
+    torch.cuda.synchronize()
+    t_net = (time.time() - t) / 3
+    qq = torch.empty_like(f_te)
+    t = time.time()
+    for r in range(32):
+        plan.coeffs_to_q(f_te[r].view(N, N, N), q=qq[r].view(N, N, N))
+    torch.cuda.synchronize()
+    t_plain = (time.time() - t) / 32
+    p64 = pgc.Plan(dim=3, n_modes=N, scale=5.0, map=pgc.MAP_ALGEBRAIC, sphere=pgc.SPHERE_PRODUCT_3D,
+                   n_theta=8, n_phi=8, precision=pgc.FP64)
+    c64 = f_te[0].double().view(N, N, N).contiguous()
+    p64.coeffs_to_q(c64)
+    torch.cuda.synchronize()
+    t = time.time()
+    for _ in range(2):
+        p64.coeffs_to_q(c64)
+    torch.cuda.synchronize()
+    t_fp64 = (time.time() - t) / 2
+    out = {"value": f_te.shape[0] / t_dep, "unit": "Q-evals/s (gates and judge on)",
+           "network_only_evals_per_s": f_te.shape[0] / t_net,
+           "plain_fp32_evals_per_s": 1.0 / t_plain, "plain_fp64_evals_per_s": 1.0 / t_fp64,
+           "speedup_vs_plain_fp64": (f_te.shape[0] / t_dep) * t_fp64,
+           "network_rel_l2_vs_plain_median": float(np.median(err)), "network_rel_l2_vs_plain_max": max(err),
+           "fallbacks": nfb, "of": int(f_te.shape[0]), "judge_max_rel_err": jerr,
+           "training_pairs": n_pairs, "symmetric_images": 16, "epochs": epochs,
+           "loss_first_last": [float(losses[0]), float(losses[-1])],
+           "pair_generation_s": t_gen, "training_s": t_train,
+           "workload": "3D N=24 (13824 coeffs), algebraic map, S=5, Maxwell, 8x8 product rule; MLP "
+                       "13824-1024-1024-1024-13824 (BF16 MFMA, FP32 accumulation)"}
+    for x in (s, raw, p64, plan):
+        x.close()
+    return out
+
+
 def bkw_curve(torch, pgc, inputs, np, steps=20):
     """3D BKW: RK4 from t = 6.5 with dt = 0.1 for `steps` steps in FP64 and FP32.
     Prints, per step, the rel-L2 distance of each state from the projection of
@@ -151,6 +319,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp32-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--batch-cells", type=int, default=4096)
+    ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--surrogate-pairs", type=int, default=1024)
+    ap.add_argument("--surrogate-epochs", type=int, default=30)
     ap.add_argument("--mode", choices=["bench", "profile", "copy", "bkw"], default="bench",
                     help="profile: two evaluations per precision (for rocprofv3); "
                          "copy: a 1 GiB device copy (calibrates the HBM byte counters); "
@@ -230,6 +404,11 @@ def main():
         },
         "moments_fp64_final": r64["moments"],
     }
+    if not args.no_batched:
+        line["variants"]["batched"] = batched_variant(torch, pgc, inputs, np, args.batch_cells, args.batch_reps)
+    if not args.no_surrogate:
+        line["variants"]["surrogate"] = surrogate_variant(torch, pgc, inputs, np, args.surrogate_pairs,
+                                                          args.surrogate_epochs)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inputs)
     print(json.dumps(line), flush=True)
