@@ -225,13 +225,16 @@ typedef struct pgc_batch_info {
     int32_t group_cells[8];     /* cells in each group */
     int64_t coeffs_total;       /* length of the dense packing, sum of N_c^2 */
     int32_t kernel_width;       /* W of the spreading kernel (the same for every N) */
-    int32_t cells_per_wave;     /* C: cells a gain work unit serves (1, 2, 4 or 8) */
+    int32_t cells_per_wave;     /* C: cells a gain work unit serves: 1, 2, 4, 8 (register tiles,
+                                   each lane generates points for its C cells) or 16, 32, 64
+                                   (lane per cell, 64 / C point streams per wave) */
     int32_t waves;              /* persistent 64-lane workgroups of the gain launch */
     int64_t n_units;            /* gain work units per evaluation */
     int64_t n_points;           /* merged transform points over all cells */
     int64_t workspace_bytes;    /* device memory owned by the batch and its plans */
-    double tuned_ms[4];         /* autotuner: gain time for C = 1, 2, 4, 8 (0 = not tried) */
+    double tuned_ms[7];         /* autotuner: gain time for C = 1, 2, 4, 8, 16, 32, 64 (0 = not tried) */
     int32_t has_graph;          /* a captured graph is ready for pgc_batch_graph_launch */
+    int32_t scheme;             /* 0 register tiles, 1 lane per cell */
 } pgc_batch_info;
 
 /* Build a batch of n_cells cells; n_modes_host[c] is the N of cell c.
@@ -247,7 +250,7 @@ pgc_status pgc_batch_destroy(pgc_batch batch);
 pgc_status pgc_batch_query(pgc_batch batch, pgc_batch_info* info);
 /* The n_cells offsets of the dense packing (host array). */
 pgc_status pgc_batch_offsets(pgc_batch batch, int64_t* offsets_host);
-/* Force C cells per work unit (1, 2, 4 or 8, subject to C W^2 <= 200), or re-run
+/* Force C cells per work unit (1, 2, 4 or 8 with C W^2 <= 200, or 16, 32, 64), or re-run
  * the autotuner.  Both drop a captured graph and synchronise `stream`. */
 pgc_status pgc_batch_set_tile(pgc_batch batch, int32_t cells_per_wave, void* stream);
 pgc_status pgc_batch_autotune(pgc_batch batch, void* stream);

@@ -7,10 +7,13 @@
 // every cell with the same N shares one plan: its node tables, its sphere rule
 // and its plan-time bin index.  Only the orbit-sum weight of a point differs
 // between cells.  One work unit of the gain is (bin run, group of C cells of
-// one N): each lane regenerates points of the run once, forms C orbit sums and
-// accumulates C private W x W footprint tiles in registers; a single
-// persistent launch pulls the units of every N group from one counter, the
-// longest runs first.  The dense stages (synthesis, loss, grid to modes) are
+// one N).  Two schemes: register tiles (each lane regenerates points of the
+// run, forms C orbit sums and accumulates C private W x W footprint tiles), and
+// lane per cell (the wave stages the geometry of 64 points in LDS once and
+// each lane accumulates the tile of its own cell over every staged point,
+// reading its cell's G from a cell-minor copy, so 64 cells share one
+// geometry).  A single persistent launch pulls the units of every N group from
+// one counter, the longest runs first; the autotuner picks the scheme and C.  The dense stages (synthesis, loss, grid to modes) are
 // batched contractions over the cells of each group, in FP64.
 #include <hip/hip_runtime.h>
 
@@ -36,8 +39,10 @@ struct GroupDev {
     const int* item_count;
     const unsigned long long* ids;
     const float* Gg;     // n_cells x nid, G of every cell rounded to FP32
+    const float* Gt;     // nid x ldg, the same with the cell index fastest
     double* grid;        // n_cells x ngd FP64 fine grids
     int nb, off, n_cells, ncg;  // ncg = cell groups of C cells
+    int ldg;             // row length of Gt (n_cells rounded up to 64)
     int64_t nid, ngd, unit_begin;
 };
 
@@ -141,6 +146,138 @@ __global__ void __launch_bounds__(64) gain_batched(const GroupDev* __restrict__ 
     }
 }
 
+// Lane-per-cell scheme: CW cells per wave, NS = 64 / CW point streams.  Lane
+// l serves cell c = C0 + l % CW and the staged points j = l / CW (mod NS).
+// The geometry of each 64-point batch is generated once (lane = point) and
+// read from LDS by every cell; a batch and the batch sums are summed in FP32
+// (at most 64 and 128 terms), the streams and the grid in FP64.
+template <int W, int CW>
+__global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restrict__ groups, int n_groups,
+                                                         unsigned long long n_units,
+                                                         unsigned long long* __restrict__ counter)
+{
+    constexpr int TERMS = W + 2;
+    constexpr int CELLS = W * W;
+    constexpr int NS = 64 / CW;
+    __shared__ float sq[64];
+    __shared__ float sk[64][2 * W];
+    __shared__ int sx[64][4];
+    __shared__ double red[(NS > 1) ? (NS - 1) * CW * CELLS : 1];
+    // the kernel polynomial depends on W and the upsampling only, the same for
+    // every group: read from LDS it is not hoisted into registers
+    __shared__ double spoly[TERMS * W];
+    const int lane = threadIdx.x;
+    const int cl = lane % CW, stream = lane / CW;
+    const double halfW = 0.5 * W;
+    for (int i = lane; i < TERMS * W; i += 64) spoly[i] = groups[0].gp.poly64[i];
+    __syncthreads();
+
+    for (;;) {
+        unsigned long long u = 0;
+        if (lane == 0) u = atomicAdd(counter, 1ull);
+        u = lane0(u);
+        if (u >= n_units) break;
+        int g = 0;
+        while (g + 1 < n_groups && (long long)u >= groups[g + 1].unit_begin) ++g;
+        const GroupDev& D = groups[g];
+        const long long local = (long long)u - D.unit_begin;
+        const int item = (int)(local / D.ncg);
+        const int c = (int)(local % D.ncg) * CW + cl;
+        const bool valid = c < D.n_cells;
+        const int bin = D.item_bin[item];
+        const long long first = D.item_begin[item];
+        const int n = D.item_count[item];
+        const int t0x = bin / D.nb - D.off;
+        const int t0y = bin % D.nb - D.off;
+        const float* Gt = D.Gt;
+        const int ldg = D.ldg;
+
+        float acc[CELLS];
+#pragma unroll
+        for (int e = 0; e < CELLS; ++e) acc[e] = 0.f;
+
+        for (int base = 0; base < n; base += 64) {
+            const int nv = min(64, n - base);
+            if (lane < nv) {
+                const unsigned long long id = D.ids[first + base + lane];
+                const int b1 = (int)(id & 0xffull), a1 = (int)((id >> 8) & 0xffull);
+                const int s = (int)((id >> 16) & 0x3ffull);
+                const int p2 = (int)((id >> 26) & 0xffffull);
+                float q;
+                double xs[2];
+                int64_t si;
+                point_geometry<float, 2>(D.gp, s, a1, b1, p2, 0, halfW, q, xs, si);
+                float kx[W], ky[W];
+                kernel_cells64<float, W, TERMS>(spoly, 2.0 * ((double)t0x - xs[0]) - 1.0, kx);
+                kernel_cells64<float, W, TERMS>(spoly, 2.0 * ((double)t0y - xs[1]) - 1.0, ky);
+                int ix[2], iy[2];
+                sq[lane] = q * orbit_terms<float, 2>(D.gp, a1, b1, p2, 0, ix, iy);
+#pragma unroll
+                for (int a = 0; a < W; ++a) {
+                    sk[lane][a] = kx[a];
+                    sk[lane][W + a] = ky[a];
+                }
+                sx[lane][0] = ix[0] * ldg;
+                sx[lane][1] = iy[0] * ldg;
+                sx[lane][2] = ix[1] * ldg;
+                sx[lane][3] = iy[1] * ldg;
+            }
+            __syncthreads();
+            if (valid) {
+                float ab[CELLS];
+#pragma unroll
+                for (int e = 0; e < CELLS; ++e) ab[e] = 0.f;
+#pragma unroll 2
+                for (int j = stream; j < nv; j += NS) {
+                    const float w =
+                        sq[j] * fmaf(Gt[sx[j][0] + c], Gt[sx[j][1] + c], Gt[sx[j][2] + c] * Gt[sx[j][3] + c]);
+#pragma unroll
+                    for (int a = 0; a < W; ++a) {
+                        const float t = w * sk[j][a];
+#pragma unroll
+                        for (int b = 0; b < W; ++b) ab[a * W + b] = fmaf(t, sk[j][W + b], ab[a * W + b]);
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < CELLS; ++e) acc[e] += ab[e];
+            }
+            __syncthreads();
+        }
+
+        if constexpr (NS > 1) {
+            if (stream > 0) {
+#pragma unroll
+                for (int e = 0; e < CELLS; ++e) red[((stream - 1) * CW + cl) * CELLS + e] = (double)acc[e];
+            }
+            __syncthreads();
+        }
+        if (stream == 0 && valid) {
+            double* grid = D.grid + (int64_t)c * D.ngd;
+            for (int e = 0; e < CELLS; ++e) {
+                double v = (double)acc[e];
+                for (int r = 1; r < NS; ++r) v += red[((r - 1) * CW + cl) * CELLS + e];
+                if (v != 0.0) {
+                    const int64_t cell = (int64_t)fold_index(t0x + e / W, D.gp.nh) * D.gp.ng +
+                                         fold_index(t0y + e % W, D.gp.nh);
+                    __hip_atomic_fetch_add(grid + cell, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+        if constexpr (NS > 1) __syncthreads();
+    }
+}
+
+// Gt[node][c] = Gg[c][node] for the cell-minor copy read by the lane-per-cell scheme
+__global__ void transpose_g(const float* __restrict__ Gg, float* __restrict__ Gt, int n_cells, int64_t nid,
+                            int ldg)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= nid * ldg) return;
+    const int c = (int)(e % ldg);
+    const int64_t node = e / ldg;
+    Gt[e] = c < n_cells ? Gg[(int64_t)c * nid + node] : 0.f;
+}
+
 __global__ void reset_counter(unsigned long long* __restrict__ counter)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0ull;
@@ -182,10 +319,12 @@ __global__ void batch_scatter(const double* __restrict__ qp, const double* __res
 
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// the cells-per-wave values the gain kernel is built for, by kernel width
+// the cells-per-wave values the gain kernels are built for, by kernel width:
+// C = 1, 2, 4, 8 register tiles (C W^2 <= 200), C = 16, 32, 64 lane per cell
 bool tile_supported(int W, int C)
 {
     if (W < 4 || W > 8) return false;
+    if (C == 16 || C == 32 || C == 64) return true;
     if (C != 1 && C != 2 && C != 4 && C != 8) return false;
     return C * W * W <= 200;
 }
@@ -203,11 +342,23 @@ hipError_t gain_launch_wc(const GroupDev* groups, int n_groups, unsigned long lo
     }
 }
 
+template <int W, int CW>
+hipError_t lanes_launch(const GroupDev* groups, int n_groups, unsigned long long n_units,
+                        unsigned long long* counter, int waves, hipStream_t s)
+{
+    hipLaunchKernelGGL((gain_batched_lanes<W, CW>), dim3(waves), dim3(64), 0, s, groups, n_groups, n_units,
+                       counter);
+    return hipGetLastError();
+}
+
 template <int W>
 hipError_t gain_launch_w(int C, const GroupDev* groups, int n_groups, unsigned long long n_units,
                          unsigned long long* counter, int waves, hipStream_t s)
 {
     switch (C) {
+    case 16: return lanes_launch<W, 16>(groups, n_groups, n_units, counter, waves, s);
+    case 32: return lanes_launch<W, 32>(groups, n_groups, n_units, counter, waves, s);
+    case 64: return lanes_launch<W, 64>(groups, n_groups, n_units, counter, waves, s);
     case 1: return gain_launch_wc<W, 1>(groups, n_groups, n_units, counter, waves, s);
     case 2: return gain_launch_wc<W, 2>(groups, n_groups, n_units, counter, waves, s);
     case 4: return gain_launch_wc<W, 4>(groups, n_groups, n_units, counter, waves, s);
@@ -245,10 +396,24 @@ int resident_waves_wc()
     }
 }
 
+template <int W, int CW>
+int resident_waves_lanes()
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gain_batched_lanes<W, CW>, 64, 0) != hipSuccess)
+        return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return std::max(1, per_cu) * std::max(1, cus);
+}
+
 template <int W>
 int resident_waves_w(int C)
 {
     switch (C) {
+    case 16: return resident_waves_lanes<W, 16>();
+    case 32: return resident_waves_lanes<W, 32>();
+    case 64: return resident_waves_lanes<W, 64>();
     case 1: return resident_waves_wc<W, 1>();
     case 2: return resident_waves_wc<W, 2>();
     case 4: return resident_waves_wc<W, 4>();
@@ -311,6 +476,8 @@ struct BatchGroup {
     int* cells_dev = nullptr;
     double* cin = nullptr;    // n_cells x N^d FP64 coefficients
     double* grid = nullptr;   // n_cells x n_g^d
+    float* Gt = nullptr;      // n_i^d x ldg, cell-minor G (lane-per-cell scheme)
+    int ldg = 0;
     pgc::DenseBufs b;
 };
 
@@ -326,7 +493,7 @@ struct pgc_batch_s {
     int C = 0, waves = 0;
     unsigned long long n_units = 0;
     int64_t n_points = 0;
-    double tuned_ms[4] = {0, 0, 0, 0};
+    double tuned_ms[7] = {0, 0, 0, 0, 0, 0, 0};  // C = 1, 2, 4, 8, 16, 32, 64
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<void*> allocations;
@@ -389,6 +556,8 @@ hipError_t set_units(pgc_batch_s& b, int C, hipStream_t s)
         d.item_count = p.bins.item_count;
         d.ids = p.bins.ids;
         d.Gg = static_cast<const float*>(G.b.Gg);
+        d.Gt = G.Gt;
+        d.ldg = G.ldg;
         d.grid = G.grid;
         d.nb = p.bins.nb;
         d.off = p.bins.off;
@@ -416,6 +585,11 @@ hipError_t enqueue_gain(const pgc_batch_s& b, hipStream_t s)
         const Plan& p = G.plan->p;
         const int64_t n = (int64_t)G.cells.size() * p.ngd;
         hipLaunchKernelGGL(pgc::fill_zero64, dim3(pgc::nblocks(n, 256)), dim3(256), 0, s, G.grid, n);
+        if (b.C >= 16) {
+            const int64_t nt = p.nid * G.ldg;
+            hipLaunchKernelGGL(pgc::transpose_g, dim3(pgc::nblocks(nt, 256)), dim3(256), 0, s,
+                               static_cast<const float*>(G.b.Gg), G.Gt, (int)G.cells.size(), p.nid, G.ldg);
+        }
     }
     hipLaunchKernelGGL(pgc::reset_counter, dim3(1), dim3(64), 0, s, b.counter);
     hipError_t e = hipGetLastError();
@@ -451,6 +625,19 @@ hipError_t enqueue_all(const pgc_batch_s& b, const float* packed, const int64_t*
     return hipSuccess;
 }
 
+// the lane-per-cell scheme indexes the cell-minor G with 32-bit offsets
+bool lanes_fit(const pgc_batch_s& b)
+{
+    for (const BatchGroup& G : b.groups)
+        if (G.plan->p.nid * (int64_t)G.ldg >= 2147483647ll) return false;
+    return true;
+}
+
+bool tile_ok(const pgc_batch_s& b, int C)
+{
+    return pgc::tile_supported(b.W, C) && (C < 16 || lanes_fit(b));
+}
+
 // time the gain for every supported C on G = 1 and keep the fastest
 hipError_t autotune(pgc_batch_s& b, hipStream_t s)
 {
@@ -467,12 +654,12 @@ hipError_t autotune(pgc_batch_s& b, hipStream_t s)
         (void)hipEventDestroy(t0);
         return e;
     }
-    const int cands[4] = {1, 2, 4, 8};
+    const int cands[7] = {1, 2, 4, 8, 16, 32, 64};
     int best = 0;
     double best_ms = 0.0;
-    for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+    for (int k = 0; k < 7 && e == hipSuccess; ++k) {
         b.tuned_ms[k] = 0.0;
-        if (!pgc::tile_supported(b.W, cands[k])) continue;
+        if (!tile_ok(b, cands[k])) continue;
         if ((e = set_units(b, cands[k], s)) != hipSuccess) break;
         if ((e = enqueue_gain(b, s)) != hipSuccess) break;  // warm-up
         if ((e = hipEventRecord(t0, s)) != hipSuccess) break;
@@ -569,6 +756,8 @@ pgc_status pgc_batch_create(const pgc_plan_desc* base, int32_t n_cells, const in
         if ((e = batch_alloc_n(*b, &g.b.tmpB, nb * t)) != hipSuccess) break;
         if ((e = batch_alloc_n(*b, &g.b.red, nb)) != hipSuccess) break;
         if ((e = batch_alloc_n(*b, &g.grid, nb * p.ngd)) != hipSuccess) break;
+        g.ldg = (int)((nb + 63) / 64 * 64);
+        if ((e = batch_alloc_n(*b, &g.Gt, p.nid * g.ldg)) != hipSuccess) break;
         if ((e = hipMemcpyAsync(g.cells_dev, g.cells.data(), nb * sizeof(int), hipMemcpyHostToDevice, s)) !=
             hipSuccess)
             break;
@@ -616,7 +805,8 @@ pgc_status pgc_batch_query(pgc_batch b, pgc_batch_info* info)
     info->n_points = b->n_points;
     info->workspace_bytes = b->workspace_bytes;
     for (const BatchGroup& g : b->groups) info->workspace_bytes += g.plan->p.workspace_bytes;
-    for (int k = 0; k < 4; ++k) info->tuned_ms[k] = b->tuned_ms[k];
+    for (int k = 0; k < 7; ++k) info->tuned_ms[k] = b->tuned_ms[k];
+    info->scheme = b->C >= 16 ? 1 : 0;
     info->has_graph = b->exec != nullptr;
     return PGC_OK;
 }
@@ -631,7 +821,7 @@ pgc_status pgc_batch_offsets(pgc_batch b, int64_t* offsets_host)
 pgc_status pgc_batch_set_tile(pgc_batch b, int32_t cells_per_wave, void* stream)
 {
     if (!b) return PGC_ERR_INVALID_ARG;
-    if (!pgc::tile_supported(b->W, cells_per_wave)) return PGC_ERR_UNSUPPORTED;
+    if (!tile_ok(*b, cells_per_wave)) return PGC_ERR_UNSUPPORTED;
     drop_graph(*b);
     return pgc::status_of(set_units(*b, cells_per_wave, static_cast<hipStream_t>(stream)));
 }

@@ -69,7 +69,7 @@ class BatchInfo(ctypes.Structure):
         ("coeffs_total", ctypes.c_int64), ("kernel_width", ctypes.c_int32),
         ("cells_per_wave", ctypes.c_int32), ("waves", ctypes.c_int32), ("n_units", ctypes.c_int64),
         ("n_points", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
-        ("tuned_ms", ctypes.c_double * 4), ("has_graph", ctypes.c_int32),
+        ("tuned_ms", ctypes.c_double * 7), ("has_graph", ctypes.c_int32), ("scheme", ctypes.c_int32),
     ]
 
 

@@ -65,8 +65,8 @@ def test_batch_small_mixed_vs_oracle(torch_cuda):
         "units", b.info.n_units)
     packed = b.pack(coeffs)
     W = b.info.kernel_width
-    for C in (1, 2, 4, 8):
-        if C * W * W > 200:  # beyond the register tile the kernel is built for
+    for C in (1, 2, 4, 8, 16, 32, 64):
+        if C <= 8 and C * W * W > 200:  # beyond the register tile the kernel is built for
             with pytest.raises(pgc.PgcError):
                 b.set_tile(C)
             continue
