@@ -19,6 +19,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -269,18 +270,36 @@ def surrogate_variant(torch, pgc, inputs, np, n_pairs, epochs):
         p64.coeffs_to_q(c64)
     torch.cuda.synchronize()
     t_fp64 = (time.time() - t) / 2
-    out = {"value": f_te.shape[0] / t_dep, "unit": "Q-evals/s (gates and judge on)",
+    # the same network with a judge tolerance above its measured error: what the
+    # surrogate gains where that accuracy is acceptable
+    loose = pgc.Surrogate(plan, width=1024, n_layers=4, batch_max=256, seed=3, judge_tol=0.5)
+    with tempfile.TemporaryDirectory() as d:  # parameters and gate calibration
+        s.save(os.path.join(d, "net.bin"))
+        loose.load(os.path.join(d, "net.bin"))
+    loose.coeffs_to_q(f_te)
+    torch.cuda.synchronize()
+    t = time.time()
+    q_l, _, nfb_l, jerr_l = loose.coeffs_to_q(f_te)
+    torch.cuda.synchronize()
+    t_loose = time.time() - t
+    err_l = [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in
+             zip(q_l.double().cpu().numpy(), q_te.double().cpu().numpy())]
+    out = {"value": f_te.shape[0] / t_dep, "unit": "Q-evals/s (gates and judge on, judge tol 5e-2)",
            "network_only_evals_per_s": f_te.shape[0] / t_net,
            "plain_fp32_evals_per_s": 1.0 / t_plain, "plain_fp64_evals_per_s": 1.0 / t_fp64,
            "speedup_vs_plain_fp64": (f_te.shape[0] / t_dep) * t_fp64,
            "network_rel_l2_vs_plain_median": float(np.median(err)), "network_rel_l2_vs_plain_max": max(err),
            "fallbacks": nfb, "of": int(f_te.shape[0]), "judge_max_rel_err": jerr,
+           "judge_tol_0.5": {"evals_per_s": f_te.shape[0] / t_loose, "fallbacks": nfb_l,
+                             "speedup_vs_plain_fp64": (f_te.shape[0] / t_loose) * t_fp64,
+                             "rel_l2_vs_plain_median": float(np.median(err_l)),
+                             "rel_l2_vs_plain_max": max(err_l)},
            "training_pairs": n_pairs, "symmetric_images": 16, "epochs": epochs,
            "loss_first_last": [float(losses[0]), float(losses[-1])],
            "pair_generation_s": t_gen, "training_s": t_train,
            "workload": "3D N=24 (13824 coeffs), algebraic map, S=5, Maxwell, 8x8 product rule; MLP "
                        "13824-1024-1024-1024-13824 (BF16 MFMA, FP32 accumulation)"}
-    for x in (s, raw, p64, plan):
+    for x in (s, raw, loose, p64, plan):
         x.close()
     return out
 
@@ -323,8 +342,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--batch-cells", type=int, default=4096)
     ap.add_argument("--batch-reps", type=int, default=3)
-    ap.add_argument("--surrogate-pairs", type=int, default=1024)
-    ap.add_argument("--surrogate-epochs", type=int, default=30)
+    ap.add_argument("--surrogate-pairs", type=int, default=2048)
+    ap.add_argument("--surrogate-epochs", type=int, default=60)
     ap.add_argument("--mode", choices=["bench", "profile", "copy", "bkw"], default="bench",
                     help="profile: two evaluations per precision (for rocprofv3); "
                          "copy: a 1 GiB device copy (calibrates the HBM byte counters); "

@@ -303,6 +303,9 @@ typedef struct pgc_surrogate_desc {
     double gate_raw_factor;  /* default 4 */
     int32_t judge_stride;    /* default 64 */
     double judge_tol;        /* default 5e-2 */
+    double norm_floor_in;    /* per-feature standard deviations of the inputs are held at or
+                                above this fraction of the largest; default 0.1 */
+    double norm_floor_out;   /* the same for the outputs; default 1 (one common scale) */
 } pgc_surrogate_desc;
 
 typedef struct pgc_surrogate_info {

@@ -444,6 +444,7 @@ struct pgc_surrogate_s {
     int n = 0, width = 0, n_layers = 0, bmax = 0;
     uint64_t seed = 0;
     double gate_residual = 1e-6, gate_raw_factor = 0.0, judge_tol = 0.0;
+    float floor_in = 0.1f, floor_out = 1.0f;  // standard deviation floors, relative to the largest
     int judge_stride = 0;
     double raw_calib = 0.0;  // largest raw residual seen on the training set
     double z_calib = 0.0;    // largest RMS z-score of a training input
@@ -697,6 +698,8 @@ pgc_status pgc_surrogate_desc_init(pgc_surrogate_desc* d)
     d->gate_raw_factor = 4.0;
     d->judge_stride = 64;
     d->judge_tol = 5e-2;
+    d->norm_floor_in = 0.1;
+    d->norm_floor_out = 1.0;
     return PGC_OK;
 }
 
@@ -707,7 +710,8 @@ pgc_status pgc_surrogate_create(pgc_plan plan, const pgc_surrogate_desc* d, void
     const pgc::Plan& p = plan->p;
     if (p.precision != PGC_PRECISION_FP32) return PGC_ERR_UNSUPPORTED;
     if (d->width < 16 || d->width > 8192 || d->n_layers < 2 || d->n_layers > 16 || d->batch_max < 1 ||
-        d->batch_max > 65536 || d->gate_residual < 0 || d->judge_stride < 0 || d->gate_raw_factor < 0)
+        d->batch_max > 65536 || d->gate_residual < 0 || d->judge_stride < 0 || d->gate_raw_factor < 0 ||
+        !(d->norm_floor_in > 0 && d->norm_floor_in <= 1) || !(d->norm_floor_out > 0 && d->norm_floor_out <= 1))
         return PGC_ERR_INVALID_ARG;
     if (p.Nd > (1 << 22)) return PGC_ERR_UNSUPPORTED;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -727,6 +731,8 @@ pgc_status pgc_surrogate_create(pgc_plan plan, const pgc_surrogate_desc* d, void
     s->gate_raw_factor = d->gate_raw_factor;
     s->judge_stride = d->judge_stride;
     s->judge_tol = d->judge_tol;
+    s->floor_in = (float)d->norm_floor_in;
+    s->floor_out = (float)d->norm_floor_out;
     hipError_t e = hipSuccess;
     std::vector<double> cons, ginv, cnorm;
     try {
@@ -843,11 +849,14 @@ pgc_status pgc_surrogate_set_normalization(pgc_surrogate s, const float* f_dev, 
                        s->sd_in);
     hipLaunchKernelGGL(pgc::feature_stats, dim3(pgc::nb(n, 256)), dim3(256), 0, st, q_dev, n_samples, n, s->mu_out,
                        s->sd_out);
-    // standard deviations below 1e-3 of the largest are held at that level
+    // standard deviations are held at or above floor x the largest one: the
+    // output floor 1 scales every output alike, so that the loss measures the
+    // L2 error of Q itself rather than inflating its smallest modes
     hipLaunchKernelGGL(pgc::max_reduce, dim3(1), dim3(1024), 0, st, s->sd_in, n, s->scratch);
-    hipLaunchKernelGGL(pgc::floor_sd, dim3(pgc::nb(n, 256)), dim3(256), 0, st, s->sd_in, n, s->scratch, 1e-3f);
+    hipLaunchKernelGGL(pgc::floor_sd, dim3(pgc::nb(n, 256)), dim3(256), 0, st, s->sd_in, n, s->scratch, s->floor_in);
     hipLaunchKernelGGL(pgc::max_reduce, dim3(1), dim3(1024), 0, st, s->sd_out, n, s->scratch + 1);
-    hipLaunchKernelGGL(pgc::floor_sd, dim3(pgc::nb(n, 256)), dim3(256), 0, st, s->sd_out, n, s->scratch + 1, 1e-3f);
+    hipLaunchKernelGGL(pgc::floor_sd, dim3(pgc::nb(n, 256)), dim3(256), 0, st, s->sd_out, n, s->scratch + 1,
+                       s->floor_out);
     return pgc::status_of(hipGetLastError());
 }
 

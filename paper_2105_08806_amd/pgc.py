@@ -78,6 +78,7 @@ class SurrogateDesc(ctypes.Structure):
         ("width", ctypes.c_int32), ("n_layers", ctypes.c_int32), ("batch_max", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("gate_residual", ctypes.c_double), ("gate_raw_factor", ctypes.c_double),
         ("judge_stride", ctypes.c_int32), ("judge_tol", ctypes.c_double),
+        ("norm_floor_in", ctypes.c_double), ("norm_floor_out", ctypes.c_double),
     ]
 
 
