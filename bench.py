@@ -29,7 +29,27 @@ METRIC = "Q(f,f) evals/s, 3D N=32^3: FP64 plain vs FP32/batched/surrogate at sta
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}  # MI355X vector peaks, FLOP/s
 N, S, T0, DT = 32, 5.0, 6.5, 0.1
 N_THETA, N_PHI = 8, 8
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2105_08806_amd", "csrc", "pgc_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2105_08806_amd", "csrc")
+# the sources each profiled kernel is built from (a counter record is valid
+# only while their hash is unchanged)
+KERNEL_SOURCES = {
+    "gain_binned": ("pgc_kernels.hip", "pgc_device.h"),
+    "gain_batched_lanes": ("pgc_batch.hip", "pgc_device.h"),
+    "gemm_bf16": ("pgc_mlp.hip",),
+}
+TRAFFIC_KERNELS = {  # record tag -> (kernel name prefix, source set)
+    "gain_binned_fp64_3d_n32": ("void pgc::(anonymous namespace)::gain_binned<double, 3, 11>", "gain_binned"),
+    "gain_binned_fp32_3d_n32": ("void pgc::(anonymous namespace)::gain_binned<float, 3, 5>", "gain_binned"),
+    "gain_batched_lanes_2d_4096": ("void pgc::(anonymous namespace)::gain_batched_lanes<7, 64>",
+                                   "gain_batched_lanes"),
+}
+
+
+def sources_sha(kind):
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[kind]:
+        h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()
 
 
 def log(*a):
@@ -86,11 +106,52 @@ def traffic_for(kernel_tag):
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     entry = rec.get(kernel_tag)
-    if not entry or entry.get("kernel_source_sha256") != sha:
+    if not entry or kernel_tag not in TRAFFIC_KERNELS:
+        return None
+    if entry.get("kernel_source_sha256") != sources_sha(TRAFFIC_KERNELS[kernel_tag][1]):
         return None
     return entry.get("bytes_per_launch")
+
+
+def counter_per_dispatch(csv_path, counter):
+    """Mean value of `counter` per dispatch, by kernel name, from a rocprofv3
+    counter-collection CSV."""
+    import csv
+    tot, cnt = {}, {}
+    with open(csv_path) as fp:
+        for row in csv.DictReader(fp):
+            if row["Counter_Name"] != counter:
+                continue
+            k = row["Kernel_Name"]
+            tot[k] = tot.get(k, 0.0) + float(row["Counter_Value"])
+            cnt[k] = cnt.get(k, 0) + 1
+    return {k: tot[k] / cnt[k] for k in tot}
+
+
+def write_traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv):
+    """profiles/traffic.json from FETCH_SIZE / WRITE_SIZE passes over
+    `--mode profile` and over `--mode copy` (1 GiB copy: the byte scale of
+    each counter)."""
+    f, w = counter_per_dispatch(fetch_csv, "FETCH_SIZE"), counter_per_dispatch(write_csv, "WRITE_SIZE")
+    cf, cw = counter_per_dispatch(cfetch_csv, "FETCH_SIZE"), counter_per_dispatch(cwrite_csv, "WRITE_SIZE")
+    copy = [k for k in cf if "copyBuffer" in k or "copy" in k.lower()]
+    gib_kib = float(1 << 20)
+    fscale = gib_kib / max(cf[k] for k in copy)
+    wscale = gib_kib / max(cw[k] for k in copy)
+    rec = {}
+    for tag, (prefix, kind) in TRAFFIC_KERNELS.items():
+        fk = [k for k in f if k.startswith(prefix)]
+        wk = [k for k in w if k.startswith(prefix)]
+        if not fk or not wk:
+            continue
+        fr, wr = f[fk[0]], w[wk[0]]
+        rec[tag] = {"kernel": prefix, "kernel_source_sha256": sources_sha(kind),
+                    "bytes_per_launch": 1024.0 * (fr * fscale + wr * wscale),
+                    "fetch_kib_raw": fr, "write_kib_raw": wr, "fetch_scale": fscale, "write_scale": wscale}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fp:
+        json.dump(rec, fp, indent=1)
+    return rec
 
 
 def cpu_baseline(inputs, budget_s=15.0):
@@ -164,7 +225,14 @@ def batched_variant(torch, pgc, inputs, np, n_cells, reps):
             errs.append(float(np.linalg.norm(qs[i] - ref.cpu().numpy()) / np.linalg.norm(ref.cpu().numpy())))
     counts = {N: sum(1 for c in cells if c["N"] == N) for N in (32, 48, 64)}
     fp64_s = sum(counts[N] * min(t_cell[N]) for N in counts)
+    W = b.info.kernel_width
+    achieved = 2.0 * W * W * b.info.n_points / (ms / 1e3)  # spreading multiply-adds, whole evaluation
     out = {"value": n_cells / (ms / 1e3), "unit": "cell Q-evals/s", "ms_per_eval": ms,
+           "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK["fp32"],
+                        "traffic": traffic_for("gain_batched_lanes_2d_4096") if b.info.cells_per_wave == 64
+                        and W == 7 else None,
+                        "note": "2 W^2 flops per merged point and cell over the whole batched evaluation"},
            "workload": "2D batch of %d cells, N from {32,48,64} (%s), S=6, Maxwell, 32 directions, "
                        "perturbed Maxwellians, FP32 gain (W=%d), graph replay" % (
                            n_cells, counts, b.info.kernel_width),
@@ -344,15 +412,26 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--surrogate-pairs", type=int, default=2048)
     ap.add_argument("--surrogate-epochs", type=int, default=60)
-    ap.add_argument("--mode", choices=["bench", "profile", "copy", "bkw"], default="bench",
+    ap.add_argument("--pmc-dir", default="gpurun_out/prof")
+    ap.add_argument("--mode", choices=["bench", "profile", "copy", "bkw", "traffic"], default="bench",
                     help="profile: two evaluations per precision (for rocprofv3); "
                          "copy: a 1 GiB device copy (calibrates the HBM byte counters); "
-                         "bkw: the 20-step RK4 BKW error curve in FP64 and FP32")
+                         "bkw: the 20-step RK4 BKW error curve in FP64 and FP32; "
+                         "traffic: write profiles/traffic.json from the counter CSVs under --pmc-dir")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.mode == "traffic":  # host only: parse the counter passes
+        d = args.pmc_dir
+        rec = write_traffic(os.path.join(d, "fetch", "fetch_counter_collection.csv"),
+                            os.path.join(d, "write", "write_counter_collection.csv"),
+                            os.path.join(d, "cfetch", "cfetch_counter_collection.csv"),
+                            os.path.join(d, "cwrite", "cwrite_counter_collection.csv"))
+        print(json.dumps(rec, indent=1))
+        return
 
     import numpy as np
     import torch
@@ -379,6 +458,32 @@ def main():
             log("profiled %s: W=%d points=%d" % ("fp64" if prec == pgc.FP64 else "fp32",
                                                  plan.info.kernel_width, plan.info.n_points))
             plan.close()
+        # the batched workload in the lane-per-cell scheme (64 cells per wave)
+        cells = inputs.cell_maxwellians_2d(4096, seed=8806)
+        rng = np.random.default_rng(8806)
+        packed = torch.tensor(np.concatenate([inputs.random_coeffs((c["N"], c["N"]), seed=i).ravel()
+                                              for i, c in enumerate(cells)]).astype(np.float32), device="cuda")
+        b = pgc.Batch([c["N"] for c in cells], scale=6.0, n_sigma=32, nufft_tol=1e-8, autotune=False)
+        b.set_tile(64)
+        for _ in range(2):
+            b.coeffs_to_q(packed)
+        torch.cuda.synchronize()
+        log("profiled batched: %d cells, W=%d, C=%d" % (len(cells), b.info.kernel_width, b.info.cells_per_wave))
+        b.close()
+        # surrogate training steps and inference at N=24 (random rows: kernel timing only)
+        plan = pgc.Plan(dim=3, n_modes=24, scale=5.0, map=pgc.MAP_ALGEBRAIC, sphere=pgc.SPHERE_PRODUCT_3D,
+                        n_theta=8, n_phi=8, precision=pgc.FP32)
+        s = pgc.Surrogate(plan, width=1024, n_layers=4, batch_max=256, judge_stride=0, gate_raw_factor=0.0,
+                          gate_residual=1.0)
+        f = torch.tensor(rng.normal(size=(512, 24 ** 3)).astype(np.float32), device="cuda")
+        q = torch.tensor(rng.normal(size=(512, 24 ** 3)).astype(np.float32), device="cuda")
+        s.set_normalization(f, q)
+        s.train(f, q, epochs=1, batch=256)
+        s.coeffs_to_q(f[:256])
+        torch.cuda.synchronize()
+        log("profiled surrogate: 2 training steps and 256 inferences")
+        s.close()
+        plan.close()
         return
 
     r64 = time_variant(torch, pgc, inputs, pgc.FP64, args.steps, args.warmup)
