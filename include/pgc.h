@@ -103,7 +103,9 @@ typedef struct pgc_plan_desc {
     int32_t gain_mode;    /* spreading scheme: 0 = automatic (binned, falling back to slabs when the
                              bin index does not fit in device memory), 1 = LDS slabs with one atomic per
                              contribution, 2 = plan-time bins by footprint corner with register
-                             accumulation (the index holds 8 bytes per merged point) */
+                             accumulation (the index holds 8 bytes per merged point), 3 = the same bins
+                             contracted on the FP64 matrix cores (FP64 3D plans with W <= 12 only,
+                             UNSUPPORTED otherwise) */
 } pgc_plan_desc;
 
 typedef struct pgc_plan_s* pgc_plan;
@@ -122,7 +124,7 @@ typedef struct pgc_plan_info {
     int64_t n_points;       /* distinct transform points after merging the triples that share
                                v' (exchanging i_l and j_l in any dimension): n_sigma * (n_i (n_i+1)/2)^dim */
     int64_t workspace_bytes;/* device memory owned by the plan */
-    int32_t gain_mode;      /* 1 = slabs, 2 = bins */
+    int32_t gain_mode;      /* 1 = slabs, 2 = bins, 3 = bins on the FP64 matrix cores */
     int64_t n_bin_items;    /* binned mode: work items (runs of one bin) per evaluation */
 } pgc_plan_info;
 
@@ -235,6 +237,8 @@ typedef struct pgc_batch_info {
     double tuned_ms[7];         /* autotuner: gain time for C = 1, 2, 4, 8, 16, 32, 64 (0 = not tried) */
     int32_t has_graph;          /* a captured graph is ready for pgc_batch_graph_launch */
     int32_t scheme;             /* 0 register tiles, 1 lane per cell */
+    int32_t spatial_order;      /* 1: bin runs in raster order of their bins, 0: longest first */
+    double order_ms[2];         /* autotuner: gain time at the chosen C, longest-first / raster order */
 } pgc_batch_info;
 
 /* Build a batch of n_cells cells; n_modes_host[c] is the N of cell c.

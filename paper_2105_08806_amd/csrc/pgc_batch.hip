@@ -40,6 +40,7 @@ struct GroupDev {
     const unsigned long long* ids;
     const float* Gg;     // n_cells x nid, G of every cell rounded to FP32
     const float* Gt;     // nid x ldg, the same with the cell index fastest
+    const int* order;    // bin runs in processing order (NULL: the plan's longest-first order)
     double* grid;        // n_cells x ngd FP64 fine grids
     int nb, off, n_cells, ncg;  // ncg = cell groups of C cells
     int ldg;             // row length of Gt (n_cells rounded up to 64)
@@ -79,7 +80,7 @@ __global__ void __launch_bounds__(64) gain_batched(const GroupDev* __restrict__ 
         while (g + 1 < n_groups && (long long)u >= groups[g + 1].unit_begin) ++g;
         const GroupDev& D = groups[g];
         const long long local = (long long)u - D.unit_begin;
-        const int item = (int)(local / D.ncg);
+        const int item = D.order ? D.order[local / D.ncg] : (int)(local / D.ncg);
         const int c0 = (int)(local % D.ncg) * C;
         const int nc = min(C, D.n_cells - c0);
         const int bin = D.item_bin[item];
@@ -181,7 +182,7 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
         while (g + 1 < n_groups && (long long)u >= groups[g + 1].unit_begin) ++g;
         const GroupDev& D = groups[g];
         const long long local = (long long)u - D.unit_begin;
-        const int item = (int)(local / D.ncg);
+        const int item = D.order ? D.order[local / D.ncg] : (int)(local / D.ncg);
         const int c = (int)(local % D.ncg) * CW + cl;
         const bool valid = c < D.n_cells;
         const int bin = D.item_bin[item];
@@ -478,6 +479,7 @@ struct BatchGroup {
     double* grid = nullptr;   // n_cells x n_g^d
     float* Gt = nullptr;      // n_i^d x ldg, cell-minor G (lane-per-cell scheme)
     int ldg = 0;
+    int* order = nullptr;     // the plan's bin runs in raster order of their bins
     pgc::DenseBufs b;
 };
 
@@ -491,6 +493,8 @@ struct pgc_batch_s {
     pgc::GroupDev* groups_dev = nullptr;
     unsigned long long* counter = nullptr;
     int C = 0, waves = 0;
+    int spatial = 1;          // process bin runs in raster order (else longest first)
+    double order_ms[2] = {0, 0};  // autotuner: best C in longest-first / raster order
     unsigned long long n_units = 0;
     int64_t n_points = 0;
     double tuned_ms[7] = {0, 0, 0, 0, 0, 0, 0};  // C = 1, 2, 4, 8, 16, 32, 64
@@ -558,6 +562,7 @@ hipError_t set_units(pgc_batch_s& b, int C, hipStream_t s)
         d.Gg = static_cast<const float*>(G.b.Gg);
         d.Gt = G.Gt;
         d.ldg = G.ldg;
+        d.order = b.spatial ? G.order : nullptr;
         d.grid = G.grid;
         d.nb = p.bins.nb;
         d.off = p.bins.off;
@@ -674,6 +679,20 @@ hipError_t autotune(pgc_batch_s& b, hipStream_t s)
             best_ms = ms;
         }
     }
+    if (e == hipSuccess && best != 0) {
+        // the other processing order at the best C
+        const int keep = b.spatial;
+        b.order_ms[keep] = best_ms;
+        b.spatial = 1 - keep;
+        float ms = 0.f;
+        if ((e = set_units(b, best, s)) == hipSuccess && (e = enqueue_gain(b, s)) == hipSuccess &&
+            (e = hipEventRecord(t0, s)) == hipSuccess && (e = enqueue_gain(b, s)) == hipSuccess &&
+            (e = hipEventRecord(t1, s)) == hipSuccess && (e = hipEventSynchronize(t1)) == hipSuccess &&
+            (e = hipEventElapsedTime(&ms, t0, t1)) == hipSuccess) {
+            b.order_ms[b.spatial] = ms;
+            if (!(ms < best_ms)) b.spatial = keep;
+        }
+    }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     if (e != hipSuccess) return e;
@@ -758,6 +777,20 @@ pgc_status pgc_batch_create(const pgc_plan_desc* base, int32_t n_cells, const in
         if ((e = batch_alloc_n(*b, &g.grid, nb * p.ngd)) != hipSuccess) break;
         g.ldg = (int)((nb + 63) / 64 * 64);
         if ((e = batch_alloc_n(*b, &g.Gt, p.nid * g.ldg)) != hipSuccess) break;
+        {
+            // raster order of the bins: consecutive runs flush into overlapping grid lines
+            std::vector<int> bins((size_t)p.bins.n_items), ord((size_t)p.bins.n_items);
+            if (p.bins.n_items > 0 &&
+                (e = hipMemcpy(bins.data(), p.bins.item_bin, bins.size() * sizeof(int), hipMemcpyDeviceToHost)) !=
+                    hipSuccess)
+                break;
+            for (size_t k = 0; k < ord.size(); ++k) ord[k] = (int)k;
+            std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return bins[x] < bins[y]; });
+            if ((e = batch_alloc_n(*b, &g.order, std::max<int64_t>(1, p.bins.n_items))) != hipSuccess) break;
+            if (!ord.empty() &&
+                (e = hipMemcpy(g.order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+                break;
+        }
         if ((e = hipMemcpyAsync(g.cells_dev, g.cells.data(), nb * sizeof(int), hipMemcpyHostToDevice, s)) !=
             hipSuccess)
             break;
@@ -807,6 +840,9 @@ pgc_status pgc_batch_query(pgc_batch b, pgc_batch_info* info)
     for (const BatchGroup& g : b->groups) info->workspace_bytes += g.plan->p.workspace_bytes;
     for (int k = 0; k < 7; ++k) info->tuned_ms[k] = b->tuned_ms[k];
     info->scheme = b->C >= 16 ? 1 : 0;
+    info->spatial_order = b->spatial;
+    info->order_ms[0] = b->order_ms[0];
+    info->order_ms[1] = b->order_ms[1];
     info->has_graph = b->exec != nullptr;
     return PGC_OK;
 }

@@ -153,7 +153,7 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
     if (d.block_threads != 0 && d.block_threads != 256 && d.block_threads != 512 &&
         d.block_threads != 1024)
         return PGC_ERR_INVALID_ARG;
-    if (d.gain_mode < 0 || d.gain_mode > 2) return PGC_ERR_INVALID_ARG;
+    if (d.gain_mode < 0 || d.gain_mode > 3) return PGC_ERR_INVALID_ARG;
 
     p.dim = d.dim;
     p.N = d.n_modes;
@@ -242,9 +242,13 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
     p.W = d.kernel_width > 0 ? d.kernel_width : width_for(p.tol, p.upsample);
     p.gain_mode = d.gain_mode == 1 ? kGainSlab : kGainBinned;
     if (p.gain_mode == kGainBinned && p.W > 14) {
-        if (d.gain_mode == 2) return PGC_ERR_UNSUPPORTED;
+        if (d.gain_mode >= 2) return PGC_ERR_UNSUPPORTED;
         p.gain_mode = kGainSlab;
     }
+    // the matrix-core binned gain: FP64 3D plans with W <= 12
+    p.mfma = d.gain_mode == 3;
+    if (p.mfma && (p.precision != PGC_PRECISION_FP64 || p.dim != 3 || p.W < 4 || p.W > 12))
+        return PGC_ERR_UNSUPPORTED;
     p.auto_gain = d.gain_mode == 0;
     p.terms = p.W + 2;
     p.beta = beta_for(p.W, p.upsample);
@@ -771,7 +775,7 @@ pgc_status pgc_plan_query(pgc_plan plan, pgc_plan_info* info)
     info->block_threads = p.block_threads;
     info->n_triples = p.n_triples;
     info->n_points = p.n_points;
-    info->gain_mode = p.gain_mode;
+    info->gain_mode = p.mfma && p.gain_mode == pgc::kGainBinned ? 3 : p.gain_mode;
     info->n_bin_items = p.bins.n_items;
     info->workspace_bytes = p.workspace_bytes;
     return PGC_OK;

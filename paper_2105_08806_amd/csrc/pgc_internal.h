@@ -109,6 +109,7 @@ struct Plan {
 
     size_t elt = 8;
     int gain_mode = kGainBinned;
+    bool mfma = false;         // binned gain on the FP64 matrix cores (FP64 3D plans)
     bool auto_gain = true;
     Profiler* prof = nullptr;  // stage timing, off unless requested
     int prof_set = -1;         // event set of the call being recorded

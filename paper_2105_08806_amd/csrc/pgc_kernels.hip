@@ -586,12 +586,18 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
     const int e0 = lane % LP;
     const bool lane_on = g < G;
 
-    double acc64[NPASS][W];
+    // FP32 tiles are summed over one 64-point batch and then added into FP64;
+    // FP64 tiles accumulate directly
+    constexpr bool TWO_LEVEL = sizeof(T) < sizeof(double);
+    double acc64[TWO_LEVEL ? NPASS : 1][TWO_LEVEL ? W : 1];
     T acc[NPASS][W];
 #pragma unroll
     for (int r = 0; r < NPASS; ++r)
 #pragma unroll
-        for (int a = 0; a < W; ++a) acc64[r][a] = 0.0;
+        for (int a = 0; a < W; ++a) {
+            acc[r][a] = (T)0;
+            if constexpr (TWO_LEVEL) acc64[r][a] = 0.0;
+        }
 
     for (int base = 0; base < n; base += 64) {
         const int nv = min(64, n - base);
@@ -623,50 +629,69 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
             }
         }
         __syncthreads();
+        if constexpr (TWO_LEVEL) {
 #pragma unroll
-        for (int r = 0; r < NPASS; ++r)
+            for (int r = 0; r < NPASS; ++r)
 #pragma unroll
-            for (int a = 0; a < W; ++a) acc[r][a] = (T)0;
-        const int steps = (nv + G - 1) / G;
-        for (int st_i = 0; st_i < steps; ++st_i) {
-            const int pnt = st_i * G + g;
-            if (lane_on && pnt < nv) {
-                const T* sp = stage + pnt * STRIDE;
-                const T qp = sp[0];
-                T k1[W];
+                for (int a = 0; a < W; ++a) acc[r][a] = (T)0;
+        }
+        // one staged point into the lane's columns
+        auto spread_point = [&](int pnt) {
+            const T* sp = stage + pnt * STRIDE;
+            const T qp = sp[0];
+            T k1[W];
 #pragma unroll
-                for (int a = 0; a < W; ++a) k1[a] = sp[1 + a];
+            for (int a = 0; a < W; ++a) k1[a] = sp[1 + a];
 #pragma unroll
-                for (int r = 0; r < NPASS; ++r) {
-                    const int e = e0 + 64 * r;
-                    if (e < CELLS) {
-                        T t;
-                        if constexpr (DIM == 2) t = qp * sp[1 + W + e];
-                        else t = qp * sp[1 + W + e / W] * sp[1 + 2 * W + e % W];
+            for (int r = 0; r < NPASS; ++r) {
+                const int e = e0 + 64 * r;
+                if (e < CELLS) {
+                    T t;
+                    if constexpr (DIM == 2) t = qp * sp[1 + W + e];
+                    else t = qp * sp[1 + W + e / W] * sp[1 + 2 * W + e % W];
 #pragma unroll
-                        for (int a = 0; a < W; ++a) acc[r][a] = fma(t, k1[a], acc[r][a]);
-                    }
+                    for (int a = 0; a < W; ++a) acc[r][a] = fma(t, k1[a], acc[r][a]);
                 }
             }
+        };
+        // full steps carry a point for every lane group (no per-lane guard, so
+        // the LDS reads of the next step can be issued under this step's
+        // arithmetic); a last partial step follows
+        const int full = nv / G;
+        if (lane_on) {
+#pragma unroll 2
+            for (int st_i = 0; st_i < full; ++st_i) spread_point(st_i * G + g);
+            const int pnt = full * G + g;
+            if (pnt < nv) spread_point(pnt);
         }
+        if constexpr (TWO_LEVEL) {
 #pragma unroll
-        for (int r = 0; r < NPASS; ++r)
+            for (int r = 0; r < NPASS; ++r)
 #pragma unroll
-            for (int a = 0; a < W; ++a) acc64[r][a] += (double)acc[r][a];
+                for (int a = 0; a < W; ++a) acc64[r][a] += (double)acc[r][a];
+        }
         __syncthreads();
     }
+    double tot[NPASS][W];
+#pragma unroll
+    for (int r = 0; r < NPASS; ++r)
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            if constexpr (TWO_LEVEL) tot[r][a] = acc64[r][a];
+            else tot[r][a] = (double)acc[r][a];
+        }
 
     // groups of lanes that served different points hold partial sums of the same cells
     if constexpr (G > 1) {
         if (lane_on && g > 0) {
 #pragma unroll
-            for (int a = 0; a < W; ++a) red[((g - 1) * LP + e0) * W + a] = acc64[0][a];
+            for (int a = 0; a < W; ++a) red[((g - 1) * LP + e0) * W + a] = tot[0][a];
         }
         __syncthreads();
         if (g == 0) {
             for (int gg = 1; gg < G; ++gg)
 #pragma unroll
-                for (int a = 0; a < W; ++a) acc64[0][a] += red[((gg - 1) * LP + e0) * W + a];
+                for (int a = 0; a < W; ++a) tot[0][a] += red[((gg - 1) * LP + e0) * W + a];
         }
     }
     if (g != 0) return;
@@ -680,10 +705,106 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
         const int64_t plane = (DIM == 2) ? P.ng : (int64_t)P.ng * P.ng;
 #pragma unroll
         for (int a = 0; a < W; ++a) {
-            const double v = acc64[r][a];
+            const double v = tot[r][a];
             if (v != 0.0)
                 __hip_atomic_fetch_add(BI.grid + fold_index(t0[0] + a, P.nh) * plane + rest, v,
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Matrix-core variant of the binned gain for FP64 3D plans.  For one bin the
+// footprint is tile[a][(b, c)] = sum_p kx_p[a] (q_p ky_p[b] kz_p[c]): a product
+// of a W x P and a P x W^2 matrix over the P points of the bin.  Every staged
+// batch of 64 points is contracted with v_mfma_f64_16x16x4f64 (rows a padded
+// to 16, columns (b, c) in tiles of 16, four points per instruction), so the
+// vector units only regenerate points and form the operands.
+template <int W>
+__global__ void __launch_bounds__(64) gain_binned_mfma(GainParams<double> P, BinItems BI)
+{
+    constexpr int TERMS = W + 2;
+    constexpr int CELLS = W * W;
+    constexpr int NT = (CELLS + 15) / 16;
+    constexpr int STRIDE = 1 + 3 * W;  // kx[W], q ky[W], kz[W] after one pad slot
+    typedef double dvec4 __attribute__((ext_vector_type(4)));
+    __shared__ double stage[64 * STRIDE];
+
+    const int lane = threadIdx.x;
+    const int item = blockIdx.x;
+    const int bin = BI.bin[item];
+    const long long first = BI.begin[item];
+    const int n = BI.count[item];
+    const double halfW = 0.5 * W;
+    int t0[3];
+    {
+        int r = bin;
+        for (int l = 2; l >= 0; --l) {
+            t0[l] = r % BI.geo.nb - BI.geo.off;
+            r /= BI.geo.nb;
+        }
+    }
+    // operand lanes: A[i][k] and B[k][j] come from lane i + 16 k (j = i), k < 4
+    const int i16 = lane & 15, k4 = lane >> 4;
+    dvec4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = dvec4{0.0, 0.0, 0.0, 0.0};
+
+    for (int base = 0; base < n; base += 64) {
+        const int nv = min(64, n - base);
+        {
+            double* st = stage + lane * STRIDE;
+            if (lane < nv) {
+                const unsigned long long id = BI.ids[first + base + lane];
+                const int b1 = (int)(id & 0xffull), a1 = (int)((id >> 8) & 0xffull);
+                const int s = (int)((id >> 16) & 0x3ffull);
+                const int p2 = (int)((id >> 26) & 0xffffull), p3 = (int)((id >> 42) & 0xffffull);
+                double q, xs[3];
+                int64_t si;
+                point_geometry<double, 3>(P, s, a1, b1, p2, p3, halfW, q, xs, si);
+                q *= orbit_sum<double, 3>(P, a1, b1, p2, p3);
+                double k[W];
+                kernel_cells64<double, W, TERMS>(P.poly64, 2.0 * ((double)t0[0] - xs[0]) - 1.0, k);
+#pragma unroll
+                for (int a = 0; a < W; ++a) st[1 + a] = k[a];
+                kernel_cells64<double, W, TERMS>(P.poly64, 2.0 * ((double)t0[1] - xs[1]) - 1.0, k);
+#pragma unroll
+                for (int a = 0; a < W; ++a) st[1 + W + a] = q * k[a];
+                kernel_cells64<double, W, TERMS>(P.poly64, 2.0 * ((double)t0[2] - xs[2]) - 1.0, k);
+#pragma unroll
+                for (int a = 0; a < W; ++a) st[1 + 2 * W + a] = k[a];
+            } else {
+                for (int a = 0; a < STRIDE; ++a) st[a] = 0.0;
+            }
+        }
+        __syncthreads();
+        const int ksteps = (nv + 3) >> 2;
+        for (int ks = 0; ks < ksteps; ++ks) {
+            const double* sp = stage + (4 * ks + k4) * STRIDE;
+            const double av = i16 < W ? sp[1 + i16] : 0.0;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int col = 16 * t + i16;
+                const double bv = col < CELLS ? sp[1 + W + col / W] * sp[1 + 2 * W + col % W] : 0.0;
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // lane l holds rows l / 16 + 4 r of column l % 16 of every tile (the FP64
+    // 16 x 16 x 4 instruction interleaves rows over the lane groups)
+    const int64_t plane = (int64_t)P.ng * P.ng;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int col = 16 * t + i16;
+        if (col >= CELLS) continue;
+        const int64_t rest = (int64_t)fold_index(t0[1] + col / W, P.nh) * P.ng + fold_index(t0[2] + col % W, P.nh);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int a = k4 + 4 * r;
+            const double v = acc[t][r];
+            if (a < W && v != 0.0)
+                __hip_atomic_fetch_add(BI.grid + fold_index(t0[0] + a, P.nh) * plane + rest, v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -1017,6 +1138,28 @@ hipError_t binned_launch(const Plan& p, const GainParams<T>& gp, const BinItems&
     return hipGetLastError();
 }
 
+hipError_t mfma_dispatch(const Plan& p, const GainParams<double>& gp, const BinItems& bi, hipStream_t s)
+{
+    if (p.bins.n_items == 0) return hipSuccess;
+    const dim3 grid((unsigned)p.bins.n_items);
+    switch (p.W) {
+#define PGC_M_CASE(w) \
+    case w: hipLaunchKernelGGL(gain_binned_mfma<w>, grid, dim3(64), 0, s, gp, bi); break;
+        PGC_M_CASE(4)
+        PGC_M_CASE(5)
+        PGC_M_CASE(6)
+        PGC_M_CASE(7)
+        PGC_M_CASE(8)
+        PGC_M_CASE(9)
+        PGC_M_CASE(10)
+        PGC_M_CASE(11)
+        PGC_M_CASE(12)
+#undef PGC_M_CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename T, int DIM>
 hipError_t binned_dispatch(const Plan& p, const GainParams<T>& gp, const BinItems& bi, hipStream_t s)
 {
@@ -1099,7 +1242,12 @@ hipError_t gain_t(const Plan& p, hipStream_t s)
         bi.geo.off = p.bins.off;
         bi.geo.W = p.W;
         bi.geo.n_items = 0;
-        e = (p.dim == 2) ? binned_dispatch<T, 2>(p, gp, bi, s) : binned_dispatch<T, 3>(p, gp, bi, s);
+        if constexpr (sizeof(T) == sizeof(double)) {
+            if (p.mfma) e = mfma_dispatch(p, gp, bi, s);
+            else e = (p.dim == 2) ? binned_dispatch<T, 2>(p, gp, bi, s) : binned_dispatch<T, 3>(p, gp, bi, s);
+        } else {
+            e = (p.dim == 2) ? binned_dispatch<T, 2>(p, gp, bi, s) : binned_dispatch<T, 3>(p, gp, bi, s);
+        }
         if (e != hipSuccess) return e;
         prof_mark(p, 4, s);
         e = separable(p, p.ws.grid64, p.ws.qplus, p.dt.E, p.N, p.ng, 1, p.ws.tmpA, p.ws.tmpB, s);

@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
                                                  const bf16* __restrict__ A, int lda,
                                                  const bf16* __restrict__ B, int ldb,
                                                  float* __restrict__ C, int ldc,
-                                                 const float* __restrict__ bias, int accumulate)
+                                                 const float* __restrict__ bias, int accumulate, int vec)
 {
     __shared__ __attribute__((aligned(16))) bf16 sA[kBM][kBK + kPad];
     __shared__ __attribute__((aligned(16))) bf16 sB[kBN][kBK + kPad];
@@ -79,34 +79,88 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
     for (int k0 = kbeg; k0 < kend; k0 += kBK) {
-        for (int e = tid; e < kBM * kBK; e += 256) {
-            int m, k;
-            if (TA) {
-                m = e % kBM;
-                k = e / kBM;
+        // A tile (64 x 32): with vec, every thread moves one 16-byte run of 8
+        // elements along the contiguous dimension (k, or m when transposed)
+        if (vec) {
+            if (!TA) {
+                const int m = tid >> 2, k8 = (tid & 3) * 8;
+                const int gm = m0 + m, gk = k0 + k8;
+                u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+                if (gm < M && gk + 8 <= kend) {
+                    v = *reinterpret_cast<const u16x8*>(A + (size_t)gm * lda + gk);
+                } else if (gm < M) {
+                    for (int q = 0; q < 8; ++q)
+                        if (gk + q < kend) v[q] = A[(size_t)gm * lda + gk + q];
+                }
+                *reinterpret_cast<u16x8*>(&sA[m][k8]) = v;
             } else {
-                k = e % kBK;
-                m = e / kBK;
+                const int k = tid >> 3, m8 = (tid & 7) * 8;
+                const int gk = k0 + k, gm = m0 + m8;
+                u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+                if (gk < kend && gm + 8 <= M) {
+                    v = *reinterpret_cast<const u16x8*>(A + (size_t)gk * lda + gm);
+                } else if (gk < kend) {
+                    for (int q = 0; q < 8; ++q)
+                        if (gm + q < M) v[q] = A[(size_t)gk * lda + gm + q];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) sA[m8 + q][k] = v[q];
             }
-            const int gm = m0 + m, gk = k0 + k;
-            bf16 v = 0;
-            if (gm < M && gk < kend) v = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
-            sA[m][k] = v;
-        }
-        for (int e = tid; e < kBN * kBK; e += 256) {
-            int n, k;
             if (TB) {
-                k = e % kBK;
-                n = e / kBK;
+                const int n = tid >> 2, k8 = (tid & 3) * 8;
+                const int gn = n0 + n, gk = k0 + k8;
+                u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+                if (gn < N && gk + 8 <= kend) {
+                    v = *reinterpret_cast<const u16x8*>(B + (size_t)gn * ldb + gk);
+                } else if (gn < N) {
+                    for (int q = 0; q < 8; ++q)
+                        if (gk + q < kend) v[q] = B[(size_t)gn * ldb + gk + q];
+                }
+                *reinterpret_cast<u16x8*>(&sB[n][k8]) = v;
             } else {
-                n = e % kBN;
-                k = e / kBN;
+                const int k = tid >> 3, n8 = (tid & 7) * 8;
+                const int gk = k0 + k, gn = n0 + n8;
+                u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+                if (gk < kend && gn + 8 <= N) {
+                    v = *reinterpret_cast<const u16x8*>(B + (size_t)gk * ldb + gn);
+                } else if (gk < kend) {
+                    for (int q = 0; q < 8; ++q)
+                        if (gn + q < N) v[q] = B[(size_t)gk * ldb + gn + q];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) sB[n8 + q][k] = v[q];
             }
-            const int gn = n0 + n, gk = k0 + k;
-            bf16 v = 0;
-            if (gn < N && gk < kend) v = TB ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
-            sB[n][k] = v;
+        } else {
+            for (int e = tid; e < kBM * kBK; e += 256) {
+                int m, k;
+                if (TA) {
+                    m = e % kBM;
+                    k = e / kBM;
+                } else {
+                    k = e % kBK;
+                    m = e / kBK;
+                }
+                const int gm = m0 + m, gk = k0 + k;
+                bf16 v = 0;
+                if (gm < M && gk < kend) v = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
+                sA[m][k] = v;
+            }
+            for (int e = tid; e < kBN * kBK; e += 256) {
+                int n, k;
+                if (TB) {
+                    k = e % kBK;
+                    n = e / kBK;
+                } else {
+                    n = e % kBN;
+                    k = e / kBN;
+                }
+                const int gn = n0 + n, gk = k0 + k;
+                bf16 v = 0;
+                if (gn < N && gk < kend) v = TB ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
+                sB[n][k] = v;
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -508,18 +562,24 @@ hipError_t gemm(int M, int N, int K, const bf16* A, int lda, bool ta, const bf16
         hipLaunchKernelGGL(pgc::zero_rows, dim3(pgc::nb((int64_t)M * N, 256)), dim3(256), 0, st, C, ldc, M, N);
     dim3 grid((N + pgc::kBN - 1) / pgc::kBN, (M + pgc::kBM - 1) / pgc::kBM, split);
     const int acc = accumulate ? 1 : 0;
+    // 16-byte runs need 16-byte aligned rows: leading dimensions that are
+    // multiples of 8 elements on 16-byte aligned bases (kc is a multiple of 32)
+    const int vec = (lda % 8 == 0 && ldb % 8 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
+                     (reinterpret_cast<uintptr_t>(B) & 15) == 0)
+                        ? 1
+                        : 0;
     if (!ta && !tb)
         hipLaunchKernelGGL((pgc::gemm_bf16<false, false>), grid, dim3(256), 0, st, M, N, K, kc, A, lda, B, ldb, C, ldc,
-                           bias, acc);
+                           bias, acc, vec);
     else if (!ta && tb)
         hipLaunchKernelGGL((pgc::gemm_bf16<false, true>), grid, dim3(256), 0, st, M, N, K, kc, A, lda, B, ldb, C, ldc,
-                           bias, acc);
+                           bias, acc, vec);
     else if (ta && !tb)
         hipLaunchKernelGGL((pgc::gemm_bf16<true, false>), grid, dim3(256), 0, st, M, N, K, kc, A, lda, B, ldb, C, ldc,
-                           bias, acc);
+                           bias, acc, vec);
     else
         hipLaunchKernelGGL((pgc::gemm_bf16<true, true>), grid, dim3(256), 0, st, M, N, K, kc, A, lda, B, ldb, C, ldc,
-                           bias, acc);
+                           bias, acc, vec);
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ SCALE_DIRECT, SCALE_FROM_DOMAIN = 0, 1
 KERNEL_MAXWELL, KERNEL_VHS = 0, 1
 SPHERE_UNIFORM_2D, SPHERE_PRODUCT_3D, SPHERE_USER = 0, 1, 2
 FP64, FP32 = 0, 1
-GAIN_AUTO, GAIN_SLAB, GAIN_BINNED = 0, 1, 2
+GAIN_AUTO, GAIN_SLAB, GAIN_BINNED, GAIN_MFMA = 0, 1, 2, 3
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported configuration", 3: "out of device memory",
           4: "device error", 5: "non-finite result"}
@@ -70,6 +70,7 @@ class BatchInfo(ctypes.Structure):
         ("cells_per_wave", ctypes.c_int32), ("waves", ctypes.c_int32), ("n_units", ctypes.c_int64),
         ("n_points", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
         ("tuned_ms", ctypes.c_double * 7), ("has_graph", ctypes.c_int32), ("scheme", ctypes.c_int32),
+        ("spatial_order", ctypes.c_int32), ("order_ms", ctypes.c_double * 2),
     ]
 
 

@@ -223,3 +223,25 @@ def test_q_parity_both_gain_modes(torch_cuda, dim, prec):
         check_q(torch_cuda, ora, plan, c.astype(np.float32).astype(np.float64) if prec else c, tol,
                 "%dD mode=%d prec=%d" % (dim, mode, prec))
         plan.close()
+
+
+@pytest.mark.parametrize("map_", [0, 1])
+@pytest.mark.parametrize("kernel", ["maxwell", "vhs"])
+def test_q_parity_3d_fp64_matrix_cores(torch_cuda, map_, kernel):
+    """The FP64 binned gain on the matrix cores (gain_mode 3) against the oracle."""
+    from paper_2105_08806_amd import pgc
+    ora, plan = make_pair(3, 8, 2.0, map_=map_, kernel=kernel, gamma=1.0 if kernel == "vhs" else 0.0,
+                          b0=0.3 if kernel == "vhs" else None, n_theta=2, n_phi=4, gain_mode=pgc.GAIN_MFMA)
+    assert plan.info.gain_mode == pgc.GAIN_MFMA
+    c = I.random_coeffs((8, 8, 8), seed=31 + map_)
+    check_q(torch_cuda, ora, plan, c, FP64_TOL, "3D N=8 map=%d %s matrix cores" % (map_, kernel))
+    plan.close()
+
+
+def test_matrix_core_gain_rejects_unsupported_plans(torch_cuda):
+    from paper_2105_08806_amd import pgc
+    with pytest.raises(pgc.PgcError):
+        pgc.Plan(dim=3, n_modes=8, sphere=pgc.SPHERE_PRODUCT_3D, n_theta=2, n_phi=4, precision=pgc.FP32,
+                 gain_mode=pgc.GAIN_MFMA)
+    with pytest.raises(pgc.PgcError):
+        pgc.Plan(dim=2, n_modes=8, n_sigma=8, gain_mode=pgc.GAIN_MFMA)
