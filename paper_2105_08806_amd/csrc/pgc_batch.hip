@@ -150,8 +150,9 @@ __global__ void __launch_bounds__(64) gain_batched(const GroupDev* __restrict__ 
 // Lane-per-cell scheme: CW cells per wave, NS = 64 / CW point streams.  Lane
 // l serves cell c = C0 + l % CW and the staged points j = l / CW (mod NS).
 // The geometry of each 64-point batch is generated once (lane = point) and
-// read from LDS by every cell; a batch and the batch sums are summed in FP32
-// (at most 64 and 128 terms), the streams and the grid in FP64.
+// read from LDS by every cell; a batch is summed in registers and the batch
+// sums in LDS (FP32, at most 64 and 128 terms; the running tile stays out of
+// the registers that point regeneration needs), the streams and the grid in FP64.
 template <int W, int CW>
 __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restrict__ groups, int n_groups,
                                                          unsigned long long n_units,
@@ -167,6 +168,7 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
     // the kernel polynomial depends on W and the upsampling only, the same for
     // every group: read from LDS it is not hoisted into registers
     __shared__ double spoly[TERMS * W];
+    __shared__ float sacc[CELLS * 64];  // running tile of every lane, lane fastest
     const int lane = threadIdx.x;
     const int cl = lane % CW, stream = lane / CW;
     const double halfW = 0.5 * W;
@@ -193,9 +195,8 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
         const float* Gt = D.Gt;
         const int ldg = D.ldg;
 
-        float acc[CELLS];
 #pragma unroll
-        for (int e = 0; e < CELLS; ++e) acc[e] = 0.f;
+        for (int e = 0; e < CELLS; ++e) sacc[e * 64 + lane] = 0.f;
 
         for (int base = 0; base < n; base += 64) {
             const int nv = min(64, n - base);
@@ -240,7 +241,7 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
                     }
                 }
 #pragma unroll
-                for (int e = 0; e < CELLS; ++e) acc[e] += ab[e];
+                for (int e = 0; e < CELLS; ++e) sacc[e * 64 + lane] += ab[e];
             }
             __syncthreads();
         }
@@ -248,14 +249,14 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
         if constexpr (NS > 1) {
             if (stream > 0) {
 #pragma unroll
-                for (int e = 0; e < CELLS; ++e) red[((stream - 1) * CW + cl) * CELLS + e] = (double)acc[e];
+                for (int e = 0; e < CELLS; ++e) red[((stream - 1) * CW + cl) * CELLS + e] = (double)sacc[e * 64 + lane];
             }
             __syncthreads();
         }
         if (stream == 0 && valid) {
             double* grid = D.grid + (int64_t)c * D.ngd;
             for (int e = 0; e < CELLS; ++e) {
-                double v = (double)acc[e];
+                double v = (double)sacc[e * 64 + lane];
                 for (int r = 1; r < NS; ++r) v += red[((r - 1) * CW + cl) * CELLS + e];
                 if (v != 0.0) {
                     const int64_t cell = (int64_t)fold_index(t0x + e / W, D.gp.nh) * D.gp.ng +
