@@ -520,6 +520,8 @@ def main():
                    "kernel_width": W, "upsample": info.upsample, "n_points": info.n_points,
                    "n_triples": info.n_triples},
         "roofline": roofline,
+        "triples_per_s": info.n_triples * evals64,
+        "points_per_s": info.n_points * evals64,
         "stage_ms_per_eval_fp64": {k: v / max(1, r64["calls"]) for k, v in r64["stages"].items()},
         "variants": {
             "fp32": {"value": evals32, "unit": "evals/s", "ms_per_step": r32["ms"] / args.fp32_steps,

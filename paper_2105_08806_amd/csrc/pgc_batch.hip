@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(64) gain_batched(const GroupDev* __restrict__ 
                                                    unsigned long long n_units,
                                                    unsigned long long* __restrict__ counter)
 {
-    constexpr int TERMS = W + 2;
+    constexpr int TERMS = poly_terms(W);
     constexpr int CELLS = W * W;
     constexpr int NOUT = C * CELLS;
     constexpr int RS = 65;  // row stride of the reduction buffer (no bank conflicts)
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
                                                          unsigned long long n_units,
                                                          unsigned long long* __restrict__ counter)
 {
-    constexpr int TERMS = W + 2;
+    constexpr int TERMS = poly_terms(W);
     constexpr int CELLS = W * W;
     constexpr int NS = 64 / CW;
     __shared__ float sq[64];

@@ -250,7 +250,7 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
     if (p.mfma && (p.precision != PGC_PRECISION_FP64 || p.dim != 3 || p.W < 4 || p.W > 12))
         return PGC_ERR_UNSUPPORTED;
     p.auto_gain = d.gain_mode == 0;
-    p.terms = p.W + 2;
+    p.terms = poly_terms(p.W);
     p.beta = beta_for(p.W, p.upsample);
     // n >= 2 sigma N, and n >= 4 W so that a footprint folds back at most once and
     // the kernel stays narrow against the period (small N only: a finer grid is

@@ -11,6 +11,12 @@
 namespace pgc {
 
 constexpr int kMaxWidth = 16;         // largest spreading kernel width W
+
+// Horner terms of the kernel polynomial of one cell (degree + 1).  Beyond
+// W + 1 terms the interpolation error of the cells stops falling (it is set by
+// the kernel's value at the edge of its support, exp(-beta)); narrow kernels
+// keep one more term.
+constexpr int poly_terms(int w) { return w >= 10 ? w + 1 : w + 2; }
 constexpr int kMaxPolyTerms = 18;     // Horner terms per kernel cell (degree + 1)
 constexpr int kMaxLdsBytes = 160 * 1024;
 constexpr int kLdsBudget = 155 * 1024;  // slab bytes per workgroup

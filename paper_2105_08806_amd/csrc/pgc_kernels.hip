@@ -320,7 +320,7 @@ __device__ __forceinline__ T horner(const T* c, T s)
 template <typename T, int DIM, int W>
 __global__ void __launch_bounds__(spread_max_threads<T>()) gain_spread(GainParams<T> P)
 {
-    constexpr int TERMS = W + 2;
+    constexpr int TERMS = poly_terms(W);
     constexpr int NPASS = (W * W + 63) / 64;
     extern __shared__ unsigned char lds_raw[];
     double* slab = reinterpret_cast<double*>(lds_raw);
@@ -557,7 +557,7 @@ struct BinItems {
 template <typename T, int DIM, int W>
 __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
 {
-    constexpr int TERMS = W + 2;
+    constexpr int TERMS = poly_terms(W);
     constexpr int CELLS = (DIM == 2) ? W : W * W;          // lanes per point, all passes
     constexpr int LP = CELLS <= 64 ? CELLS : 64;
     constexpr int G = CELLS <= 64 ? 64 / CELLS : 1;
@@ -659,7 +659,7 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
         // arithmetic); a last partial step follows
         const int full = nv / G;
         if (lane_on) {
-#pragma unroll 2
+#pragma unroll 4
             for (int st_i = 0; st_i < full; ++st_i) spread_point(st_i * G + g);
             const int pnt = full * G + g;
             if (pnt < nv) spread_point(pnt);
@@ -722,7 +722,7 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
 template <int W>
 __global__ void __launch_bounds__(64) gain_binned_mfma(GainParams<double> P, BinItems BI)
 {
-    constexpr int TERMS = W + 2;
+    constexpr int TERMS = poly_terms(W);
     constexpr int CELLS = W * W;
     constexpr int NT = (CELLS + 15) / 16;
     constexpr int STRIDE = 1 + 3 * W;  // kx[W], q ky[W], kz[W] after one pad slot
