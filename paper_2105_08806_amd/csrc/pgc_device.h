@@ -7,6 +7,8 @@
 
 #include <cstdint>
 
+#include "pgc_internal.h"
+
 namespace pgc {
 namespace {
 
@@ -29,6 +31,8 @@ struct GainParams {
     const T* wfac;      // n_sigma  W_s b0 S^d, formed in FP64 and rounded once
     const T* poly;      // terms x W  (slab scheme)
     const double* poly64;  // terms x W  the same coefficients in FP64 (binned schemes)
+    const double* kpoly_eo;  // even and odd parts of the cells a < W/2 (binned scheme)
+    const double* cellfit;   // per bin coordinate: w_c, 1/delta and the offset polynomial
     const T* slab_vlo;  // n_slabs
     const T* slab_vhi;
     double* partial;    // n_chunks x n_g^d
@@ -58,6 +62,47 @@ __device__ __forceinline__ void map_point(T v, const GainParams<T>& P, double& z
         z = atan2(1.0, t);
         m2 = (T)fma(t, t, 1.0);
     }
+}
+
+// 1/x for positive normal x: the hardware reciprocal refined by two Newton steps
+__device__ __forceinline__ double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Both maps send a velocity to the transform angle as z = pi/2 - 2 atan(w) with
+// w in (-1, 1):
+//   r = 0: w = tanh(t/2) = (1 - e^-t) / (1 + e^-t),  mu^-2 / S = cosh t
+//   r = 1: w = t / (1 + sqrt(1 + t^2)),               mu^-2 / S = 1 + t^2
+// (t = v/S).  Returns w; the arctangent itself is never formed: inside one grid
+// cell the kernel offset is a short polynomial in w (cell_offset).
+template <typename T>
+__device__ __forceinline__ double map_w(T v, const GainParams<T>& P, T& m2)
+{
+    const double t = (double)v * P.inv_S64;
+    if (P.map == 0) {
+        const double e = exp(-t);
+        m2 = (T)(0.5 * (e + rcp64(e)));
+        return (1.0 - e) * rcp64(1.0 + e);
+    }
+    const double r = fma(t, t, 1.0);
+    m2 = (T)r;
+    return t * rcp64(1.0 + sqrt(r));
+}
+
+// kernel offset s = 2 (t0 - z/h + W/2) - 1 of a point whose footprint corner
+// in this dimension is t0, from the fit of that cell
+__device__ __forceinline__ double cell_offset(const double* __restrict__ cf, double w)
+{
+    const double x = (w - cf[0]) * cf[1];
+    double s = cf[2 + kCellFitDeg];
+#pragma unroll
+    for (int k = kCellFitDeg - 1; k >= 0; --k) s = fma(s, x, cf[2 + k]);
+    return s;
 }
 
 // values of the W kernel cells at offset s in [-1, 1): Horner in s
@@ -94,6 +139,89 @@ __device__ __forceinline__ void kernel_cells64(const double* __restrict__ poly, 
     for (int a = 0; a < W; ++a) out[a] = (T)v[a];
 }
 
+// The same values from the mirror symmetry of the cells: cell W-1-a at s is
+// cell a at -s, so with u = s^2 and the even and odd parts E_a(u), O_a(u) of
+// cell a (a < W/2) the pair is E_a + s O_a and E_a - s O_a; a middle cell is
+// even.  Layout: even parts [TERMS+1 / 2][(W+1)/2], then odd parts [TERMS/2][W/2].
+template <typename T, int W, int TERMS>
+__device__ __forceinline__ void kernel_cells_eo(const double* __restrict__ eo, double s, T* out)
+{
+    constexpr int H = (W + 1) / 2, HP = W / 2;
+    constexpr int NE = (TERMS + 1) / 2, NO = TERMS / 2;
+    const double* ev = eo;
+    const double* od = eo + NE * H;
+    const double u = s * s;
+    double e[H], o[HP];
+#pragma unroll
+    for (int a = 0; a < H; ++a) e[a] = ev[(NE - 1) * H + a];
+#pragma unroll
+    for (int j = NE - 2; j >= 0; --j) {
+#pragma unroll
+        for (int a = 0; a < H; ++a) e[a] = fma(e[a], u, ev[j * H + a]);
+    }
+#pragma unroll
+    for (int a = 0; a < HP; ++a) o[a] = od[(NO - 1) * HP + a];
+#pragma unroll
+    for (int j = NO - 2; j >= 0; --j) {
+#pragma unroll
+        for (int a = 0; a < HP; ++a) o[a] = fma(o[a], u, od[j * HP + a]);
+    }
+#pragma unroll
+    for (int a = 0; a < HP; ++a) {
+        out[a] = (T)fma(s, o[a], e[a]);
+        out[W - 1 - a] = (T)fma(-s, o[a], e[a]);
+    }
+    if constexpr ((W & 1) != 0) out[H - 1] = (T)e[H - 1];
+}
+
+// kernel_cells_eo for the DIM offsets of one point at once, cell pair by cell
+// pair: each coefficient is loaded once (a scalar load: the table is the same
+// for every lane) and used DIM times, so few coefficients are live at a time.
+template <typename T, int W, int TERMS, int DIM>
+__device__ __forceinline__ void kernel_cells_eo_dims(const double* __restrict__ eo, const double* sv,
+                                                     T (*out)[W])
+{
+    constexpr int H = (W + 1) / 2, HP = W / 2;
+    constexpr int NE = (TERMS + 1) / 2, NO = TERMS / 2;
+    const double* ev = eo;
+    const double* od = eo + NE * H;
+    double u[DIM];
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) u[l] = sv[l] * sv[l];
+#pragma unroll
+    for (int a = 0; a < H; ++a) {
+        double e[DIM], o[DIM];
+        const double ce = ev[(NE - 1) * H + a];
+#pragma unroll
+        for (int l = 0; l < DIM; ++l) e[l] = ce;
+#pragma unroll
+        for (int j = NE - 2; j >= 0; --j) {
+            const double c = ev[j * H + a];
+#pragma unroll
+            for (int l = 0; l < DIM; ++l) e[l] = fma(e[l], u[l], c);
+        }
+        if (a < HP) {
+            const double co = od[(NO - 1) * HP + a];
+#pragma unroll
+            for (int l = 0; l < DIM; ++l) o[l] = co;
+#pragma unroll
+            for (int j = NO - 2; j >= 0; --j) {
+                const double c = od[j * HP + a];
+#pragma unroll
+                for (int l = 0; l < DIM; ++l) o[l] = fma(o[l], u[l], c);
+            }
+#pragma unroll
+            for (int l = 0; l < DIM; ++l) {
+                out[l][a] = (T)fma(sv[l], o[l], e[l]);
+                out[l][W - 1 - a] = (T)fma(-sv[l], o[l], e[l]);
+            }
+        } else {
+#pragma unroll
+            for (int l = 0; l < DIM; ++l) out[l][a] = (T)e[l];
+        }
+    }
+}
+
 // Merged point ids pack (b_1, a_1, s, p_2, p_3) as
 // b1 | a1 << 8 | s << 16 | p2 << 26 | p3 << 42.
 __device__ __forceinline__ unsigned long long pack_id(int s, int a1, int b1, int p2, int p3)
@@ -102,12 +230,11 @@ __device__ __forceinline__ unsigned long long pack_id(int s, int a1, int b1, int
            ((unsigned long long)p2 << 26) | ((unsigned long long)p3 << 42);
 }
 
-// geometry of one merged point: weight without the orbit sum, and z/h - W/2
-// (in FP64 from z, so that bins and kernel offsets agree for both precisions)
+// post-collision velocity of one merged point and its weight without the map
+// factors and the orbit sum: q = W_s b0 S^d (times |u|^gamma for VHS)
 template <typename T, int DIM>
-__device__ __forceinline__ void point_geometry(const GainParams<T>& P, int s, int a1, int b1, int p2,
-                                               int p3, double halfW, T& q, double* xs,
-                                               int64_t& sym_idx)
+__device__ __forceinline__ void point_velocity(const GainParams<T>& P, int s, int a1, int b1, int p2,
+                                               int p3, T& q, T* vp)
 {
     const T half = (T)0.5;
     const T va = P.v1[a1], vb = P.v1[b1];
@@ -124,11 +251,21 @@ __device__ __forceinline__ void point_geometry(const GainParams<T>& P, int s, in
         r2 += (x - y) * (x - y);
     }
     const T un = sqrt(d * d + r2);
-    T vp[DIM];
     vp[0] = (va + vb) * half + un * P.sigma[s * DIM] * half;
     for (int l = 1; l < DIM; ++l) vp[l] = cen[l] + un * P.sigma[s * DIM + l] * half;
     q = P.wfac[s];
     if (P.vhs) q *= (P.gamma == (T)1) ? un : (un > (T)0 ? pow(un, P.gamma) : (T)(P.gamma == (T)0));
+}
+
+// geometry of one merged point: weight without the orbit sum, and z/h - W/2
+// (in FP64 from z, so that bins and kernel offsets agree for both precisions)
+template <typename T, int DIM>
+__device__ __forceinline__ void point_geometry(const GainParams<T>& P, int s, int a1, int b1, int p2,
+                                               int p3, double halfW, T& q, double* xs,
+                                               int64_t& sym_idx)
+{
+    T vp[DIM];
+    point_velocity<T, DIM>(P, s, a1, b1, p2, p3, q, vp);
 #pragma unroll
     for (int l = 0; l < DIM; ++l) {
         double z;

@@ -300,6 +300,65 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
 
 // ---------------------------------------------------------------- tables
 
+// For every bin coordinate c of one dimension (footprint corner t0 = c - W/2,
+// int division) the points of the cell have z in ((t0 - 1 + W/2) h, (t0 + W/2) h]
+// and kernel offset s = 2 t0 + W - 1 - 2 z / h.  With z = pi/2 - 2 atan(w) the
+// offset is a smooth function of w over the cell's w-interval [w_c - d, w_c + d];
+// it is interpolated at the Chebyshev points of x = (w - w_c)/d in long double
+// and stored as w_c, 1/d and the monomial coefficients in x.
+void build_cell_fits(Plan& p)
+{
+    constexpr int K = kCellFitDeg, n = K + 1;
+    const int nb = p.nh + 2, off = p.W / 2;
+    const long double pi = acosl(-1.0L), h = pi / p.nh, hw = 0.5L * p.W;
+    p.cellfit.assign((size_t)nb * kCellFitStride, 0.0);
+    p.cellfit_err = 0.0;
+    std::vector<long double> fx(n), cc(n), tm(n), t(n), tn(n), mono(n);
+    for (int c = 0; c < nb; ++c) {
+        const int t0 = c - off;
+        const long double zlo = std::max(0.0L, (t0 - 1 + hw) * h);
+        const long double zhi = std::min(pi, (t0 + hw) * h);
+        double* out = p.cellfit.data() + (size_t)c * kCellFitStride;
+        if (!(zhi > zlo)) continue;  // no point has this corner
+        const long double wlo = tanl(0.25L * pi - 0.5L * zhi), whi = tanl(0.25L * pi - 0.5L * zlo);
+        const long double wc = 0.5L * (wlo + whi), d = 0.5L * (whi - wlo);
+        auto offset = [&](long double x) {
+            const long double z = 0.5L * pi - 2.0L * atanl(wc + d * x);
+            return (long double)(2 * t0 + p.W - 1) - 2.0L * z / h;
+        };
+        for (int j = 0; j < n; ++j) fx[j] = offset(cosl(pi * (j + 0.5L) / n));
+        for (int k = 0; k < n; ++k) {
+            long double acc = 0.0L;
+            for (int j = 0; j < n; ++j) acc += fx[j] * cosl(pi * k * (j + 0.5L) / n);
+            cc[k] = (k == 0 ? 1.0L : 2.0L) * acc / n;
+        }
+        // sum_k cc_k T_k(x) -> monomials with T_{k+1} = 2 x T_k - T_{k-1}
+        std::fill(mono.begin(), mono.end(), 0.0L);
+        std::fill(tm.begin(), tm.end(), 0.0L);
+        std::fill(t.begin(), t.end(), 0.0L);
+        tm[0] = 1.0L;
+        t[1] = 1.0L;
+        mono[0] = cc[0];
+        mono[1] = cc[1];
+        for (int k = 2; k < n; ++k) {
+            for (int e = 0; e < n; ++e) tn[e] = -tm[e] + (e > 0 ? 2.0L * t[e - 1] : 0.0L);
+            for (int e = 0; e < n; ++e) mono[e] += cc[k] * tn[e];
+            tm = t;
+            t = tn;
+        }
+        out[0] = (double)wc;
+        out[1] = (double)(1.0L / d);
+        for (int k = 0; k < n; ++k) out[2 + k] = (double)mono[k];
+        // deviation of the stored (rounded) fit from the exact offset
+        for (int i = 0; i <= 64; ++i) {
+            const long double x = -1.0L + i / 32.0L;
+            long double v = out[2 + K];
+            for (int k = K - 1; k >= 0; --k) v = v * x + out[2 + k];
+            p.cellfit_err = std::max(p.cellfit_err, (double)fabsl(v - offset(x)));
+        }
+    }
+}
+
 void build_tables(Plan& p)
 {
     const int m = p.m_v;
@@ -344,6 +403,18 @@ void build_tables(Plan& p)
             terms, mono.data());
         for (int d = 0; d < terms; ++d) p.poly[(size_t)d * W + a] = mono[d];
     }
+
+    // even and odd parts of the cells a < W/2 (cell W-1-a at s is cell a at -s)
+    {
+        const int H = (W + 1) / 2, HP = W / 2, NE = (terms + 1) / 2, NO = terms / 2;
+        p.kpoly_eo.assign((size_t)NE * H + (size_t)NO * HP, 0.0);
+        for (int j = 0; j < NE; ++j)
+            for (int a = 0; a < H; ++a) p.kpoly_eo[(size_t)j * H + a] = p.poly[(size_t)(2 * j) * W + a];
+        for (int j = 0; j < NO; ++j)
+            for (int a = 0; a < HP; ++a)
+                p.kpoly_eo[(size_t)NE * H + (size_t)j * HP + a] = p.poly[(size_t)(2 * j + 1) * W + a];
+    }
+    build_cell_fits(p);
 
     // Fourier transform of the kernel in z units, psi^(k) = int psi(x/alpha) cos(k x) dx,
     // alpha = W h / 2, by a 256-point Gauss-Legendre rule in x/alpha
@@ -567,6 +638,8 @@ hipError_t allocate(Plan& p, hipStream_t s)
         p.dt.poly64 = static_cast<double*>(p.dt.poly);
     else
         PGC_TRY(upload64(p, &p.dt.poly64, p.poly, s));
+    PGC_TRY(upload64(p, &p.dt.kpoly_eo, p.kpoly_eo, s));
+    PGC_TRY(upload64(p, &p.dt.cellfit, p.cellfit, s));
     PGC_TRY(upload(p, &p.dt.sigma, p.sigma, s));
     {
         // W_s b0 S^d: the constant factors of every point's weight, one rounding in FP32

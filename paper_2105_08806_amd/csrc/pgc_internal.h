@@ -18,6 +18,11 @@ constexpr int kMaxWidth = 16;         // largest spreading kernel width W
 // keep one more term.
 constexpr int poly_terms(int w) { return w >= 10 ? w + 1 : w + 2; }
 constexpr int kMaxPolyTerms = 18;     // Horner terms per kernel cell (degree + 1)
+// Degree of the per-cell polynomial that gives the kernel offset from w: a
+// Chebyshev interpolant of degree 12 over one grid cell is within 5e-16 of the
+// exact offset on every grid with at least 8 cells per half period.
+constexpr int kCellFitDeg = 12;
+constexpr int kCellFitStride = kCellFitDeg + 3;  // w_c, 1/delta, c_0 .. c_12
 constexpr int kMaxLdsBytes = 160 * 1024;
 constexpr int kLdsBudget = 155 * 1024;  // slab bytes per workgroup
 
@@ -35,6 +40,8 @@ struct DeviceTables {
     double* E = nullptr;      // N x n_g  cos(k m h) h / (psi^(k) sqrt(c_k))
     void* poly = nullptr;     // terms x W Horner coefficients of the kernel cells
     double* poly64 = nullptr; // the same in FP64 (aliases poly for FP64 plans)
+    double* kpoly_eo = nullptr;  // even/odd parts of the cells a < W/2 (FP64)
+    double* cellfit = nullptr;   // (n_h + 2) x (deg + 3) kernel-offset fits per grid cell (FP64)
     void* sigma = nullptr;    // n_sigma x dim
     void* wfac = nullptr;     // n_sigma  W_s b0 S^d (direction weight, kernel constant, map scale)
     void* slab_vlo = nullptr; // n_slabs  v'_1 window of each slab
@@ -112,6 +119,8 @@ struct Plan {
     // host tables (FP64)
     std::vector<double> xi_all, v_all, w_all;
     std::vector<double> v1, w1, mu21, C, CT, E, poly, slab_vlo, slab_vhi, mom;
+    std::vector<double> kpoly_eo, cellfit;
+    double cellfit_err = 0.0;  // largest deviation of a cell fit from the exact offset
 
     size_t elt = 8;
     int gain_mode = kGainBinned;

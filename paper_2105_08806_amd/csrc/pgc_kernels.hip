@@ -550,35 +550,63 @@ struct BinItems {
     BinGeo geo;
 };
 
-// One wave per work item (a run of ids of one bin).  LP lanes serve one point:
-// in 3D lane e <-> footprint column (b, c) = (e / W, e % W) with the W cells
-// along the first dimension in registers; in 2D lane e <-> b.  G = 64 / LP
-// points are processed per step; NPASS > 1 when W^2 > 64.
+// Lane layout of the binned gain.  A point's footprint has CELLS columns
+// (3D: (b, c) pairs, 2D: b) of W cells each along the first dimension, which
+// a lane keeps in registers.  LP lanes serve one point and G = 64 / LP points
+// are spread per step; a lane holds NPASS columns e = e0 + LP r.  Wide 3D
+// footprints use two groups of 32 lanes when the accumulators fit (at most 48
+// FP64 or 96 FP32 values per lane): every broadcast read of a first-dimension
+// kernel vector then serves two points, which halves the LDS traffic that
+// bounds the kernel.
+template <typename T, int DIM, int W>
+struct BinLayout {
+    static constexpr int CELLS = (DIM == 2) ? W : W * W;
+    static constexpr bool WIDE = CELLS > 64;
+    static constexpr int ACC_MAX = sizeof(T) == 8 ? 48 : 96;
+    static constexpr int VEC = 16 / (int)sizeof(T);
+    static constexpr int STRIDE = (DIM * W + VEC - 1) / VEC * VEC;  // staged values per point
+    // the second group's FP64 partial tile goes through the stage buffer
+    static constexpr bool PAIRED = WIDE && ((CELLS + 31) / 32) * W <= ACC_MAX &&
+                                   32 * ((CELLS + 31) / 32) * W * 8 <= 64 * STRIDE * (int)sizeof(T);
+    static constexpr int LP = !WIDE ? CELLS : (PAIRED ? 32 : 64);
+    static constexpr int G = 64 / LP;
+    static constexpr int NPASS = (CELLS + LP - 1) / LP;
+};
+
+// One wave per work item (a run of ids of one bin), BinLayout lanes per point.
+//
+// Regeneration: a lane forms one point's velocity, its w in every dimension
+// (map_w), the kernel offset from the fit of the bin's cell (cell_offset) and
+// the W kernel values from the even and odd parts of the cells; the staged
+// vectors are k_1, q k_2 (q the full weight with the orbit sum) and, in 3D, k_3.
 template <typename T, int DIM, int W>
 __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
 {
+    using L = BinLayout<T, DIM, W>;
     constexpr int TERMS = poly_terms(W);
-    constexpr int CELLS = (DIM == 2) ? W : W * W;          // lanes per point, all passes
-    constexpr int LP = CELLS <= 64 ? CELLS : 64;
-    constexpr int G = CELLS <= 64 ? 64 / CELLS : 1;
-    constexpr int NPASS = (CELLS + 63) / 64;
-    constexpr int STRIDE = 1 + DIM * W;                      // staged values per point
-    __shared__ T stage[64 * STRIDE];
-    __shared__ double red[(G > 1) ? 64 * W : 1];
+    constexpr int CELLS = L::CELLS, LP = L::LP, G = L::G, NPASS = L::NPASS;
+    constexpr int STRIDE = L::STRIDE;
+    // columns past the last one (partial last pass) read values of the same point
+    static_assert(!L::WIDE || W + (LP * NPASS - 1) / W < STRIDE, "spare columns read out of the point");
+    // the partial tiles of the lane groups are reduced through the stage buffer
+    static_assert((G - 1) * LP * NPASS * W * 8 <= 64 * STRIDE * (int)sizeof(T), "reduction buffer");
+    __shared__ __align__(16) T stage[64 * STRIDE];
 
     const int lane = threadIdx.x;
     const int item = blockIdx.x;
     const int bin = BI.bin[item];
     const long long first = BI.begin[item];
     const int n = BI.count[item];
-    const double halfW = 0.5 * W;
 
-    // base cell of the bin
+    // base cell of the bin and the offset fit of its cell in every dimension
     int t0[DIM];
+    const double* fit[DIM];
     {
         int r = bin;
         for (int l = DIM - 1; l >= 0; --l) {
-            t0[l] = r % BI.geo.nb - BI.geo.off;
+            const int c = r % BI.geo.nb;
+            t0[l] = c - BI.geo.off;
+            fit[l] = P.cellfit + (int64_t)c * kCellFitStride;
             r /= BI.geo.nb;
         }
     }
@@ -601,7 +629,7 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
 
     for (int base = 0; base < n; base += 64) {
         const int nv = min(64, n - base);
-        // regenerate one point per lane and stage q and its kernel vectors
+        // regenerate one point per lane and stage its kernel vectors
         {
             T* st = stage + lane * STRIDE;
             if (lane < nv) {
@@ -609,23 +637,26 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
                 const int b1 = (int)(id & 0xffull), a1 = (int)((id >> 8) & 0xffull);
                 const int s = (int)((id >> 16) & 0x3ffull);
                 const int p2 = (int)((id >> 26) & 0xffffull), p3 = (int)((id >> 42) & 0xffffull);
-                T q;
-                double xs[DIM];
-                int64_t si;
-                point_geometry<T, DIM>(P, s, a1, b1, p2, p3, halfW, q, xs, si);
-                st[0] = q * orbit_sum<T, DIM>(P, a1, b1, p2, p3);
+                T q, vp[DIM];
+                point_velocity<T, DIM>(P, s, a1, b1, p2, p3, q, vp);
+                q *= orbit_sum<T, DIM>(P, a1, b1, p2, p3);
+                double sv[DIM];
 #pragma unroll
                 for (int l = 0; l < DIM; ++l) {
-                    T k[W];
-                    // offset relative to the bin's corner: s = 2 (t0 - xs) - 1
-                    kernel_cells64<T, W, TERMS>(P.poly64, 2.0 * ((double)t0[l] - xs[l]) - 1.0, k);
-#pragma unroll
-                    for (int a = 0; a < W; ++a) st[1 + l * W + a] = k[a];
+                    T m2;
+                    const double w = map_w(vp[l], P, m2);
+                    q *= m2;
+                    sv[l] = cell_offset(fit[l], w);
                 }
-            } else {
-                st[0] = (T)0;
+                T k[DIM][W];
+                kernel_cells_eo_dims<T, W, TERMS, DIM>(P.kpoly_eo, sv, k);
 #pragma unroll
-                for (int a = 0; a < DIM * W; ++a) st[1 + a] = (T)0;
+                for (int l = 0; l < DIM; ++l)
+#pragma unroll
+                    for (int a = 0; a < W; ++a) st[l * W + a] = (l == 1) ? k[l][a] * q : k[l][a];
+            } else {
+#pragma unroll
+                for (int a = 0; a < STRIDE; ++a) st[a] = (T)0;
             }
         }
         __syncthreads();
@@ -635,23 +666,22 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
 #pragma unroll
                 for (int a = 0; a < W; ++a) acc[r][a] = (T)0;
         }
-        // one staged point into the lane's columns
+        // one staged point into the lane's columns.  Spare columns of a
+        // partial last pass read values of the same point and accumulate
+        // cells that are never flushed, so no pass carries a per-lane branch.
         auto spread_point = [&](int pnt) {
             const T* sp = stage + pnt * STRIDE;
-            const T qp = sp[0];
             T k1[W];
 #pragma unroll
-            for (int a = 0; a < W; ++a) k1[a] = sp[1 + a];
+            for (int a = 0; a < W; ++a) k1[a] = sp[a];
 #pragma unroll
             for (int r = 0; r < NPASS; ++r) {
-                const int e = e0 + 64 * r;
-                if (e < CELLS) {
-                    T t;
-                    if constexpr (DIM == 2) t = qp * sp[1 + W + e];
-                    else t = qp * sp[1 + W + e / W] * sp[1 + 2 * W + e % W];
+                const int e = e0 + LP * r;
+                T t;
+                if constexpr (DIM == 2) t = sp[W + e];
+                else t = sp[W + e / W] * sp[2 * W + e % W];
 #pragma unroll
-                    for (int a = 0; a < W; ++a) acc[r][a] = fma(t, k1[a], acc[r][a]);
-                }
+                for (int a = 0; a < W; ++a) acc[r][a] = fma(t, k1[a], acc[r][a]);
             }
         };
         // full steps carry a point for every lane group (no per-lane guard, so
@@ -659,7 +689,7 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
         // arithmetic); a last partial step follows
         const int full = nv / G;
         if (lane_on) {
-#pragma unroll 4
+#pragma unroll 2
             for (int st_i = 0; st_i < full; ++st_i) spread_point(st_i * G + g);
             const int pnt = full * G + g;
             if (pnt < nv) spread_point(pnt);
@@ -681,23 +711,29 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
             else tot[r][a] = (double)acc[r][a];
         }
 
-    // groups of lanes that served different points hold partial sums of the same cells
+    // groups of lanes that served different points hold partial sums of the
+    // same cells: reduce them through the (now idle) stage buffer
     if constexpr (G > 1) {
+        double* red = reinterpret_cast<double*>(stage);
         if (lane_on && g > 0) {
 #pragma unroll
-            for (int a = 0; a < W; ++a) red[((g - 1) * LP + e0) * W + a] = tot[0][a];
+            for (int r = 0; r < NPASS; ++r)
+#pragma unroll
+                for (int a = 0; a < W; ++a) red[(((g - 1) * LP + e0) * NPASS + r) * W + a] = tot[r][a];
         }
         __syncthreads();
         if (g == 0) {
             for (int gg = 1; gg < G; ++gg)
 #pragma unroll
-                for (int a = 0; a < W; ++a) tot[0][a] += red[((gg - 1) * LP + e0) * W + a];
+                for (int r = 0; r < NPASS; ++r)
+#pragma unroll
+                    for (int a = 0; a < W; ++a) tot[r][a] += red[(((gg - 1) * LP + e0) * NPASS + r) * W + a];
         }
     }
     if (g != 0) return;
 #pragma unroll
     for (int r = 0; r < NPASS; ++r) {
-        const int e = e0 + 64 * r;
+        const int e = e0 + LP * r;
         if (e >= CELLS) continue;
         int64_t rest;
         if constexpr (DIM == 2) rest = fold_index(t0[1] + e, P.nh);
@@ -1114,6 +1150,8 @@ GainParams<T> gain_params(const Plan& p)
     gp.h_inv = (T)(1.0 / p.h);
     gp.h_inv64 = 1.0 / p.h;
     gp.poly64 = p.dt.poly64;
+    gp.kpoly_eo = p.dt.kpoly_eo;
+    gp.cellfit = p.dt.cellfit;
     gp.b0 = (T)p.b0;
     gp.gamma = (T)p.gamma;
     gp.map = p.map;
