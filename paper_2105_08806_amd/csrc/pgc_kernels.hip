@@ -761,21 +761,23 @@ __global__ void __launch_bounds__(64) gain_binned_mfma(GainParams<double> P, Bin
     constexpr int TERMS = poly_terms(W);
     constexpr int CELLS = W * W;
     constexpr int NT = (CELLS + 15) / 16;
-    constexpr int STRIDE = 1 + 3 * W;  // kx[W], q ky[W], kz[W] after one pad slot
+    constexpr int STRIDE = (3 * W + 1) / 2 * 2;  // kx[W], q ky[W], kz[W], padded to 16 bytes
     typedef double dvec4 __attribute__((ext_vector_type(4)));
-    __shared__ double stage[64 * STRIDE];
+    __shared__ __align__(16) double stage[64 * STRIDE];
 
     const int lane = threadIdx.x;
     const int item = blockIdx.x;
     const int bin = BI.bin[item];
     const long long first = BI.begin[item];
     const int n = BI.count[item];
-    const double halfW = 0.5 * W;
     int t0[3];
+    const double* fit[3];
     {
         int r = bin;
         for (int l = 2; l >= 0; --l) {
-            t0[l] = r % BI.geo.nb - BI.geo.off;
+            const int c = r % BI.geo.nb;
+            t0[l] = c - BI.geo.off;
+            fit[l] = P.cellfit + (int64_t)c * kCellFitStride;
             r /= BI.geo.nb;
         }
     }
@@ -787,6 +789,7 @@ __global__ void __launch_bounds__(64) gain_binned_mfma(GainParams<double> P, Bin
 
     for (int base = 0; base < n; base += 64) {
         const int nv = min(64, n - base);
+        // regenerate one point per lane (as in gain_binned)
         {
             double* st = stage + lane * STRIDE;
             if (lane < nv) {
@@ -794,33 +797,38 @@ __global__ void __launch_bounds__(64) gain_binned_mfma(GainParams<double> P, Bin
                 const int b1 = (int)(id & 0xffull), a1 = (int)((id >> 8) & 0xffull);
                 const int s = (int)((id >> 16) & 0x3ffull);
                 const int p2 = (int)((id >> 26) & 0xffffull), p3 = (int)((id >> 42) & 0xffffull);
-                double q, xs[3];
-                int64_t si;
-                point_geometry<double, 3>(P, s, a1, b1, p2, p3, halfW, q, xs, si);
+                double q, vp[3];
+                point_velocity<double, 3>(P, s, a1, b1, p2, p3, q, vp);
                 q *= orbit_sum<double, 3>(P, a1, b1, p2, p3);
-                double k[W];
-                kernel_cells64<double, W, TERMS>(P.poly64, 2.0 * ((double)t0[0] - xs[0]) - 1.0, k);
+                double sv[3];
 #pragma unroll
-                for (int a = 0; a < W; ++a) st[1 + a] = k[a];
-                kernel_cells64<double, W, TERMS>(P.poly64, 2.0 * ((double)t0[1] - xs[1]) - 1.0, k);
+                for (int l = 0; l < 3; ++l) {
+                    double m2;
+                    const double w = map_w(vp[l], P, m2);
+                    q *= m2;
+                    sv[l] = cell_offset(fit[l], w);
+                }
+                double k[3][W];
+                kernel_cells_eo_dims<double, W, TERMS, 3>(P.kpoly_eo, sv, k);
 #pragma unroll
-                for (int a = 0; a < W; ++a) st[1 + W + a] = q * k[a];
-                kernel_cells64<double, W, TERMS>(P.poly64, 2.0 * ((double)t0[2] - xs[2]) - 1.0, k);
+                for (int l = 0; l < 3; ++l)
 #pragma unroll
-                for (int a = 0; a < W; ++a) st[1 + 2 * W + a] = k[a];
+                    for (int a = 0; a < W; ++a) st[l * W + a] = (l == 1) ? k[l][a] * q : k[l][a];
             } else {
                 for (int a = 0; a < STRIDE; ++a) st[a] = 0.0;
             }
         }
         __syncthreads();
+        // lanes with i16 >= W (rows past the footprint) and columns past W^2
+        // contribute zeros; their reads stay inside the point's staged values
         const int ksteps = (nv + 3) >> 2;
         for (int ks = 0; ks < ksteps; ++ks) {
             const double* sp = stage + (4 * ks + k4) * STRIDE;
-            const double av = i16 < W ? sp[1 + i16] : 0.0;
+            const double av = i16 < W ? sp[i16] : 0.0;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const int col = 16 * t + i16;
-                const double bv = col < CELLS ? sp[1 + W + col / W] * sp[1 + 2 * W + col % W] : 0.0;
+                const double bv = col < CELLS ? sp[W + col / W] * sp[2 * W + col % W] : 0.0;
                 acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
             }
         }
