@@ -238,7 +238,8 @@ def batched_variant(torch, pgc, inputs, np, n_cells, reps):
                            n_cells, counts, b.info.kernel_width),
            "rel_l2_vs_fp64_path_max": max(errs), "cells_checked": len(errs),
            "plain_fp64_est_s_per_batch": fp64_s, "speedup_vs_plain_fp64": fp64_s / (ms / 1e3),
-           "cells_per_wave": b.info.cells_per_wave, "points_per_s": b.info.n_points / (ms / 1e3)}
+           "cells_per_wave": b.info.cells_per_wave, "group_major": b.info.group_major,
+           "points_per_s": b.info.n_points / (ms / 1e3)}
     b.close()
     for p in plans.values():
         p.close()

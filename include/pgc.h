@@ -239,6 +239,9 @@ typedef struct pgc_batch_info {
     int32_t scheme;             /* 0 register tiles, 1 lane per cell */
     int32_t spatial_order;      /* 1: bin runs in raster order of their bins, 0: longest first */
     double order_ms[2];         /* autotuner: gain time at the chosen C, longest-first / raster order */
+    int32_t group_major;        /* 1: work units run through all bin runs of one cell group before the
+                                   next group (the G rows in use stay in L2); 0: bin-run major */
+    double major_ms[2];         /* autotuner: gain time at the chosen C and order, bin-run / cell-group major */
 } pgc_batch_info;
 
 /* Build a batch of n_cells cells; n_modes_host[c] is the N of cell c.

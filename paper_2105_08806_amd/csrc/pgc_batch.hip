@@ -44,8 +44,24 @@ struct GroupDev {
     double* grid;        // n_cells x ngd FP64 fine grids
     int nb, off, n_cells, ncg;  // ncg = cell groups of C cells
     int ldg;             // row length of Gt (n_cells rounded up to 64)
-    int64_t nid, ngd, unit_begin;
+    int group_major;     // units run through every bin run of one cell group before the next
+    int64_t nid, ngd, unit_begin, n_items;
 };
+
+// bin run and first cell of unit `local` of a group
+__device__ __forceinline__ void unit_of(const GroupDev& D, long long local, int C, int& item, int& c0)
+{
+    long long run, cg;
+    if (D.group_major) {
+        run = local % D.n_items;
+        cg = local / D.n_items;
+    } else {
+        run = local / D.ncg;
+        cg = local % D.ncg;
+    }
+    item = D.order ? D.order[run] : (int)run;
+    c0 = (int)cg * C;
+}
 
 __device__ __forceinline__ unsigned long long lane0(unsigned long long x)
 {
@@ -56,8 +72,10 @@ __device__ __forceinline__ unsigned long long lane0(unsigned long long x)
 
 // Persistent gain over every group: one 64-lane wave per workgroup takes units
 // u = atomicAdd(counter) until the counter passes n_units (every wave reaches
-// that exit).  Unit u of group g covers bin run (u - begin_g) / ncg_g and cells
-// C ((u - begin_g) % ncg_g) .. + C - 1 of the group.
+// that exit).  Unit u of group g covers one bin run and C cells of the group:
+// bin run (u - begin_g) / ncg_g and cells C ((u - begin_g) % ncg_g) .. + C - 1
+// (bin-run major), or with the roles swapped (cell-group major: the waves
+// that run at the same time read the G rows of one cell group, which stay in L2).
 template <int W, int C>
 __global__ void __launch_bounds__(64) gain_batched(const GroupDev* __restrict__ groups, int n_groups,
                                                    unsigned long long n_units,
@@ -80,8 +98,8 @@ __global__ void __launch_bounds__(64) gain_batched(const GroupDev* __restrict__ 
         while (g + 1 < n_groups && (long long)u >= groups[g + 1].unit_begin) ++g;
         const GroupDev& D = groups[g];
         const long long local = (long long)u - D.unit_begin;
-        const int item = D.order ? D.order[local / D.ncg] : (int)(local / D.ncg);
-        const int c0 = (int)(local % D.ncg) * C;
+        int item, c0;
+        unit_of(D, local, C, item, c0);
         const int nc = min(C, D.n_cells - c0);
         const int bin = D.item_bin[item];
         const long long first = D.item_begin[item];
@@ -161,6 +179,7 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
     constexpr int TERMS = poly_terms(W);
     constexpr int CELLS = W * W;
     constexpr int NS = 64 / CW;
+    constexpr int PB = 8;  // points whose G rows are gathered together
     __shared__ float sq[64];
     __shared__ float sk[64][2 * W];
     __shared__ int sx[64][4];
@@ -184,15 +203,19 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
         while (g + 1 < n_groups && (long long)u >= groups[g + 1].unit_begin) ++g;
         const GroupDev& D = groups[g];
         const long long local = (long long)u - D.unit_begin;
-        const int item = D.order ? D.order[local / D.ncg] : (int)(local / D.ncg);
-        const int c = (int)(local % D.ncg) * CW + cl;
+        int item, c0;
+        unit_of(D, local, CW, item, c0);
+        const int c = c0 + cl;
         const bool valid = c < D.n_cells;
         const int bin = D.item_bin[item];
         const long long first = D.item_begin[item];
         const int n = D.item_count[item];
         const int t0x = bin / D.nb - D.off;
         const int t0y = bin % D.nb - D.off;
-        const float* Gt = D.Gt;
+        // the cell-minor G copy is device memory: global loads, not flat ones
+        // (which would also count against the LDS wait counter)
+        const __attribute__((address_space(1))) float* Gt =
+            (const __attribute__((address_space(1))) float*)D.Gt;
         const int ldg = D.ldg;
 
 #pragma unroll
@@ -229,15 +252,29 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
                 float ab[CELLS];
 #pragma unroll
                 for (int e = 0; e < CELLS; ++e) ab[e] = 0.f;
-#pragma unroll 2
-                for (int j = stream; j < nv; j += NS) {
-                    const float w =
-                        sq[j] * fmaf(Gt[sx[j][0] + c], Gt[sx[j][1] + c], Gt[sx[j][2] + c] * Gt[sx[j][3] + c]);
+                // The G rows of PB points are gathered together (4 PB loads in
+                // flight) before their arithmetic, so the memory latency is
+                // paid once per PB points.  Points past the batch repeat the
+                // last one with weight 0.
+                for (int j0 = stream; j0 < nv; j0 += PB * NS) {
+                    float gv[PB][4];
 #pragma unroll
-                    for (int a = 0; a < W; ++a) {
-                        const float t = w * sk[j][a];
+                    for (int k = 0; k < PB; ++k) {
+                        const int j = min(j0 + k * NS, nv - 1);
 #pragma unroll
-                        for (int b = 0; b < W; ++b) ab[a * W + b] = fmaf(t, sk[j][W + b], ab[a * W + b]);
+                        for (int m = 0; m < 4; ++m) gv[k][m] = Gt[sx[j][m] + c];
+                    }
+#pragma unroll
+                    for (int k = 0; k < PB; ++k) {
+                        const int j = min(j0 + k * NS, nv - 1);
+                        const float live = (j0 + k * NS < nv) ? 1.f : 0.f;
+                        const float w = live * sq[j] * fmaf(gv[k][0], gv[k][1], gv[k][2] * gv[k][3]);
+#pragma unroll
+                        for (int a = 0; a < W; ++a) {
+                            const float t = w * sk[j][a];
+#pragma unroll
+                            for (int b = 0; b < W; ++b) ab[a * W + b] = fmaf(t, sk[j][W + b], ab[a * W + b]);
+                        }
                     }
                 }
 #pragma unroll
@@ -496,6 +533,8 @@ struct pgc_batch_s {
     int C = 0, waves = 0;
     int spatial = 1;          // process bin runs in raster order (else longest first)
     double order_ms[2] = {0, 0};  // autotuner: best C in longest-first / raster order
+    int group_major = 0;      // units cell-group major (else bin-run major)
+    double major_ms[2] = {0, 0};  // autotuner: bin-run major / cell-group major at the chosen C and order
     unsigned long long n_units = 0;
     int64_t n_points = 0;
     double tuned_ms[7] = {0, 0, 0, 0, 0, 0, 0};  // C = 1, 2, 4, 8, 16, 32, 64
@@ -569,6 +608,8 @@ hipError_t set_units(pgc_batch_s& b, int C, hipStream_t s)
         d.off = p.bins.off;
         d.n_cells = (int)G.cells.size();
         d.ncg = (d.n_cells + C - 1) / C;
+        d.group_major = b.group_major;
+        d.n_items = p.bins.n_items;
         d.nid = p.nid;
         d.ngd = p.ngd;
         d.unit_begin = (int64_t)begin;
@@ -692,6 +733,21 @@ hipError_t autotune(pgc_batch_s& b, hipStream_t s)
             (e = hipEventElapsedTime(&ms, t0, t1)) == hipSuccess) {
             b.order_ms[b.spatial] = ms;
             if (!(ms < best_ms)) b.spatial = keep;
+            else best_ms = ms;
+        }
+    }
+    if (e == hipSuccess && best != 0) {
+        // the other unit order at the best C and bin-run order
+        const int keep = b.group_major;
+        b.major_ms[keep] = best_ms;
+        b.group_major = 1 - keep;
+        float ms = 0.f;
+        if ((e = set_units(b, best, s)) == hipSuccess && (e = enqueue_gain(b, s)) == hipSuccess &&
+            (e = hipEventRecord(t0, s)) == hipSuccess && (e = enqueue_gain(b, s)) == hipSuccess &&
+            (e = hipEventRecord(t1, s)) == hipSuccess && (e = hipEventSynchronize(t1)) == hipSuccess &&
+            (e = hipEventElapsedTime(&ms, t0, t1)) == hipSuccess) {
+            b.major_ms[b.group_major] = ms;
+            if (!(ms < best_ms)) b.group_major = keep;
         }
     }
     (void)hipEventDestroy(t0);
@@ -844,6 +900,9 @@ pgc_status pgc_batch_query(pgc_batch b, pgc_batch_info* info)
     info->spatial_order = b->spatial;
     info->order_ms[0] = b->order_ms[0];
     info->order_ms[1] = b->order_ms[1];
+    info->group_major = b->group_major;
+    info->major_ms[0] = b->major_ms[0];
+    info->major_ms[1] = b->major_ms[1];
     info->has_graph = b->exec != nullptr;
     return PGC_OK;
 }
