@@ -184,14 +184,14 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
     __shared__ float sk[64][2 * W];
     __shared__ int sx[64][4];
     __shared__ double red[(NS > 1) ? (NS - 1) * CW * CELLS : 1];
-    // the kernel polynomial depends on W and the upsampling only, the same for
-    // every group: read from LDS it is not hoisted into registers
-    __shared__ double spoly[TERMS * W];
+    // the kernel cells depend on W and the upsampling only, the same for every
+    // group: read from LDS they are not hoisted into registers
+    constexpr int EO = ((TERMS + 1) / 2) * ((W + 1) / 2) + (TERMS / 2) * (W / 2);
+    __shared__ double seo[EO];
     __shared__ float sacc[CELLS * 64];  // running tile of every lane, lane fastest
     const int lane = threadIdx.x;
     const int cl = lane % CW, stream = lane / CW;
-    const double halfW = 0.5 * W;
-    for (int i = lane; i < TERMS * W; i += 64) spoly[i] = groups[0].gp.poly64[i];
+    for (int i = lane; i < EO; i += 64) seo[i] = groups[0].gp.kpoly_eo[i];
     __syncthreads();
 
     for (;;) {
@@ -224,23 +224,30 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
         for (int base = 0; base < n; base += 64) {
             const int nv = min(64, n - base);
             if (lane < nv) {
+                // the regeneration of gain_binned: w per dimension, the offset
+                // from the cell fit, the mirrored kernel cells
                 const unsigned long long id = D.ids[first + base + lane];
                 const int b1 = (int)(id & 0xffull), a1 = (int)((id >> 8) & 0xffull);
                 const int s = (int)((id >> 16) & 0x3ffull);
                 const int p2 = (int)((id >> 26) & 0xffffull);
-                float q;
-                double xs[2];
-                int64_t si;
-                point_geometry<float, 2>(D.gp, s, a1, b1, p2, 0, halfW, q, xs, si);
-                float kx[W], ky[W];
-                kernel_cells64<float, W, TERMS>(spoly, 2.0 * ((double)t0x - xs[0]) - 1.0, kx);
-                kernel_cells64<float, W, TERMS>(spoly, 2.0 * ((double)t0y - xs[1]) - 1.0, ky);
+                float q, vp[2];
+                point_velocity<float, 2>(D.gp, s, a1, b1, p2, 0, q, vp);
+                double sv[2];
+#pragma unroll
+                for (int l = 0; l < 2; ++l) {
+                    float m2;
+                    const double w = map_w(vp[l], D.gp, m2);
+                    q *= m2;
+                    sv[l] = cell_offset(D.gp.cellfit + (int64_t)((l == 0 ? t0x : t0y) + D.off) * kCellFitStride, w);
+                }
+                float k[2][W];
+                kernel_cells_eo_dims<float, W, TERMS, 2>(seo, sv, k);
                 int ix[2], iy[2];
                 sq[lane] = q * orbit_terms<float, 2>(D.gp, a1, b1, p2, 0, ix, iy);
 #pragma unroll
                 for (int a = 0; a < W; ++a) {
-                    sk[lane][a] = kx[a];
-                    sk[lane][W + a] = ky[a];
+                    sk[lane][a] = k[0][a];
+                    sk[lane][W + a] = k[1][a];
                 }
                 sx[lane][0] = ix[0] * ldg;
                 sx[lane][1] = iy[0] * ldg;
@@ -490,6 +497,8 @@ GainParams<float> group_gain_params(const Plan& p)
     gp.h_inv = (float)(1.0 / p.h);
     gp.h_inv64 = 1.0 / p.h;
     gp.poly64 = p.dt.poly64;
+    gp.kpoly_eo = p.dt.kpoly_eo;
+    gp.cellfit = p.dt.cellfit;
     gp.b0 = (float)p.b0;
     gp.gamma = (float)p.gamma;
     gp.map = p.map;
