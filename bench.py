@@ -230,8 +230,9 @@ def batched_variant(torch, pgc, inputs, np, n_cells, reps):
     out = {"value": n_cells / (ms / 1e3), "unit": "cell Q-evals/s", "ms_per_eval": ms,
            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12,
                         "unit": "TFLOP/s", "frac": achieved / PEAK["fp32"],
+                        # counters were taken in the profiled configuration only
                         "traffic": traffic_for("gain_batched_lanes_2d_4096") if b.info.cells_per_wave == 64
-                        and W == 7 else None,
+                        and W == 7 and b.info.spatial_order == 1 and b.info.group_major == 1 else None,
                         "note": "2 W^2 flops per merged point and cell over the whole batched evaluation"},
            "workload": "2D batch of %d cells, N from {32,48,64} (%s), S=6, Maxwell, 32 directions, "
                        "perturbed Maxwellians, FP32 gain (W=%d), graph replay" % (
@@ -466,6 +467,7 @@ def main():
                                               for i, c in enumerate(cells)]).astype(np.float32), device="cuda")
         b = pgc.Batch([c["N"] for c in cells], scale=6.0, n_sigma=32, nufft_tol=1e-8, autotune=False)
         b.set_tile(64)
+        b.set_order(1, 1)  # raster bin runs, cell-group major: the autotuner's choice here
         for _ in range(2):
             b.coeffs_to_q(packed)
         torch.cuda.synchronize()

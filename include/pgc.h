@@ -261,6 +261,13 @@ pgc_status pgc_batch_offsets(pgc_batch batch, int64_t* offsets_host);
  * the autotuner.  Both drop a captured graph and synchronise `stream`. */
 pgc_status pgc_batch_set_tile(pgc_batch batch, int32_t cells_per_wave, void* stream);
 pgc_status pgc_batch_autotune(pgc_batch batch, void* stream);
+/* Force the order of the gain's work units at the current C: raster = 1 takes
+ * the bin runs in raster order of their bins (0: longest first); group_major = 1
+ * runs through all bin runs of one cell group before the next (0: all cell
+ * groups of one bin run first).  The result does not depend on the order up to
+ * FP64 summation order.  Drops a captured graph and synchronises `stream`.
+ * Errors: INVALID_ARG (a flag other than 0 or 1), DEVICE. */
+pgc_status pgc_batch_set_order(pgc_batch batch, int32_t raster, int32_t group_major, void* stream);
 /* Q of every cell: packed_q_dev receives Q_c at offsets[c] (float).  Stream
  * ordered, allocates nothing.  The input and output ranges must not overlap. */
 pgc_status pgc_batch_coeffs_to_q(pgc_batch batch, const void* packed_coeffs_dev, const int64_t* offsets_dev,

@@ -931,6 +931,15 @@ pgc_status pgc_batch_set_tile(pgc_batch b, int32_t cells_per_wave, void* stream)
     return pgc::status_of(set_units(*b, cells_per_wave, static_cast<hipStream_t>(stream)));
 }
 
+pgc_status pgc_batch_set_order(pgc_batch b, int32_t raster, int32_t group_major, void* stream)
+{
+    if (!b || (raster != 0 && raster != 1) || (group_major != 0 && group_major != 1)) return PGC_ERR_INVALID_ARG;
+    drop_graph(*b);
+    b->spatial = raster;
+    b->group_major = group_major;
+    return pgc::status_of(set_units(*b, b->C, static_cast<hipStream_t>(stream)));
+}
+
 pgc_status pgc_batch_autotune(pgc_batch b, void* stream)
 {
     if (!b) return PGC_ERR_INVALID_ARG;

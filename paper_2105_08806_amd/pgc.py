@@ -128,6 +128,7 @@ def lib():
         L.pgc_batch_offsets.argtypes = [vp, ctypes.POINTER(i64)]
         L.pgc_batch_set_tile.argtypes = [vp, i32, vp]
         L.pgc_batch_autotune.argtypes = [vp, vp]
+        L.pgc_batch_set_order.argtypes = [vp, i32, i32, vp]
         L.pgc_batch_coeffs_to_q.argtypes = [vp, vp, vp, vp, vp]
         L.pgc_batch_capture.argtypes = [vp, vp, vp, vp, vp]
         L.pgc_batch_graph_launch.argtypes = [vp, vp]
@@ -154,7 +155,7 @@ def lib():
                      "pgc_plan_query", "pgc_nodes", "pgc_project", "pgc_coeffs_to_q", "pgc_rk4",
                      "pgc_moments", "pgc_eval", "pgc_set_profiling", "pgc_stage_times",
                      "pgc_batch_create", "pgc_batch_destroy", "pgc_batch_query", "pgc_batch_offsets",
-                     "pgc_batch_set_tile", "pgc_batch_autotune", "pgc_batch_coeffs_to_q",
+                     "pgc_batch_set_tile", "pgc_batch_set_order", "pgc_batch_autotune", "pgc_batch_coeffs_to_q",
                      "pgc_batch_capture", "pgc_batch_graph_launch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -392,6 +393,10 @@ class Batch:
 
     def set_tile(self, cells_per_wave):
         _check(lib().pgc_batch_set_tile(self._h, int(cells_per_wave), _stream()), "pgc_batch_set_tile")
+        self.refresh_info()
+
+    def set_order(self, raster, group_major):
+        _check(lib().pgc_batch_set_order(self._h, int(raster), int(group_major), _stream()), "pgc_batch_set_order")
         self.refresh_info()
 
     def autotune(self):

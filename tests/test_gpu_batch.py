@@ -119,6 +119,36 @@ def test_batch_custom_offsets_and_zero_cells(torch_cuda):
     b.close()
 
 
+def test_batch_unit_orders_agree(torch_cuda):
+    """The four orders of the gain's work units (bin runs longest first or in
+    raster order, bin-run or cell-group major) give the same Q up to FP64
+    summation order, for a register-tile and a lane-per-cell C; flags other
+    than 0 and 1 are rejected."""
+    torch = torch_cuda
+    from paper_2105_08806_amd import pgc
+    S, M = 3.0, 8
+    cells = I.cell_maxwellians_2d(40, seed=13, modes=(7, 10))
+    coeffs, _ = cell_coeffs(cells, S, M)
+    b = pgc.Batch([c["N"] for c in cells], scale=S, n_sigma=M, nufft_tol=TOL, autotune=False)
+    packed = b.pack(coeffs)
+    for C in (2, 16):
+        b.set_tile(C)
+        ref = None
+        for raster in (0, 1):
+            for major in (0, 1):
+                b.set_order(raster, major)
+                assert (b.info.spatial_order, b.info.group_major) == (raster, major)
+                got = b.unpack(b.coeffs_to_q(packed))
+                if ref is None:
+                    ref = got
+                    continue
+                for c in range(len(cells)):
+                    assert rel(got[c], ref[c]) <= 1e-6, (C, raster, major, c)
+    with pytest.raises(pgc.PgcError):
+        b.set_order(2, 0)
+    b.close()
+
+
 def test_batch_graph_replays(torch_cuda):
     """The captured graph, replayed three times with new input and eager work
     in between, matches the eager batched call every time."""
