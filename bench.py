@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Q(f,f) evals/s, 3D N=32^3: FP64 plain vs FP32/batched/surrogate at stated rel-L2"
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}  # MI355X vector peaks, FLOP/s
+LOOSE_JUDGE = 0.15  # second judge tolerance reported for the surrogate: about its worst held-out error
 N, S, T0, DT = 32, 5.0, 6.5, 0.1
 N_THETA, N_PHI = 8, 8
 CSRC = os.path.join(ROOT, "paper_2105_08806_amd", "csrc")
@@ -297,10 +298,12 @@ def surrogate_variant(torch, pgc, inputs, np, n_pairs, epochs):
     f_te, q_te = pairs(128, 77)
     t_gen = time.time() - t0
     fa, qa = symmetric_copies(torch, f_tr, N), symmetric_copies(torch, q_tr, N)
-    s = pgc.Surrogate(plan, width=1024, n_layers=4, batch_max=256, seed=3)
+    # trained on the mean squared relative error of every sample (the judge's
+    # measure), not the error of the normalised outputs
+    s = pgc.Surrogate(plan, width=1024, n_layers=4, batch_max=256, seed=3, loss_relative=1)
     s.set_normalization(fa, qa)
     t = time.time()
-    losses = s.train(fa, qa, epochs=epochs, batch=256, lr=1e-3, seed=5)
+    losses = s.train(fa, qa, epochs=epochs, batch=256, lr=3e-4, seed=5)
     torch.cuda.synchronize()
     t_train = time.time() - t
     log("surrogate: %d pairs (x16 images) in %.1f s, %d epochs in %.1f s, loss %.3e -> %.3e" % (
@@ -340,9 +343,9 @@ def surrogate_variant(torch, pgc, inputs, np, n_pairs, epochs):
         p64.coeffs_to_q(c64)
     torch.cuda.synchronize()
     t_fp64 = (time.time() - t) / 2
-    # the same network with a judge tolerance above its measured error: what the
-    # surrogate gains where that accuracy is acceptable
-    loose = pgc.Surrogate(plan, width=1024, n_layers=4, batch_max=256, seed=3, judge_tol=0.5)
+    # the same network with a judge tolerance at its measured worst error: what
+    # the surrogate gains where that accuracy is acceptable
+    loose = pgc.Surrogate(plan, width=1024, n_layers=4, batch_max=256, seed=3, judge_tol=LOOSE_JUDGE)
     with tempfile.TemporaryDirectory() as d:  # parameters and gate calibration
         s.save(os.path.join(d, "net.bin"))
         loose.load(os.path.join(d, "net.bin"))
@@ -360,7 +363,7 @@ def surrogate_variant(torch, pgc, inputs, np, n_pairs, epochs):
            "speedup_vs_plain_fp64": (f_te.shape[0] / t_dep) * t_fp64,
            "network_rel_l2_vs_plain_median": float(np.median(err)), "network_rel_l2_vs_plain_max": max(err),
            "fallbacks": nfb, "of": int(f_te.shape[0]), "judge_max_rel_err": jerr,
-           "judge_tol_0.5": {"evals_per_s": f_te.shape[0] / t_loose, "fallbacks": nfb_l,
+           "judge_tol_%g" % LOOSE_JUDGE: {"evals_per_s": f_te.shape[0] / t_loose, "fallbacks": nfb_l,
                              "speedup_vs_plain_fp64": (f_te.shape[0] / t_loose) * t_fp64,
                              "rel_l2_vs_plain_median": float(np.median(err_l)),
                              "rel_l2_vs_plain_max": max(err_l)},
@@ -412,8 +415,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--batch-cells", type=int, default=4096)
     ap.add_argument("--batch-reps", type=int, default=3)
-    ap.add_argument("--surrogate-pairs", type=int, default=2048)
-    ap.add_argument("--surrogate-epochs", type=int, default=60)
+    ap.add_argument("--surrogate-pairs", type=int, default=4096)
+    ap.add_argument("--surrogate-epochs", type=int, default=150)
     ap.add_argument("--pmc-dir", default="gpurun_out/prof")
     ap.add_argument("--mode", choices=["bench", "profile", "copy", "bkw", "traffic"], default="bench",
                     help="profile: two evaluations per precision (for rocprofv3); "

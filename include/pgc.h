@@ -126,6 +126,9 @@ typedef struct pgc_plan_info {
     int64_t workspace_bytes;/* device memory owned by the plan */
     int32_t gain_mode;      /* 1 = slabs, 2 = bins, 3 = bins on the FP64 matrix cores */
     int64_t n_bin_items;    /* binned mode: work items (runs of one bin) per evaluation */
+    double offset_fit_err;  /* largest deviation, over every grid cell, of the stored per-cell
+                               polynomial that gives a point's kernel offset from w (binned
+                               gain) from the exact offset, in units of the offset's range [-1, 1] */
 } pgc_plan_info;
 
 /* Human-readable text of a status code (static storage, never NULL). */
@@ -246,8 +249,10 @@ typedef struct pgc_batch_info {
 
 /* Build a batch of n_cells cells; n_modes_host[c] is the N of cell c.
  * With autotune != 0 the call times the gain for every supported C on the
- * device (a few evaluations of the gain) and keeps the fastest; otherwise
- * C = 1.  `stream` orders the set-up work, which the call synchronises.
+ * device (the best of two evaluations; one when the first is over 1.5x the
+ * best so far) and keeps the fastest, then times the other bin-run order and
+ * the other unit order at that C and keeps each only when it is over 3%
+ * faster; otherwise C = 1, raster order, bin-run major.  `stream` orders the set-up work, which the call synchronises.
  * Errors: INVALID_ARG, UNSUPPORTED (dim != 2, precision != FP32, more than 8
  * distinct N, a kernel width outside 4..8), OUT_OF_MEMORY, DEVICE. */
 pgc_status pgc_batch_create(const pgc_plan_desc* base, int32_t n_cells, const int32_t* n_modes_host,
@@ -320,6 +325,12 @@ typedef struct pgc_surrogate_desc {
     double norm_floor_in;    /* per-feature standard deviations of the inputs are held at or
                                 above this fraction of the largest; default 0.1 */
     double norm_floor_out;   /* the same for the outputs; default 1 (one common scale) */
+    int32_t loss_relative;   /* training loss: 0 (default) the mean squared error of the
+                                normalised outputs, (1 / (B n)) sum_r sum_c d_rc^2 with
+                                d = yhat - (q - mu_out) / sd_out; 1 the mean squared relative
+                                error of every sample in the units of q,
+                                (1 / B) sum_r sum_c (sd_out_c d_rc)^2 / sum_c q_rc^2, which
+                                weights every sample by its own scale as the judge does */
 } pgc_surrogate_desc;
 
 typedef struct pgc_surrogate_info {

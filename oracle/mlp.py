@@ -53,14 +53,21 @@ def forward(params, f, mu_in, sd_in, bf16=True):
     return zs[-1], (hs, zs)
 
 
-def loss_and_grad(params, f, q, mu_in, sd_in, mu_out, sd_out, bf16=True):
-    """Mean squared error of the normalised output and its gradient [(dW, db), ...]."""
+def loss_and_grad(params, f, q, mu_in, sd_in, mu_out, sd_out, bf16=True, relative=False):
+    """Loss and its gradient [(dW, db), ...].  relative=False: mean squared
+    error of the normalised output.  relative=True: mean over rows of the
+    squared relative error in the units of q, |sd_out * d_r|^2 / |q_r|^2."""
     yhat, (hs, zs) = forward(params, f, mu_in, sd_in, bf16)
-    y = (np.asarray(q, np.float64) - mu_out) / sd_out
+    qq = np.asarray(q, np.float64)
+    y = (qq - mu_out) / sd_out
     rows, n = yhat.shape
     d = yhat - y
-    loss = float(np.sum(d * d) / (rows * n))
-    g32 = 2.0 * d / (rows * n)
+    if relative:
+        wt = np.asarray(sd_out, np.float64) ** 2 / np.sum(qq * qq, axis=1, keepdims=True) / rows
+    else:
+        wt = np.full_like(d, 1.0 / (rows * n))
+    loss = float(np.sum(wt * d * d))
+    g32 = 2.0 * wt * d
     g = _r(g32, bf16)
     grads = [None] * len(params)
     for li in range(len(params) - 1, -1, -1):

@@ -850,6 +850,7 @@ pgc_status pgc_plan_query(pgc_plan plan, pgc_plan_info* info)
     info->n_points = p.n_points;
     info->gain_mode = p.mfma && p.gain_mode == pgc::kGainBinned ? 3 : p.gain_mode;
     info->n_bin_items = p.bins.n_items;
+    info->offset_fit_err = p.cellfit_err;
     info->workspace_bytes = p.workspace_bytes;
     return PGC_OK;
 }

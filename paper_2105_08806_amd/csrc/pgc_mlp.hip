@@ -262,9 +262,32 @@ __global__ void silu_bwd(const float* __restrict__ dh, const float* __restrict__
 }
 
 // loss = mean over rows and features of (yhat - (q - mu)/sd)^2 and its gradient
+// sq[r] = sum_c q[src_r][c]^2 (FP64), one block per row
+__global__ void __launch_bounds__(256) row_sqnorm(const float* __restrict__ q, const int* __restrict__ idx,
+                                                  int n, double* __restrict__ sq)
+{
+    __shared__ double sh[4];
+    const int r = blockIdx.x;
+    const int64_t src = idx ? idx[r] : r;
+    double part = 0.0;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        const double v = q[src * n + c];
+        part += v * v;
+    }
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) sq[r] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// Loss and its gradient with respect to the normalised outputs.  Without row
+// norms: mean squared error of the normalised outputs.  With row norms rn (the
+// squared L2 norms of the target rows): mean over rows of the squared relative
+// error in the units of q, sum_c (sd_c d_rc)^2 / rn_r.
 __global__ void __launch_bounds__(256) mse_grad(const float* __restrict__ yhat, const float* __restrict__ q,
                                                 const int* __restrict__ idx, int rows, int n,
                                                 const float* __restrict__ mu, const float* __restrict__ sd,
+                                                const double* __restrict__ rn,
                                                 float* __restrict__ dy32, bf16* __restrict__ dy,
                                                 double* __restrict__ loss)
 {
@@ -275,10 +298,13 @@ __global__ void __launch_bounds__(256) mse_grad(const float* __restrict__ yhat, 
         const int r = (int)(e / n), c = (int)(e % n);
         const int64_t src = idx ? idx[r] : r;
         const float d = yhat[e] - (q[src * n + c] - mu[c]) / sd[c];
-        const float g = 2.f * d / ((float)rows * (float)n);
+        // weight of d^2 in the loss
+        const double wt = rn ? (double)sd[c] * (double)sd[c] / (rn[r] > 0.0 ? rn[r] : 1.0) / (double)rows
+                             : 1.0 / ((double)rows * (double)n);
+        const float g = (float)(2.0 * wt * (double)d);
         dy32[e] = g;
         dy[e] = to_bf16(g);
-        part = (double)d * (double)d / ((double)rows * (double)n);
+        part = wt * (double)d * (double)d;
     }
     for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = part;
@@ -500,6 +526,8 @@ struct pgc_surrogate_s {
     double gate_residual = 1e-6, gate_raw_factor = 0.0, judge_tol = 0.0;
     float floor_in = 0.1f, floor_out = 1.0f;  // standard deviation floors, relative to the largest
     int judge_stride = 0;
+    int loss_relative = 0;   // training loss: normalised MSE (0) or per-sample relative error (1)
+    double* rownorm = nullptr;  // Bmax  squared norms of the target rows of a training batch
     double raw_calib = 0.0;  // largest raw residual seen on the training set
     double z_calib = 0.0;    // largest RMS z-score of a training input
     int64_t steps = 0;       // Adam steps taken
@@ -609,8 +637,10 @@ hipError_t backward(pgc_surrogate_s& s, int rows, const float* q, const int* idx
     Layer& out = s.layers.back();
     const int64_t m = (int64_t)rows * n;
     hipLaunchKernelGGL(pgc::zero_f64, dim3(1), dim3(64), 0, st, s.loss, 2);
+    if (s.loss_relative)
+        hipLaunchKernelGGL(pgc::row_sqnorm, dim3(rows), dim3(256), 0, st, q, idx, n, s.rownorm);
     hipLaunchKernelGGL(pgc::mse_grad, dim3(pgc::nb(m, 256)), dim3(256), 0, st, out.Z, q, idx, rows, n, s.mu_out,
-                       s.sd_out, s.dY32, s.dY, s.loss);
+                       s.sd_out, s.loss_relative ? s.rownorm : nullptr, s.dY32, s.dY, s.loss);
     const bf16* g = s.dY;
     const float* g32 = s.dY32;
     for (int l = (int)s.layers.size() - 1; l >= 0; --l) {
@@ -771,7 +801,8 @@ pgc_status pgc_surrogate_create(pgc_plan plan, const pgc_surrogate_desc* d, void
     if (p.precision != PGC_PRECISION_FP32) return PGC_ERR_UNSUPPORTED;
     if (d->width < 16 || d->width > 8192 || d->n_layers < 2 || d->n_layers > 16 || d->batch_max < 1 ||
         d->batch_max > 65536 || d->gate_residual < 0 || d->judge_stride < 0 || d->gate_raw_factor < 0 ||
-        !(d->norm_floor_in > 0 && d->norm_floor_in <= 1) || !(d->norm_floor_out > 0 && d->norm_floor_out <= 1))
+        !(d->norm_floor_in > 0 && d->norm_floor_in <= 1) || !(d->norm_floor_out > 0 && d->norm_floor_out <= 1) ||
+        (d->loss_relative != 0 && d->loss_relative != 1))
         return PGC_ERR_INVALID_ARG;
     if (p.Nd > (1 << 22)) return PGC_ERR_UNSUPPORTED;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -793,6 +824,7 @@ pgc_status pgc_surrogate_create(pgc_plan plan, const pgc_surrogate_desc* d, void
     s->judge_tol = d->judge_tol;
     s->floor_in = (float)d->norm_floor_in;
     s->floor_out = (float)d->norm_floor_out;
+    s->loss_relative = d->loss_relative;
     hipError_t e = hipSuccess;
     std::vector<double> cons, ginv, cnorm;
     try {
@@ -849,6 +881,7 @@ pgc_status pgc_surrogate_create(pgc_plan plan, const pgc_surrogate_desc* d, void
     if (e == hipSuccess) e = s_alloc_n(*s, &s->idx, B);
     if (e == hipSuccess) e = s_alloc_n(*s, &s->loss, 2);
     if (e == hipSuccess) e = s_alloc_n(*s, &s->res_raw, B);
+    if (e == hipSuccess) e = s_alloc_n(*s, &s->rownorm, B);
     if (e == hipSuccess) e = s_alloc_n(*s, &s->res_out, B);
     if (e == hipSuccess) e = s_alloc_n(*s, &s->err, B);
     if (e == hipSuccess) e = s_alloc_n(*s, &s->zs, B);

@@ -59,6 +59,7 @@ class PlanInfo(ctypes.Structure):
         ("block_threads", ctypes.c_int32), ("n_triples", ctypes.c_int64),
         ("n_points", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
         ("gain_mode", ctypes.c_int32), ("n_bin_items", ctypes.c_int64),
+        ("offset_fit_err", ctypes.c_double),
     ]
 
 
@@ -81,6 +82,7 @@ class SurrogateDesc(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("gate_residual", ctypes.c_double), ("gate_raw_factor", ctypes.c_double),
         ("judge_stride", ctypes.c_int32), ("judge_tol", ctypes.c_double),
         ("norm_floor_in", ctypes.c_double), ("norm_floor_out", ctypes.c_double),
+        ("loss_relative", ctypes.c_int32),
     ]
 
 

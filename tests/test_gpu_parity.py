@@ -61,6 +61,9 @@ def check_q(torch, ora, plan, coeffs, tol, label):
     say("case:", label, plan.info.n_triples, "triples,", plan.info.n_points, "points, W =",
         plan.info.kernel_width, "mode =", plan.info.gain_mode, "slabs =", plan.info.n_slabs,
         "bin items =", plan.info.n_bin_items)
+    # the binned gain's per-cell offset polynomials reproduce the exact kernel
+    # offset to the rounding of their coefficients
+    assert 0.0 < plan.info.offset_fit_err <= 1e-15, plan.info.offset_fit_err
     q, qp = gpu_q(torch, plan, coeffs)
     q_ref, qp_ref, _ = ora.collision(coeffs)
     r, rp = rel_l2(q, q_ref), rel_l2(qp, qp_ref)

@@ -59,13 +59,15 @@ def small_plan(pgc, N=5):
                     n_theta=4, n_phi=4, precision=pgc.FP32)
 
 
-def test_gradients_match_oracle(torch_cuda):
+@pytest.mark.parametrize("relative", [0, 1])
+def test_gradients_match_oracle(torch_cuda, relative):
     """Loss and every parameter gradient of a 4-layer network at random
-    parameters and normalisation, against the FP64 reference."""
+    parameters and normalisation, against the FP64 reference, for both
+    training losses."""
     torch = torch_cuda
     from paper_2105_08806_amd import pgc
     plan = small_plan(pgc)
-    s = pgc.Surrogate(plan, width=48, n_layers=4, batch_max=16, seed=1)
+    s = pgc.Surrogate(plan, width=48, n_layers=4, batch_max=16, seed=1, loss_relative=relative)
     n = s.n
     rng = np.random.default_rng(11)
     dims = s.layer_dims()
@@ -78,9 +80,10 @@ def test_gradients_match_oracle(torch_cuda):
     assert np.array_equal(back, flat)
     params32, norms32 = s.unflatten(back.astype(np.float64))
     f = rng.normal(size=(13, n)).astype(np.float32)
-    q = rng.normal(size=(13, n)).astype(np.float32)
+    q = (rng.normal(size=(13, n)) * np.exp(rng.normal(size=(13, 1)))).astype(np.float32)
     loss, g = s.loss_grad(torch.tensor(f, device="cuda"), torch.tensor(q, device="cuda"))
-    ref_loss, ref_g = mlp.loss_and_grad(params32, f.astype(np.float64), q.astype(np.float64), *norms32, bf16=True)
+    ref_loss, ref_g = mlp.loss_and_grad(params32, f.astype(np.float64), q.astype(np.float64), *norms32, bf16=True,
+                                        relative=bool(relative))
     say("loss gpu %.8f oracle %.8f" % (loss, ref_loss))
     assert abs(loss - ref_loss) <= 1e-5 * ref_loss
     off = 0

@@ -34,15 +34,17 @@ def test_bf16_matches_torch():
     assert np.array_equal(mlp.to_bf16(x), ref)
 
 
-def test_gradient_matches_finite_differences():
+@pytest.mark.parametrize("relative", [False, True])
+def test_gradient_matches_finite_differences(relative):
     dims = [7, 11, 9, 7]
     params = small_net(3, dims)
     rng = np.random.default_rng(4)
     f = rng.normal(size=(5, 7))
-    q = rng.normal(size=(5, 7))
+    q = rng.normal(size=(5, 7)) * np.array([[1.0], [0.1], [3.0], [1.0], [0.5]])
     mu_in, sd_in = rng.normal(size=7) * 0.1, 1 + rng.random(7)
     mu_out, sd_out = rng.normal(size=7) * 0.1, 1 + rng.random(7)
-    _, grads = mlp.loss_and_grad(params, f, q, mu_in, sd_in, mu_out, sd_out, bf16=False)
+    kw = dict(bf16=False, relative=relative)
+    _, grads = mlp.loss_and_grad(params, f, q, mu_in, sd_in, mu_out, sd_out, **kw)
     h = 1e-6
     for li, (W, b) in enumerate(params):
         for (arr, g) in ((W, grads[li][0]), (b, grads[li][1])):
@@ -50,12 +52,32 @@ def test_gradient_matches_finite_differences():
             for idx in np.random.default_rng(li).choice(flat.size, size=min(6, flat.size), replace=False):
                 old = flat[idx]
                 flat[idx] = old + h
-                lp, _ = mlp.loss_and_grad(params, f, q, mu_in, sd_in, mu_out, sd_out, bf16=False)
+                lp, _ = mlp.loss_and_grad(params, f, q, mu_in, sd_in, mu_out, sd_out, **kw)
                 flat[idx] = old - h
-                lm, _ = mlp.loss_and_grad(params, f, q, mu_in, sd_in, mu_out, sd_out, bf16=False)
+                lm, _ = mlp.loss_and_grad(params, f, q, mu_in, sd_in, mu_out, sd_out, **kw)
                 flat[idx] = old
                 fd = (lp - lm) / (2 * h)
                 assert abs(fd - g.reshape(-1)[idx]) <= 1e-7 * max(1.0, abs(fd)), (li, idx, fd, g.reshape(-1)[idx])
+
+
+def test_relative_loss_special_values():
+    """With mu_out = 0 a network whose output is zero has relative error 1 for
+    every row (loss 1), and one that returns the normalised target exactly has
+    loss 0, whatever the row scales and sd_out."""
+    dims = [6, 8, 5]
+    rng = np.random.default_rng(9)
+    f = rng.normal(size=(4, 6))
+    q = rng.normal(size=(4, 5)) * np.array([[1e-3], [1.0], [10.0], [0.2]])
+    z_in, o_in = np.zeros(6), np.ones(6)
+    sd_out = 0.5 + rng.random(5)
+    zero = [(np.zeros((o, i)), np.zeros(o)) for i, o in zip(dims[:-1], dims[1:])]
+    loss, _ = mlp.loss_and_grad(zero, f, q, z_in, o_in, np.zeros(5), sd_out, bf16=False, relative=True)
+    assert abs(loss - 1.0) <= 1e-14
+    # a last layer that outputs y = q / sd_out exactly: weights 0, bias per row is impossible,
+    # so use one row and put the target in the bias
+    W = [(np.zeros((8, 6)), np.zeros(8)), (np.zeros((5, 8)), q[1] / sd_out)]
+    loss, _ = mlp.loss_and_grad(W, f[1:2], q[1:2], z_in, o_in, np.zeros(5), sd_out, bf16=False, relative=True)
+    assert loss <= 1e-28
 
 
 def test_bf16_gradient_close_to_fp64():
