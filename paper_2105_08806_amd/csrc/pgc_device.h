@@ -177,9 +177,9 @@ __device__ __forceinline__ void kernel_cells_eo(const double* __restrict__ eo, d
 // kernel_cells_eo for the DIM offsets of one point at once, cell pair by cell
 // pair: each coefficient is loaded once (a scalar load: the table is the same
 // for every lane) and used DIM times, so few coefficients are live at a time.
-template <typename T, int W, int TERMS, int DIM>
-__device__ __forceinline__ void kernel_cells_eo_dims(const double* __restrict__ eo, const double* sv,
-                                                     T (*out)[W])
+// Every value goes to sink(l, a, value) as soon as it is formed.
+template <typename T, int W, int TERMS, int DIM, typename Sink>
+__device__ __forceinline__ void kernel_cells_eo_each(const double* __restrict__ eo, const double* sv, Sink&& sink)
 {
     constexpr int H = (W + 1) / 2, HP = W / 2;
     constexpr int NE = (TERMS + 1) / 2, NO = TERMS / 2;
@@ -212,14 +212,22 @@ __device__ __forceinline__ void kernel_cells_eo_dims(const double* __restrict__ 
             }
 #pragma unroll
             for (int l = 0; l < DIM; ++l) {
-                out[l][a] = (T)fma(sv[l], o[l], e[l]);
-                out[l][W - 1 - a] = (T)fma(-sv[l], o[l], e[l]);
+                sink(l, a, (T)fma(sv[l], o[l], e[l]));
+                sink(l, W - 1 - a, (T)fma(-sv[l], o[l], e[l]));
             }
         } else {
 #pragma unroll
-            for (int l = 0; l < DIM; ++l) out[l][a] = (T)e[l];
+            for (int l = 0; l < DIM; ++l) sink(l, a, (T)e[l]);
         }
     }
+}
+
+// the same into an array out[l][a]
+template <typename T, int W, int TERMS, int DIM>
+__device__ __forceinline__ void kernel_cells_eo_dims(const double* __restrict__ eo, const double* sv,
+                                                     T (*out)[W])
+{
+    kernel_cells_eo_each<T, W, TERMS, DIM>(eo, sv, [&](int l, int a, T v) { out[l][a] = v; });
 }
 
 // Merged point ids pack (b_1, a_1, s, p_2, p_3) as

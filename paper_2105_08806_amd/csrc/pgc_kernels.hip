@@ -552,12 +552,14 @@ struct BinItems {
 
 // Lane layout of the binned gain.  A point's footprint has CELLS columns
 // (3D: (b, c) pairs, 2D: b) of W cells each along the first dimension, which
-// a lane keeps in registers.  LP lanes serve one point and G = 64 / LP points
-// are spread per step; a lane holds NPASS columns e = e0 + LP r.  Wide 3D
-// footprints use two groups of 32 lanes when the accumulators fit (at most 48
-// FP64 or 96 FP32 values per lane): every broadcast read of a first-dimension
-// kernel vector then serves two points, which halves the LDS traffic that
-// bounds the kernel.
+// a lane keeps in registers.  LP lanes serve one point and G points are spread
+// per step; a lane holds NPASS columns e = e0 + LP r.  Wide 3D footprints
+// split the wave into G = 3 or 2 groups when the accumulators fit (ACC_MAX
+// values per lane): every broadcast read of a first-dimension kernel vector
+// then serves G points, which cuts the LDS traffic per point.  For FP64 the
+// bound admits two groups: three (66 accumulators at W = 11) need more than
+// 256 registers with the regeneration, and ran 1.1x slower at two waves per
+// SIMD with spills, 1.6x slower at one.
 template <typename T, int DIM, int W>
 struct BinLayout {
     static constexpr int CELLS = (DIM == 2) ? W : W * W;
@@ -565,11 +567,14 @@ struct BinLayout {
     static constexpr int ACC_MAX = sizeof(T) == 8 ? 48 : 96;
     static constexpr int VEC = 16 / (int)sizeof(T);
     static constexpr int STRIDE = (DIM * W + VEC - 1) / VEC * VEC;  // staged values per point
-    // the second group's FP64 partial tile goes through the stage buffer
-    static constexpr bool PAIRED = WIDE && ((CELLS + 31) / 32) * W <= ACC_MAX &&
-                                   32 * ((CELLS + 31) / 32) * W * 8 <= 64 * STRIDE * (int)sizeof(T);
-    static constexpr int LP = !WIDE ? CELLS : (PAIRED ? 32 : 64);
-    static constexpr int G = 64 / LP;
+    static constexpr int STAGE_BYTES = 64 * STRIDE * (int)sizeof(T);
+    // a wide layout with g groups fits when its accumulators do and one group's
+    // FP64 partial tile fits in the stage buffer (groups are reduced one by one)
+    static constexpr int lp_of(int g) { return 64 / g; }
+    static constexpr int np_of(int g) { return (CELLS + lp_of(g) - 1) / lp_of(g); }
+    static constexpr bool fits(int g) { return np_of(g) * W <= ACC_MAX && lp_of(g) * np_of(g) * W * 8 <= STAGE_BYTES; }
+    static constexpr int G = !WIDE ? 64 / CELLS : (fits(3) ? 3 : (fits(2) ? 2 : 1));
+    static constexpr int LP = !WIDE ? CELLS : lp_of(G);
     static constexpr int NPASS = (CELLS + LP - 1) / LP;
 };
 
@@ -588,8 +593,8 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
     constexpr int STRIDE = L::STRIDE;
     // columns past the last one (partial last pass) read values of the same point
     static_assert(!L::WIDE || W + (LP * NPASS - 1) / W < STRIDE, "spare columns read out of the point");
-    // the partial tiles of the lane groups are reduced through the stage buffer
-    static_assert((G - 1) * LP * NPASS * W * 8 <= 64 * STRIDE * (int)sizeof(T), "reduction buffer");
+    // the partial tile of one lane group is reduced through the stage buffer at a time
+    static_assert(G == 1 || LP * NPASS * W * 8 <= L::STAGE_BYTES, "reduction buffer");
     __shared__ __align__(16) T stage[64 * STRIDE];
 
     const int lane = threadIdx.x;
@@ -648,12 +653,10 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
                     q *= m2;
                     sv[l] = cell_offset(fit[l], w);
                 }
-                T k[DIM][W];
-                kernel_cells_eo_dims<T, W, TERMS, DIM>(P.kpoly_eo, sv, k);
-#pragma unroll
-                for (int l = 0; l < DIM; ++l)
-#pragma unroll
-                    for (int a = 0; a < W; ++a) st[l * W + a] = (l == 1) ? k[l][a] * q : k[l][a];
+                // each kernel value is staged as soon as it is formed
+                kernel_cells_eo_each<T, W, TERMS, DIM>(P.kpoly_eo, sv, [&](int l, int a, T v) {
+                    st[l * W + a] = (l == 1) ? v * q : v;
+                });
             } else {
 #pragma unroll
                 for (int a = 0; a < STRIDE; ++a) st[a] = (T)0;
@@ -712,22 +715,25 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
         }
 
     // groups of lanes that served different points hold partial sums of the
-    // same cells: reduce them through the (now idle) stage buffer
+    // same cells: group 0 adds the others', one group at a time, through the
+    // (now idle) stage buffer
     if constexpr (G > 1) {
         double* red = reinterpret_cast<double*>(stage);
-        if (lane_on && g > 0) {
-#pragma unroll
-            for (int r = 0; r < NPASS; ++r)
-#pragma unroll
-                for (int a = 0; a < W; ++a) red[(((g - 1) * LP + e0) * NPASS + r) * W + a] = tot[r][a];
-        }
-        __syncthreads();
-        if (g == 0) {
-            for (int gg = 1; gg < G; ++gg)
+        for (int gg = 1; gg < G; ++gg) {
+            if (g == gg) {
 #pragma unroll
                 for (int r = 0; r < NPASS; ++r)
 #pragma unroll
-                    for (int a = 0; a < W; ++a) tot[r][a] += red[(((gg - 1) * LP + e0) * NPASS + r) * W + a];
+                    for (int a = 0; a < W; ++a) red[(e0 * NPASS + r) * W + a] = tot[r][a];
+            }
+            __syncthreads();
+            if (g == 0) {
+#pragma unroll
+                for (int r = 0; r < NPASS; ++r)
+#pragma unroll
+                    for (int a = 0; a < W; ++a) tot[r][a] += red[(e0 * NPASS + r) * W + a];
+            }
+            __syncthreads();
         }
     }
     if (g != 0) return;
