@@ -99,10 +99,12 @@ def time_variant(torch, pgc, inputs, precision, steps, warmup):
     return out
 
 
-def traffic_for(kernel_tag):
+TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def traffic_for(kernel_tag, path=TRAFFIC_PATH):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken from the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
@@ -130,7 +132,7 @@ def counter_per_dispatch(csv_path, counter):
     return {k: tot[k] / cnt[k] for k in tot}
 
 
-def write_traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv):
+def write_traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv, path=TRAFFIC_PATH):
     """profiles/traffic.json from FETCH_SIZE / WRITE_SIZE passes over
     `--mode profile` and over `--mode copy` (1 GiB copy: the byte scale of
     each counter)."""
@@ -150,7 +152,7 @@ def write_traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv):
         rec[tag] = {"kernel": prefix, "kernel_source_sha256": sources_sha(kind),
                     "bytes_per_launch": 1024.0 * (fr * fscale + wr * wscale),
                     "fetch_kib_raw": fr, "write_kib_raw": wr, "fetch_scale": fscale, "write_scale": wscale}
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fp:
+    with open(path, "w") as fp:
         json.dump(rec, fp, indent=1)
     return rec
 
