@@ -228,6 +228,22 @@ def test_q_parity_both_gain_modes(torch_cuda, dim, prec):
         plan.close()
 
 
+@pytest.mark.parametrize("upsample", [2.0, 4.0])
+@pytest.mark.parametrize("map_", [0, 1])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_q_parity_fp64_other_upsampling(torch_cuda, dim, map_, upsample):
+    """The binned FP64 gain at upsampling 2 and 4 (other grid spacings for the
+    per-cell offset fits, other kernel widths from the same tolerance) against
+    the oracle."""
+    N = 12 if dim == 2 else 7
+    rule = dict(n_sigma=8) if dim == 2 else dict(n_theta=2, n_phi=4)
+    ora, plan = make_pair(dim, N, 2.5, map_=map_, upsample=upsample, **rule)
+    assert plan.info.upsample == upsample
+    c = I.random_coeffs((N,) * dim, seed=41 + dim + 2 * map_)
+    check_q(torch_cuda, ora, plan, c, FP64_TOL, "%dD N=%d map=%d upsample %.0f" % (dim, N, map_, upsample))
+    plan.close()
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_binned_matches_slabs_every_width(torch_cuda, dim):
     """For every kernel width the binned gain is built for (W = 4 .. 14: lane
