@@ -190,7 +190,9 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
     __shared__ double seo[EO];
     __shared__ float sacc[CELLS * 64];  // running tile of every lane, lane fastest
     const int lane = threadIdx.x;
-    const int cl = lane % CW, stream = lane / CW;
+    // one stream (CW = 64): the point index is the same for every lane, and the
+    // compiler knows it
+    const int cl = lane % CW, stream = (NS == 1) ? 0 : lane / CW;
     for (int i = lane; i < EO; i += 64) seo[i] = groups[0].gp.kpoly_eo[i];
     __syncthreads();
 
@@ -207,9 +209,11 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
         unit_of(D, local, CW, item, c0);
         const int c = c0 + cl;
         const bool valid = c < D.n_cells;
-        const int bin = D.item_bin[item];
-        const long long first = D.item_begin[item];
-        const int n = D.item_count[item];
+        // the unit is the same for the whole wave: keep its run in scalar registers
+        item = __builtin_amdgcn_readfirstlane(item);
+        const int bin = __builtin_amdgcn_readfirstlane(D.item_bin[item]);
+        const long long first = lane0((unsigned long long)D.item_begin[item]);
+        const int n = __builtin_amdgcn_readfirstlane(D.item_count[item]);
         const int t0x = bin / D.nb - D.off;
         const int t0y = bin % D.nb - D.off;
         // the cell-minor G copy is device memory: global loads, not flat ones
