@@ -292,9 +292,10 @@ __global__ void __launch_bounds__(256) mse_grad(const float* __restrict__ yhat, 
                                                 double* __restrict__ loss)
 {
     __shared__ double sh[4];
-    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double part = 0.0;
-    if (e < (int64_t)rows * n) {
+    // grid-stride: a bounded grid keeps the atomic additions to the loss few
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)rows * n;
+         e += (int64_t)gridDim.x * blockDim.x) {
         const int r = (int)(e / n), c = (int)(e % n);
         const int64_t src = idx ? idx[r] : r;
         const float d = yhat[e] - (q[src * n + c] - mu[c]) / sd[c];
@@ -304,7 +305,7 @@ __global__ void __launch_bounds__(256) mse_grad(const float* __restrict__ yhat, 
         const float g = (float)(2.0 * wt * (double)d);
         dy32[e] = g;
         dy[e] = to_bf16(g);
-        part = wt * (double)d * (double)d;
+        part += wt * (double)d * (double)d;
     }
     for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = part;
@@ -313,13 +314,24 @@ __global__ void __launch_bounds__(256) mse_grad(const float* __restrict__ yhat, 
 }
 
 // db[c] = sum over rows of g[r][c]
-__global__ void col_sum(const float* __restrict__ g, int rows, int cols, float* __restrict__ db)
+__global__ void __launch_bounds__(256) col_sum(const float* __restrict__ g, int rows, int cols,
+                                               float* __restrict__ db)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
+    // 16 columns per block, 16 row phases each (rows p, p + 16, ...), summed
+    // in a fixed order, so the result does not depend on scheduling
+    __shared__ float part[16][17];
+    const int cx = threadIdx.x & 15, p = threadIdx.x >> 4;
+    const int c = blockIdx.x * 16 + cx;
     float s = 0.f;
-    for (int r = 0; r < rows; ++r) s += g[(size_t)r * cols + c];
-    db[c] = s;
+    if (c < cols)
+        for (int r = p; r < rows; r += 16) s += g[(size_t)r * cols + c];
+    part[p][cx] = s;
+    __syncthreads();
+    if (p == 0 && c < cols) {
+        float t = 0.f;
+        for (int q = 0; q < 16; ++q) t += part[q][cx];
+        db[c] = t;
+    }
 }
 
 // Adam (Kingma and Ba 2015) on FP32 master weights; refreshes the BF16 copy
@@ -379,9 +391,10 @@ __global__ void __launch_bounds__(1024) max_reduce(const float* __restrict__ x, 
 }
 
 // sums over the workgroup of nv values per thread (nv <= 8); result in out[0..nv)
+// sums of nv <= 8 per-thread values over a workgroup of at most 1024 threads
 __device__ void block_sums(double* vals, int nv, double* out)
 {
-    __shared__ double sh[8][4];
+    __shared__ double sh[8][16];
     for (int a = 0; a < nv; ++a)
         for (int off = 32; off > 0; off >>= 1) vals[a] += __shfl_down(vals[a], off, 64);
     if ((threadIdx.x & 63) == 0)
@@ -396,11 +409,13 @@ __device__ void block_sums(double* vals, int nv, double* out)
     __syncthreads();
 }
 
-// Output stage, one 256-thread workgroup per sample (nc <= 5 invariants):
+// Output stage, one 1024-thread workgroup per sample (nc <= 5 invariants):
 // q = yhat sd + mu (FP64); the raw residual rho_raw = max_c |<C_c, q>| / (|C_c| |q|);
 // the projection q -= C^T (C C^T)^{-1} C q onto the coefficient vectors that
 // conserve every invariant; q stored in FP32; rho_out of the stored q.
-__global__ void __launch_bounds__(256) output_stage(const float* __restrict__ yhat, int rows, int n,
+constexpr int kOutThreads = 1024;  // threads per sample in output_stage
+
+__global__ void __launch_bounds__(kOutThreads) output_stage(const float* __restrict__ yhat, int rows, int n,
                                                     const float* __restrict__ mu, const float* __restrict__ sd,
                                                     const double* __restrict__ cons, int nc,
                                                     const double* __restrict__ ginv,
@@ -639,7 +654,8 @@ hipError_t backward(pgc_surrogate_s& s, int rows, const float* q, const int* idx
     hipLaunchKernelGGL(pgc::zero_f64, dim3(1), dim3(64), 0, st, s.loss, 2);
     if (s.loss_relative)
         hipLaunchKernelGGL(pgc::row_sqnorm, dim3(rows), dim3(256), 0, st, q, idx, n, s.rownorm);
-    hipLaunchKernelGGL(pgc::mse_grad, dim3(pgc::nb(m, 256)), dim3(256), 0, st, out.Z, q, idx, rows, n, s.mu_out,
+    hipLaunchKernelGGL(pgc::mse_grad, dim3(std::min<unsigned>(pgc::nb(m, 256), 1024u)), dim3(256), 0, st, out.Z, q,
+                       idx, rows, n, s.mu_out,
                        s.sd_out, s.loss_relative ? s.rownorm : nullptr, s.dY32, s.dY, s.loss);
     const bf16* g = s.dY;
     const float* g32 = s.dY32;
@@ -649,7 +665,7 @@ hipError_t backward(pgc_surrogate_s& s, int rows, const float* q, const int* idx
         // dW = g^T h_in  (out x in), db = column sums of g
         hipError_t e = gemm(L.out, L.in, rows, g, L.out, true, hin, L.in, false, L.gW, L.in, nullptr, false, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(pgc::col_sum, dim3(pgc::nb(L.out, 256)), dim3(256), 0, st, g32, rows, L.out, L.gb);
+        hipLaunchKernelGGL(pgc::col_sum, dim3(pgc::nb(L.out, 16)), dim3(256), 0, st, g32, rows, L.out, L.gb);
         if (l == 0) break;
         Layer& P = s.layers[l - 1];
         // dh_in = g W (rows x in), then through the activation of layer l - 1
@@ -994,7 +1010,7 @@ pgc_status pgc_surrogate_train(pgc_surrogate s, const float* f_dev, const float*
         e = normalise_rows(*s, f_dev, nullptr, b0, rows, st);
         if (e == hipSuccess) e = forward(*s, rows, st);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(pgc::output_stage, dim3(rows), dim3(256), 0, st, s->layers.back().Z, rows, s->n,
+            hipLaunchKernelGGL(pgc::output_stage, dim3(rows), dim3(pgc::kOutThreads), 0, st, s->layers.back().Z, rows, s->n,
                                s->mu_out, s->sd_out, s->cons, s->nc, s->ginv, s->cnorm, s->qtmp, s->res_raw,
                                s->res_out);
             e = hipGetLastError();
@@ -1037,7 +1053,7 @@ pgc_status pgc_surrogate_coeffs_to_q(pgc_surrogate s, const float* f_dev, int64_
         e = normalise_rows(*s, f_dev, nullptr, b0, rows, st);
         if (e == hipSuccess) e = forward(*s, rows, st);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(pgc::output_stage, dim3(rows), dim3(256), 0, st, s->layers.back().Z, rows, n, s->mu_out,
+            hipLaunchKernelGGL(pgc::output_stage, dim3(rows), dim3(pgc::kOutThreads), 0, st, s->layers.back().Z, rows, n, s->mu_out,
                                s->sd_out, s->cons, s->nc, s->ginv, s->cnorm, qo, s->res_raw, s->res_out);
             e = hipGetLastError();
         }
