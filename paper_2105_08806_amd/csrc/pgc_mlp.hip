@@ -49,16 +49,20 @@ __device__ __forceinline__ bf16 to_bf16(float f)
 
 __device__ __forceinline__ float from_bf16(bf16 b) { return __uint_as_float((unsigned int)b << 16); }
 
-constexpr int kBM = 64, kBN = 64, kBK = 32, kPad = 8;
+constexpr int kBM = 64, kBN = 64, kBK = 64, kPad = 8;
 
 // C[M x N] = op(A) op(B) (+ bias[n]), or C += ... when `accumulate`; A and B
 // BF16, C FP32, all row-major:
 //   op(A)[m][k] = TA ? A[k lda + m] : A[m lda + k]
 //   op(B)[k][n] = TB ? B[n ldb + k] : B[k ldb + n]
 // A 256-thread workgroup owns a 64 x 64 tile of C (four waves of 32 x 32, each
-// 2 x 2 MFMA tiles of 16 x 16); blockIdx.z takes the K range [z kc, (z+1) kc)
+// 2 x 2 tiles of 16 x 16); blockIdx.z takes the K range [z kc, (z+1) kc)
 // and, when gridDim.z > 1, adds its partial tile into C atomically (C holds
-// zeros or the values to accumulate onto).
+// zeros or the values to accumulate onto).  Each 64-deep K slice is two
+// v_mfma_f32_16x16x32_bf16 per 16 x 16 tile: lane l supplies row (column)
+// l % 16 at k = 32 s + 8 (l / 16) .. + 7 and holds rows 4 (l / 16) + r, column
+// l % 16 of the result.  With `vec` (16-byte aligned rows) the next slice's
+// global loads are issued before the current slice's products.
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
                                                  const bf16* __restrict__ A, int lda,
@@ -66,6 +70,8 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
                                                  float* __restrict__ C, int ldc,
                                                  const float* __restrict__ bias, int accumulate, int vec)
 {
+    typedef __bf16 bf16x8m __attribute__((ext_vector_type(8)));
+    typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
     __shared__ __attribute__((aligned(16))) bf16 sA[kBM][kBK + kPad];
     __shared__ __attribute__((aligned(16))) bf16 sB[kBN][kBK + kPad];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -79,60 +85,106 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
-    for (int k0 = kbeg; k0 < kend; k0 += kBK) {
-        // A tile (64 x 32): with vec, every thread moves one 16-byte run of 8
-        // elements along the contiguous dimension (k, or m when transposed)
-        if (vec) {
-            if (!TA) {
-                const int m = tid >> 2, k8 = (tid & 3) * 8;
-                const int gm = m0 + m, gk = k0 + k8;
-                u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-                if (gm < M && gk + 8 <= kend) {
-                    v = *reinterpret_cast<const u16x8*>(A + (size_t)gm * lda + gk);
-                } else if (gm < M) {
-                    for (int q = 0; q < 8; ++q)
-                        if (gk + q < kend) v[q] = A[(size_t)gm * lda + gk + q];
-                }
-                *reinterpret_cast<u16x8*>(&sA[m][k8]) = v;
-            } else {
-                const int k = tid >> 3, m8 = (tid & 7) * 8;
-                const int gk = k0 + k, gm = m0 + m8;
-                u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-                if (gk < kend && gm + 8 <= M) {
-                    v = *reinterpret_cast<const u16x8*>(A + (size_t)gk * lda + gm);
-                } else if (gk < kend) {
-                    for (int q = 0; q < 8; ++q)
-                        if (gm + q < M) v[q] = A[(size_t)gk * lda + gm + q];
-                }
+    // 16 x 16 x 32 products of the wave's tiles over the staged slice
+    auto compute = [&]() {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) sA[m8 + q][k] = v[q];
-            }
-            if (TB) {
-                const int n = tid >> 2, k8 = (tid & 3) * 8;
-                const int gn = n0 + n, gk = k0 + k8;
-                u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-                if (gn < N && gk + 8 <= kend) {
-                    v = *reinterpret_cast<const u16x8*>(B + (size_t)gn * ldb + gk);
-                } else if (gn < N) {
-                    for (int q = 0; q < 8; ++q)
-                        if (gk + q < kend) v[q] = B[(size_t)gn * ldb + gk + q];
-                }
-                *reinterpret_cast<u16x8*>(&sB[n][k8]) = v;
-            } else {
-                const int k = tid >> 3, n8 = (tid & 7) * 8;
-                const int gk = k0 + k, gn = n0 + n8;
-                u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-                if (gk < kend && gn + 8 <= N) {
-                    v = *reinterpret_cast<const u16x8*>(B + (size_t)gk * ldb + gn);
-                } else if (gk < kend) {
-                    for (int q = 0; q < 8; ++q)
-                        if (gn + q < N) v[q] = B[(size_t)gk * ldb + gn + q];
-                }
+        for (int kk = 0; kk < kBK; kk += 32) {
+            const int kq = kk + 8 * (lane >> 4);
+            bf16x8m a[2], b[2];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) sB[n8 + q][k] = v[q];
+            for (int i = 0; i < 2; ++i)
+                a[i] = __builtin_bit_cast(bf16x8m,
+                                          *reinterpret_cast<const u16x8*>(&sA[wm + i * 16 + (lane & 15)][kq]));
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                b[j] = __builtin_bit_cast(bf16x8m,
+                                          *reinterpret_cast<const u16x8*>(&sB[wn + j * 16 + (lane & 15)][kq]));
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    };
+
+    if (vec) {
+        // every thread moves CH 16-byte runs of 8 elements of each operand along
+        // its contiguous dimension (k, or m / n when the operand is transposed):
+        // run c = tid + 256 h covers, untransposed, row c / 8 at k = 8 (c % 8),
+        // transposed, k = c / 8 at rows 8 (c % 8) .. + 7
+        constexpr int CH = kBM * kBK / 8 / 256;
+        static_assert(kBM == kBN && kBM * kBK == 8 * 256 * CH && kBK == 64 && kBM == 64, "tile shape");
+        auto gload = [&](int k0, u16x8* va, u16x8* vb) {
+#pragma unroll
+            for (int h = 0; h < CH; ++h) {
+                const int c = tid + 256 * h;
+                va[h] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                vb[h] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                if (!TA) {
+                    const int gm = m0 + (c >> 3), gk = k0 + (c & 7) * 8;
+                    if (gm < M && gk + 8 <= kend) {
+                        va[h] = *reinterpret_cast<const u16x8*>(A + (size_t)gm * lda + gk);
+                    } else if (gm < M) {
+                        for (int q = 0; q < 8; ++q)
+                            if (gk + q < kend) va[h][q] = A[(size_t)gm * lda + gk + q];
+                    }
+                } else {
+                    const int gk = k0 + (c >> 3), gm = m0 + (c & 7) * 8;
+                    if (gk < kend && gm + 8 <= M) {
+                        va[h] = *reinterpret_cast<const u16x8*>(A + (size_t)gk * lda + gm);
+                    } else if (gk < kend) {
+                        for (int q = 0; q < 8; ++q)
+                            if (gm + q < M) va[h][q] = A[(size_t)gk * lda + gm + q];
+                    }
+                }
+                if (TB) {
+                    const int gn = n0 + (c >> 3), gk = k0 + (c & 7) * 8;
+                    if (gn < N && gk + 8 <= kend) {
+                        vb[h] = *reinterpret_cast<const u16x8*>(B + (size_t)gn * ldb + gk);
+                    } else if (gn < N) {
+                        for (int q = 0; q < 8; ++q)
+                            if (gk + q < kend) vb[h][q] = B[(size_t)gn * ldb + gk + q];
+                    }
+                } else {
+                    const int gk = k0 + (c >> 3), gn = n0 + (c & 7) * 8;
+                    if (gk < kend && gn + 8 <= N) {
+                        vb[h] = *reinterpret_cast<const u16x8*>(B + (size_t)gk * ldb + gn);
+                    } else if (gk < kend) {
+                        for (int q = 0; q < 8; ++q)
+                            if (gn + q < N) vb[h][q] = B[(size_t)gk * ldb + gn + q];
+                    }
+                }
             }
-        } else {
+        };
+        auto sstore = [&](const u16x8* va, const u16x8* vb) {
+#pragma unroll
+            for (int h = 0; h < CH; ++h) {
+                const int c = tid + 256 * h;
+                if (!TA) {
+                    *reinterpret_cast<u16x8*>(&sA[c >> 3][(c & 7) * 8]) = va[h];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) sA[(c & 7) * 8 + q][c >> 3] = va[h][q];
+                }
+                if (TB) {
+                    *reinterpret_cast<u16x8*>(&sB[c >> 3][(c & 7) * 8]) = vb[h];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) sB[(c & 7) * 8 + q][c >> 3] = vb[h][q];
+                }
+            }
+        };
+        u16x8 va[CH], vb[CH];
+        gload(kbeg, va, vb);
+        for (int k0 = kbeg; k0 < kend; k0 += kBK) {
+            sstore(va, vb);
+            __syncthreads();
+            if (k0 + kBK < kend) gload(k0 + kBK, va, vb);
+            compute();
+            __syncthreads();
+        }
+    } else {
+        for (int k0 = kbeg; k0 < kend; k0 += kBK) {
             for (int e = tid; e < kBM * kBK; e += 256) {
                 int m, k;
                 if (TA) {
@@ -161,24 +213,10 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
                 if (gn < N && gk < kend) v = TB ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
                 sB[n][k] = v;
             }
+            __syncthreads();
+            compute();
+            __syncthreads();
         }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < kBK; kk += 16) {
-            // lane l supplies rows/columns l % 16 at k = kk + 4 (l / 16) .. + 3
-            const int kq = kk + 4 * (lane >> 4);
-            bf16x4 a[2], b[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x4*>(&sA[wm + i * 16 + (lane & 15)][kq]);
-#pragma unroll
-            for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x4*>(&sB[wn + j * 16 + (lane & 15)][kq]);
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
-        __syncthreads();
     }
     const bool add = gridDim.z > 1;
 #pragma unroll
