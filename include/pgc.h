@@ -355,10 +355,11 @@ pgc_status pgc_surrogate_query(pgc_surrogate s, pgc_surrogate_info* info);
 pgc_status pgc_surrogate_set_normalization(pgc_surrogate s, const float* f_dev, const float* q_dev,
                                            int64_t n_samples, void* stream);
 /* `epochs` passes of mini-batch Adam (batch <= batch_max rows, step size lr
- * with cosine decay over the epochs) on the mean squared error of the
- * normalised output; loss_host (may be NULL) receives the mean loss of each
- * epoch.  Then calibrates the raw-residual gate on the training set.
- * Synchronises `stream` after every step. */
+ * with cosine decay over the epochs) on the loss chosen by desc.loss_relative;
+ * loss_host (may be NULL) receives the mean batch loss of each epoch.  Then
+ * calibrates the raw-residual gate on the training set.  Allocates a device
+ * copy of each epoch's sample order (n_samples ints, freed before returning)
+ * and synchronises `stream` once per epoch. */
 pgc_status pgc_surrogate_train(pgc_surrogate s, const float* f_dev, const float* q_dev, int64_t n_samples,
                                int32_t epochs, int32_t batch, double lr, uint64_t seed, double* loss_host,
                                void* stream);

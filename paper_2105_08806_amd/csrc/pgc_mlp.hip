@@ -684,12 +684,15 @@ hipError_t forward(pgc_surrogate_s& s, int rows, hipStream_t st)
 }
 
 // loss and gradients of the rows in s.X against targets q (rows idx, or 0..rows-1)
-hipError_t backward(pgc_surrogate_s& s, int rows, const float* q, const int* idx, hipStream_t st)
+// gradients of one batch; the batch loss is added to s.loss[0], which is first
+// cleared when zero_loss is set (training clears it once per epoch instead)
+hipError_t backward(pgc_surrogate_s& s, int rows, const float* q, const int* idx, hipStream_t st,
+                    bool zero_loss = true)
 {
     const int n = s.n;
     Layer& out = s.layers.back();
     const int64_t m = (int64_t)rows * n;
-    hipLaunchKernelGGL(pgc::zero_f64, dim3(1), dim3(64), 0, st, s.loss, 2);
+    if (zero_loss) hipLaunchKernelGGL(pgc::zero_f64, dim3(1), dim3(64), 0, st, s.loss, 2);
     if (s.loss_relative)
         hipLaunchKernelGGL(pgc::row_sqnorm, dim3(rows), dim3(256), 0, st, q, idx, n, s.rownorm);
     hipLaunchKernelGGL(pgc::mse_grad, dim3(std::min<unsigned>(pgc::nb(m, 256), 1024u)), dim3(256), 0, st, out.Z, q,
@@ -1017,28 +1020,38 @@ pgc_status pgc_surrogate_train(pgc_surrogate s, const float* f_dev, const float*
     hipStream_t st = static_cast<hipStream_t>(stream);
     std::mt19937_64 rng(seed);
     std::vector<int> perm((size_t)n_samples);
-    hipError_t e = hipSuccess;
+    // the epoch's sample order on the device: the steps of an epoch are queued
+    // without host round trips, and the stream is synchronised once per epoch
+    int* perm_dev = nullptr;
+    hipError_t e = hipMalloc(&perm_dev, (size_t)n_samples * sizeof(int));
+    if (e != hipSuccess) return pgc::status_of(e);
     for (int ep = 0; ep < epochs && e == hipSuccess; ++ep) {
         std::iota(perm.begin(), perm.end(), 0);
         std::shuffle(perm.begin(), perm.end(), rng);
-        double ep_loss = 0.0;
-        int64_t seen = 0;
+        e = hipMemcpyAsync(perm_dev, perm.data(), (size_t)n_samples * sizeof(int), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(pgc::zero_f64, dim3(1), dim3(64), 0, st, s->loss, 2);
+            e = hipGetLastError();
+        }
+        int64_t steps = 0;
         // cosine decay of the step size over the epochs
         const double lr_ep = lr * 0.5 * (1.0 + std::cos(3.141592653589793 * ep / std::max(1, epochs)));
         for (int64_t b0 = 0; b0 + batch <= n_samples && e == hipSuccess; b0 += batch) {
-            e = hipMemcpyAsync(s->idx, perm.data() + b0, batch * sizeof(int), hipMemcpyHostToDevice, st);
-            if (e == hipSuccess) e = normalise_rows(*s, f_dev, s->idx, 0, batch, st);
+            const int* idx = perm_dev + b0;
+            e = normalise_rows(*s, f_dev, idx, 0, batch, st);
             if (e == hipSuccess) e = forward(*s, batch, st);
-            if (e == hipSuccess) e = backward(*s, batch, q_dev, s->idx, st);
+            if (e == hipSuccess) e = backward(*s, batch, q_dev, idx, st, false);
             if (e == hipSuccess) e = adam_all(*s, lr_ep, st);
-            double l = 0.0;
-            if (e == hipSuccess) e = hipMemcpyAsync(&l, s->loss, sizeof(double), hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);  // perm slice and l are host memory
-            ep_loss += l * batch;
-            seen += batch;
+            ++steps;
         }
-        if (loss_host) loss_host[ep] = seen ? ep_loss / (double)seen : 0.0;
+        // s->loss[0] holds the sum of the batch losses of the epoch; the
+        // synchronisation also keeps perm until its copy has been read
+        double l = 0.0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&l, s->loss, sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (loss_host) loss_host[ep] = steps ? l / (double)steps : 0.0;
     }
+    (void)hipFree(perm_dev);
     if (e != hipSuccess) return pgc::status_of(e);
     // calibrate the out-of-distribution gate: largest raw residual on the training set
     double worst = 0.0, worst_z = 0.0;
