@@ -379,12 +379,12 @@ def surrogate_variant(torch, pgc, inputs, np, n_pairs, epochs):
     return out
 
 
-def bkw_curve(torch, pgc, inputs, np, steps=20):
+def bkw_curve(torch, pgc, inputs, np, steps=20, echo=True):
     """3D BKW: RK4 from t = 6.5 with dt = 0.1 for `steps` steps in FP64 and FP32.
-    Prints, per step, the rel-L2 distance of each state from the projection of
-    the exact BKW solution at that time, and of the FP32 state from the FP64
-    one (one JSON object per step)."""
-    plans, states = {}, {}
+    Per step, the rel-L2 distance of each state from the projection of the
+    exact BKW solution at that time, and of the FP32 state from the FP64 one
+    (printed as one JSON object per step when `echo`); returns the rows."""
+    plans, states, rows = {}, {}, []
     for prec in (pgc.FP64, pgc.FP32):
         plans[prec] = make_plan(pgc, prec)
         states[prec] = plans[prec].project(inputs.bkw_f(T0, plans[prec].interior_velocities())).double()
@@ -397,13 +397,18 @@ def bkw_curve(torch, pgc, inputs, np, steps=20):
         s64 = states[pgc.FP64].cpu().numpy()
         s32 = states[pgc.FP32].cpu().numpy()
         nx = np.linalg.norm(exact)
-        print(json.dumps({"step": k, "t": round(t, 6),
-                          "fp64_vs_exact": float(np.linalg.norm(s64 - exact) / nx),
-                          "fp32_vs_exact": float(np.linalg.norm(s32 - exact) / nx),
-                          "fp32_vs_fp64": float(np.linalg.norm(s32 - s64) / np.linalg.norm(s64))}),
-              flush=True)
+        row = {"step": k, "t": round(t, 6),
+               "fp64_vs_exact": float(np.linalg.norm(s64 - exact) / nx),
+               "fp32_vs_exact": float(np.linalg.norm(s32 - exact) / nx),
+               "fp32_vs_fp64": float(np.linalg.norm(s32 - s64) / np.linalg.norm(s64))}
+        rows.append(row)
+        if echo:
+            print(json.dumps(row), flush=True)
+        elif k % 5 == 0:
+            log("  bkw: step %d/%d, FP64 vs exact %.2e" % (k, steps, row["fp64_vs_exact"]))
     for p in plans.values():
         p.close()
+    return rows
 
 
 def main():
@@ -415,6 +420,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-bkw", action="store_true", help="skip the 20-step RK4 BKW error curve")
     ap.add_argument("--batch-cells", type=int, default=4096)
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--surrogate-pairs", type=int, default=4096)
@@ -543,6 +549,16 @@ def main():
     if not args.no_surrogate:
         line["variants"]["surrogate"] = surrogate_variant(torch, pgc, inputs, np, args.surrogate_pairs,
                                                           args.surrogate_epochs)
+    if not args.no_bkw:
+        # the BKW dynamics of the same workload: 20 RK4 steps of dt = 0.1 from t0
+        rows = bkw_curve(torch, pgc, inputs, np, steps=20, echo=False)
+        line["bkw_curve"] = {"t0": T0, "dt": DT, "steps": len(rows),
+                             "note": "rel-L2 of the RK4 state against the projection of the exact BKW "
+                                     "solution at each step (FP64 and FP32 paths), and FP32 against FP64",
+                             "t": [r["t"] for r in rows],
+                             "fp64_vs_exact": [r["fp64_vs_exact"] for r in rows],
+                             "fp32_vs_exact": [r["fp32_vs_exact"] for r in rows],
+                             "fp32_vs_fp64": [r["fp32_vs_fp64"] for r in rows]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inputs)
     print(json.dumps(line), flush=True)
