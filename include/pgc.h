@@ -101,11 +101,13 @@ typedef struct pgc_plan_desc {
     int32_t n_chunks;     /* collision-unit chunks (partial grids); 0 = automatic */
     int32_t block_threads;/* threads per spreading workgroup (256, 512 or 1024); 0 = automatic */
     int32_t gain_mode;    /* spreading scheme: 0 = automatic (binned, falling back to slabs when the
-                             bin index does not fit in device memory), 1 = LDS slabs with one atomic per
-                             contribution, 2 = plan-time bins by footprint corner with register
-                             accumulation (the index holds 8 bytes per merged point), 3 = the same bins
-                             contracted on the FP64 matrix cores (FP64 3D plans with W <= 12 only,
-                             UNSUPPORTED otherwise) */
+                             bin index does not fit in device memory or the plan is outside the
+                             binned limits), 1 = LDS slabs with one atomic per contribution,
+                             2 = plan-time bins by footprint corner with register accumulation (the
+                             index holds 8 bytes per merged point; W <= 14, at most 256 interior
+                             nodes per dimension and 1024 directions, UNSUPPORTED otherwise), 3 = the
+                             same bins contracted on the FP64 matrix cores (FP64 3D plans with
+                             W <= 12 only, UNSUPPORTED otherwise) */
 } pgc_plan_desc;
 
 typedef struct pgc_plan_s* pgc_plan;

@@ -241,7 +241,10 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
     p.tol = d.nufft_tol > 0.0 ? d.nufft_tol : (p.precision == PGC_PRECISION_FP64 ? 5e-13 : 1e-6);
     p.W = d.kernel_width > 0 ? d.kernel_width : width_for(p.tol, p.upsample);
     p.gain_mode = d.gain_mode == 1 ? kGainSlab : kGainBinned;
-    if (p.gain_mode == kGainBinned && p.W > 14) {
+    // the binned scheme: kernels built for W <= 14, and point ids that hold the
+    // first-dimension nodes in 8 bits, the direction in 10 and the pairs of the
+    // other dimensions in 16 (n_i <= 256, n_sigma <= 1024)
+    if (p.gain_mode == kGainBinned && (p.W > 14 || p.ni > kMaxBinnedNodes || p.n_sigma > kMaxBinnedDirections)) {
         if (d.gain_mode >= 2) return PGC_ERR_UNSUPPORTED;
         p.gain_mode = kGainSlab;
     }

@@ -65,6 +65,8 @@ struct BinIndex {
     unsigned long long* ids = nullptr;  // n_points packed point ids, grouped by bin
 };
 constexpr int kBinChunk = 8192;
+constexpr int kMaxBinnedNodes = 256;        // n_i: 8-bit node fields of a point id
+constexpr int kMaxBinnedDirections = 1024;  // n_sigma: 10-bit direction field
 
 // Buffers marked FP64 are FP64 for both plan precisions.
 struct Workspace {

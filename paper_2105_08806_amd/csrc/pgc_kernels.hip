@@ -556,10 +556,10 @@ struct BinItems {
 // per step; a lane holds NPASS columns e = e0 + LP r.  Wide 3D footprints
 // split the wave into G = 3 or 2 groups when the accumulators fit (ACC_MAX
 // values per lane): every broadcast read of a first-dimension kernel vector
-// then serves G points, which cuts the LDS traffic per point.  For FP64 the
-// bound admits two groups: three (66 accumulators at W = 11) need more than
-// 256 registers with the regeneration, and ran 1.1x slower at two waves per
-// SIMD with spills, 1.6x slower at one.
+// then serves G points, which cuts the LDS traffic per point.  The FP64 bound
+// gives three groups at W = 9 and two at W = 10 and 11: three at W = 11 (66
+// accumulators) need more than 256 registers with the regeneration, and ran
+// 1.1x slower at two waves per SIMD with spills, 1.6x slower at one.
 template <typename T, int DIM, int W>
 struct BinLayout {
     static constexpr int CELLS = (DIM == 2) ? W : W * W;

@@ -275,6 +275,36 @@ def test_binned_matches_slabs_every_width(torch_cuda, dim, prec):
         assert rp <= tol_qp and r <= tol_q, (W, r, rp)
 
 
+def test_binned_limits_at_the_largest_node_count(torch_cuda):
+    """The binned scheme's point ids hold a first-dimension node in 8 bits: at
+    the largest node count (2D, m_v = 258, 256 interior nodes) binned and slab
+    schemes agree within 5e-12 (2.2e9 points summed in different orders, with
+    kernel offsets from the direct map in one and the cell fits in the other:
+    measured 9e-13); one node more falls back to the slabs automatically and
+    is refused when the bins are asked for."""
+    from paper_2105_08806_amd import pgc
+    torch = torch_cuda
+    N = 6
+    c = I.random_coeffs((N, N), seed=51)
+    out = []
+    for mode in (pgc.GAIN_SLAB, pgc.GAIN_BINNED):
+        plan = pgc.Plan(dim=2, n_modes=N, m_v=258, scale=4.0, sphere=pgc.SPHERE_UNIFORM_2D, n_sigma=2,
+                        gain_mode=mode)
+        assert plan.info.gain_mode == mode and plan.info.m_v - 2 == 256
+        out.append(gpu_q(torch, plan, c))
+        plan.close()
+    (q_s, qp_s), (q_b, qp_b) = out
+    r, rp = rel_l2(q_b, q_s), rel_l2(qp_b, qp_s)
+    say("2D 256 interior nodes binned vs slabs: rel-L2 Q %.2e Q+ %.2e" % (r, rp))
+    assert rp <= 5e-12 and r <= 5e-12
+    plan = pgc.Plan(dim=2, n_modes=N, m_v=259, scale=4.0, sphere=pgc.SPHERE_UNIFORM_2D, n_sigma=2)
+    assert plan.info.gain_mode == pgc.GAIN_SLAB
+    plan.close()
+    with pytest.raises(pgc.PgcError):
+        pgc.Plan(dim=2, n_modes=N, m_v=259, scale=4.0, sphere=pgc.SPHERE_UNIFORM_2D, n_sigma=2,
+                 gain_mode=pgc.GAIN_BINNED)
+
+
 @pytest.mark.parametrize("map_", [0, 1])
 @pytest.mark.parametrize("kernel", ["maxwell", "vhs"])
 def test_q_parity_3d_fp64_matrix_cores(torch_cuda, map_, kernel):
