@@ -176,6 +176,38 @@ def test_batch_graph_replays(torch_cuda):
     b.close()
 
 
+def test_batch_order_change_drops_the_graph(torch_cuda):
+    """Changing the unit order drops a captured graph (a replay is refused
+    until the next capture); the graph captured in the new order replays to
+    the eager result, and the eager results of both orders agree."""
+    torch = torch_cuda
+    from paper_2105_08806_amd import pgc
+    S, M = 3.0, 8
+    cells = I.cell_maxwellians_2d(70, seed=9, modes=(8, 11))
+    b = pgc.Batch([c["N"] for c in cells], scale=S, n_sigma=M, nufft_tol=TOL, autotune=False)
+    b.set_tile(64)
+    src = [I.random_coeffs((n, n), seed=300 + c) for c, n in enumerate(b.n_modes)]
+    packed = b.pack(src)
+    q = torch.zeros_like(packed)
+    b.set_order(1, 0)
+    eager0 = b.coeffs_to_q(packed.clone()).double().cpu().numpy()
+    b.capture(packed, q)
+    assert b.info.has_graph
+    b.set_order(1, 1)
+    assert not b.info.has_graph
+    with pytest.raises(pgc.PgcError):
+        b.graph_launch()
+    eager1 = b.coeffs_to_q(packed.clone()).double().cpu().numpy()
+    assert rel(eager1, eager0) <= 1e-6
+    b.capture(packed, q)
+    for _ in range(2):
+        q.zero_()
+        b.graph_launch()
+        torch.cuda.synchronize()
+        assert rel(q.double().cpu().numpy(), eager1) <= 1e-6
+    b.close()
+
+
 def test_batch_workload_sizes_vs_fp64_plans(torch_cuda):
     """The batched workload's discretisation (S = 6, 32 directions, Maxwell,
     N in {32, 48, 64}) on 12 cells: each cell against the FP64 single-cell path."""
