@@ -562,9 +562,13 @@ namespace {
 hipError_t batch_alloc(pgc_batch_s& b, void** ptr, size_t bytes)
 {
     *ptr = nullptr;
-    hipError_t e = hipMalloc(ptr, std::max<size_t>(bytes, 16));
-    if (e != hipSuccess) return e;
-    b.allocations.push_back(*ptr);
+    b.allocations.push_back(nullptr);  // the slot first: a throwing push_back leaks no device memory
+    hipError_t e = hipMalloc(&b.allocations.back(), std::max<size_t>(bytes, 16));
+    if (e != hipSuccess) {
+        b.allocations.pop_back();
+        return e;
+    }
+    *ptr = b.allocations.back();
     b.workspace_bytes += (int64_t)bytes;
     return hipSuccess;
 }
@@ -600,7 +604,12 @@ void drop_graph(pgc_batch_s& b)
 // lay out the work units for C cells per wave and upload the group table
 hipError_t set_units(pgc_batch_s& b, int C, hipStream_t s)
 {
-    std::vector<pgc::GroupDev> gd(b.groups.size());
+    std::vector<pgc::GroupDev> gd;
+    try {
+        gd.resize(b.groups.size());
+    } catch (...) {
+        return hipErrorOutOfMemory;
+    }
     unsigned long long begin = 0;
     for (size_t g = 0; g < b.groups.size(); ++g) {
         const BatchGroup& G = b.groups[g];
@@ -822,66 +831,70 @@ pgc_status pgc_batch_create(const pgc_plan_desc* base, int32_t n_cells, const in
 
     pgc_status st = PGC_OK;
     hipError_t e = hipSuccess;
-    for (BatchGroup& g : b->groups) {
-        pgc_plan_desc d = *base;
-        d.n_modes = g.N;
-        d.m_v = 0;
-        d.gain_mode = pgc::kGainBinned;
-        st = pgc_plan_create(&d, stream, &g.plan);
-        if (st != PGC_OK) break;
-        const Plan& p = g.plan->p;
-        if (b->W == 0) b->W = p.W;
-        if (p.W != b->W || !pgc::tile_supported(p.W, 1) || p.gain_mode != pgc::kGainBinned) {
-            st = PGC_ERR_UNSUPPORTED;
-            break;
-        }
-        b->n_points += p.n_points * (int64_t)g.cells.size();
-        const int64_t nb = (int64_t)g.cells.size();
-        const int64_t L = std::max<int64_t>(std::max(p.N, p.ni), p.ng);
-        const int64_t t = L * L;
-        if ((e = batch_alloc_n(*b, &g.cells_dev, nb)) != hipSuccess) break;
-        if ((e = batch_alloc_n(*b, &g.cin, nb * p.Nd)) != hipSuccess) break;
-        if ((e = batch_alloc_n(*b, &g.b.P, nb * p.nid)) != hipSuccess) break;
-        if ((e = batch_alloc_n(*b, &g.b.G, nb * p.nid)) != hipSuccess) break;
-        float* gg = nullptr;
-        if ((e = batch_alloc_n(*b, &gg, nb * p.nid)) != hipSuccess) break;
-        g.b.Gg = gg;
-        if ((e = batch_alloc_n(*b, &g.b.H, nb * p.nid)) != hipSuccess) break;
-        if ((e = batch_alloc_n(*b, &g.b.qminus, nb * p.Nd)) != hipSuccess) break;
-        if ((e = batch_alloc_n(*b, &g.b.qplus, nb * p.Nd)) != hipSuccess) break;
-        if ((e = batch_alloc_n(*b, &g.b.tmpA, nb * t)) != hipSuccess) break;
-        if ((e = batch_alloc_n(*b, &g.b.tmpB, nb * t)) != hipSuccess) break;
-        if ((e = batch_alloc_n(*b, &g.b.red, nb)) != hipSuccess) break;
-        if ((e = batch_alloc_n(*b, &g.grid, nb * p.ngd)) != hipSuccess) break;
-        g.ldg = (int)((nb + 63) / 64 * 64);
-        if ((e = batch_alloc_n(*b, &g.Gt, p.nid * g.ldg)) != hipSuccess) break;
-        {
-            // raster order of the bins: consecutive runs flush into overlapping grid lines
-            std::vector<int> bins((size_t)p.bins.n_items), ord((size_t)p.bins.n_items);
-            if (p.bins.n_items > 0 &&
-                (e = hipMemcpy(bins.data(), p.bins.item_bin, bins.size() * sizeof(int), hipMemcpyDeviceToHost)) !=
-                    hipSuccess)
+    try {  // host containers below throw only on allocation failure
+        for (BatchGroup& g : b->groups) {
+            pgc_plan_desc d = *base;
+            d.n_modes = g.N;
+            d.m_v = 0;
+            d.gain_mode = pgc::kGainBinned;
+            st = pgc_plan_create(&d, stream, &g.plan);
+            if (st != PGC_OK) break;
+            const Plan& p = g.plan->p;
+            if (b->W == 0) b->W = p.W;
+            if (p.W != b->W || !pgc::tile_supported(p.W, 1) || p.gain_mode != pgc::kGainBinned) {
+                st = PGC_ERR_UNSUPPORTED;
                 break;
-            for (size_t k = 0; k < ord.size(); ++k) ord[k] = (int)k;
-            std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return bins[x] < bins[y]; });
-            if ((e = batch_alloc_n(*b, &g.order, std::max<int64_t>(1, p.bins.n_items))) != hipSuccess) break;
-            if (!ord.empty() &&
-                (e = hipMemcpy(g.order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+            }
+            b->n_points += p.n_points * (int64_t)g.cells.size();
+            const int64_t nb = (int64_t)g.cells.size();
+            const int64_t L = std::max<int64_t>(std::max(p.N, p.ni), p.ng);
+            const int64_t t = L * L;
+            if ((e = batch_alloc_n(*b, &g.cells_dev, nb)) != hipSuccess) break;
+            if ((e = batch_alloc_n(*b, &g.cin, nb * p.Nd)) != hipSuccess) break;
+            if ((e = batch_alloc_n(*b, &g.b.P, nb * p.nid)) != hipSuccess) break;
+            if ((e = batch_alloc_n(*b, &g.b.G, nb * p.nid)) != hipSuccess) break;
+            float* gg = nullptr;
+            if ((e = batch_alloc_n(*b, &gg, nb * p.nid)) != hipSuccess) break;
+            g.b.Gg = gg;
+            if ((e = batch_alloc_n(*b, &g.b.H, nb * p.nid)) != hipSuccess) break;
+            if ((e = batch_alloc_n(*b, &g.b.qminus, nb * p.Nd)) != hipSuccess) break;
+            if ((e = batch_alloc_n(*b, &g.b.qplus, nb * p.Nd)) != hipSuccess) break;
+            if ((e = batch_alloc_n(*b, &g.b.tmpA, nb * t)) != hipSuccess) break;
+            if ((e = batch_alloc_n(*b, &g.b.tmpB, nb * t)) != hipSuccess) break;
+            if ((e = batch_alloc_n(*b, &g.b.red, nb)) != hipSuccess) break;
+            if ((e = batch_alloc_n(*b, &g.grid, nb * p.ngd)) != hipSuccess) break;
+            g.ldg = (int)((nb + 63) / 64 * 64);
+            if ((e = batch_alloc_n(*b, &g.Gt, p.nid * g.ldg)) != hipSuccess) break;
+            {
+                // raster order of the bins: consecutive runs flush into overlapping grid lines
+                std::vector<int> bins((size_t)p.bins.n_items), ord((size_t)p.bins.n_items);
+                if (p.bins.n_items > 0 &&
+                    (e = hipMemcpy(bins.data(), p.bins.item_bin, bins.size() * sizeof(int), hipMemcpyDeviceToHost)) !=
+                        hipSuccess)
+                    break;
+                for (size_t k = 0; k < ord.size(); ++k) ord[k] = (int)k;
+                std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return bins[x] < bins[y]; });
+                if ((e = batch_alloc_n(*b, &g.order, std::max<int64_t>(1, p.bins.n_items))) != hipSuccess) break;
+                if (!ord.empty() &&
+                    (e = hipMemcpy(g.order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+                    break;
+            }
+            if ((e = hipMemcpyAsync(g.cells_dev, g.cells.data(), nb * sizeof(int), hipMemcpyHostToDevice, s)) !=
+                hipSuccess)
                 break;
         }
-        if ((e = hipMemcpyAsync(g.cells_dev, g.cells.data(), nb * sizeof(int), hipMemcpyHostToDevice, s)) !=
-            hipSuccess)
-            break;
-    }
-    if (st == PGC_OK && e == hipSuccess) {
-        if ((e = batch_alloc_n(*b, &b->offsets_dev, b->n_cells)) == hipSuccess &&
-            (e = hipMemcpyAsync(b->offsets_dev, b->offsets.data(), b->n_cells * sizeof(int64_t),
-                                hipMemcpyHostToDevice, s)) == hipSuccess &&
-            (e = batch_alloc_n(*b, &b->groups_dev, (int64_t)b->groups.size())) == hipSuccess &&
-            (e = batch_alloc_n(*b, &b->counter, 1)) == hipSuccess) {
-            e = autotune_on ? autotune(*b, s) : set_units(*b, 1, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (st == PGC_OK && e == hipSuccess) {
+            if ((e = batch_alloc_n(*b, &b->offsets_dev, b->n_cells)) == hipSuccess &&
+                (e = hipMemcpyAsync(b->offsets_dev, b->offsets.data(), b->n_cells * sizeof(int64_t),
+                                    hipMemcpyHostToDevice, s)) == hipSuccess &&
+                (e = batch_alloc_n(*b, &b->groups_dev, (int64_t)b->groups.size())) == hipSuccess &&
+                (e = batch_alloc_n(*b, &b->counter, 1)) == hipSuccess) {
+                e = autotune_on ? autotune(*b, s) : set_units(*b, 1, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+            }
         }
+    } catch (...) {
+        st = PGC_ERR_OUT_OF_MEMORY;
     }
     if (st == PGC_OK && e != hipSuccess) st = pgc::status_of(e);
     if (st != PGC_OK) {

@@ -507,9 +507,13 @@ hipError_t dev_alloc(Plan& p, void** ptr, size_t bytes)
 {
     *ptr = nullptr;
     if (bytes == 0) bytes = 16;
-    hipError_t e = hipMalloc(ptr, bytes);
-    if (e != hipSuccess) return e;
-    p.allocations.push_back(*ptr);
+    p.allocations.push_back(nullptr);  // the slot first: a throwing push_back leaks no device memory
+    hipError_t e = hipMalloc(&p.allocations.back(), bytes);
+    if (e != hipSuccess) {
+        p.allocations.pop_back();
+        return e;
+    }
+    *ptr = p.allocations.back();
     p.workspace_bytes += (int64_t)bytes;
     return hipSuccess;
 }
@@ -557,11 +561,11 @@ hipError_t build_bins(Plan& p, hipStream_t s)
     for (int l = 0; l < p.dim; ++l) nbins *= B.nb;
     unsigned int* count = nullptr;
     unsigned long long* cursor = nullptr;
+    std::vector<unsigned int> hc(nbins);  // before the temporary, which nothing below may leak
     hipError_t e = hipMalloc(&count, nbins * sizeof(unsigned int));
     if (e != hipSuccess) return e;
     e = hipMemsetAsync(count, 0, nbins * sizeof(unsigned int), s);
     if (e == hipSuccess) e = launch_bin_build(p, count, nullptr, nullptr, 0, s);
-    std::vector<unsigned int> hc(nbins);
     if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), count, nbins * sizeof(unsigned int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(count);
@@ -796,22 +800,21 @@ pgc_status pgc_plan_create(const pgc_plan_desc* desc, void* stream, pgc_plan* pl
     } catch (const std::bad_alloc&) {
         return PGC_ERR_OUT_OF_MEMORY;
     }
-    pgc_status st = pgc::resolve(*desc, h->p);
-    if (st != PGC_OK) {
-        delete h;
-        return st;
-    }
+    // host containers are the only thing here that throws (allocation failure)
+    pgc_status st = PGC_OK;
     try {
-        pgc::build_tables(h->p);
-    } catch (const std::bad_alloc&) {
-        delete h;
-        return PGC_ERR_OUT_OF_MEMORY;
+        st = pgc::resolve(*desc, h->p);
+        if (st == PGC_OK) {
+            pgc::build_tables(h->p);
+            st = pgc::from_hip(pgc::allocate(h->p, static_cast<hipStream_t>(stream)));
+        }
+    } catch (...) {
+        st = PGC_ERR_OUT_OF_MEMORY;
     }
-    hipError_t e = pgc::allocate(h->p, static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) {
+    if (st != PGC_OK) {
         pgc::free_all(h->p);
         delete h;
-        return pgc::from_hip(e);
+        return st;
     }
     *plan_out = h;
     return PGC_OK;
@@ -928,9 +931,16 @@ pgc_status pgc_set_profiling(pgc_plan plan, int32_t on)
     if (on && !p.prof) {
         pgc::Profiler* pr = new (std::nothrow) pgc::Profiler();
         if (!pr) return PGC_ERR_OUT_OF_MEMORY;
-        for (int r = 0; r < pgc::kProfRing; ++r)
-            for (int k = 0; k <= pgc::kStages; ++k)
-                if (hipEventCreate(&pr->ev[r][k]) != hipSuccess) return PGC_ERR_DEVICE;
+        int made = 0;  // events created so far, destroyed again on failure
+        hipError_t e = hipSuccess;
+        for (int r = 0; r < pgc::kProfRing && e == hipSuccess; ++r)
+            for (int k = 0; k <= pgc::kStages && e == hipSuccess; ++k)
+                if ((e = hipEventCreate(&pr->ev[r][k])) == hipSuccess) ++made;
+        if (e != hipSuccess) {
+            for (int i = 0; i < made; ++i) (void)hipEventDestroy(pr->ev[i / (pgc::kStages + 1)][i % (pgc::kStages + 1)]);
+            delete pr;
+            return pgc::from_hip(e);
+        }
         p.prof = pr;
     } else if (!on && p.prof) {
         (void)hipDeviceSynchronize();

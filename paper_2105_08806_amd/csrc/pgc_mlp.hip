@@ -605,9 +605,13 @@ namespace {
 hipError_t s_alloc(pgc_surrogate_s& s, void** p, size_t bytes)
 {
     *p = nullptr;
-    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
-    if (e != hipSuccess) return e;
-    s.allocations.push_back(*p);
+    s.allocations.push_back(nullptr);  // the slot first: a throwing push_back leaks no device memory
+    hipError_t e = hipMalloc(&s.allocations.back(), std::max<size_t>(bytes, 16));
+    if (e != hipSuccess) {
+        s.allocations.pop_back();
+        return e;
+    }
+    *p = s.allocations.back();
     s.bytes += (int64_t)bytes;
     return hipSuccess;
 }
@@ -884,46 +888,46 @@ pgc_status pgc_surrogate_create(pgc_plan plan, const pgc_surrogate_desc* d, void
     s->loss_relative = d->loss_relative;
     hipError_t e = hipSuccess;
     std::vector<double> cons, ginv, cnorm;
-    try {
-        build_constraints(p, cons, ginv, cnorm, s->nc);
-    } catch (const std::bad_alloc&) {
-        s_free(s);
-        return PGC_ERR_OUT_OF_MEMORY;
-    }
     std::mt19937_64 rng(d->seed);
     std::vector<float> hostw;
     const int B = s->bmax;
-    for (int l = 0; l < d->n_layers && e == hipSuccess; ++l) {
-        Layer L;
-        L.in = l == 0 ? s->n : d->width;
-        L.out = l + 1 == d->n_layers ? s->n : d->width;
-        const int64_t nw = (int64_t)L.in * L.out;
-        if ((e = s_alloc_n(*s, &L.W, nw)) != hipSuccess) break;
-        if ((e = s_alloc_n(*s, &L.gW, nw)) != hipSuccess) break;
-        if ((e = s_alloc_n(*s, &L.mW, nw)) != hipSuccess) break;
-        if ((e = s_alloc_n(*s, &L.vW, nw)) != hipSuccess) break;
-        if ((e = s_alloc_n(*s, &L.Wb, nw)) != hipSuccess) break;
-        if ((e = s_alloc_n(*s, &L.b, L.out)) != hipSuccess) break;
-        if ((e = s_alloc_n(*s, &L.gb, L.out)) != hipSuccess) break;
-        if ((e = s_alloc_n(*s, &L.mb, L.out)) != hipSuccess) break;
-        if ((e = s_alloc_n(*s, &L.vb, L.out)) != hipSuccess) break;
-        if ((e = s_alloc_n(*s, &L.Z, (int64_t)B * L.out)) != hipSuccess) break;
-        if ((e = s_alloc_n(*s, &L.H, (int64_t)B * L.out)) != hipSuccess) break;
-        if ((e = s_alloc_n(*s, &L.dH, (int64_t)B * L.out)) != hipSuccess) break;
-        if ((e = s_alloc_n(*s, &L.dZ32, (int64_t)B * L.out)) != hipSuccess) break;
-        if ((e = s_alloc_n(*s, &L.dZ, (int64_t)B * L.out)) != hipSuccess) break;
-        // He-style uniform initialisation, bound sqrt(6 / in) (SiLU ~ ReLU scale)
-        hostw.resize((size_t)nw);
-        const double bound = std::sqrt(6.0 / L.in) * (l + 1 == d->n_layers ? 0.1 : 1.0);
-        std::uniform_real_distribution<double> U(-bound, bound);
-        for (auto& w : hostw) w = (float)U(rng);
-        if ((e = hipMemcpy(L.W, hostw.data(), nw * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) break;
-        hipLaunchKernelGGL(pgc::fill_f32, dim3(pgc::nb(L.out, 256)), dim3(256), 0, st, L.b, 0.f, (int64_t)L.out);
-        hipLaunchKernelGGL(pgc::fill_f32, dim3(pgc::nb(nw, 256)), dim3(256), 0, st, L.mW, 0.f, nw);
-        hipLaunchKernelGGL(pgc::fill_f32, dim3(pgc::nb(nw, 256)), dim3(256), 0, st, L.vW, 0.f, nw);
-        hipLaunchKernelGGL(pgc::fill_f32, dim3(pgc::nb(L.out, 256)), dim3(256), 0, st, L.mb, 0.f, (int64_t)L.out);
-        hipLaunchKernelGGL(pgc::fill_f32, dim3(pgc::nb(L.out, 256)), dim3(256), 0, st, L.vb, 0.f, (int64_t)L.out);
-        s->layers.push_back(L);
+    try {  // host containers throw only on allocation failure
+        build_constraints(p, cons, ginv, cnorm, s->nc);
+        for (int l = 0; l < d->n_layers && e == hipSuccess; ++l) {
+            Layer L;
+            L.in = l == 0 ? s->n : d->width;
+            L.out = l + 1 == d->n_layers ? s->n : d->width;
+            const int64_t nw = (int64_t)L.in * L.out;
+            if ((e = s_alloc_n(*s, &L.W, nw)) != hipSuccess) break;
+            if ((e = s_alloc_n(*s, &L.gW, nw)) != hipSuccess) break;
+            if ((e = s_alloc_n(*s, &L.mW, nw)) != hipSuccess) break;
+            if ((e = s_alloc_n(*s, &L.vW, nw)) != hipSuccess) break;
+            if ((e = s_alloc_n(*s, &L.Wb, nw)) != hipSuccess) break;
+            if ((e = s_alloc_n(*s, &L.b, L.out)) != hipSuccess) break;
+            if ((e = s_alloc_n(*s, &L.gb, L.out)) != hipSuccess) break;
+            if ((e = s_alloc_n(*s, &L.mb, L.out)) != hipSuccess) break;
+            if ((e = s_alloc_n(*s, &L.vb, L.out)) != hipSuccess) break;
+            if ((e = s_alloc_n(*s, &L.Z, (int64_t)B * L.out)) != hipSuccess) break;
+            if ((e = s_alloc_n(*s, &L.H, (int64_t)B * L.out)) != hipSuccess) break;
+            if ((e = s_alloc_n(*s, &L.dH, (int64_t)B * L.out)) != hipSuccess) break;
+            if ((e = s_alloc_n(*s, &L.dZ32, (int64_t)B * L.out)) != hipSuccess) break;
+            if ((e = s_alloc_n(*s, &L.dZ, (int64_t)B * L.out)) != hipSuccess) break;
+            // He-style uniform initialisation, bound sqrt(6 / in) (SiLU ~ ReLU scale)
+            hostw.resize((size_t)nw);
+            const double bound = std::sqrt(6.0 / L.in) * (l + 1 == d->n_layers ? 0.1 : 1.0);
+            std::uniform_real_distribution<double> U(-bound, bound);
+            for (auto& w : hostw) w = (float)U(rng);
+            if ((e = hipMemcpy(L.W, hostw.data(), nw * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) break;
+            hipLaunchKernelGGL(pgc::fill_f32, dim3(pgc::nb(L.out, 256)), dim3(256), 0, st, L.b, 0.f, (int64_t)L.out);
+            hipLaunchKernelGGL(pgc::fill_f32, dim3(pgc::nb(nw, 256)), dim3(256), 0, st, L.mW, 0.f, nw);
+            hipLaunchKernelGGL(pgc::fill_f32, dim3(pgc::nb(nw, 256)), dim3(256), 0, st, L.vW, 0.f, nw);
+            hipLaunchKernelGGL(pgc::fill_f32, dim3(pgc::nb(L.out, 256)), dim3(256), 0, st, L.mb, 0.f, (int64_t)L.out);
+            hipLaunchKernelGGL(pgc::fill_f32, dim3(pgc::nb(L.out, 256)), dim3(256), 0, st, L.vb, 0.f, (int64_t)L.out);
+            s->layers.push_back(L);
+        }
+    } catch (...) {
+        s_free(s);
+        return PGC_ERR_OUT_OF_MEMORY;
     }
     const int64_t n = s->n;
     if (e == hipSuccess) e = s_alloc_n(*s, &s->mu_in, n);
@@ -1019,7 +1023,15 @@ pgc_status pgc_surrogate_train(pgc_surrogate s, const float* f_dev, const float*
     if (n_samples > 2147483647ll) return PGC_ERR_UNSUPPORTED;
     hipStream_t st = static_cast<hipStream_t>(stream);
     std::mt19937_64 rng(seed);
-    std::vector<int> perm((size_t)n_samples);
+    std::vector<int> perm;
+    std::vector<double> rr, zz;
+    try {
+        perm.resize((size_t)n_samples);
+        rr.resize((size_t)s->bmax);
+        zz.resize((size_t)s->bmax);
+    } catch (...) {
+        return PGC_ERR_OUT_OF_MEMORY;
+    }
     // the epoch's sample order on the device: the steps of an epoch are queued
     // without host round trips, and the stream is synchronised once per epoch
     int* perm_dev = nullptr;
@@ -1055,7 +1067,6 @@ pgc_status pgc_surrogate_train(pgc_surrogate s, const float* f_dev, const float*
     if (e != hipSuccess) return pgc::status_of(e);
     // calibrate the out-of-distribution gate: largest raw residual on the training set
     double worst = 0.0, worst_z = 0.0;
-    std::vector<double> rr((size_t)s->bmax), zz((size_t)s->bmax);
     for (int64_t b0 = 0; b0 < n_samples && e == hipSuccess; b0 += s->bmax) {
         const int rows = (int)std::min<int64_t>(s->bmax, n_samples - b0);
         e = normalise_rows(*s, f_dev, nullptr, b0, rows, st);
@@ -1094,8 +1105,14 @@ pgc_status pgc_surrogate_coeffs_to_q(pgc_surrogate s, const float* f_dev, int64_
     int64_t nfb = 0;
     double worst_judge = 0.0;
     bool judge_failed = false;
-    std::vector<double> rr((size_t)s->bmax), ro((size_t)s->bmax), er((size_t)s->bmax), zz((size_t)s->bmax);
-    std::vector<int> fb((size_t)s->bmax);
+    std::vector<double> rr, ro, er, zz;
+    std::vector<int> fb;
+    try {
+        for (auto* v : {&rr, &ro, &er, &zz}) v->resize((size_t)s->bmax);
+        fb.resize((size_t)s->bmax);
+    } catch (...) {
+        return PGC_ERR_OUT_OF_MEMORY;
+    }
     const bool ood_on = s->gate_raw_factor > 0 && s->raw_calib > 0;
     const double raw_gate = s->gate_raw_factor * s->raw_calib, z_gate = s->gate_raw_factor * s->z_calib;
     for (int64_t b0 = 0; b0 < n_samples && e == hipSuccess; b0 += s->bmax) {
