@@ -38,8 +38,9 @@
  *  - `stream` is a hipStream_t (NULL = the default stream).  Calls only
  *    enqueue work on it and return; no call synchronises the host unless its
  *    comment says so.  A plan owns all its workspace (allocated in
- *    pgc_plan_create, freed in pgc_plan_destroy); the calls that take a
- *    stream allocate nothing.
+ *    pgc_plan_create, freed in pgc_plan_destroy); the calls that enqueue
+ *    work on a plan (pgc_project, pgc_coeffs_to_q, pgc_rk4, pgc_moments,
+ *    pgc_eval) allocate nothing.
  *  - A plan must not be used by two calls that can run concurrently.
  *  - Every call returns a pgc_status.  On an error return the outputs are
  *    untouched (for argument errors) or unspecified (device errors).  No C++
