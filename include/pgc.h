@@ -387,7 +387,10 @@ pgc_status pgc_surrogate_load(pgc_surrogate s, const char* path, void* stream);
 /* The matrix-core product the surrogate is built on, exposed for testing:
  * C (M x N, FP32, row stride ldc) = op(A) op(B) + bias (or C += ... when
  * accumulate != 0), A and B BF16 device matrices given as uint16 bit
- * patterns, op(A)[m][k] = trans_a ? A[k lda + m] : A[m lda + k], likewise B. */
+ * patterns, op(A)[m][k] = trans_a ? A[k lda + m] : A[m lda + k], likewise B.
+ * INVALID_ARG for negative sizes, missing pointers, or a row stride shorter
+ * than its row (lda < K, or < M when transposed; ldb likewise; ldc < N).
+ * K = 0 gives C = bias (zero without one), or C += bias. */
 pgc_status pgc_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* a_dev, int32_t lda, int32_t trans_a,
                          const uint16_t* b_dev, int32_t ldb, int32_t trans_b, float* c_dev, int32_t ldc,
                          const float* bias_dev, int32_t accumulate, void* stream);

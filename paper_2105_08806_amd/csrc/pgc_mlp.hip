@@ -261,6 +261,16 @@ __global__ void zero_rows(float* __restrict__ C, int ldc, int M, int N)
     C[(e / N) * ldc + e % N] = 0.f;
 }
 
+// the empty product (K = 0): C = bias (zero without one), or C += bias
+__global__ void bias_rows(float* __restrict__ C, int ldc, int M, int N, const float* __restrict__ bias, int accumulate)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)M * N) return;
+    float* c = C + (e / N) * ldc + e % N;
+    const float v = bias ? bias[e % N] : 0.f;
+    *c = accumulate ? *c + v : v;
+}
+
 __global__ void f32_to_bf16(const float* __restrict__ x, bf16* __restrict__ y, int64_t n)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -636,7 +646,12 @@ void s_free(pgc_surrogate_s* s)
 hipError_t gemm(int M, int N, int K, const bf16* A, int lda, bool ta, const bf16* B, int ldb, bool tb, float* C,
                 int ldc, const float* bias, bool accumulate, hipStream_t st)
 {
-    if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (K <= 0) {
+        hipLaunchKernelGGL(pgc::bias_rows, dim3(pgc::nb((int64_t)M * N, 256)), dim3(256), 0, st, C, ldc, M, N, bias,
+                           accumulate ? 1 : 0);
+        return hipGetLastError();
+    }
     const int tiles = ((M + pgc::kBM - 1) / pgc::kBM) * ((N + pgc::kBN - 1) / pgc::kBN);
     // split K until the tiles cover the device about four times over
     int split = 1;
@@ -1317,7 +1332,13 @@ pgc_status pgc_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* a_dev,
                          const uint16_t* b_dev, int32_t ldb, int32_t trans_b, float* c_dev, int32_t ldc,
                          const float* bias_dev, int32_t accumulate, void* stream)
 {
-    if (M < 0 || N < 0 || K < 0 || (M > 0 && N > 0 && (!a_dev || !b_dev || !c_dev))) return PGC_ERR_INVALID_ARG;
+    if (M < 0 || N < 0 || K < 0) return PGC_ERR_INVALID_ARG;
+    if (M > 0 && N > 0) {
+        // row strides cover the rows they step over
+        if (!c_dev || ldc < N) return PGC_ERR_INVALID_ARG;
+        if (K > 0 && (!a_dev || !b_dev || lda < (trans_a ? M : K) || ldb < (trans_b ? K : N)))
+            return PGC_ERR_INVALID_ARG;
+    }
     return pgc::status_of(gemm(M, N, K, a_dev, lda, trans_a != 0, b_dev, ldb, trans_b != 0, c_dev, ldc, bias_dev,
                                accumulate != 0, static_cast<hipStream_t>(stream)));
 }

@@ -441,8 +441,12 @@ def gemm_bf16(a, b, trans_a=False, trans_b=False, bias=None, out=None, accumulat
         raise ValueError("inner dimensions differ")
     if out is None:
         out = torch.zeros(M, N, dtype=torch.float32, device=a.device)
+    if tuple(out.shape) != (M, N) or out.dtype != torch.float32 or (N > 1 and out.stride(1) != 1):
+        raise ValueError("out must be a float32 (M, N) matrix with unit column stride")
+    if bias is not None and (tuple(bias.shape) != (N,) or bias.dtype != torch.float32 or not bias.is_contiguous()):
+        raise ValueError("bias must be a contiguous float32 vector of length N")
     _check(lib().pgc_gemm_bf16(M, N, K, _ptr(a), a.shape[1], int(trans_a), _ptr(b), b.shape[1], int(trans_b),
-                               _ptr(out), out.shape[1], _ptr(bias) if bias is not None else None,
+                               _ptr(out), max(out.stride(0), N), _ptr(bias) if bias is not None else None,
                                int(accumulate), _stream()), "pgc_gemm_bf16")
     return out
 

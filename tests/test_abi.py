@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from conftest import ROOT
@@ -99,3 +100,74 @@ def test_batch_argument_errors_without_a_device():
     d64 = pgc.default_desc()   # FP64 batches are not built
     assert L.pgc_batch_create(ctypes.byref(d64), 3, modes, 0, None, ctypes.byref(h)) == 2
     assert not h.value
+
+
+def _create_status(pgc, L, **fields):
+    d = pgc.default_desc()
+    for k, v in fields.items():
+        setattr(d, k, v)
+    h = ctypes.c_void_p()
+    st = L.pgc_plan_create(ctypes.byref(d), None, ctypes.byref(h))
+    assert not h.value  # a rejected descriptor leaves no plan behind
+    return st
+
+
+def test_plan_descriptor_rejections_without_a_device():
+    """Descriptor validation runs on the host before any device call: every
+    out-of-range field is an argument error, and the combinations the kernels
+    do not cover are unsupported."""
+    from paper_2105_08806_amd import pgc
+    L = pgc.lib()
+    bad = [dict(dim=1), dict(dim=4), dict(n_modes=2), dict(m_v=2), dict(map=7), dict(scale=0.0),
+           dict(scale=float("inf")), dict(scale=float("nan")), dict(scale_mode=5), dict(kernel=9),
+           dict(kernel=pgc.KERNEL_VHS, kernel_gamma=1.5), dict(kernel=pgc.KERNEL_VHS, kernel_gamma=-0.1),
+           dict(kernel_b0=-1.0), dict(precision=3), dict(nufft_tol=-1e-6), dict(upsample=1.2),
+           dict(upsample=5.0), dict(kernel_width=3), dict(kernel_width=99), dict(slab_planes=-1),
+           dict(n_chunks=-2), dict(block_threads=300), dict(gain_mode=4), dict(gain_mode=-1),
+           dict(n_sigma=7),                                  # a circle rule needs antipodal pairs
+           dict(n_sigma=0), dict(sphere=9),
+           dict(dim=3),                                      # the circle rule is a 2D rule
+           dict(dim=3, sphere=pgc.SPHERE_PRODUCT_3D, n_theta=4, n_phi=5),
+           dict(dim=3, sphere=pgc.SPHERE_PRODUCT_3D, n_theta=0, n_phi=8),
+           dict(sphere=pgc.SPHERE_USER, n_sigma=4)]          # user rule without its arrays
+    for fields in bad:
+        assert _create_status(pgc, L, **fields) == 1, fields
+    # user rules: unit vectors with positive weights in antipodal pairs
+    def user(sig, wts):
+        s = np.ascontiguousarray(sig, dtype=np.float64)
+        w = np.ascontiguousarray(wts, dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        return _create_status(pgc, L, sphere=pgc.SPHERE_USER, n_sigma=len(w),
+                              user_sigma_host=s.ctypes.data_as(dp), user_weights_host=w.ctypes.data_as(dp))
+    assert user([[1, 0], [0, 1]], [1.0, 1.0]) == 1                   # not antipodal
+    assert user([[1, 0], [-1, 0]], [1.0, 2.0]) == 1                  # opposite weights differ
+    assert user([[2, 0], [-2, 0]], [1.0, 1.0]) == 1                  # not unit vectors
+    assert user([[1, 0], [-1, 0]], [1.0, 0.0]) == 1                  # zero weight
+    assert user([[np.nan, 0], [-1, 0]], [1.0, 1.0]) == 1             # not finite
+    # the matrix-core gain covers FP64 3D plans only; an explicit binned mode
+    # beyond the binned scheme's node limit is refused rather than replaced
+    assert _create_status(pgc, L, gain_mode=3) == 2
+    assert _create_status(pgc, L, gain_mode=2, n_modes=300) == 2
+
+
+def test_gemm_argument_errors_without_a_device():
+    """The BF16 product rejects negative sizes, missing operands and row
+    strides shorter than their rows before it launches anything (the pointers
+    here are never dereferenced)."""
+    from paper_2105_08806_amd import pgc
+    L = pgc.lib()
+    fake = ctypes.c_void_p(0x1000)
+
+    def call(M, N, K, lda, ta, ldb, tb, ldc, a=fake, b=fake, c=fake):
+        return L.pgc_gemm_bf16(M, N, K, a, lda, ta, b, ldb, tb, c, ldc, None, 0, None)
+    assert call(-1, 4, 4, 4, 0, 4, 0, 4) == 1
+    assert call(4, 4, -1, 4, 0, 4, 0, 4) == 1
+    assert call(8, 6, 5, 4, 0, 6, 0, 6) == 1       # lda < K
+    assert call(8, 6, 5, 5, 1, 6, 0, 6) == 1       # transposed A: lda < M
+    assert call(8, 6, 5, 5, 0, 5, 0, 6) == 1       # ldb < N
+    assert call(8, 6, 5, 5, 0, 4, 1, 6) == 1       # transposed B: ldb < K
+    assert call(8, 6, 5, 5, 0, 6, 0, 5) == 1       # ldc < N
+    assert call(8, 6, 5, 5, 0, 6, 0, 6, a=None) == 1
+    assert call(8, 6, 5, 5, 0, 6, 0, 6, c=None) == 1
+    # empty outputs need no operands at all
+    assert call(0, 6, 5, 0, 0, 0, 0, 0, a=None, b=None, c=None) == 0

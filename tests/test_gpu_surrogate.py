@@ -53,6 +53,35 @@ def test_gemm_bf16_layouts(torch_cuda, ta, tb, M, N, K):
     assert rel(c2.double().cpu().numpy(), ref2.numpy()) <= 1e-5
 
 
+def test_gemm_bf16_edges(torch_cuda):
+    """The empty inner dimension gives C = bias (zero without one) or C += bias;
+    an output with a row stride wider than N is written in its columns only."""
+    torch = torch_cuda
+    from paper_2105_08806_amd import pgc
+    a = torch.zeros((5, 0), dtype=torch.bfloat16, device="cuda")
+    b = torch.zeros((0, 7), dtype=torch.bfloat16, device="cuda")
+    bias = torch.arange(7, dtype=torch.float32, device="cuda")
+    c = pgc.gemm_bf16(a, b, out=torch.full((5, 7), 3.0, device="cuda"), bias=bias)
+    c2 = pgc.gemm_bf16(a, b, out=torch.full((5, 7), 2.0, device="cuda"), bias=bias, accumulate=True)
+    c3 = pgc.gemm_bf16(a, b, out=torch.full((5, 7), 3.0, device="cuda"))
+    torch.cuda.synchronize()
+    assert torch.equal(c.cpu(), bias.cpu().expand(5, 7))
+    assert torch.equal(c2.cpu(), 2.0 + bias.cpu().expand(5, 7))
+    assert torch.equal(c3.cpu(), torch.zeros(5, 7))
+    g = torch.Generator().manual_seed(11)
+    x = torch.randn((33, 70), generator=g).to(torch.bfloat16)
+    y = torch.randn((70, 21), generator=g).to(torch.bfloat16)
+    wide = torch.full((33, 40), -5.0, device="cuda")
+    pgc.gemm_bf16(x.cuda(), y.cuda(), out=wide[:, 4:25])
+    torch.cuda.synchronize()
+    ref = x.double() @ y.double()
+    w = wide.cpu()
+    assert rel(w[:, 4:25].double().numpy(), ref.numpy()) <= 1e-5
+    assert torch.all(w[:, :4] == -5.0) and torch.all(w[:, 25:] == -5.0)
+    with pytest.raises(ValueError):
+        pgc.gemm_bf16(x.cuda(), y.cuda(), out=torch.zeros((32, 21), device="cuda"))
+
+
 def small_plan(pgc, N=5):
     # algebraic map, which conserves mass, momentum and energy (Sec. 3.2)
     return pgc.Plan(dim=3, n_modes=N, scale=3.0, map=pgc.MAP_ALGEBRAIC, sphere=pgc.SPHERE_PRODUCT_3D,
