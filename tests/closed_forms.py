@@ -49,7 +49,8 @@ def one_minus_xi2(v, S, map_):
     """1 - xi(v)^2 written in v (sech^2(v/S), resp. S^2/(S^2 + v^2))."""
     v = np.asarray(v, dtype=np.float64)
     if map_ == 0:
-        return 1.0 / np.cosh(v / S) ** 2
+        e = np.exp(-2.0 * np.abs(v / S))   # sech^2 x = 4 e^{-2|x|} / (1 + e^{-2|x|})^2, no overflow
+        return 4.0 * e / (1.0 + e) ** 2
     return S * S / (S * S + v * v)
 
 
