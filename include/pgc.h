@@ -395,6 +395,41 @@ pgc_status pgc_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* a_dev,
                          const uint16_t* b_dev, int32_t ldb, int32_t trans_b, float* c_dev, int32_t ldc,
                          const float* bias_dev, int32_t accumulate, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * The direct algorithm (Sec. 4.1, eqs. direct_online, tensor_I1, tensor_I2)
+ * for many cells that share one FP64 plan.  The discrete Q is a bilinear form
+ * in the weighted nodal values G_a = w_a mu_a^2 P_a, with a tensor that does
+ * not depend on f; it is built once, over unordered pairs a <= b of interior
+ * nodes (n_pairs = n_i^d (n_i^d + 1) / 2 rows of N^d entries), and each call
+ * forms the pair products G_a G_b of its cells and multiplies them by the
+ * tensor on the FP64 matrix cores.  The result is the same discrete sum the
+ * plan's fast path approximates, with no transform tolerance.
+ * ------------------------------------------------------------------------- */
+typedef struct pgc_direct_s* pgc_direct;
+
+typedef struct pgc_direct_info {
+    int64_t n_pairs;          /* tensor rows */
+    int64_t n_modes_total;    /* N^d, tensor columns */
+    int32_t max_cells;        /* cells per product (the chunk of a call) */
+    int64_t tensor_bytes;
+    int64_t workspace_bytes;  /* tensor, pair products of max_cells cells, synthesis buffers */
+    double setup_ms;          /* device time of the tensor build */
+    double flops_per_cell;    /* 2 n_pairs N^d: the product's share of one cell */
+} pgc_direct_info;
+
+/* Build the tensor of `plan` (FP64 plans only) and the workspace for
+ * max_cells (1..65535) cells per product; synchronises `stream`.  The plan
+ * must outlive the object.  UNSUPPORTED for FP32 plans, N^d > 4096, or a
+ * tensor above 96 GiB (2D N <= 56, 3D N <= 14 fit). */
+pgc_status pgc_direct_create(pgc_plan plan, int32_t max_cells, void* stream, pgc_direct* out);
+pgc_status pgc_direct_destroy(pgc_direct d);
+pgc_status pgc_direct_query(pgc_direct d, pgc_direct_info* info);
+/* q_dev[c][k] = Q_k of the coefficients coeffs_dev[c][k] (FP64, row-major
+ * k_d fastest, n_cells x N^d each), max_cells at a time; stream-ordered,
+ * allocates nothing (the product runs through rocBLAS on `stream`). */
+pgc_status pgc_direct_coeffs_to_q(pgc_direct d, const double* coeffs_dev, int64_t n_cells, double* q_dev,
+                                  void* stream);
+
 #ifdef __cplusplus
 }
 #endif

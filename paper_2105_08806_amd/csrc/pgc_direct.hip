@@ -1,0 +1,358 @@
+// The direct algorithm (Sec. 4.1): the discrete collision operator is a
+// bilinear form whose tensor does not depend on f, so it is built once per
+// plan, and Q of a batch of cells that share the plan is then one dense
+// product on the FP64 matrix cores.
+//
+// The paper's tensors (eqs. tensor_I1, tensor_I2) pair Chebyshev modes and
+// are contracted with the coefficients (eq. direct_online). Here the tensor
+// pairs interior CGL nodes instead, and is contracted with the weighted nodal
+// values G_a = w_a mu_a^2 P_a that the synthesis produces. Both orders of a
+// pair give the same post-collision velocity, so the two orders share one
+// entry. For the unordered pair a <= b of flat node indices:
+//
+//   K[p][k] = B(|u|) * (2 gain_k - wsum (L_k(a) + L_k(b)))   (a < b)
+//   K[p][k] = B(|u|) * (gain_k - wsum L_k(a))                (a = b)
+//   gain_k  = sum_s W_s T^_k(v'_s),  v'_s = (v_a + v_b)/2 + |u| sigma_s / 2
+//   L_k(a)  = T^_k(v_a),  T^_k(v) = prod_l mu(xi(v_l))^-2 T_{k_l}(xi(v_l)) / sqrt(c_{k_l})
+//
+// and Q_k = sum_p G_a G_b K[p][k], which is the quadrature of eqs. Qplus and
+// Qminus on the CGL nodes with the sphere rule, the same discrete sum the fast
+// algorithm approximates, without its transform tolerance.
+#include "pgc.h"
+#include "pgc_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace pgc {
+namespace {
+
+constexpr int kDirThreads = 256;
+constexpr int kSigChunk = 32;      // directions staged in LDS at a time
+constexpr int kMaxPerThread = 16;  // N^d <= 4096 outputs per pair
+constexpr int64_t kMaxTensorBytes = 96ll << 30;
+
+// zeta = xi(v) and mu(xi(v))^-2, both written in v (no cancellation near +-1)
+__device__ __forceinline__ void dir_map(int map, double S, double v, double& zeta, double& m2)
+{
+    if (map == 0) {
+        const double e = exp(v / S), ei = 1.0 / e;
+        zeta = (e - ei) / (e + ei);
+        m2 = 0.5 * S * (e + ei);
+    } else {
+        const double d = S * S + v * v;
+        zeta = v / sqrt(d);
+        m2 = d / S;
+    }
+}
+
+// One workgroup per unordered node pair: the pair's N^d tensor entries.
+template <int DIM>
+__global__ void __launch_bounds__(kDirThreads)
+    direct_tensor(const int* __restrict__ pa, const int* __restrict__ pb, int64_t n_pairs,
+                  const double* __restrict__ v1, const double* __restrict__ ltab,
+                  const double* __restrict__ sig, const double* __restrict__ sw, int n_sigma, int N,
+                  int ni, int Nd, int map, double S, double b0, double gamma, int vhs, double wsum,
+                  double* __restrict__ K)
+{
+    extern __shared__ double vec[];  // [kSigChunk][DIM][N]
+    const int64_t p = blockIdx.x;
+    if (p >= n_pairs) return;
+    int a = pa[p], b = pb[p];
+    const bool diag = a == b;
+    int ia[DIM], ib[DIM];
+#pragma unroll
+    for (int l = DIM - 1; l >= 0; --l) {
+        ia[l] = a % ni;
+        a /= ni;
+        ib[l] = b % ni;
+        b /= ni;
+    }
+    double vm[DIM], u2 = 0.0;
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) {
+        const double x = v1[ia[l]], y = v1[ib[l]];
+        vm[l] = 0.5 * (x + y);
+        u2 += (x - y) * (x - y);
+    }
+    const double un = sqrt(u2);
+    const double B = vhs ? b0 * pow(un, gamma) : b0;
+    const double r0 = 1.0 / sqrt(M_PI), r1 = sqrt(2.0 / M_PI);
+
+    double gain[kMaxPerThread];
+#pragma unroll
+    for (int r = 0; r < kMaxPerThread; ++r) gain[r] = 0.0;
+
+    for (int s0 = 0; s0 < n_sigma; s0 += kSigChunk) {
+        const int ns = min(kSigChunk, n_sigma - s0);
+        __syncthreads();  // the previous chunk's vectors are no longer read
+        for (int row = threadIdx.x; row < ns * DIM; row += kDirThreads) {
+            const int s = row / DIM, l = row % DIM;
+            const double vp = vm[l] + 0.5 * un * sig[(int64_t)(s0 + s) * DIM + l];
+            double zeta, m2;
+            dir_map(map, S, vp, zeta, m2);
+            const double sc = l == 0 ? m2 * sw[s0 + s] : m2;  // W_s rides on the first dimension
+            double* out = vec + (s * DIM + l) * N;
+            double tm = 1.0, t = zeta;
+            out[0] = sc * r0;
+            if (N > 1) out[1] = sc * r1 * zeta;
+            for (int k = 2; k < N; ++k) {
+                const double tn = 2.0 * zeta * t - tm;
+                tm = t;
+                t = tn;
+                out[k] = sc * r1 * t;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kMaxPerThread; ++r) {
+            const int k = threadIdx.x + r * kDirThreads;
+            if (k >= Nd) break;
+            int kk[DIM], f = k;
+#pragma unroll
+            for (int l = DIM - 1; l >= 0; --l) {
+                kk[l] = f % N;
+                f /= N;
+            }
+            double acc = 0.0;
+            for (int s = 0; s < ns; ++s) {
+                const double* vs = vec + s * DIM * N;
+                double t = vs[kk[0]];
+#pragma unroll
+                for (int l = 1; l < DIM; ++l) t *= vs[l * N + kk[l]];
+                acc += t;
+            }
+            gain[r] += acc;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kMaxPerThread; ++r) {
+        const int k = threadIdx.x + r * kDirThreads;
+        if (k >= Nd) break;
+        int kk[DIM], f = k;
+#pragma unroll
+        for (int l = DIM - 1; l >= 0; --l) {
+            kk[l] = f % N;
+            f /= N;
+        }
+        double la = 1.0, lb = 1.0;
+#pragma unroll
+        for (int l = 0; l < DIM; ++l) {
+            la *= ltab[ia[l] * N + kk[l]];
+            lb *= ltab[ib[l] * N + kk[l]];
+        }
+        K[p * Nd + k] = diag ? B * (gain[r] - wsum * la) : B * (2.0 * gain[r] - wsum * (la + lb));
+    }
+}
+
+// X[c][p] = G[c][a_p] G[c][b_p] for the cells of one chunk
+__global__ void pair_products(const double* __restrict__ G, const int* __restrict__ pa,
+                              const int* __restrict__ pb, int64_t n_pairs, int64_t nid,
+                              double* __restrict__ X)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n_pairs) return;
+    const double* g = G + (int64_t)blockIdx.y * nid;
+    X[(int64_t)blockIdx.y * n_pairs + p] = g[pa[p]] * g[pb[p]];
+}
+
+}  // namespace
+}  // namespace pgc
+
+struct pgc_direct_s {
+    pgc_plan plan = nullptr;
+    int max_cells = 0;
+    int64_t n_pairs = 0, nid = 0, Nd = 0;
+    double* K = nullptr;      // n_pairs x N^d
+    double* X = nullptr;      // max_cells x n_pairs
+    int* pa = nullptr;
+    int* pb = nullptr;
+    pgc::DenseBufs bufs;      // synthesis of max_cells cells
+    rocblas_handle blas = nullptr;
+    double setup_ms = 0.0;
+    int64_t bytes = 0;
+    std::vector<void*> allocations;
+};
+
+namespace {
+
+hipError_t d_alloc(pgc_direct_s& d, void** ptr, size_t bytes)
+{
+    *ptr = nullptr;
+    d.allocations.push_back(nullptr);  // the slot first: a throwing push_back leaks no device memory
+    hipError_t e = hipMalloc(&d.allocations.back(), std::max<size_t>(bytes, 16));
+    if (e != hipSuccess) {
+        d.allocations.pop_back();
+        return e;
+    }
+    *ptr = d.allocations.back();
+    d.bytes += (int64_t)bytes;
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t d_alloc_n(pgc_direct_s& d, T** ptr, int64_t n)
+{
+    void* v = nullptr;
+    hipError_t e = d_alloc(d, &v, (size_t)n * sizeof(T));
+    *ptr = static_cast<T*>(v);
+    return e;
+}
+
+template <typename T>
+hipError_t d_upload(pgc_direct_s& d, T** ptr, const std::vector<T>& src)
+{
+    hipError_t e = d_alloc_n(d, ptr, (int64_t)src.size());
+    if (e == hipSuccess && !src.empty())
+        e = hipMemcpy(*ptr, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+}
+
+void d_free(pgc_direct_s* d)
+{
+    if (!d) return;
+    (void)hipDeviceSynchronize();
+    if (d->blas) (void)rocblas_destroy_handle(d->blas);
+    for (void* p : d->allocations) (void)hipFree(p);
+    delete d;
+}
+
+}  // namespace
+
+extern "C" {
+
+pgc_status pgc_direct_create(pgc_plan plan, int32_t max_cells, void* stream, pgc_direct* out)
+{
+    if (!plan || !out || max_cells < 1 || max_cells > 65535) return PGC_ERR_INVALID_ARG;
+    *out = nullptr;
+    const pgc::Plan& p = plan->p;
+    if (p.precision != PGC_PRECISION_FP64) return PGC_ERR_UNSUPPORTED;
+    const int64_t nid = p.nid, Nd = p.Nd;
+    const int64_t n_pairs = nid * (nid + 1) / 2;
+    // one workgroup per pair: the grid's work-items must fit 32 bits
+    if (Nd > (int64_t)pgc::kMaxPerThread * pgc::kDirThreads || n_pairs * pgc::kDirThreads > 4294967295ll ||
+        n_pairs * Nd * (int64_t)sizeof(double) > pgc::kMaxTensorBytes)
+        return PGC_ERR_UNSUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    pgc_direct_s* d = nullptr;
+    pgc_status st = PGC_OK;
+    hipError_t e = hipSuccess;
+    try {  // host containers throw only on allocation failure
+        d = new pgc_direct_s();
+        d->plan = plan;
+        d->max_cells = max_cells;
+        d->n_pairs = n_pairs;
+        d->nid = nid;
+        d->Nd = Nd;
+        // unordered pairs a <= b of flat interior-node indices, row by row
+        std::vector<int> pa((size_t)n_pairs), pb((size_t)n_pairs);
+        int64_t q = 0;
+        for (int64_t a = 0; a < nid; ++a)
+            for (int64_t b = a; b < nid; ++b) {
+                pa[(size_t)q] = (int)a;
+                pb[(size_t)q] = (int)b;
+                ++q;
+            }
+        // per-dimension factor of T^_k at the nodes: T_k(xi_i) / sqrt(c_k) / mu_i^2
+        std::vector<double> ltab((size_t)p.ni * p.N);
+        for (int i = 0; i < p.ni; ++i)
+            for (int k = 0; k < p.N; ++k) ltab[(size_t)i * p.N + k] = p.C[(size_t)i * p.N + k] / p.mu21[i];
+        if ((e = d_upload(*d, &d->pa, pa)) == hipSuccess && (e = d_upload(*d, &d->pb, pb)) == hipSuccess) {
+            double *v1 = nullptr, *lt = nullptr, *sig = nullptr, *sw = nullptr;
+            const int64_t L = std::max(p.N, p.ni);
+            int64_t t = 1;
+            for (int l = 0; l < p.dim; ++l) t *= L;
+            if ((e = d_upload(*d, &v1, p.v1)) == hipSuccess && (e = d_upload(*d, &lt, ltab)) == hipSuccess &&
+                (e = d_upload(*d, &sig, p.sigma)) == hipSuccess && (e = d_upload(*d, &sw, p.sigma_w)) == hipSuccess &&
+                (e = d_alloc_n(*d, &d->K, n_pairs * Nd)) == hipSuccess &&
+                (e = d_alloc_n(*d, &d->X, (int64_t)max_cells * n_pairs)) == hipSuccess &&
+                (e = d_alloc_n(*d, &d->bufs.P, (int64_t)max_cells * nid)) == hipSuccess &&
+                (e = d_alloc_n(*d, &d->bufs.G, (int64_t)max_cells * nid)) == hipSuccess &&
+                (e = d_alloc_n(*d, &d->bufs.tmpA, (int64_t)max_cells * t)) == hipSuccess &&
+                (e = d_alloc_n(*d, &d->bufs.tmpB, (int64_t)max_cells * t)) == hipSuccess) {
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                (void)hipEventCreate(&e0);
+                (void)hipEventCreate(&e1);
+                (void)hipEventRecord(e0, s);
+                const size_t lds = sizeof(double) * pgc::kSigChunk * p.dim * p.N;
+                const int vhs = p.kernel == PGC_KERNEL_VHS ? 1 : 0;
+                if (p.dim == 2)
+                    hipLaunchKernelGGL(pgc::direct_tensor<2>, dim3((unsigned)n_pairs), dim3(pgc::kDirThreads), lds, s,
+                                       d->pa, d->pb, n_pairs, v1, lt, sig, sw, p.n_sigma, p.N, p.ni, (int)Nd, p.map,
+                                       p.S, p.b0, p.gamma, vhs, p.wsum, d->K);
+                else
+                    hipLaunchKernelGGL(pgc::direct_tensor<3>, dim3((unsigned)n_pairs), dim3(pgc::kDirThreads), lds, s,
+                                       d->pa, d->pb, n_pairs, v1, lt, sig, sw, p.n_sigma, p.N, p.ni, (int)Nd, p.map,
+                                       p.S, p.b0, p.gamma, vhs, p.wsum, d->K);
+                e = hipGetLastError();
+                (void)hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+                float ms = 0.0f;
+                if (e == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) d->setup_ms = ms;
+                if (e0) (void)hipEventDestroy(e0);
+                if (e1) (void)hipEventDestroy(e1);
+            }
+        }
+        if (e == hipSuccess && rocblas_create_handle(&d->blas) != rocblas_status_success) st = PGC_ERR_DEVICE;
+    } catch (...) {
+        st = PGC_ERR_OUT_OF_MEMORY;
+    }
+    if (st == PGC_OK && e != hipSuccess) st = pgc::status_of(e);
+    if (st != PGC_OK) {
+        d_free(d);
+        return st;
+    }
+    *out = d;
+    return PGC_OK;
+}
+
+pgc_status pgc_direct_destroy(pgc_direct d)
+{
+    d_free(d);
+    return PGC_OK;
+}
+
+pgc_status pgc_direct_query(pgc_direct d, pgc_direct_info* info)
+{
+    if (!d || !info) return PGC_ERR_INVALID_ARG;
+    std::memset(info, 0, sizeof(*info));
+    info->n_pairs = d->n_pairs;
+    info->n_modes_total = d->Nd;
+    info->max_cells = d->max_cells;
+    info->tensor_bytes = d->n_pairs * d->Nd * (int64_t)sizeof(double);
+    info->workspace_bytes = d->bytes;
+    info->setup_ms = d->setup_ms;
+    info->flops_per_cell = 2.0 * (double)d->n_pairs * (double)d->Nd;
+    return PGC_OK;
+}
+
+pgc_status pgc_direct_coeffs_to_q(pgc_direct d, const double* coeffs_dev, int64_t n_cells, double* q_dev,
+                                  void* stream)
+{
+    if (!d || n_cells < 0 || (n_cells > 0 && (!coeffs_dev || !q_dev))) return PGC_ERR_INVALID_ARG;
+    const pgc::Plan& p = d->plan->p;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n_cells > 0 && rocblas_set_stream(d->blas, s) != rocblas_status_success) return PGC_ERR_DEVICE;
+    for (int64_t c0 = 0; c0 < n_cells; c0 += d->max_cells) {
+        const int nc = (int)std::min<int64_t>(d->max_cells, n_cells - c0);
+        hipError_t e = pgc::launch_dense_synthesis(p, coeffs_dev + c0 * d->Nd, nc, d->bufs, s);
+        if (e != hipSuccess) return pgc::status_of(e);
+        hipLaunchKernelGGL(pgc::pair_products, dim3((unsigned)((d->n_pairs + 255) / 256), (unsigned)nc), dim3(256), 0,
+                           s, d->bufs.G, d->pa, d->pb, d->n_pairs, d->nid, d->X);
+        if ((e = hipGetLastError()) != hipSuccess) return pgc::status_of(e);
+        // column major: Q^T (N^d x nc) = K^T (N^d x n_pairs) X^T (n_pairs x nc)
+        const double one = 1.0, zero = 0.0;
+        if (rocblas_dgemm(d->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)d->Nd, nc,
+                          (rocblas_int)d->n_pairs, &one, d->K, (rocblas_int)d->Nd, d->X, (rocblas_int)d->n_pairs,
+                          &zero, q_dev + c0 * d->Nd, (rocblas_int)d->Nd) != rocblas_status_success)
+            return PGC_ERR_DEVICE;
+    }
+    return PGC_OK;
+}
+
+}  // extern "C"

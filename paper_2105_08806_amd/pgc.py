@@ -76,6 +76,14 @@ class BatchInfo(ctypes.Structure):
     ]
 
 
+class DirectInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_pairs", ctypes.c_int64), ("n_modes_total", ctypes.c_int64), ("max_cells", ctypes.c_int32),
+        ("tensor_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64), ("setup_ms", ctypes.c_double),
+        ("flops_per_cell", ctypes.c_double),
+    ]
+
+
 class SurrogateDesc(ctypes.Structure):
     _fields_ = [
         ("width", ctypes.c_int32), ("n_layers", ctypes.c_int32), ("batch_max", ctypes.c_int32),
@@ -148,6 +156,12 @@ def lib():
         L.pgc_surrogate_save.argtypes = [vp, ctypes.c_char_p, vp]
         L.pgc_surrogate_load.argtypes = [vp, ctypes.c_char_p, vp]
         L.pgc_gemm_bf16.argtypes = [i32, i32, i32, vp, i32, i32, vp, i32, i32, vp, i32, vp, i32, vp]
+        L.pgc_direct_create.argtypes = [vp, i32, vp, ctypes.POINTER(vp)]
+        L.pgc_direct_destroy.argtypes = [vp]
+        L.pgc_direct_query.argtypes = [vp, ctypes.POINTER(DirectInfo)]
+        L.pgc_direct_coeffs_to_q.argtypes = [vp, vp, i64, vp, vp]
+        for name in ("pgc_direct_create", "pgc_direct_destroy", "pgc_direct_query", "pgc_direct_coeffs_to_q"):
+            getattr(L, name).restype = ctypes.c_int
         for name in ("pgc_surrogate_desc_init", "pgc_surrogate_create", "pgc_surrogate_destroy",
                      "pgc_surrogate_query", "pgc_surrogate_set_normalization", "pgc_surrogate_train",
                      "pgc_surrogate_coeffs_to_q", "pgc_surrogate_loss_grad", "pgc_surrogate_get_params",
@@ -449,6 +463,49 @@ def gemm_bf16(a, b, trans_a=False, trans_b=False, bias=None, out=None, accumulat
                                _ptr(out), max(out.stride(0), N), _ptr(bias) if bias is not None else None,
                                int(accumulate), _stream()), "pgc_gemm_bf16")
     return out
+
+
+class Direct:
+    """The direct algorithm for many cells that share one FP64 plan: the
+    plan's bilinear tensor is built once, then Q of a batch of cells is one
+    FP64 matrix product (``max_cells`` cells per product)."""
+
+    def __init__(self, plan, max_cells=256):
+        import torch
+        self._torch = torch
+        self.plan = plan  # the tensor reads the plan's tables: keep it alive
+        h = ctypes.c_void_p()
+        _check(lib().pgc_direct_create(plan._h, int(max_cells), _stream(), ctypes.byref(h)), "pgc_direct_create")
+        self._h = h
+        self.info = DirectInfo()
+        _check(lib().pgc_direct_query(self._h, ctypes.byref(self.info)), "pgc_direct_query")
+        self.nd = int(self.info.n_modes_total)
+
+    def coeffs_to_q(self, coeffs, q=None):
+        """coeffs: float64 CUDA tensor (n_cells, N^d) or (n_cells, N, ..., N)."""
+        torch = self._torch
+        if not (coeffs.is_cuda and coeffs.dtype == torch.float64 and coeffs.is_contiguous()):
+            raise ValueError("coefficients must be a contiguous float64 CUDA tensor")
+        if coeffs.numel() % self.nd:
+            raise ValueError("coefficients must hold whole cells of N^d values")
+        n = coeffs.numel() // self.nd
+        if q is None:
+            q = torch.empty_like(coeffs)
+        elif not (q.is_cuda and q.dtype == torch.float64 and q.is_contiguous() and q.numel() == coeffs.numel()):
+            raise ValueError("q must be a contiguous float64 CUDA tensor of the coefficients' size")
+        _check(lib().pgc_direct_coeffs_to_q(self._h, _ptr(coeffs), n, _ptr(q), _stream()), "pgc_direct_coeffs_to_q")
+        return q
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pgc_direct_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Surrogate:

@@ -171,3 +171,15 @@ def test_gemm_argument_errors_without_a_device():
     assert call(8, 6, 5, 5, 0, 6, 0, 6, c=None) == 1
     # empty outputs need no operands at all
     assert call(0, 6, 5, 0, 0, 0, 0, 0, a=None, b=None, c=None) == 0
+
+
+def test_direct_argument_errors_without_a_device():
+    from paper_2105_08806_amd import pgc
+    L = pgc.lib()
+    h = ctypes.c_void_p()
+    assert L.pgc_direct_create(None, 4, None, ctypes.byref(h)) == 1
+    assert not h.value
+    assert L.pgc_direct_destroy(None) == 0
+    info = pgc.DirectInfo()
+    assert L.pgc_direct_query(None, ctypes.byref(info)) == 1
+    assert L.pgc_direct_coeffs_to_q(None, None, 0, None, None) == 1
