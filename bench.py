@@ -250,6 +250,58 @@ def batched_variant(torch, pgc, inputs, np, n_cells, reps):
     return out
 
 
+def direct_variant(torch, pgc, inputs, np, n_cells, reps):
+    """The direct algorithm on the batched workload's recipe with every cell at
+    N = 32 (S = 6, Maxwell, 32 directions, perturbed Maxwellians): the plan's
+    node-pair tensor is built once, then each evaluation of all cells is one
+    FP64 product.  Accuracy: sampled cells against the FP64 fast path,
+    normalised by |Q+| (near equilibrium Q is a few percent of Q+)."""
+    N, S, M = 32, 6.0, 32
+    cells = inputs.cell_maxwellians_2d(n_cells, seed=8806, modes=(N,))
+    plan = pgc.Plan(dim=2, n_modes=N, scale=S, n_sigma=M, precision=pgc.FP64)
+    V = plan.interior_velocities()
+    c = torch.stack([plan.project(inputs.perturbed_maxwellian_2d(V, cell)).reshape(-1) for cell in cells])
+    d = pgc.Direct(plan, max_cells=n_cells)
+    q = d.coeffs_to_q(c)
+    torch.cuda.synchronize()
+    log("direct: %d cells at N=%d, tensor %.2f GB built in %.1f ms" % (
+        n_cells, N, d.info.tensor_bytes / 1e9, d.info.setup_ms))
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        d.coeffs_to_q(c, q)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    log("direct: %.1f ms per evaluation of %d cells" % (ms, n_cells))
+    errs, t_cell = [], []
+    for i in range(0, n_cells, max(1, n_cells // 4))[:4]:
+        ref, refp = plan.coeffs_to_q(c[i].reshape(N, N).contiguous(), want_qplus=True)
+        torch.cuda.synchronize()
+        t = time.time()
+        for _ in range(2):
+            plan.coeffs_to_q(c[i].reshape(N, N).contiguous())
+        torch.cuda.synchronize()
+        t_cell.append((time.time() - t) / 2)
+        errs.append(float(torch.linalg.norm(q[i] - ref.reshape(-1)) / torch.linalg.norm(refp)))
+    achieved = d.info.flops_per_cell * n_cells / (ms / 1e3)
+    out = {"value": n_cells / (ms / 1e3), "unit": "cell Q-evals/s", "ms_per_eval": ms,
+           "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["fp64"] / 1e12,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK["fp64"], "traffic": None,
+                        "note": "2 n_pairs N^2 flops of the product per cell over the whole call "
+                                "(synthesis and pair products included in the time)"},
+           "workload": "2D batch of %d cells at N=%d, S=6, Maxwell, 32 directions, perturbed Maxwellians, "
+                       "FP64 direct algorithm (node-pair tensor %.2f GB, %d pairs)" % (
+                           n_cells, N, d.info.tensor_bytes / 1e9, d.info.n_pairs),
+           "tensor_setup_ms": d.info.setup_ms,
+           "max_diff_vs_fp64_fast_path_over_qplus": max(errs), "cells_checked": len(errs),
+           "fp64_fast_path_s_per_cell": min(t_cell),
+           "speedup_vs_fp64_fast_path": min(t_cell) * n_cells / (ms / 1e3)}
+    d.close()
+    plan.close()
+    return out
+
+
 def symmetric_copies(torch, f, N):
     """The 16 images of coefficient rows under the symmetries of the 8 x 8
     product rule: v_l -> -v_l (c_k -> (-1)^k_l c_k) and v_1 <-> v_2."""
@@ -421,6 +473,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-bkw", action="store_true", help="skip the 20-step RK4 BKW error curve")
+    ap.add_argument("--no-direct", action="store_true", help="skip the direct-algorithm leg")
+    ap.add_argument("--direct-cells", type=int, default=4096)
+    ap.add_argument("--direct-reps", type=int, default=3)
     ap.add_argument("--batch-cells", type=int, default=4096)
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--surrogate-pairs", type=int, default=4096)
@@ -484,6 +539,17 @@ def main():
         torch.cuda.synchronize()
         log("profiled batched: %d cells, W=%d, C=%d" % (len(cells), b.info.kernel_width, b.info.cells_per_wave))
         b.close()
+        # the direct algorithm: 4096 cells at N = 32 in one FP64 product
+        plan = pgc.Plan(dim=2, n_modes=32, scale=6.0, n_sigma=32, precision=pgc.FP64)
+        c = torch.tensor(np.stack([inputs.random_coeffs((32, 32), seed=i).ravel() for i in range(4096)]),
+                         device="cuda")
+        d = pgc.Direct(plan, max_cells=4096)
+        for _ in range(2):
+            d.coeffs_to_q(c)
+        torch.cuda.synchronize()
+        log("profiled direct: 4096 cells at N=32, %d pairs" % d.info.n_pairs)
+        d.close()
+        plan.close()
         # surrogate training steps and inference at N=24 (random rows: kernel timing only)
         plan = pgc.Plan(dim=3, n_modes=24, scale=5.0, map=pgc.MAP_ALGEBRAIC, sphere=pgc.SPHERE_PRODUCT_3D,
                         n_theta=8, n_phi=8, precision=pgc.FP32)
@@ -546,6 +612,8 @@ def main():
     }
     if not args.no_batched:
         line["variants"]["batched"] = batched_variant(torch, pgc, inputs, np, args.batch_cells, args.batch_reps)
+    if not args.no_direct:
+        line["variants"]["direct"] = direct_variant(torch, pgc, inputs, np, args.direct_cells, args.direct_reps)
     if not args.no_surrogate:
         line["variants"]["surrogate"] = surrogate_variant(torch, pgc, inputs, np, args.surrogate_pairs,
                                                           args.surrogate_epochs)
