@@ -150,15 +150,30 @@ __global__ void __launch_bounds__(kDirThreads)
     }
 }
 
-// X[c][p] = G[c][a_p] G[c][b_p] for the cells of one chunk
-__global__ void pair_products(const double* __restrict__ G, const int* __restrict__ pa,
-                              const int* __restrict__ pb, int64_t n_pairs, int64_t nid,
-                              double* __restrict__ X)
+// X[c][p] = G[c][a_p] G[c][b_p] for the cells of one chunk.  A thread keeps
+// its pair for kPairCells cells: the pair indices are read once and the
+// cells' gathers are independent (HBM bound: the writes of X).
+constexpr int kPairCells = 16;
+
+__global__ void __launch_bounds__(256)
+    pair_products(const double* __restrict__ G, const int* __restrict__ pa, const int* __restrict__ pb,
+                  int64_t n_pairs, int64_t nid, int n_cells, double* __restrict__ X)
 {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n_pairs) return;
-    const double* g = G + (int64_t)blockIdx.y * nid;
-    X[(int64_t)blockIdx.y * n_pairs + p] = g[pa[p]] * g[pb[p]];
+    const int a = pa[p], b = pb[p];
+    const int c0 = blockIdx.y * kPairCells;
+    const int nc = min(kPairCells, n_cells - c0);
+    double v[kPairCells];
+#pragma unroll
+    for (int c = 0; c < kPairCells; ++c)
+        if (c < nc) {
+            const double* g = G + (int64_t)(c0 + c) * nid;
+            v[c] = g[a] * g[b];
+        }
+#pragma unroll
+    for (int c = 0; c < kPairCells; ++c)
+        if (c < nc) X[(int64_t)(c0 + c) * n_pairs + p] = v[c];
 }
 
 }  // namespace
@@ -342,8 +357,9 @@ pgc_status pgc_direct_coeffs_to_q(pgc_direct d, const double* coeffs_dev, int64_
         const int nc = (int)std::min<int64_t>(d->max_cells, n_cells - c0);
         hipError_t e = pgc::launch_dense_synthesis(p, coeffs_dev + c0 * d->Nd, nc, d->bufs, s);
         if (e != hipSuccess) return pgc::status_of(e);
-        hipLaunchKernelGGL(pgc::pair_products, dim3((unsigned)((d->n_pairs + 255) / 256), (unsigned)nc), dim3(256), 0,
-                           s, d->bufs.G, d->pa, d->pb, d->n_pairs, d->nid, d->X);
+        hipLaunchKernelGGL(pgc::pair_products, dim3((unsigned)((d->n_pairs + 255) / 256),
+                                                    (unsigned)((nc + pgc::kPairCells - 1) / pgc::kPairCells)),
+                           dim3(256), 0, s, d->bufs.G, d->pa, d->pb, d->n_pairs, d->nid, nc, d->X);
         if ((e = hipGetLastError()) != hipSuccess) return pgc::status_of(e);
         // column major: Q^T (N^d x nc) = K^T (N^d x n_pairs) X^T (n_pairs x nc)
         const double one = 1.0, zero = 0.0;
