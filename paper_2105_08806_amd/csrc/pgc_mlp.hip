@@ -8,7 +8,7 @@
 // space keeps, Sec. 3.2), so what it returns conserves them by construction.
 //
 // Every product runs on the matrix cores: BF16 operands, FP32 accumulation
-// (v_mfma_f32_16x16x16bf16_1k).  Weights are kept in FP32 (Adam state too) and
+// (v_mfma_f32_16x16x32_bf16).  Weights are kept in FP32 (Adam state too) and
 // copied to BF16 after every step; activations are stored in BF16 for the
 // products and in FP32 where the backward pass needs them.
 //
