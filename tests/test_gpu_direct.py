@@ -106,10 +106,14 @@ def test_direct_rejects_unsupported_plans(torch_cuda):
         with pytest.raises(pgc.PgcError):
             pgc.Direct(p64, max_cells=bad)
     p64.close()
-    big = pgc.Plan(dim=2, n_modes=64, scale=6.0, n_sigma=8)
-    with pytest.raises(pgc.PgcError):        # a 258 GB tensor
-        pgc.Direct(big)
-    big.close()
+    # the first sizes past the tensor limit (96 GiB): 2D N = 56 (115 GB) and
+    # 3D N = 16 (N^3 = 4096 entries per pair, 187 GB)
+    for dim, N, extra in ((2, 56, dict(n_sigma=8)),
+                          (3, 16, dict(sphere=pgc.SPHERE_PRODUCT_3D, n_theta=2, n_phi=2))):
+        big = pgc.Plan(dim=dim, n_modes=N, scale=6.0, **extra)
+        with pytest.raises(pgc.PgcError):
+            pgc.Direct(big)
+        big.close()
 
 
 def test_direct_n32_batched_cells(torch_cuda):
