@@ -46,6 +46,7 @@ class _Problem(ctypes.Structure):
         ("n_sigma", ctypes.c_int),
         ("sigma", ctypes.POINTER(ctypes.c_double)),
         ("sigma_w", ctypes.POINTER(ctypes.c_double)),
+        ("aniso", ctypes.c_double),
     ]
 
 
@@ -103,18 +104,21 @@ def sphere_product_rule(n_t: int, n_p: int):
 class Problem:
     """One discretised collision operator: dimension, modes, map, kernel, sphere rule.
 
-    ``kernel`` is "maxwell" (B = b0) or "vhs" (B = b0 |u|^gamma).  ``sphere`` is
-    an (n_sigma x dim) array of unit vectors with ``sphere_w`` its weights.
+    ``kernel`` is "maxwell" (B = b0), "vhs" (B = b0 |u|^gamma) or "aniso"
+    (B = b0 |u|^gamma (1 + aniso cos^2 theta), cos theta = u.sigma/|u|).
+    ``sphere`` is an (n_sigma x dim) array of unit vectors with ``sphere_w``
+    its weights.
     """
 
     def __init__(self, dim, n_modes, S, map_=0, m_v=None, kernel="maxwell", b0=None,
-                 gamma=0.0, sphere=None, sphere_w=None):
+                 gamma=0.0, sphere=None, sphere_w=None, aniso=0.0):
         self.dim = int(dim)
         self.n_modes = int(n_modes)
         self.m_v = int(m_v) if m_v else self.n_modes + 1
         self.map = int(map_)
         self.S = float(S)
-        self.kernel = 0 if kernel == "maxwell" else 1
+        self.kernel = {"maxwell": 0, "vhs": 1, "aniso": 2}[kernel]
+        self.aniso = float(aniso)
         if b0 is None:
             # Maxwell molecules normalised to int B dsigma = 1 (the BKW kernels)
             b0 = 1.0 / (2 * np.pi) if self.dim == 2 else 1.0 / (4 * np.pi)
@@ -125,7 +129,7 @@ class Problem:
         assert self.sphere.shape == (self.sphere_w.size, self.dim)
         self._c = _Problem(self.dim, self.n_modes, self.m_v, self.map, self.S, self.kernel,
                            self.b0, self.gamma, int(self.sphere_w.size),
-                           _dp(self.sphere), _dp(self.sphere_w))
+                           _dp(self.sphere), _dp(self.sphere_w), self.aniso)
 
     @property
     def n_int(self):

@@ -222,7 +222,8 @@ typedef struct {
 static int check_problem(const ora_problem* p)
 {
     if (!p || (p->dim != 2 && p->dim != 3) || p->n_modes < 1 || p->m_v < 3 ||
-        p->S <= 0.0 || (p->map != 0 && p->map != 1) || (p->kernel != 0 && p->kernel != 1))
+        p->S <= 0.0 || (p->map != 0 && p->map != 1) || p->kernel < 0 || p->kernel > 2 ||
+        (p->kernel == 2 && !(p->aniso >= -1.0 && p->aniso <= 10.0)))
         return -1;
     return 0;
 }
@@ -323,12 +324,25 @@ int ora_project(const ora_problem* p, const double* f_int, double* coeffs)
     return 0;
 }
 
-/* B(|v - v_*|), independent of the scattering angle for both kernels */
-static double kernel_b(const ora_problem* p, double un)
+/* B(|u|, cos theta), u = v - v_*, cos theta = u.sigma/|u| (0 when u = 0).
+ * Maxwell (b0) and VHS (b0 |u|^gamma) do not depend on the angle; kernel 2
+ * weights the VHS rate by 1 + aniso cos^2 theta.  Q(f, f) sees only the part
+ * of B that is even in cos theta (relabelling v and v_* flips its sign), and
+ * an even polynomial keeps B smooth where cos theta = -1 or 1. */
+static double kernel_b(const ora_problem* p, double un, double c)
 {
     if (p->kernel == 0) return p->b0;
-    if (un == 0.0) return p->gamma == 0.0 ? p->b0 : 0.0;
-    return p->b0 * pow(un, p->gamma);
+    double b = un == 0.0 ? (p->gamma == 0.0 ? p->b0 : 0.0) : p->b0 * pow(un, p->gamma);
+    if (p->kernel == 2) b *= 1.0 + p->aniso * c * c;
+    return b;
+}
+
+static double cos_theta(const double* vi, const double* vj, const double* sg, int dim, double un)
+{
+    if (un == 0.0) return 0.0;
+    double d = 0.0;
+    for (int l = 0; l < dim; ++l) d += (vi[l] - vj[l]) * sg[l];
+    return d / un;
 }
 
 /* Per-node data: v_i (dim), w_i g_i where g = f_N / mu^2 = mu^2 P, and P_i. */
@@ -369,7 +383,7 @@ static void nodes_free(ora_nodes* nd)
     free(nd->w);
 }
 
-/* The loss, eq. (Qminus) discretised: A_i = sum_s W_s sum_j w_j g_j B(|v_i - v_j|)
+/* The loss, eq. (Qminus) discretised: A_i = sum_s W_s sum_j w_j g_j B(|v_i - v_j|, cos theta)
  * is the inner integral, and Q-_k = sum_i w_i A_i f_N(v_i) T^_k(v_i) / mu_i^2
  * = sum_i w_i A_i P_i T_k(xi_i)/sqrt(c_k) is the outer one. */
 static void loss_field(const ora_problem* p, const ora_tables* t, const ora_nodes* nd, double* A)
@@ -381,14 +395,21 @@ static void loss_field(const ora_problem* p, const ora_tables* t, const ora_node
     for (int64_t i = 0; i < t->nd; ++i) {
         double acc = 0.0;
         for (int64_t j = 0; j < t->nd; ++j) {
+            const double* vi = nd->v + i * dim;
+            const double* vj = nd->v + j * dim;
             double un2 = 0.0;
-            for (int l = 0; l < dim; ++l) {
-                double d = nd->v[i * dim + l] - nd->v[j * dim + l];
-                un2 += d * d;
+            for (int l = 0; l < dim; ++l) un2 += (vi[l] - vj[l]) * (vi[l] - vj[l]);
+            const double un = sqrt(un2);
+            if (p->kernel == 2) {
+                /* an angle-dependent rate: the inner integral over sigma itself */
+                for (int s = 0; s < p->n_sigma; ++s)
+                    acc += p->sigma_w[s] * nd->wg[j] *
+                           kernel_b(p, un, cos_theta(vi, vj, p->sigma + (size_t)s * dim, dim, un));
+            } else {
+                acc += nd->wg[j] * kernel_b(p, un, 0.0);
             }
-            acc += nd->wg[j] * kernel_b(p, sqrt(un2));
         }
-        A[i] = wsum * acc;
+        A[i] = p->kernel == 2 ? acc : wsum * acc;
     }
 }
 
@@ -445,7 +466,7 @@ static void gain_sum(const ora_problem* p, const ora_tables* t, const ora_nodes*
                 double un2 = 0.0;
                 for (int l = 0; l < dim; ++l) un2 += (vi[l] - vj[l]) * (vi[l] - vj[l]);
                 double un = sqrt(un2);
-                double wt = wi * nd->wg[j] * kernel_b(p, un);
+                double wt = wi * nd->wg[j] * kernel_b(p, un, cos_theta(vi, vj, sg, dim, un));
                 if (wt == 0.0) continue;
                 for (int l = 0; l < dim; ++l) {
                     double vp = 0.5 * (vi[l] + vj[l]) + 0.5 * un * sg[l];

@@ -29,12 +29,13 @@ typedef struct {
     int m_v;               /* CGL nodes per dimension incl. endpoints */
     int map;               /* 0: r = 0, 1: r = 1 */
     double S;              /* map scale */
-    int kernel;            /* 0 Maxwell, 1 VHS */
+    int kernel;            /* 0 Maxwell, 1 VHS, 2 angle-dependent */
     double b0;             /* kernel constant */
-    double gamma;          /* VHS exponent */
+    double gamma;          /* exponent of |u| (kernels 1 and 2) */
     int n_sigma;           /* quadrature points on the unit sphere / circle */
     const double* sigma;   /* n_sigma x dim unit vectors */
     const double* sigma_w; /* n_sigma weights */
+    double aniso;          /* kernel 2: B = b0 |u|^gamma (1 + aniso cos^2 theta), aniso >= -1 */
 } ora_problem;
 
 /* CGL nodes xi_j = -cos(pi j/(m_v-1)), weights, mapped v_j and mu(xi_j)^2

@@ -365,3 +365,93 @@ def test_gain_units_partition_the_gain():
     cut = [0, 5, 117, n_units]
     parts = sum(p.gain_units(c, a, b) for a, b in zip(cut[:-1], cut[1:]))
     assert np.max(np.abs(parts - qp)) < 1e-13 * np.max(np.abs(qp))
+
+
+# ------------------------------------------------------- angle-dependent rate
+
+
+def aniso_pair(dim, N, S, map_, beta, gamma, n_sigma=8):
+    """B = b0 |u|^gamma (1 + beta cos^2 theta) and the same rate with beta = 0."""
+    if dim == 2:
+        sg, sw = circle(n_sigma)
+    else:
+        sg, sw = O.sphere_product_rule(2, 4)
+    kw = dict(sphere=sg, sphere_w=sw, gamma=gamma)
+    return (O.Problem(dim, N, S, map_, kernel="aniso", aniso=beta, **kw),
+            O.Problem(dim, N, S, map_, kernel="vhs" if gamma > 0 else "maxwell", **kw))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_aniso_at_zero_is_the_angle_free_rate(dim):
+    N = 7 if dim == 2 else 4
+    an, vhs = aniso_pair(dim, N, 3.0, 0, 0.0, 0.5)
+    c = I.random_coeffs((N,) * dim, seed=21)
+    for a, b in zip(an.collision(c), vhs.collision(c)):
+        assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("beta,gamma", [(0.8, 0.5), (-0.6, 0.0), (3.0, 1.0)])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_aniso_conservation_algebraic_map(dim, beta, gamma):
+    """The pair (s, i, j) meets (-s, j, i) at the swapped post-collision
+    velocities with the same cos theta, so an angle-dependent rate keeps the
+    discrete mass and energy balance of the r = 1 map (Sec. 3.2)."""
+    N = 9 if dim == 2 else 5
+    an, _ = aniso_pair(dim, N, 2.5, 1, beta, gamma)
+    comps = ([(0.6, (0.5, -0.3), 0.7), (0.4, (-0.8, 0.6), 1.2)] if dim == 2 else
+             [(0.6, (0.5, -0.3, 0.1), 0.7), (0.4, (-0.8, 0.6, 0.2), 1.2)])
+    c = an.project(I.mixture(an.interior_velocities(), comps))
+    q, qp, _ = an.collision(c)
+    mq, mqp = an.moments(q), an.moments(qp)
+    assert abs(mq[0]) < 1e-13 * abs(mqp[0])
+    assert abs(mq[-1]) < 1e-13 * abs(mqp[-1])
+
+
+@pytest.mark.parametrize("beta", [0.7, -1.0])
+def test_aniso_maxwell_type_loss(beta):
+    """With gamma = 0 the loss rate is b0 sum_s W_s (1 + beta (u.sigma_s/|u|)^2).
+    The circle rule integrates cos^2 exactly, sum_s W_s cos^2 = (sum_s W_s)/2,
+    so for j != i the rate is (1 + beta/2) times the Maxwell rate; the j = i
+    term has u = 0, cos theta = 0 and the factor 1.  Hence
+    Q-(beta) = (1 + beta/2) Q-(Maxwell) - (beta/2) b0 (sum_s W_s) L[w_i g_i],
+    L[a]_k = sum_i w_i a_i P_i T_k(xi_i)/sqrt(c_k) the outer loss sum."""
+    N, S = 9, 3.0
+    an, mx = aniso_pair(2, N, S, 0, beta, 0.0, n_sigma=10)
+    c = I.random_coeffs((N, N), seed=22)
+    _, _, qm = an.collision(c)
+    _, _, rm = mx.collision(c)
+    xi, _, w, mu2 = O.cgl(N + 1, 0, S)
+    wi, mi = w[1:-1], mu2[1:-1]
+    P = an.nodal(c)
+    T = np.array([[cheb(k, x) / np.sqrt(c_k(k)) for k in range(N)] for x in xi[1:-1]])
+    W, M = np.outer(wi, wi), np.outer(mi, mi)
+    self_term = mx.b0 * 2 * np.pi * np.einsum("ab,ak,bl->kl", W * (W * M * P) * P, T, T)
+    expect = (1 + beta / 2) * rm - (beta / 2) * self_term
+    assert np.max(np.abs(qm - expect)) <= 1e-13 * np.max(np.abs(rm))
+
+
+def test_aniso_second_moment_derivatives_2d():
+    """For a rate b(cos theta) the weak form gives
+    d/dt int f v v^T = (C/2) [rho (tr P - rho |u|^2) I - d rho (P - rho u u^T)],
+    C = int b (1 - cos^2 theta) dsigma / (d - 1), linear in C.  With
+    b = b0 (1 + beta cos^2 theta), C / C_Maxwell = 1 + beta/4 in 2D, so the
+    second-moment rates of the two-Maxwellian test (Sec. 5.1.2) scale by it."""
+    beta = 1.2
+    rows = {r[0]: float(r[1]) for r in load_golden("moments2d_closed_forms.txt")}
+    c_ratio = (integrate.quad(lambda t: (1 + beta * np.cos(t) ** 2) * np.sin(t) ** 2, 0, 2 * np.pi)[0] /
+               integrate.quad(lambda t: np.sin(t) ** 2, 0, 2 * np.pi)[0])
+    assert abs(c_ratio - (1 + beta / 4)) < 1e-12
+    d = {k: -0.5 * a * c_ratio for k, a in rows.items()}   # d/dt (a e^{-t/2} + b) at t = 0, scaled
+    N, S = 25, 4.0
+    sg, sw = circle(24)
+    p = O.Problem(2, N, S, 0, kernel="aniso", aniso=beta, sphere=sg, sphere_w=sw)
+    c = p.project(I.mixture(p.interior_velocities(), I.moments_test_2d()))
+    q, _, _ = p.collision(c)
+    m0, m1, m2, _ = O.moment_functionals(N, 0, S, 3)
+
+    def mom(a, b):
+        return float(np.einsum("ij,i,j->", q, a, b))
+
+    got = {"P11": mom(m2, m0), "P12": mom(m1, m1), "P22": mom(m0, m2)}
+    for k in got:
+        assert abs(got[k] - d[k]) < 2e-3 * max(1.0, abs(d[k])), (k, got[k], d[k])
