@@ -67,7 +67,7 @@ typedef enum pgc_status {
 
 enum { PGC_MAP_LOG = 0, PGC_MAP_ALGEBRAIC = 1 };
 enum { PGC_SCALE_DIRECT = 0, PGC_SCALE_FROM_DOMAIN = 1 };
-enum { PGC_KERNEL_MAXWELL = 0, PGC_KERNEL_VHS = 1 };
+enum { PGC_KERNEL_MAXWELL = 0, PGC_KERNEL_VHS = 1, PGC_KERNEL_ANISO = 2 };
 enum { PGC_SPHERE_UNIFORM_2D = 0, PGC_SPHERE_PRODUCT_3D = 1, PGC_SPHERE_USER = 2 };
 enum { PGC_PRECISION_FP64 = 0, PGC_PRECISION_FP32 = 1 };
 
@@ -82,9 +82,12 @@ typedef struct pgc_plan_desc {
                              the second and second-to-last nodes map to -scale and +scale
                              (the adaptive choice of Sec. 5) */
     double scale;         /* > 0 */
-    int32_t kernel;       /* PGC_KERNEL_MAXWELL or PGC_KERNEL_VHS */
+    int32_t kernel;       /* PGC_KERNEL_MAXWELL (B = b0), PGC_KERNEL_VHS (B = b0 |u|^gamma) or
+                             PGC_KERNEL_ANISO (B = b0 |u|^gamma (1 + kernel_aniso cos^2 theta),
+                             cos theta = u.sigma/|u|: an angle-dependent rate, evaluated by the
+                             direct algorithm only; the fast path returns UNSUPPORTED for it) */
     double kernel_b0;     /* kernel constant; 0 = 1/|S^{d-1}| (so that int B dsigma = 1 for Maxwell) */
-    double kernel_gamma;  /* VHS exponent in [0, 1] */
+    double kernel_gamma;  /* exponent of |u| in [0, 1] (VHS and ANISO) */
     int32_t sphere;       /* PGC_SPHERE_UNIFORM_2D (theta_s = 2 pi s/n_sigma, W_s = 2 pi/n_sigma),
                              PGC_SPHERE_PRODUCT_3D (n_theta Gauss-Legendre nodes in cos(theta)
                              x n_phi uniform phi), or PGC_SPHERE_USER */
@@ -109,6 +112,9 @@ typedef struct pgc_plan_desc {
                              nodes per dimension and 1024 directions, UNSUPPORTED otherwise), 3 = the
                              same bins contracted on the FP64 matrix cores (FP64 3D plans with
                              W <= 12 only, UNSUPPORTED otherwise) */
+    double kernel_aniso;  /* ANISO: beta in [-1, 10] (B >= 0); Q(f, f) sees only the part of B
+                             even in cos theta, so an even polynomial is the general smooth
+                             low-order angular law */
 } pgc_plan_desc;
 
 typedef struct pgc_plan_s* pgc_plan;

@@ -796,7 +796,8 @@ pgc_status pgc_batch_create(const pgc_plan_desc* base, int32_t n_cells, const in
 {
     if (!base || !n_modes_host || !out || n_cells <= 0) return PGC_ERR_INVALID_ARG;
     *out = nullptr;
-    if (base->dim != 2 || base->precision != PGC_PRECISION_FP32) return PGC_ERR_UNSUPPORTED;
+    if (base->dim != 2 || base->precision != PGC_PRECISION_FP32 || base->kernel == PGC_KERNEL_ANISO)
+        return PGC_ERR_UNSUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
     pgc_batch_s* b = nullptr;
     try {

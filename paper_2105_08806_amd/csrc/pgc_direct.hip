@@ -7,12 +7,16 @@
 // are contracted with the coefficients (eq. direct_online). Here the tensor
 // pairs interior CGL nodes instead, and is contracted with the weighted nodal
 // values G_a = w_a mu_a^2 P_a that the synthesis produces. Both orders of a
-// pair give the same post-collision velocity, so the two orders share one
-// entry. For the unordered pair a <= b of flat node indices:
+// pair give the same post-collision velocity, and cos theta = u.sigma/|u|
+// only changes sign, so with a rate even in cos theta the two orders share
+// one entry. For the unordered pair a <= b of flat node indices, with
+// B = R(|u|) A(cos theta), R = b0 |u|^gamma (b0 for Maxwell) and
+// A = 1 + beta cos^2 theta (1 for the angle-free rates):
 //
-//   K[p][k] = B(|u|) * (2 gain_k - wsum (L_k(a) + L_k(b)))   (a < b)
-//   K[p][k] = B(|u|) * (gain_k - wsum L_k(a))                (a = b)
-//   gain_k  = sum_s W_s T^_k(v'_s),  v'_s = (v_a + v_b)/2 + |u| sigma_s / 2
+//   K[p][k] = R * (2 gain_k - Lw (L_k(a) + L_k(b)))   (a < b)
+//   K[p][k] = R * (gain_k - Lw L_k(a))                (a = b: u = 0, A = 1)
+//   gain_k  = sum_s W_s A_s T^_k(v'_s),  v'_s = (v_a + v_b)/2 + |u| sigma_s / 2
+//   Lw      = sum_s W_s A_s   (the loss's inner integral over sigma)
 //   L_k(a)  = T^_k(v_a),  T^_k(v) = prod_l mu(xi(v_l))^-2 T_{k_l}(xi(v_l)) / sqrt(c_{k_l})
 //
 // and Q_k = sum_p G_a G_b K[p][k], which is the quadrature of eqs. Qplus and
@@ -57,10 +61,11 @@ __global__ void __launch_bounds__(kDirThreads)
     direct_tensor(const int* __restrict__ pa, const int* __restrict__ pb, int64_t n_pairs,
                   const double* __restrict__ v1, const double* __restrict__ ltab,
                   const double* __restrict__ sig, const double* __restrict__ sw, int n_sigma, int N,
-                  int ni, int Nd, int map, double S, double b0, double gamma, int vhs, double wsum,
+                  int ni, int Nd, int map, double S, double b0, double gamma, int radial, double aniso,
                   double* __restrict__ K)
 {
-    extern __shared__ double vec[];  // [kSigChunk][DIM][N]
+    extern __shared__ double vec[];  // [kSigChunk][DIM][N], then the chunk's W_s A_s
+    double* lw = vec + kSigChunk * DIM * N;
     const int64_t p = blockIdx.x;
     if (p >= n_pairs) return;
     int a = pa[p], b = pb[p];
@@ -73,15 +78,17 @@ __global__ void __launch_bounds__(kDirThreads)
         ib[l] = b % ni;
         b /= ni;
     }
-    double vm[DIM], u2 = 0.0;
+    double vm[DIM], ud[DIM], u2 = 0.0;
 #pragma unroll
     for (int l = 0; l < DIM; ++l) {
         const double x = v1[ia[l]], y = v1[ib[l]];
         vm[l] = 0.5 * (x + y);
-        u2 += (x - y) * (x - y);
+        ud[l] = x - y;
+        u2 += ud[l] * ud[l];
     }
     const double un = sqrt(u2);
-    const double B = vhs ? b0 * pow(un, gamma) : b0;
+    const double B = radial ? b0 * pow(un, gamma) : b0;
+    double Lw = 0.0;
     const double r0 = 1.0 / sqrt(M_PI), r1 = sqrt(2.0 / M_PI);
 
     double gain[kMaxPerThread];
@@ -96,7 +103,18 @@ __global__ void __launch_bounds__(kDirThreads)
             const double vp = vm[l] + 0.5 * un * sig[(int64_t)(s0 + s) * DIM + l];
             double zeta, m2;
             dir_map(map, S, vp, zeta, m2);
-            const double sc = l == 0 ? m2 * sw[s0 + s] : m2;  // W_s rides on the first dimension
+            double sc = m2;
+            if (l == 0) {  // W_s A_s (twice off the diagonal) rides on the first dimension
+                double c = 0.0;
+                if (un > 0.0) {
+#pragma unroll
+                    for (int l2 = 0; l2 < DIM; ++l2) c += ud[l2] * sig[(int64_t)(s0 + s) * DIM + l2];
+                    c /= un;
+                }
+                const double ws = sw[s0 + s] * (1.0 + aniso * c * c);
+                lw[s] = ws;
+                sc *= diag ? ws : 2.0 * ws;
+            }
             double* out = vec + (s * DIM + l) * N;
             double tm = 1.0, t = zeta;
             out[0] = sc * r0;
@@ -109,6 +127,7 @@ __global__ void __launch_bounds__(kDirThreads)
             }
         }
         __syncthreads();
+        for (int s = 0; s < ns; ++s) Lw += lw[s];
 #pragma unroll
         for (int r = 0; r < kMaxPerThread; ++r) {
             const int k = threadIdx.x + r * kDirThreads;
@@ -146,7 +165,7 @@ __global__ void __launch_bounds__(kDirThreads)
             la *= ltab[ia[l] * N + kk[l]];
             lb *= ltab[ib[l] * N + kk[l]];
         }
-        K[p * Nd + k] = diag ? B * (gain[r] - wsum * la) : B * (2.0 * gain[r] - wsum * (la + lb));
+        K[p * Nd + k] = diag ? B * (gain[r] - Lw * la) : B * (gain[r] - Lw * (la + lb));
     }
 }
 
@@ -294,16 +313,16 @@ pgc_status pgc_direct_create(pgc_plan plan, int32_t max_cells, void* stream, pgc
                 (void)hipEventCreate(&e0);
                 (void)hipEventCreate(&e1);
                 (void)hipEventRecord(e0, s);
-                const size_t lds = sizeof(double) * pgc::kSigChunk * p.dim * p.N;
-                const int vhs = p.kernel == PGC_KERNEL_VHS ? 1 : 0;
+                const size_t lds = sizeof(double) * pgc::kSigChunk * (p.dim * p.N + 1);
+                const int radial = p.kernel == PGC_KERNEL_MAXWELL ? 0 : 1;
                 if (p.dim == 2)
                     hipLaunchKernelGGL(pgc::direct_tensor<2>, dim3((unsigned)n_pairs), dim3(pgc::kDirThreads), lds, s,
                                        d->pa, d->pb, n_pairs, v1, lt, sig, sw, p.n_sigma, p.N, p.ni, (int)Nd, p.map,
-                                       p.S, p.b0, p.gamma, vhs, p.wsum, d->K);
+                                       p.S, p.b0, p.gamma, radial, p.aniso, d->K);
                 else
                     hipLaunchKernelGGL(pgc::direct_tensor<3>, dim3((unsigned)n_pairs), dim3(pgc::kDirThreads), lds, s,
                                        d->pa, d->pb, n_pairs, v1, lt, sig, sw, p.n_sigma, p.N, p.ni, (int)Nd, p.map,
-                                       p.S, p.b0, p.gamma, vhs, p.wsum, d->K);
+                                       p.S, p.b0, p.gamma, radial, p.aniso, d->K);
                 e = hipGetLastError();
                 (void)hipEventRecord(e1, s);
                 if (e == hipSuccess) e = hipStreamSynchronize(s);

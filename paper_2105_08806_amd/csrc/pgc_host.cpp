@@ -139,8 +139,11 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
     if (!(d.scale > 0.0) || !std::isfinite(d.scale)) return PGC_ERR_INVALID_ARG;
     if (d.scale_mode != PGC_SCALE_DIRECT && d.scale_mode != PGC_SCALE_FROM_DOMAIN)
         return PGC_ERR_INVALID_ARG;
-    if (d.kernel != PGC_KERNEL_MAXWELL && d.kernel != PGC_KERNEL_VHS) return PGC_ERR_INVALID_ARG;
-    if (d.kernel == PGC_KERNEL_VHS && !(d.kernel_gamma >= 0.0 && d.kernel_gamma <= 1.0))
+    if (d.kernel != PGC_KERNEL_MAXWELL && d.kernel != PGC_KERNEL_VHS && d.kernel != PGC_KERNEL_ANISO)
+        return PGC_ERR_INVALID_ARG;
+    if (d.kernel != PGC_KERNEL_MAXWELL && !(d.kernel_gamma >= 0.0 && d.kernel_gamma <= 1.0))
+        return PGC_ERR_INVALID_ARG;
+    if (d.kernel == PGC_KERNEL_ANISO && !(d.kernel_aniso >= -1.0 && d.kernel_aniso <= 10.0))
         return PGC_ERR_INVALID_ARG;
     if (d.kernel_b0 < 0.0 || !std::isfinite(d.kernel_b0)) return PGC_ERR_INVALID_ARG;
     if (d.precision != PGC_PRECISION_FP64 && d.precision != PGC_PRECISION_FP32)
@@ -163,7 +166,8 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
     p.map = d.map;
     p.kernel = d.kernel;
     p.precision = d.precision;
-    p.gamma = d.kernel == PGC_KERNEL_VHS ? d.kernel_gamma : 0.0;
+    p.gamma = d.kernel == PGC_KERNEL_MAXWELL ? 0.0 : d.kernel_gamma;
+    p.aniso = d.kernel == PGC_KERNEL_ANISO ? d.kernel_aniso : 0.0;
     p.elt = p.precision == PGC_PRECISION_FP64 ? sizeof(double) : sizeof(float);
 
     // map scale: direct, or the adaptive choice v(xi_2) = -L, v(xi_{m_v-1}) = L
@@ -900,6 +904,8 @@ pgc_status pgc_coeffs_to_q(pgc_plan plan, const void* coeffs, void* q, void* qpl
 {
     if (!plan || !coeffs || !q) return PGC_ERR_INVALID_ARG;
     Plan& p = plan->p;
+    // the merged point weights and the loss field assume a rate of |u| alone
+    if (p.kernel == PGC_KERNEL_ANISO) return PGC_ERR_UNSUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (p.prof) {
         pgc::Profiler& pr = *p.prof;
@@ -977,6 +983,7 @@ pgc_status pgc_rk4(pgc_plan plan, double* coeffs, double dt, int32_t n_steps, vo
 {
     if (!plan || !coeffs || n_steps < 0 || !std::isfinite(dt)) return PGC_ERR_INVALID_ARG;
     const Plan& p = plan->p;
+    if (p.kernel == PGC_KERNEL_ANISO) return PGC_ERR_UNSUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const double a[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
     for (int st = 0; st < n_steps; ++st) {

@@ -103,7 +103,7 @@ struct Profiler {
 struct Plan {
     // resolved description
     int dim = 2, N = 0, m_v = 0, ni = 0, map = 0, kernel = 0, precision = 0;
-    double S = 0.0, b0 = 0.0, gamma = 0.0, wsum = 0.0;
+    double S = 0.0, b0 = 0.0, gamma = 0.0, wsum = 0.0, aniso = 0.0;
     int n_sigma = 0;
     std::vector<double> sigma, sigma_w, wfac;
 

@@ -874,7 +874,8 @@ pgc_status pgc_surrogate_create(pgc_plan plan, const pgc_surrogate_desc* d, void
     if (!plan || !d || !out) return PGC_ERR_INVALID_ARG;
     *out = nullptr;
     const pgc::Plan& p = plan->p;
-    if (p.precision != PGC_PRECISION_FP32) return PGC_ERR_UNSUPPORTED;
+    // the plan's fast path is the fallback and the judge: FP32, rates of |u| alone
+    if (p.precision != PGC_PRECISION_FP32 || p.kernel == PGC_KERNEL_ANISO) return PGC_ERR_UNSUPPORTED;
     if (d->width < 16 || d->width > 8192 || d->n_layers < 2 || d->n_layers > 16 || d->batch_max < 1 ||
         d->batch_max > 65536 || d->gate_residual < 0 || d->judge_stride < 0 || d->gate_raw_factor < 0 ||
         !(d->norm_floor_in > 0 && d->norm_floor_in <= 1) || !(d->norm_floor_out > 0 && d->norm_floor_out <= 1) ||

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_PKG, "libpgc.so")
 
 MAP_LOG, MAP_ALGEBRAIC = 0, 1
 SCALE_DIRECT, SCALE_FROM_DOMAIN = 0, 1
-KERNEL_MAXWELL, KERNEL_VHS = 0, 1
+KERNEL_MAXWELL, KERNEL_VHS, KERNEL_ANISO = 0, 1, 2
 SPHERE_UNIFORM_2D, SPHERE_PRODUCT_3D, SPHERE_USER = 0, 1, 2
 FP64, FP32 = 0, 1
 GAIN_AUTO, GAIN_SLAB, GAIN_BINNED, GAIN_MFMA = 0, 1, 2, 3
@@ -45,6 +45,7 @@ class PlanDesc(ctypes.Structure):
         ("kernel_width", ctypes.c_int32), ("slab_planes", ctypes.c_int32),
         ("n_chunks", ctypes.c_int32), ("block_threads", ctypes.c_int32),
         ("gain_mode", ctypes.c_int32),
+        ("kernel_aniso", ctypes.c_double),
     ]
 
 

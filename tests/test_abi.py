@@ -121,7 +121,9 @@ def test_plan_descriptor_rejections_without_a_device():
     bad = [dict(dim=1), dict(dim=4), dict(n_modes=2), dict(m_v=2), dict(map=7), dict(scale=0.0),
            dict(scale=float("inf")), dict(scale=float("nan")), dict(scale_mode=5), dict(kernel=9),
            dict(kernel=pgc.KERNEL_VHS, kernel_gamma=1.5), dict(kernel=pgc.KERNEL_VHS, kernel_gamma=-0.1),
-           dict(kernel_b0=-1.0), dict(precision=3), dict(nufft_tol=-1e-6), dict(upsample=1.2),
+           dict(kernel_b0=-1.0), dict(precision=3),
+           dict(kernel=pgc.KERNEL_ANISO, kernel_aniso=-1.5), dict(kernel=pgc.KERNEL_ANISO, kernel_aniso=11.0),
+           dict(kernel=pgc.KERNEL_ANISO, kernel_gamma=2.0), dict(kernel=3), dict(nufft_tol=-1e-6), dict(upsample=1.2),
            dict(upsample=5.0), dict(kernel_width=3), dict(kernel_width=99), dict(slab_planes=-1),
            dict(n_chunks=-2), dict(block_threads=300), dict(gain_mode=4), dict(gain_mode=-1),
            dict(n_sigma=7),                                  # a circle rule needs antipodal pairs

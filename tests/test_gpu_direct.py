@@ -72,6 +72,70 @@ def test_direct_vs_oracle(torch_cuda, case):
     plan.close()
 
 
+def make_aniso(dim, N, S, map_, beta, gamma, n_sigma=8):
+    """Oracle and FP64 plan with B = b0 |u|^gamma (1 + beta cos^2 theta)."""
+    import oracle as O
+    from paper_2105_08806_amd import pgc
+    if dim == 2:
+        sg, sw = O.circle_rule(n_sigma)
+        sph = dict(sphere=pgc.SPHERE_UNIFORM_2D, n_sigma=n_sigma)
+    else:
+        sg, sw = O.sphere_product_rule(2, 4)
+        sph = dict(sphere=pgc.SPHERE_PRODUCT_3D, n_theta=2, n_phi=4)
+    ora = O.Problem(dim, N, S, map_, kernel="aniso", aniso=beta, gamma=gamma, sphere=sg, sphere_w=sw)
+    plan = pgc.Plan(dim=dim, n_modes=N, scale=S, map=map_, kernel=pgc.KERNEL_ANISO, kernel_gamma=gamma,
+                    kernel_aniso=beta, **sph)
+    return ora, plan
+
+
+# dim, N, S, map, beta, gamma, directions (2D)
+ANISO_CASES = [
+    (2, 7, 3.0, 0, 0.8, 0.5, 8),
+    (2, 6, 2.5, 1, 3.0, 1.0, 10),
+    (3, 4, 2.0, 1, -0.6, 0.0, 0),
+    (3, 5, 3.0, 0, 1.5, 0.5, 0),
+]
+
+
+@pytest.mark.parametrize("case", ANISO_CASES, ids=lambda c: "%dd-N%d-r%d-beta%g" % (c[0], c[1], c[3], c[4]))
+def test_direct_angle_dependent_rate_vs_oracle(torch_cuda, case):
+    """The direct algorithm with B = b0 |u|^gamma (1 + beta cos^2 theta): the
+    gain weights and the loss's inner integral over sigma both carry the angle."""
+    dim, N, S, map_, beta, gamma, n_sigma = case
+    ora, plan = make_aniso(dim, N, S, map_, beta, gamma, n_sigma or 8)
+    cells = [I.random_coeffs((N,) * dim, seed=500 + c) for c in range(3)]
+    say("case: direct, angle-dependent rate", case)
+    q, _ = direct_q(torch_cuda, plan, cells, max_cells=2)
+    for c in range(3):
+        q_ref, _, _ = ora.collision(cells[c])
+        r = rel_l2(q[c].reshape(q_ref.shape), q_ref)
+        say("  cell %d rel-L2 Q = %.3e" % (c, r))
+        assert r <= FP64_TOL, (case, c, r)
+    plan.close()
+
+
+def test_fast_paths_refuse_the_angle_dependent_rate(torch_cuda):
+    """The fast path merges points whose weights assume a rate of |u| alone;
+    it, RK4 over it, batches and the surrogate (which falls back to it) refuse."""
+    torch = torch_cuda
+    from paper_2105_08806_amd import pgc
+    say("case: fast paths refuse ANISO")
+    _, plan = make_aniso(2, 6, 3.0, 0, 0.5, 0.0)
+    c = torch.tensor(I.random_coeffs((6, 6), seed=1), device="cuda")
+    with pytest.raises(pgc.PgcError):
+        plan.coeffs_to_q(c)
+    with pytest.raises(pgc.PgcError):
+        plan.rk4(c.clone(), 0.01, 1)
+    plan.close()
+    with pytest.raises(pgc.PgcError):
+        pgc.Batch([8, 8], scale=3.0, n_sigma=8, kernel=pgc.KERNEL_ANISO, kernel_aniso=0.5)
+    p32 = pgc.Plan(dim=2, n_modes=6, scale=3.0, n_sigma=8, precision=pgc.FP32, kernel=pgc.KERNEL_ANISO,
+                   kernel_aniso=0.5)
+    with pytest.raises(pgc.PgcError):
+        pgc.Surrogate(p32, width=16, n_layers=2, batch_max=4)
+    p32.close()
+
+
 def test_direct_products_of_any_size_agree(torch_cuda):
     """The chunking of a call into products changes nothing but rounding, and
     an empty batch is a no-op."""
