@@ -302,6 +302,71 @@ def direct_variant(torch, pgc, inputs, np, n_cells, reps):
     return out
 
 
+def accuracy_study(torch, pgc, inputs, np, degrees=(8, 16, 24, 32, 40, 48, 56)):
+    """The 2D BKW accuracy tests at t = 2 (Sec. 5.1.1) on the FP64 GPU path,
+    with the paper's set-up: degree N, N + 1 modes, M_v = N + 2 nodes, M_sigma =
+    N directions, transform tolerance 1e-14.  Errors of Q_N against the exact
+    Q_BKW on the uniform 200^2 grid of [-6.3, 6.3]^2 (L2 with the cell area).
+      Test 01: L2 error against S for both maps; the best over S per N is
+               Table 2 (its Chebyshev-0 and Chebyshev-1 columns).
+      Test 02: L-inf error with S chosen from a domain L = 8.83 or 13.24
+               (the adaptive scaling of Sec. 5).
+      Test 03: L-inf error at fixed S = 4 (r = 0) and S = 5 (r = 1)."""
+    t0 = 2.0
+    x = np.linspace(-6.3, 6.3, 200)
+    h = x[1] - x[0]
+    G = np.stack([a.ravel() for a in np.meshgrid(x, x, indexing="ij")], axis=1)
+    q_exact = inputs.bkw_q(t0, G)
+    Gt = torch.tensor(G, device="cuda")
+
+    def errors(deg, S, map_, scale_mode=pgc.SCALE_DIRECT):
+        plan = pgc.Plan(dim=2, n_modes=deg + 1, scale=S, map=map_, scale_mode=scale_mode, n_sigma=deg,
+                        nufft_tol=1e-14)
+        c = plan.project(inputs.bkw_f(t0, plan.interior_velocities()))
+        e = plan.eval(plan.coeffs_to_q(c), Gt).cpu().numpy() - q_exact
+        s_used = plan.info.scale
+        plan.close()
+        return float(np.sqrt(h * h * np.sum(e * e))), float(np.max(np.abs(e))), s_used
+
+    table2 = {0: [2.2289e-03, 2.2033e-05, 1.9843e-07, 3.0082e-09, 2.5434e-11, 1.6255e-13, 2.1482e-14],
+              1: [4.1388e-03, 2.9713e-04, 1.5004e-05, 5.3946e-07, 1.6120e-08, 6.0320e-10, 2.5213e-11]}
+    all_deg = (8, 16, 24, 32, 40, 48, 56)
+    out = {"test01": {}, "test02": {}, "test03": {}}
+    for map_ in (0, 1):
+        rows = []
+        for deg in degrees:
+            sweep = {}
+            for S in np.arange(1.5, 8.01, 0.5):
+                sweep[float(S)] = errors(deg, float(S), map_)[0]
+            s0 = min(sweep, key=sweep.get)
+            for S in (s0 - 0.25, s0 + 0.25):
+                if S > 0:
+                    sweep[float(S)] = errors(deg, float(S), map_)[0]
+            sb = min(sweep, key=sweep.get)
+            paper = table2[map_][all_deg.index(deg)]
+            rows.append({"N": deg, "best_S": sb, "best_l2": sweep[sb], "paper_l2": paper,
+                         "ratio": sweep[sb] / paper,
+                         "sweep": {("%.2f" % k): v for k, v in sorted(sweep.items())}})
+            log("test01 r=%d N=%d: best L2 %.3e at S=%.2f (paper %.3e)" % (map_, deg, sweep[sb], sb, paper))
+        out["test01"]["r%d" % map_] = rows
+    for L in (8.83, 13.24):
+        for map_ in (0, 1):
+            rows = []
+            for deg in degrees:
+                _, linf, s_used = errors(deg, L, map_, pgc.SCALE_FROM_DOMAIN)
+                rows.append({"N": deg, "S": s_used, "linf": linf})
+            out["test02"]["L%g_r%d" % (L, map_)] = rows
+            log("test02 L=%g r=%d: %s" % (L, map_, ["%.1e" % r["linf"] for r in rows]))
+    for map_, S in ((0, 4.0), (1, 5.0)):
+        rows = []
+        for deg in degrees:
+            _, linf, _ = errors(deg, S, map_)
+            rows.append({"N": deg, "linf": linf})
+        out["test03"]["S%g_r%d" % (S, map_)] = rows
+        log("test03 S=%g r=%d: %s" % (S, map_, ["%.1e" % r["linf"] for r in rows]))
+    return out
+
+
 def symmetric_copies(torch, f, N):
     """The 16 images of coefficient rows under the symmetries of the 8 x 8
     product rule: v_l -> -v_l (c_k -> (-1)^k_l c_k) and v_1 <-> v_2."""
@@ -481,11 +546,12 @@ def main():
     ap.add_argument("--surrogate-pairs", type=int, default=4096)
     ap.add_argument("--surrogate-epochs", type=int, default=150)
     ap.add_argument("--pmc-dir", default="gpurun_out/prof")
-    ap.add_argument("--mode", choices=["bench", "profile", "copy", "bkw", "traffic"], default="bench",
+    ap.add_argument("--mode", choices=["bench", "profile", "copy", "bkw", "traffic", "accuracy"], default="bench",
                     help="profile: two evaluations per precision (for rocprofv3); "
                          "copy: a 1 GiB device copy (calibrates the HBM byte counters); "
                          "bkw: the 20-step RK4 BKW error curve in FP64 and FP32; "
-                         "traffic: write profiles/traffic.json from the counter CSVs under --pmc-dir")
+                         "traffic: write profiles/traffic.json from the counter CSVs under --pmc-dir; "
+                         "accuracy: the 2D BKW accuracy tests (S sweeps, adaptive S, fixed S) on the GPU path")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d"
@@ -515,6 +581,9 @@ def main():
         return
     if args.mode == "bkw":
         bkw_curve(torch, pgc, inputs, np)
+        return
+    if args.mode == "accuracy":
+        print(json.dumps({"accuracy_2d_bkw_t2": accuracy_study(torch, pgc, inputs, np)}), flush=True)
         return
     if args.mode == "profile":
         for prec in (pgc.FP64, pgc.FP32):

@@ -49,6 +49,24 @@ def bkw_f(t: float, v: np.ndarray) -> np.ndarray:
     return (1.0 / (2 * (2 * np.pi * K) ** 1.5)) * np.exp(-r2 / (2 * K)) * ((5 * K - 3) / K + (1 - K) / (K * K) * r2)
 
 
+def bkw_q(t: float, v: np.ndarray) -> np.ndarray:
+    """The exact collision operator of the BKW solution, df/dt (Sec. 5.1.1,
+    eq. 2d_bkw_rhs, and its 3D counterpart of Sec. 5.2): the reference of the
+    accuracy studies."""
+    v = np.asarray(v, dtype=np.float64)
+    dim = v.shape[-1]
+    K = bkw_k(t, dim)
+    r2 = np.sum(v * v, axis=-1)
+    f = bkw_f(t, v)
+    g = np.exp(-r2 / (2 * K))
+    if dim == 2:
+        dK = np.exp(-t / 8.0) / 16.0
+        return ((-2.0 / K + r2 / (2 * K * K)) * f + g / (2 * np.pi * K * K) * (2.0 - r2 / (2 * K * K))) * dK
+    dK = np.exp(-t / 6.0) / 6.0
+    return ((-1.5 / K + r2 / (2 * K * K)) * f
+            + g / (2 * (2 * np.pi * K) ** 1.5) * (3.0 / K ** 2 + (K - 2.0) / K ** 3 * r2)) * dK
+
+
 # ---------------------------------------------------------- Maxwellian mixtures
 
 
