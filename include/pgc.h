@@ -431,8 +431,10 @@ pgc_status pgc_direct_create(pgc_plan plan, int32_t max_cells, void* stream, pgc
 pgc_status pgc_direct_destroy(pgc_direct d);
 pgc_status pgc_direct_query(pgc_direct d, pgc_direct_info* info);
 /* q_dev[c][k] = Q_k of the coefficients coeffs_dev[c][k] (FP64, row-major
- * k_d fastest, n_cells x N^d each), max_cells at a time; stream-ordered,
- * allocates nothing (the product runs through rocBLAS on `stream`). */
+ * k_d fastest, n_cells x N^d each), max_cells at a time; stream-ordered.
+ * The library allocates nothing here; the product runs through rocBLAS on
+ * `stream`, which keeps its own workspace on the object's handle and may grow
+ * it the first time a product of a new shape runs. */
 pgc_status pgc_direct_coeffs_to_q(pgc_direct d, const double* coeffs_dev, int64_t n_cells, double* q_dev,
                                   void* stream);
 
