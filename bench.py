@@ -364,6 +364,31 @@ def accuracy_study(torch, pgc, inputs, np, degrees=(8, 16, 24, 32, 40, 48, 56)):
             rows.append({"N": deg, "linf": linf})
         out["test03"]["S%g_r%d" % (S, map_)] = rows
         log("test03 S=%g r=%d: %s" % (S, map_, ["%.1e" % r["linf"] for r in rows]))
+    # 3D BKW at t = 6.5 (Sec. 5.2, Table 3): r = 0 with S from the domain
+    # L = 6.62, L-inf error on the 30^3 grid of [-6.3, 6.3]^3.  The paper's
+    # Lebedev rules are not available; product rules of about the same size
+    # stand in (n_theta x n_phi).  At N = 32 the rule has 128 directions so
+    # that the binned point index (8 bytes per merged point) stays at 150 GB.
+    x3 = np.linspace(-6.3, 6.3, 30)
+    G3 = np.stack([a.ravel() for a in np.meshgrid(x3, x3, x3, indexing="ij")], axis=1)
+    q3 = inputs.bkw_q(6.5, G3)
+    G3t = torch.tensor(G3, device="cuda")
+    table3 = {12: (14, 1.61e-02), 16: (38, 2.72e-03), 20: (86, 3.08e-06), 24: (146, 3.10e-08),
+              28: (170, 1.58e-08), 32: (230, 7.16e-10)}
+    rules = {12: (3, 6), 16: (4, 10), 20: (7, 12), 24: (8, 18), 28: (9, 18), 32: (8, 16)}
+    rows = []
+    for deg, (nt, nph) in rules.items():
+        log("table3 N=%d: %d directions ..." % (deg, nt * nph))
+        plan = pgc.Plan(dim=3, n_modes=deg + 1, scale=6.62, scale_mode=pgc.SCALE_FROM_DOMAIN,
+                        sphere=pgc.SPHERE_PRODUCT_3D, n_theta=nt, n_phi=nph)
+        c = plan.project(inputs.bkw_f(6.5, plan.interior_velocities()))
+        e = plan.eval(plan.coeffs_to_q(c), G3t).cpu().numpy() - q3
+        rows.append({"N": deg, "n_sigma": nt * nph, "S": plan.info.scale, "linf": float(np.max(np.abs(e))),
+                     "paper_n_sigma_lebedev": table3[deg][0], "paper_linf": table3[deg][1]})
+        log("table3 N=%d: %d directions, L-inf %.2e (paper %.2e with %d Lebedev points)" % (
+            deg, nt * nph, rows[-1]["linf"], table3[deg][1], table3[deg][0]))
+        plan.close()
+    out["table3_3d"] = rows
     return out
 
 
