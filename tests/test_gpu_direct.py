@@ -136,6 +136,49 @@ def test_fast_paths_refuse_the_angle_dependent_rate(torch_cuda):
     p32.close()
 
 
+def test_direct_other_nodes_rules_and_scales(torch_cuda):
+    """The tensor uses only the plan's node, weight and rule tables: more CGL
+    nodes than modes, a user rule (antipodal, unequal weights) and the
+    domain-scaled S all match the oracle."""
+    import oracle as O
+    from paper_2105_08806_amd import pgc
+    N = 6
+    # M_v = N + 3 CGL nodes
+    ora, plan = make_pair(2, N, 2.5, 0, "maxwell", n_sigma=8, m_v=N + 3)
+    cells = [I.random_coeffs((N, N), seed=600 + c) for c in range(2)]
+    say("case: direct, M_v = N + 3")
+    q, info = direct_q(torch_cuda, plan, cells, max_cells=2)
+    assert info.n_pairs == ((N + 1) ** 2) * ((N + 1) ** 2 + 1) // 2
+    for c in range(2):
+        q_ref, _, _ = ora.collision(cells[c])
+        assert rel_l2(q[c].reshape(q_ref.shape), q_ref) <= FP64_TOL
+    plan.close()
+    # a user rule: 3 antipodal pairs at uneven angles and weights
+    th = np.array([0.3, 1.4, 2.2])
+    half = np.stack([np.cos(th), np.sin(th)], axis=1)
+    sg = np.concatenate([half, -half])
+    sw = np.concatenate([[1.0, 2.5, 0.7]] * 2)
+    ora = O.Problem(2, N, 3.0, 1, kernel="vhs", gamma=0.5, sphere=sg, sphere_w=sw)
+    plan = pgc.Plan(dim=2, n_modes=N, scale=3.0, map=1, kernel=pgc.KERNEL_VHS, kernel_gamma=0.5,
+                    sigma=sg, sigma_w=sw)
+    say("case: direct, user rule")
+    q, _ = direct_q(torch_cuda, plan, cells, max_cells=1)
+    for c in range(2):
+        q_ref, _, _ = ora.collision(cells[c])
+        assert rel_l2(q[c].reshape(q_ref.shape), q_ref) <= FP64_TOL
+    plan.close()
+    # S from a domain: the plan reports the S it chose; the oracle takes it directly
+    plan = pgc.Plan(dim=2, n_modes=N, scale=6.0, scale_mode=pgc.SCALE_FROM_DOMAIN, n_sigma=8)
+    sg, sw = O.circle_rule(8)
+    ora = O.Problem(2, N, plan.info.scale, 0, sphere=sg, sphere_w=sw)
+    say("case: direct, S from the domain (S = %.4f)" % plan.info.scale)
+    q, _ = direct_q(torch_cuda, plan, cells, max_cells=2)
+    for c in range(2):
+        q_ref, _, _ = ora.collision(cells[c])
+        assert rel_l2(q[c].reshape(q_ref.shape), q_ref) <= FP64_TOL
+    plan.close()
+
+
 def test_direct_products_of_any_size_agree(torch_cuda):
     """The chunking of a call into products changes nothing but rounding, and
     an empty batch is a no-op."""
