@@ -274,6 +274,14 @@ def direct_variant(torch, pgc, inputs, np, n_cells, reps):
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / reps
     log("direct: %.1f ms per evaluation of %d cells" % (ms, n_cells))
+    # RK4 of every cell through the same product (four evaluations per step)
+    state = c.clone()
+    start.record()
+    d.rk4(state, 0.01, 2)
+    stop.record()
+    torch.cuda.synchronize()
+    rk_ms = start.elapsed_time(stop) / 2
+    log("direct: %.1f ms per RK4 step of %d cells" % (rk_ms, n_cells))
     errs, t_cell = [], []
     for i in range(0, n_cells, max(1, n_cells // 4))[:4]:
         ref, refp = plan.coeffs_to_q(c[i].reshape(N, N).contiguous(), want_qplus=True)
@@ -294,6 +302,7 @@ def direct_variant(torch, pgc, inputs, np, n_cells, reps):
                        "FP64 direct algorithm (node-pair tensor %.2f GB, %d pairs)" % (
                            n_cells, N, d.info.tensor_bytes / 1e9, d.info.n_pairs),
            "tensor_setup_ms": d.info.setup_ms,
+           "rk4_ms_per_step": rk_ms, "rk4_cell_steps_per_s": n_cells / (rk_ms / 1e3),
            "max_diff_vs_fp64_fast_path_over_qplus": max(errs), "cells_checked": len(errs),
            "fp64_fast_path_s_per_cell": min(t_cell),
            "speedup_vs_fp64_fast_path": min(t_cell) * n_cells / (ms / 1e3)}

@@ -438,6 +438,12 @@ pgc_status pgc_direct_query(pgc_direct d, pgc_direct_info* info);
  * it the first time a product of a new shape runs. */
 pgc_status pgc_direct_coeffs_to_q(pgc_direct d, const double* coeffs_dev, int64_t n_cells, double* q_dev,
                                   void* stream);
+/* n_steps classical RK4 steps (eq. spectral_ODE) of dc/dt = Q(c) for every
+ * cell, in place on coeffs_dev (FP64, n_cells x N^d), max_cells at a time,
+ * each chunk taking all its steps in turn; the stage state lives in the
+ * object.  Stream-ordered, like pgc_direct_coeffs_to_q. */
+pgc_status pgc_direct_rk4(pgc_direct d, double* coeffs_dev, int64_t n_cells, double dt, int32_t n_steps,
+                          void* stream);
 
 #ifdef __cplusplus
 }

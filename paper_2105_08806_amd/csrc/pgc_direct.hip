@@ -195,6 +195,21 @@ __global__ void __launch_bounds__(256)
         if (c < nc) X[(int64_t)(c0 + c) * n_pairs + p] = v[c];
 }
 
+// RK4 stages over the cells of one chunk: y = base + a k, and the final update
+__global__ void rk_axpy(const double* __restrict__ base, const double* __restrict__ k, double a,
+                        double* __restrict__ y, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = base[i] + a * k[i];
+}
+
+__global__ void rk_combine(double* __restrict__ base, const double* __restrict__ k1, const double* __restrict__ k2,
+                           const double* __restrict__ k3, const double* __restrict__ k4, double h, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) base[i] += h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+}
+
 }  // namespace
 }  // namespace pgc
 
@@ -207,6 +222,8 @@ struct pgc_direct_s {
     int* pa = nullptr;
     int* pb = nullptr;
     pgc::DenseBufs bufs;      // synthesis of max_cells cells
+    double* rk_y = nullptr;   // RK4 stage state and slopes, max_cells x N^d each
+    double* rk_k[4] = {nullptr, nullptr, nullptr, nullptr};
     rocblas_handle blas = nullptr;
     double setup_ms = 0.0;
     int64_t bytes = 0;
@@ -245,6 +262,25 @@ hipError_t d_upload(pgc_direct_s& d, T** ptr, const std::vector<T>& src)
     if (e == hipSuccess && !src.empty())
         e = hipMemcpy(*ptr, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
     return e;
+}
+
+// Q of nc <= max_cells cells: synthesis, pair products, the FP64 product
+pgc_status direct_chunk(pgc_direct_s& d, const double* c, int nc, double* q, hipStream_t s)
+{
+    const pgc::Plan& p = d.plan->p;
+    hipError_t e = pgc::launch_dense_synthesis(p, c, nc, d.bufs, s);
+    if (e != hipSuccess) return pgc::status_of(e);
+    hipLaunchKernelGGL(pgc::pair_products, dim3((unsigned)((d.n_pairs + 255) / 256),
+                                                (unsigned)((nc + pgc::kPairCells - 1) / pgc::kPairCells)),
+                       dim3(256), 0, s, d.bufs.G, d.pa, d.pb, d.n_pairs, d.nid, nc, d.X);
+    if ((e = hipGetLastError()) != hipSuccess) return pgc::status_of(e);
+    // column major: Q^T (N^d x nc) = K^T (N^d x n_pairs) X^T (n_pairs x nc)
+    const double one = 1.0, zero = 0.0;
+    if (rocblas_dgemm(d.blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)d.Nd, nc,
+                      (rocblas_int)d.n_pairs, &one, d.K, (rocblas_int)d.Nd, d.X, (rocblas_int)d.n_pairs, &zero, q,
+                      (rocblas_int)d.Nd) != rocblas_status_success)
+        return PGC_ERR_DEVICE;
+    return PGC_OK;
 }
 
 void d_free(pgc_direct_s* d)
@@ -308,7 +344,12 @@ pgc_status pgc_direct_create(pgc_plan plan, int32_t max_cells, void* stream, pgc
                 (e = d_alloc_n(*d, &d->bufs.P, (int64_t)max_cells * nid)) == hipSuccess &&
                 (e = d_alloc_n(*d, &d->bufs.G, (int64_t)max_cells * nid)) == hipSuccess &&
                 (e = d_alloc_n(*d, &d->bufs.tmpA, (int64_t)max_cells * t)) == hipSuccess &&
-                (e = d_alloc_n(*d, &d->bufs.tmpB, (int64_t)max_cells * t)) == hipSuccess) {
+                (e = d_alloc_n(*d, &d->bufs.tmpB, (int64_t)max_cells * t)) == hipSuccess &&
+                (e = d_alloc_n(*d, &d->rk_y, (int64_t)max_cells * Nd)) == hipSuccess &&
+                (e = d_alloc_n(*d, &d->rk_k[0], (int64_t)max_cells * Nd)) == hipSuccess &&
+                (e = d_alloc_n(*d, &d->rk_k[1], (int64_t)max_cells * Nd)) == hipSuccess &&
+                (e = d_alloc_n(*d, &d->rk_k[2], (int64_t)max_cells * Nd)) == hipSuccess &&
+                (e = d_alloc_n(*d, &d->rk_k[3], (int64_t)max_cells * Nd)) == hipSuccess) {
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 (void)hipEventCreate(&e0);
                 (void)hipEventCreate(&e1);
@@ -369,23 +410,46 @@ pgc_status pgc_direct_coeffs_to_q(pgc_direct d, const double* coeffs_dev, int64_
                                   void* stream)
 {
     if (!d || n_cells < 0 || (n_cells > 0 && (!coeffs_dev || !q_dev))) return PGC_ERR_INVALID_ARG;
-    const pgc::Plan& p = d->plan->p;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (n_cells > 0 && rocblas_set_stream(d->blas, s) != rocblas_status_success) return PGC_ERR_DEVICE;
     for (int64_t c0 = 0; c0 < n_cells; c0 += d->max_cells) {
         const int nc = (int)std::min<int64_t>(d->max_cells, n_cells - c0);
-        hipError_t e = pgc::launch_dense_synthesis(p, coeffs_dev + c0 * d->Nd, nc, d->bufs, s);
-        if (e != hipSuccess) return pgc::status_of(e);
-        hipLaunchKernelGGL(pgc::pair_products, dim3((unsigned)((d->n_pairs + 255) / 256),
-                                                    (unsigned)((nc + pgc::kPairCells - 1) / pgc::kPairCells)),
-                           dim3(256), 0, s, d->bufs.G, d->pa, d->pb, d->n_pairs, d->nid, nc, d->X);
-        if ((e = hipGetLastError()) != hipSuccess) return pgc::status_of(e);
-        // column major: Q^T (N^d x nc) = K^T (N^d x n_pairs) X^T (n_pairs x nc)
-        const double one = 1.0, zero = 0.0;
-        if (rocblas_dgemm(d->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)d->Nd, nc,
-                          (rocblas_int)d->n_pairs, &one, d->K, (rocblas_int)d->Nd, d->X, (rocblas_int)d->n_pairs,
-                          &zero, q_dev + c0 * d->Nd, (rocblas_int)d->Nd) != rocblas_status_success)
-            return PGC_ERR_DEVICE;
+        const pgc_status st = direct_chunk(*d, coeffs_dev + c0 * d->Nd, nc, q_dev + c0 * d->Nd, s);
+        if (st != PGC_OK) return st;
+    }
+    return PGC_OK;
+}
+
+pgc_status pgc_direct_rk4(pgc_direct d, double* coeffs_dev, int64_t n_cells, double dt, int32_t n_steps,
+                          void* stream)
+{
+    if (!d || n_cells < 0 || n_steps < 0 || !std::isfinite(dt) || (n_cells > 0 && !coeffs_dev))
+        return PGC_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n_cells > 0 && rocblas_set_stream(d->blas, s) != rocblas_status_success) return PGC_ERR_DEVICE;
+    const double a[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
+    // cells are independent: each chunk takes all its steps in turn
+    for (int64_t c0 = 0; c0 < n_cells; c0 += d->max_cells) {
+        const int nc = (int)std::min<int64_t>(d->max_cells, n_cells - c0);
+        const int64_t n = (int64_t)nc * d->Nd;
+        const unsigned blocks = (unsigned)((n + 255) / 256);
+        double* base = coeffs_dev + c0 * d->Nd;
+        for (int step = 0; step < n_steps; ++step) {
+            for (int r = 0; r < 4; ++r) {
+                const double* y = base;
+                if (r > 0) {
+                    hipLaunchKernelGGL(pgc::rk_axpy, dim3(blocks), dim3(256), 0, s, base, d->rk_k[r - 1], a[r],
+                                       d->rk_y, n);
+                    y = d->rk_y;
+                }
+                const pgc_status st = direct_chunk(*d, y, nc, d->rk_k[r], s);
+                if (st != PGC_OK) return st;
+            }
+            hipLaunchKernelGGL(pgc::rk_combine, dim3(blocks), dim3(256), 0, s, base, d->rk_k[0], d->rk_k[1],
+                               d->rk_k[2], d->rk_k[3], dt, n);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return pgc::status_of(e);
+        }
     }
     return PGC_OK;
 }

@@ -161,7 +161,9 @@ def lib():
         L.pgc_direct_destroy.argtypes = [vp]
         L.pgc_direct_query.argtypes = [vp, ctypes.POINTER(DirectInfo)]
         L.pgc_direct_coeffs_to_q.argtypes = [vp, vp, i64, vp, vp]
-        for name in ("pgc_direct_create", "pgc_direct_destroy", "pgc_direct_query", "pgc_direct_coeffs_to_q"):
+        L.pgc_direct_rk4.argtypes = [vp, vp, i64, dbl, i32, vp]
+        for name in ("pgc_direct_create", "pgc_direct_destroy", "pgc_direct_query", "pgc_direct_coeffs_to_q",
+                     "pgc_direct_rk4"):
             getattr(L, name).restype = ctypes.c_int
         for name in ("pgc_surrogate_desc_init", "pgc_surrogate_create", "pgc_surrogate_destroy",
                      "pgc_surrogate_query", "pgc_surrogate_set_normalization", "pgc_surrogate_train",
@@ -496,6 +498,17 @@ class Direct:
             raise ValueError("q must be a contiguous float64 CUDA tensor of the coefficients' size")
         _check(lib().pgc_direct_coeffs_to_q(self._h, _ptr(coeffs), n, _ptr(q), _stream()), "pgc_direct_coeffs_to_q")
         return q
+
+    def rk4(self, coeffs, dt, n_steps):
+        """In place on a contiguous float64 CUDA tensor of whole cells."""
+        torch = self._torch
+        if not (coeffs.is_cuda and coeffs.dtype == torch.float64 and coeffs.is_contiguous()):
+            raise ValueError("coefficients must be a contiguous float64 CUDA tensor")
+        if coeffs.numel() % self.nd:
+            raise ValueError("coefficients must hold whole cells of N^d values")
+        _check(lib().pgc_direct_rk4(self._h, _ptr(coeffs), coeffs.numel() // self.nd, float(dt), int(n_steps),
+                                    _stream()), "pgc_direct_rk4")
+        return coeffs
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

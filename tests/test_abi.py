@@ -185,3 +185,4 @@ def test_direct_argument_errors_without_a_device():
     info = pgc.DirectInfo()
     assert L.pgc_direct_query(None, ctypes.byref(info)) == 1
     assert L.pgc_direct_coeffs_to_q(None, None, 0, None, None) == 1
+    assert L.pgc_direct_rk4(None, None, 0, 0.1, 1, None) == 1

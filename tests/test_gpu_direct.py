@@ -179,6 +179,36 @@ def test_direct_other_nodes_rules_and_scales(torch_cuda):
     plan.close()
 
 
+@pytest.mark.parametrize("angle", [False, True])
+def test_direct_rk4_vs_oracle(torch_cuda, angle):
+    """Classical RK4 of every cell through the direct product against the
+    oracle's RK4, for an angle-free and an angle-dependent rate (the latter has
+    no fast path to step with)."""
+    torch = torch_cuda
+    from paper_2105_08806_amd import pgc
+    N, dt, steps = 6, 0.05, 3
+    if angle:
+        ora, plan = make_aniso(2, N, 3.0, 1, 0.8, 0.5)
+    else:
+        ora, plan = make_pair(2, N, 3.0, 1, "maxwell", n_sigma=8)
+    V = plan.interior_velocities()
+    cells = [ora.project(I.mixture(V, [(0.7, (0.4 * c, -0.2), 0.8), (0.3, (-0.5, 0.3 * c), 1.3)]))
+             for c in range(3)]
+    say("case: direct RK4, angle-dependent rate = %s" % angle)
+    d = pgc.Direct(plan, max_cells=2)   # chunks of 2 and 1
+    c = torch.tensor(np.stack(cells), device="cuda")
+    d.rk4(c, dt, steps)
+    torch.cuda.synchronize()
+    got = c.cpu().numpy()
+    for i in range(3):
+        ref = ora.rk4(cells[i], dt, steps)
+        r = rel_l2(got[i], ref)
+        say("  cell %d rel-L2 after %d steps = %.3e" % (i, steps, r))
+        assert r <= FP64_TOL
+    d.close()
+    plan.close()
+
+
 def test_direct_products_of_any_size_agree(torch_cuda):
     """The chunking of a call into products changes nothing but rounding, and
     an empty batch is a no-op."""
