@@ -51,6 +51,7 @@ CASES = [
     (2, 8, 4.0, 0, "vhs", 0.5, 10),
     (3, 4, 2.0, 1, "maxwell", 0.0, 0),
     (3, 5, 3.0, 0, "vhs", 1.0, 0),
+    (2, 5, 3.0, 0, "vhs", 1.0, 40),     # two direction chunks (32 + 8)
 ]
 
 
@@ -94,6 +95,7 @@ ANISO_CASES = [
     (2, 6, 2.5, 1, 3.0, 1.0, 10),
     (3, 4, 2.0, 1, -0.6, 0.0, 0),
     (3, 5, 3.0, 0, 1.5, 0.5, 0),
+    (2, 5, 2.0, 1, 1.5, 0.0, 48),       # two direction chunks (32 + 16)
 ]
 
 
