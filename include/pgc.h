@@ -42,6 +42,9 @@
  *    work on a plan (pgc_project, pgc_coeffs_to_q, pgc_rk4, pgc_moments,
  *    pgc_eval) allocate nothing.
  *  - A plan must not be used by two calls that can run concurrently.
+ *  - The fast path's gain accumulates with FP64 atomics whose order varies,
+ *    so repeated evaluations agree to rounding, not bit for bit; the direct
+ *    algorithm (pgc_direct_*) repeats bit for bit.
  *  - Every call returns a pgc_status.  On an error return the outputs are
  *    untouched (for argument errors) or unspecified (device errors).  No C++
  *    exception crosses this interface.

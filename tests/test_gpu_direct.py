@@ -285,3 +285,31 @@ def test_direct_n32_batched_cells(torch_cuda):
     say("  cell 0 against the oracle, 12 sampled modes: rel-L2 Q = %.3e" % r)
     assert r <= FP64_TOL
     plan.close()
+
+
+def test_reproducibility_of_the_two_algorithms(torch_cuda):
+    """The direct algorithm repeats itself bit for bit (no atomics: a fixed
+    tensor and one library product); the fast path flushes its bins into the
+    fine grid with FP64 atomics, whose order varies, so repeats agree to
+    rounding only."""
+    torch = torch_cuda
+    from paper_2105_08806_amd import pgc
+    cells = [c for c in I.cell_maxwellians_2d(96, seed=8806) if c["N"] == 32][:8]
+    _, plan = make_pair(2, 32, 6.0, 0, "maxwell", n_sigma=32)
+    V = plan.interior_velocities()
+    c = torch.stack([plan.project(I.perturbed_maxwellian_2d(V, cell)).reshape(-1) for cell in cells])
+    say("case: reproducibility, 8 cells at N=32")
+    d = pgc.Direct(plan, max_cells=8)
+    a = d.coeffs_to_q(c).clone()
+    b = d.coeffs_to_q(c).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    d.close()
+    x = c[0].reshape(32, 32).contiguous()
+    q1 = plan.coeffs_to_q(x).clone()
+    q2 = plan.coeffs_to_q(x).clone()
+    torch.cuda.synchronize()
+    diff = float(torch.linalg.norm(q1 - q2) / torch.linalg.norm(q1))
+    say("  fast path, two runs: rel-L2 difference %.2e" % diff)
+    assert diff <= 1e-13
+    plan.close()
