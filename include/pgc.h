@@ -47,7 +47,9 @@
  *    algorithm (pgc_direct_*) repeats bit for bit.
  *  - Every call returns a pgc_status.  On an error return the outputs are
  *    untouched (for argument errors) or unspecified (device errors).  No C++
- *    exception crosses this interface.
+ *    exception crosses this interface.  PGC_ERR_NUMERIC needs a result on the
+ *    host, so only calls that read one back return it (pgc_surrogate_train,
+ *    when an epoch's loss is not finite); asynchronous calls never do.
  */
 #ifndef PGC_H
 #define PGC_H
@@ -369,7 +371,9 @@ pgc_status pgc_surrogate_set_normalization(pgc_surrogate s, const float* f_dev, 
 /* `epochs` passes of mini-batch Adam (batch <= batch_max rows, step size lr
  * with cosine decay over the epochs) on the loss chosen by desc.loss_relative;
  * loss_host (may be NULL) receives the mean batch loss of each epoch.  Then
- * calibrates the raw-residual gate on the training set.  Allocates a device
+ * calibrates the raw-residual gate on the training set.  NUMERIC (training
+ * stops) when an epoch's loss is not finite, e.g. for a step size that
+ * diverges; the parameters are then unspecified.  Allocates a device
  * copy of each epoch's sample order (n_samples ints, freed before returning)
  * and synchronises `stream` once per epoch. */
 pgc_status pgc_surrogate_train(pgc_surrogate s, const float* f_dev, const float* q_dev, int64_t n_samples,

@@ -1053,7 +1053,8 @@ pgc_status pgc_surrogate_train(pgc_surrogate s, const float* f_dev, const float*
     int* perm_dev = nullptr;
     hipError_t e = hipMalloc(&perm_dev, (size_t)n_samples * sizeof(int));
     if (e != hipSuccess) return pgc::status_of(e);
-    for (int ep = 0; ep < epochs && e == hipSuccess; ++ep) {
+    bool diverged = false;  // an epoch's loss came back not finite: stop
+    for (int ep = 0; ep < epochs && e == hipSuccess && !diverged; ++ep) {
         std::iota(perm.begin(), perm.end(), 0);
         std::shuffle(perm.begin(), perm.end(), rng);
         e = hipMemcpyAsync(perm_dev, perm.data(), (size_t)n_samples * sizeof(int), hipMemcpyHostToDevice, st);
@@ -1078,9 +1079,11 @@ pgc_status pgc_surrogate_train(pgc_surrogate s, const float* f_dev, const float*
         if (e == hipSuccess) e = hipMemcpyAsync(&l, s->loss, sizeof(double), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (loss_host) loss_host[ep] = steps ? l / (double)steps : 0.0;
+        if (e == hipSuccess && !std::isfinite(l)) diverged = true;
     }
     (void)hipFree(perm_dev);
     if (e != hipSuccess) return pgc::status_of(e);
+    if (diverged) return PGC_ERR_NUMERIC;
     // calibrate the out-of-distribution gate: largest raw residual on the training set
     double worst = 0.0, worst_z = 0.0;
     for (int64_t b0 = 0; b0 < n_samples && e == hipSuccess; b0 += s->bmax) {

@@ -230,3 +230,20 @@ def test_training_gates_and_gain(torch_cuda):
     for x in (s, s2, s3):
         x.close()
     plan.close()
+
+
+def test_diverging_training_reports_numeric(torch_cuda):
+    """A step size far too large drives the loss to inf or NaN within an
+    epoch; training stops and reports PGC_ERR_NUMERIC (5)."""
+    torch = torch_cuda
+    from paper_2105_08806_amd import pgc
+    plan = small_plan(pgc, N=5)
+    f, q = make_pairs(torch, pgc, plan, 64, seed=11)
+    s = pgc.Surrogate(plan, width=64, n_layers=3, batch_max=16, seed=3, judge_stride=0)
+    s.set_normalization(f, q)
+    say("case: diverging training, lr 1e6")
+    with pytest.raises(pgc.PgcError) as err:
+        s.train(f, q, epochs=3, batch=16, lr=1e6, seed=5)
+    assert err.value.code == 5
+    s.close()
+    plan.close()
