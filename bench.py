@@ -579,7 +579,7 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--surrogate-pairs", type=int, default=4096)
     ap.add_argument("--surrogate-epochs", type=int, default=150)
-    ap.add_argument("--pmc-dir", default="gpurun_out/prof")
+    ap.add_argument("--pmc-dir", default="counters", help="folder holding the fetch/write/cfetch/cwrite counter passes")
     ap.add_argument("--mode", choices=["bench", "profile", "copy", "bkw", "traffic", "accuracy"], default="bench",
                     help="profile: two evaluations per precision (for rocprofv3); "
                          "copy: a 1 GiB device copy (calibrates the HBM byte counters); "
