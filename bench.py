@@ -311,6 +311,16 @@ def direct_variant(torch, pgc, inputs, np, n_cells, reps):
     return out
 
 
+# The paper's printed accuracy tables (Sec. 5.1.1 Table 2: best L2 error of
+# Q_BKW at t = 2 over S, per degree, for r = 0 and r = 1; Sec. 5.2 Table 3:
+# L-inf error at t = 6.5 with the Lebedev rule size used, Chebyshev-0)
+TABLE2_DEGREES = (8, 16, 24, 32, 40, 48, 56)
+TABLE2_BEST_L2 = {0: [2.2289e-03, 2.2033e-05, 1.9843e-07, 3.0082e-09, 2.5434e-11, 1.6255e-13, 2.1482e-14],
+                  1: [4.1388e-03, 2.9713e-04, 1.5004e-05, 5.3946e-07, 1.6120e-08, 6.0320e-10, 2.5213e-11]}
+TABLE3_LINF = {12: (14, 1.61e-02), 16: (38, 2.72e-03), 20: (86, 3.08e-06), 24: (146, 3.10e-08),
+               28: (170, 1.58e-08), 32: (230, 7.16e-10)}
+
+
 def accuracy_study(torch, pgc, inputs, np, degrees=(8, 16, 24, 32, 40, 48, 56)):
     """The 2D BKW accuracy tests at t = 2 (Sec. 5.1.1) on the FP64 GPU path,
     with the paper's set-up: degree N, N + 1 modes, M_v = N + 2 nodes, M_sigma =
@@ -337,9 +347,7 @@ def accuracy_study(torch, pgc, inputs, np, degrees=(8, 16, 24, 32, 40, 48, 56)):
         plan.close()
         return float(np.sqrt(h * h * np.sum(e * e))), float(np.max(np.abs(e))), s_used
 
-    table2 = {0: [2.2289e-03, 2.2033e-05, 1.9843e-07, 3.0082e-09, 2.5434e-11, 1.6255e-13, 2.1482e-14],
-              1: [4.1388e-03, 2.9713e-04, 1.5004e-05, 5.3946e-07, 1.6120e-08, 6.0320e-10, 2.5213e-11]}
-    all_deg = (8, 16, 24, 32, 40, 48, 56)
+    table2, all_deg = TABLE2_BEST_L2, TABLE2_DEGREES
     out = {"test01": {}, "test02": {}, "test03": {}}
     for map_ in (0, 1):
         rows = []
@@ -382,8 +390,7 @@ def accuracy_study(torch, pgc, inputs, np, degrees=(8, 16, 24, 32, 40, 48, 56)):
     G3 = np.stack([a.ravel() for a in np.meshgrid(x3, x3, x3, indexing="ij")], axis=1)
     q3 = inputs.bkw_q(6.5, G3)
     G3t = torch.tensor(G3, device="cuda")
-    table3 = {12: (14, 1.61e-02), 16: (38, 2.72e-03), 20: (86, 3.08e-06), 24: (146, 3.10e-08),
-              28: (170, 1.58e-08), 32: (230, 7.16e-10)}
+    table3 = TABLE3_LINF
     rules = {12: (3, 6), 16: (4, 10), 20: (7, 12), 24: (8, 18), 28: (9, 18), 32: (8, 16)}
     rows = []
     for deg, (nt, nph) in rules.items():

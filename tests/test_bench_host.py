@@ -80,3 +80,19 @@ def test_committed_traffic_record():
             stale.append(tag)
     if stale:
         pytest.skip("traffic record predates the current sources of: " + ", ".join(stale))
+
+
+def _golden(name):
+    rows = [l.split() for l in open(os.path.join(ROOT, "tests", "golden", name))
+            if l.strip() and not l.startswith("#")]
+    return rows
+
+
+def test_accuracy_tables_match_the_golden_files():
+    """The accuracy study's copies of Tables 2 and 3 are the cited golden values."""
+    for map_ in (0, 1):
+        rows = _golden("table2_bkw2d_cheb%d.txt" % map_)
+        assert [int(r[0]) for r in rows] == list(bench.TABLE2_DEGREES)
+        assert [float(r[2]) for r in rows] == bench.TABLE2_BEST_L2[map_]
+    rows = _golden("table3_bkw3d_cheb0.txt")
+    assert {int(r[0]): (int(r[2]), float(r[3])) for r in rows} == bench.TABLE3_LINF
