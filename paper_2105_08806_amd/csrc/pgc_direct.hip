@@ -169,30 +169,40 @@ __global__ void __launch_bounds__(kDirThreads)
     }
 }
 
-// X[c][p] = G[c][a_p] G[c][b_p] for the cells of one chunk.  A thread keeps
-// its pair for kPairCells cells: the pair indices are read once and the
-// cells' gathers are independent (HBM bound: the writes of X).
+// X[c][p] = G[c][a_p] G[c][b_p] for the cells of one chunk (row stride ldx,
+// n_pairs rounded up to even).  A thread keeps two neighbouring pairs for
+// kPairCells cells: the pair indices are read once, the cells' gathers are
+// independent, and each cell's two products leave in one 16-byte store
+// (HBM bound: the writes of X).
 constexpr int kPairCells = 16;
 
 __global__ void __launch_bounds__(256)
     pair_products(const double* __restrict__ G, const int* __restrict__ pa, const int* __restrict__ pb,
-                  int64_t n_pairs, int64_t nid, int n_cells, double* __restrict__ X)
+                  int64_t n_pairs, int64_t ldx, int64_t nid, int n_cells, double* __restrict__ X)
 {
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t p = 2 * (blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
     if (p >= n_pairs) return;
-    const int a = pa[p], b = pb[p];
+    const bool two = p + 1 < n_pairs;
+    const int a0 = pa[p], b0 = pb[p];
+    const int a1 = two ? pa[p + 1] : a0, b1 = two ? pb[p + 1] : b0;
     const int c0 = blockIdx.y * kPairCells;
     const int nc = min(kPairCells, n_cells - c0);
-    double v[kPairCells];
+    double2 v[kPairCells];
 #pragma unroll
     for (int c = 0; c < kPairCells; ++c)
         if (c < nc) {
             const double* g = G + (int64_t)(c0 + c) * nid;
-            v[c] = g[a] * g[b];
+            v[c] = make_double2(g[a0] * g[b0], g[a1] * g[b1]);
         }
 #pragma unroll
     for (int c = 0; c < kPairCells; ++c)
-        if (c < nc) X[(int64_t)(c0 + c) * n_pairs + p] = v[c];
+        if (c < nc) {
+            double* x = X + (int64_t)(c0 + c) * ldx + p;
+            if (two)
+                *reinterpret_cast<double2*>(x) = v[c];
+            else
+                x[0] = v[c].x;
+        }
 }
 
 // RK4 stages over the cells of one chunk: y = base + a k, and the final update
@@ -217,8 +227,9 @@ struct pgc_direct_s {
     pgc_plan plan = nullptr;
     int max_cells = 0;
     int64_t n_pairs = 0, nid = 0, Nd = 0;
+    int64_t ldx = 0;          // row stride of X: n_pairs rounded up to even (16-byte rows)
     double* K = nullptr;      // n_pairs x N^d
-    double* X = nullptr;      // max_cells x n_pairs
+    double* X = nullptr;      // max_cells x ldx
     int* pa = nullptr;
     int* pb = nullptr;
     pgc::DenseBufs bufs;      // synthesis of max_cells cells
@@ -270,14 +281,15 @@ pgc_status direct_chunk(pgc_direct_s& d, const double* c, int nc, double* q, hip
     const pgc::Plan& p = d.plan->p;
     hipError_t e = pgc::launch_dense_synthesis(p, c, nc, d.bufs, s);
     if (e != hipSuccess) return pgc::status_of(e);
-    hipLaunchKernelGGL(pgc::pair_products, dim3((unsigned)((d.n_pairs + 255) / 256),
+    const int64_t n_threads = (d.n_pairs + 1) / 2;
+    hipLaunchKernelGGL(pgc::pair_products, dim3((unsigned)((n_threads + 255) / 256),
                                                 (unsigned)((nc + pgc::kPairCells - 1) / pgc::kPairCells)),
-                       dim3(256), 0, s, d.bufs.G, d.pa, d.pb, d.n_pairs, d.nid, nc, d.X);
+                       dim3(256), 0, s, d.bufs.G, d.pa, d.pb, d.n_pairs, d.ldx, d.nid, nc, d.X);
     if ((e = hipGetLastError()) != hipSuccess) return pgc::status_of(e);
-    // column major: Q^T (N^d x nc) = K^T (N^d x n_pairs) X^T (n_pairs x nc)
+    // column major: Q^T (N^d x nc) = K^T (N^d x n_pairs) X^T (n_pairs x nc, leading dimension ldx)
     const double one = 1.0, zero = 0.0;
     if (rocblas_dgemm(d.blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)d.Nd, nc,
-                      (rocblas_int)d.n_pairs, &one, d.K, (rocblas_int)d.Nd, d.X, (rocblas_int)d.n_pairs, &zero, q,
+                      (rocblas_int)d.n_pairs, &one, d.K, (rocblas_int)d.Nd, d.X, (rocblas_int)d.ldx, &zero, q,
                       (rocblas_int)d.Nd) != rocblas_status_success)
         return PGC_ERR_DEVICE;
     return PGC_OK;
@@ -317,6 +329,7 @@ pgc_status pgc_direct_create(pgc_plan plan, int32_t max_cells, void* stream, pgc
         d->plan = plan;
         d->max_cells = max_cells;
         d->n_pairs = n_pairs;
+        d->ldx = (n_pairs + 1) / 2 * 2;
         d->nid = nid;
         d->Nd = Nd;
         // unordered pairs a <= b of flat interior-node indices, row by row
@@ -340,7 +353,7 @@ pgc_status pgc_direct_create(pgc_plan plan, int32_t max_cells, void* stream, pgc
             if ((e = d_upload(*d, &v1, p.v1)) == hipSuccess && (e = d_upload(*d, &lt, ltab)) == hipSuccess &&
                 (e = d_upload(*d, &sig, p.sigma)) == hipSuccess && (e = d_upload(*d, &sw, p.sigma_w)) == hipSuccess &&
                 (e = d_alloc_n(*d, &d->K, n_pairs * Nd)) == hipSuccess &&
-                (e = d_alloc_n(*d, &d->X, (int64_t)max_cells * n_pairs)) == hipSuccess &&
+                (e = d_alloc_n(*d, &d->X, (int64_t)max_cells * d->ldx)) == hipSuccess &&
                 (e = d_alloc_n(*d, &d->bufs.P, (int64_t)max_cells * nid)) == hipSuccess &&
                 (e = d_alloc_n(*d, &d->bufs.G, (int64_t)max_cells * nid)) == hipSuccess &&
                 (e = d_alloc_n(*d, &d->bufs.tmpA, (int64_t)max_cells * t)) == hipSuccess &&
