@@ -445,6 +445,15 @@ pgc_status pgc_direct_query(pgc_direct d, pgc_direct_info* info);
  * it the first time a product of a new shape runs. */
 pgc_status pgc_direct_coeffs_to_q(pgc_direct d, const double* coeffs_dev, int64_t n_cells, double* q_dev,
                                   void* stream);
+/* Record pgc_direct_coeffs_to_q for these pointers and n_cells into a HIP
+ * graph owned by the object (replacing any earlier one).  One eager
+ * evaluation runs first on `stream` (it writes q_dev and lets rocBLAS size its
+ * workspace for these shapes), then the capture, on a private stream.
+ * pgc_direct_graph_launch replays it on `stream` (INVALID_ARG without a
+ * graph).  The graph reads the captured pointers: refill the same input
+ * buffer between replays. */
+pgc_status pgc_direct_capture(pgc_direct d, const double* coeffs_dev, int64_t n_cells, double* q_dev, void* stream);
+pgc_status pgc_direct_graph_launch(pgc_direct d, void* stream);
 /* n_steps classical RK4 steps (eq. spectral_ODE) of dc/dt = Q(c) for every
  * cell, in place on coeffs_dev (FP64, n_cells x N^d), max_cells at a time,
  * each chunk taking all its steps in turn; the stage state lives in the

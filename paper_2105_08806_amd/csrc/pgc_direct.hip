@@ -236,6 +236,8 @@ struct pgc_direct_s {
     double* rk_y = nullptr;   // RK4 stage state and slopes, max_cells x N^d each
     double* rk_k[4] = {nullptr, nullptr, nullptr, nullptr};
     rocblas_handle blas = nullptr;
+    hipGraph_t graph = nullptr;       // a captured evaluation (pgc_direct_capture)
+    hipGraphExec_t exec = nullptr;
     double setup_ms = 0.0;
     int64_t bytes = 0;
     std::vector<void*> allocations;
@@ -299,6 +301,8 @@ void d_free(pgc_direct_s* d)
 {
     if (!d) return;
     (void)hipDeviceSynchronize();
+    if (d->exec) (void)hipGraphExecDestroy(d->exec);
+    if (d->graph) (void)hipGraphDestroy(d->graph);
     if (d->blas) (void)rocblas_destroy_handle(d->blas);
     for (void* p : d->allocations) (void)hipFree(p);
     delete d;
@@ -431,6 +435,45 @@ pgc_status pgc_direct_coeffs_to_q(pgc_direct d, const double* coeffs_dev, int64_
         if (st != PGC_OK) return st;
     }
     return PGC_OK;
+}
+
+pgc_status pgc_direct_capture(pgc_direct d, const double* coeffs_dev, int64_t n_cells, double* q_dev, void* stream)
+{
+    if (!d || n_cells < 1 || !coeffs_dev || !q_dev) return PGC_ERR_INVALID_ARG;
+    if (d->exec) (void)hipGraphExecDestroy(d->exec);
+    if (d->graph) (void)hipGraphDestroy(d->graph);
+    d->exec = nullptr;
+    d->graph = nullptr;
+    // one eager evaluation first: rocBLAS sizes its workspace for these shapes
+    // outside the capture
+    pgc_status st = pgc_direct_coeffs_to_q(d, coeffs_dev, n_cells, q_dev, stream);
+    if (st != PGC_OK) return st;
+    hipStream_t user = static_cast<hipStream_t>(stream);
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamSynchronize(user);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return pgc::status_of(e);
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = pgc_direct_coeffs_to_q(d, coeffs_dev, n_cells, q_dev, cs);
+        e = hipStreamEndCapture(cs, &d->graph);
+    }
+    if (st == PGC_OK && e == hipSuccess) e = hipGraphInstantiate(&d->exec, d->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (st == PGC_OK && e != hipSuccess) st = pgc::status_of(e);
+    if (st != PGC_OK) {
+        if (d->exec) (void)hipGraphExecDestroy(d->exec);
+        if (d->graph) (void)hipGraphDestroy(d->graph);
+        d->exec = nullptr;
+        d->graph = nullptr;
+    }
+    return st;
+}
+
+pgc_status pgc_direct_graph_launch(pgc_direct d, void* stream)
+{
+    if (!d || !d->exec) return PGC_ERR_INVALID_ARG;
+    return pgc::status_of(hipGraphLaunch(d->exec, static_cast<hipStream_t>(stream)));
 }
 
 pgc_status pgc_direct_rk4(pgc_direct d, double* coeffs_dev, int64_t n_cells, double dt, int32_t n_steps,

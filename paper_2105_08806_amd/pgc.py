@@ -162,8 +162,10 @@ def lib():
         L.pgc_direct_query.argtypes = [vp, ctypes.POINTER(DirectInfo)]
         L.pgc_direct_coeffs_to_q.argtypes = [vp, vp, i64, vp, vp]
         L.pgc_direct_rk4.argtypes = [vp, vp, i64, dbl, i32, vp]
+        L.pgc_direct_capture.argtypes = [vp, vp, i64, vp, vp]
+        L.pgc_direct_graph_launch.argtypes = [vp, vp]
         for name in ("pgc_direct_create", "pgc_direct_destroy", "pgc_direct_query", "pgc_direct_coeffs_to_q",
-                     "pgc_direct_rk4"):
+                     "pgc_direct_rk4", "pgc_direct_capture", "pgc_direct_graph_launch"):
             getattr(L, name).restype = ctypes.c_int
         for name in ("pgc_surrogate_desc_init", "pgc_surrogate_create", "pgc_surrogate_destroy",
                      "pgc_surrogate_query", "pgc_surrogate_set_normalization", "pgc_surrogate_train",
@@ -498,6 +500,21 @@ class Direct:
             raise ValueError("q must be a contiguous float64 CUDA tensor of the coefficients' size")
         _check(lib().pgc_direct_coeffs_to_q(self._h, _ptr(coeffs), n, _ptr(q), _stream()), "pgc_direct_coeffs_to_q")
         return q
+
+    def capture(self, coeffs, q):
+        """Record Q of these cells into a HIP graph (runs one eager evaluation first)."""
+        torch = self._torch
+        for t in (coeffs, q):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError("coefficients and q must be contiguous float64 CUDA tensors")
+        if coeffs.numel() % self.nd or q.numel() != coeffs.numel():
+            raise ValueError("coefficients and q must hold the same whole cells")
+        _check(lib().pgc_direct_capture(self._h, _ptr(coeffs), coeffs.numel() // self.nd, _ptr(q), _stream()),
+               "pgc_direct_capture")
+        self._graph_io = (coeffs, q)  # the graph reads these buffers
+
+    def graph_launch(self):
+        _check(lib().pgc_direct_graph_launch(self._h, _stream()), "pgc_direct_graph_launch")
 
     def rk4(self, coeffs, dt, n_steps):
         """In place on a contiguous float64 CUDA tensor of whole cells."""

@@ -186,3 +186,5 @@ def test_direct_argument_errors_without_a_device():
     assert L.pgc_direct_query(None, ctypes.byref(info)) == 1
     assert L.pgc_direct_coeffs_to_q(None, None, 0, None, None) == 1
     assert L.pgc_direct_rk4(None, None, 0, 0.1, 1, None) == 1
+    assert L.pgc_direct_capture(None, None, 1, None, None) == 1
+    assert L.pgc_direct_graph_launch(None, None) == 1

@@ -313,3 +313,32 @@ def test_reproducibility_of_the_two_algorithms(torch_cuda):
     say("  fast path, two runs: rel-L2 difference %.2e" % diff)
     assert diff <= 1e-13
     plan.close()
+
+
+def test_direct_graph_replays(torch_cuda):
+    """A captured evaluation (three chunked products) replayed several times,
+    the input buffer refilled and eager evaluations run between the replays:
+    every replay equals the eager result for its input."""
+    torch = torch_cuda
+    from paper_2105_08806_amd import pgc
+    _, plan = make_pair(2, 6, 3.0, 0, "maxwell", n_sigma=8)
+    d = pgc.Direct(plan, max_cells=2)
+    c = torch.tensor(np.stack([I.random_coeffs((6, 6), seed=700 + i) for i in range(5)]), device="cuda")
+    q = torch.empty_like(c)
+    say("case: direct graph capture, 5 cells in products of 2")
+    with pytest.raises(pgc.PgcError):
+        d.graph_launch()                     # nothing captured yet
+    d.capture(c, q)
+    for r in range(3):
+        fresh = torch.tensor(np.stack([I.random_coeffs((6, 6), seed=800 + 10 * r + i) for i in range(5)]),
+                             device="cuda")
+        c.copy_(fresh)
+        ref = d.coeffs_to_q(fresh.clone())
+        torch.cuda.synchronize()
+        d.graph_launch()
+        torch.cuda.synchronize()
+        diff = float(torch.max(torch.abs(q - ref)) / torch.max(torch.abs(ref)))
+        say("  replay %d: max difference to eager %.2e" % (r, diff))
+        assert diff <= 1e-14
+    d.close()
+    plan.close()
