@@ -433,8 +433,8 @@ typedef struct pgc_direct_info {
 /* Build the tensor of `plan` (FP64 plans only) and the workspace for
  * max_cells (1..65535) cells per product; synchronises `stream`.  The plan
  * must outlive the object.  Calls on one object share its workspace and must
- * not overlap; separate objects are independent.  UNSUPPORTED for FP32 plans, N^d > 4096, or a
- * tensor above 96 GiB (2D N <= 55, 3D N <= 15 fit). */
+ * not overlap; separate objects are independent.  UNSUPPORTED for FP32
+ * plans, N^d > 4096, or a tensor above 96 GiB (2D N <= 55, 3D N <= 15 fit). */
 pgc_status pgc_direct_create(pgc_plan plan, int32_t max_cells, void* stream, pgc_direct* out);
 pgc_status pgc_direct_destroy(pgc_direct d);
 pgc_status pgc_direct_query(pgc_direct d, pgc_direct_info* info);
