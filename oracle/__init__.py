@@ -168,14 +168,15 @@ class Problem:
                "collision")
         return q, qp, qm
 
-    def collision_at(self, coeffs, kidx):
-        """(Q+, Q-) at the multi-indices kidx (n_k x dim)."""
+    def collision_at(self, coeffs, kidx, gain=True):
+        """(Q+, Q-) at the multi-indices kidx (n_k x dim); Q+ is None when
+        gain is False (only the loss is formed)."""
         c = np.ascontiguousarray(coeffs, dtype=np.float64)
         k = np.ascontiguousarray(kidx, dtype=np.int32).reshape(-1, self.dim)
         qp, qm = np.zeros(len(k)), np.zeros(len(k))
-        _check(lib().ora_collision_at(ctypes.byref(self._c), _dp(c), len(k), _ip(k), _dp(qp),
-                                      _dp(qm)), "collision_at")
-        return qp, qm
+        _check(lib().ora_collision_at(ctypes.byref(self._c), _dp(c), len(k), _ip(k),
+                                      _dp(qp) if gain else None, _dp(qm)), "collision_at")
+        return (qp if gain else None), qm
 
     def gain_units(self, coeffs, u_lo, u_hi):
         """Q+ restricted to the collision units [u_lo, u_hi), u = s * n_i^dim + i."""

@@ -6,7 +6,7 @@ and quadratures written independently of the oracle.
 """
 import numpy as np
 import pytest
-from scipy import integrate
+from scipy import integrate, special
 
 import oracle as O
 from closed_forms import (c_k, cheb, load_golden, q_bkw, t_hat, t_tilde, uniform_grid)
@@ -314,6 +314,75 @@ def test_q_bkw_weak_form_projection():
     for k1, k2 in [(0, 0), (2, 0), (2, 2), (4, 0), (0, 6)]:
         val = h * h * np.sum(Qb * np.outer(t_hat(k1, x, S, 0), t_hat(k2, x, S, 0)))
         assert abs(q[k1, k2] - val) < 1e-6, (k1, k2, q[k1, k2], val)
+
+
+def maxwellian_mean_rate(dim, c, T, gamma):
+    """E |c + sqrt(T) Z|^gamma for Z standard normal in R^dim: the mean of
+    |v - w|^gamma over w drawn from a Maxwellian of temperature T centred at
+    distance c from v.  It is a moment of the non-central chi distribution,
+    (2T)^(gamma/2) Gamma((dim+gamma)/2) / Gamma(dim/2) 1F1(-gamma/2; dim/2; -c^2/(2T))."""
+    return ((2 * T) ** (gamma / 2) * special.gamma((dim + gamma) / 2) / special.gamma(dim / 2)
+            * special.hyp1f1(-gamma / 2, dim / 2, -c * c / (2 * T)))
+
+
+def test_maxwellian_mean_rate_hard_spheres():
+    """gamma = 1: the Rice mean in 2D and the erf form in 3D, two further
+    closed forms of the same expectation."""
+    c = np.linspace(0.0, 6.0, 13)
+    T = 0.7
+    x = c * c / (4 * T)
+    rice = np.sqrt(T) * np.sqrt(np.pi / 2) * ((1 + 2 * x) * special.i0e(x) + 2 * x * special.i1e(x))
+    assert np.allclose(maxwellian_mean_rate(2, c, T, 1.0), rice, rtol=1e-13)
+    nu = c[1:] / np.sqrt(T)
+    erf3 = np.sqrt(T) * (np.sqrt(2 / np.pi) * np.exp(-nu * nu / 2)
+                         + (nu + 1 / nu) * special.erf(nu / np.sqrt(2)))
+    assert np.allclose(maxwellian_mean_rate(3, c[1:], T, 1.0), erf3, rtol=1e-13)
+    assert abs(maxwellian_mean_rate(3, 0.0, T, 1.0) - 2 * np.sqrt(2 * T / np.pi)) < 1e-14
+
+
+def vhs_loss_error(dim, N, gamma, kidx, S=3.0, rho=0.9, u=(0.3, -0.2, 0.1), T=0.8):
+    """Largest deviation, relative to the largest entry, of the oracle's Q-_k
+    for a projected Maxwellian from (M nu, T^_k), where the collision
+    frequency nu(v) = b0 |S^(d-1)| rho E|v - w|^gamma is the closed form above
+    (eq. Qminus with B = b0 |u|^gamma, the VHS law of Sec. 2).  The reference
+    integral is a trapezoid sum over a wide uniform grid."""
+    u = np.array(u[:dim])
+    sg, sw = circle(8) if dim == 2 else O.sphere_product_rule(2, 4)
+    b0 = 0.3
+    p = O.Problem(dim, N, S, 0, kernel="vhs", b0=b0, gamma=gamma, sphere=sg, sphere_w=sw)
+    c = p.project(I.maxwellian(p.interior_velocities(), rho, tuple(u), T))
+    _, qm = p.collision_at(c, kidx, gain=False)
+    L, n = (12.0, 1201) if dim == 2 else (9.0, 121)
+    x = np.linspace(-L, L, n)
+    V = np.stack(np.meshgrid(*([x] * dim), indexing="ij"), axis=-1)
+    M = I.maxwellian(V.reshape(-1, dim), rho, tuple(u), T).reshape(V.shape[:-1])
+    nu = b0 * sw.sum() * rho * maxwellian_mean_rate(dim, np.linalg.norm(V - u, axis=-1), T, gamma)
+    ref = []
+    for k in kidx:
+        val = M * nu
+        for l in range(dim):
+            val = np.tensordot(t_hat(int(k[l]), x, S, 0), val, axes=([0], [0]))
+        ref.append(float(val) * (x[1] - x[0]) ** dim)
+    ref = np.array(ref)
+    return np.max(np.abs(qm - ref)) / np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("gamma,tol", [(1.0, 6e-4), (0.5, 3e-3)])
+def test_vhs_loss_collision_frequency_2d(gamma, tol):
+    """The 2D VHS loss converges to the closed-form collision frequency.  The
+    rate |u|^gamma has a cusp at u = 0, on a node, so the CGL sums converge
+    algebraically (about N^-3 for gamma = 1); a wrong exponent (|u|^(2 gamma)
+    or |u|^(gamma/2)) leaves an O(1) error."""
+    kidx = np.array([[0, 0], [1, 0], [2, 0], [0, 2], [3, 1], [4, 4], [6, 2]])
+    e = [vhs_loss_error(2, N, gamma, kidx) for N in (16, 32)]
+    assert e[1] < tol, e
+    assert e[0] > 3 * e[1], e
+
+
+@pytest.mark.parametrize("gamma,N,tol", [(1.0, 12, 3e-3), (1.0, 16, 1e-3), (0.5, 12, 1e-2)])
+def test_vhs_loss_collision_frequency_3d(gamma, N, tol):
+    kidx = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 2], [0, 1, 3], [2, 2, 2]])
+    assert vhs_loss_error(3, N, gamma, kidx) < tol
 
 
 def test_collision_at_matches_full():
