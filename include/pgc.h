@@ -67,7 +67,9 @@ typedef enum pgc_status {
     PGC_ERR_UNSUPPORTED = 2,
     PGC_ERR_OUT_OF_MEMORY = 3,
     PGC_ERR_DEVICE = 4,
-    PGC_ERR_NUMERIC = 5
+    PGC_ERR_NUMERIC = 5,
+    PGC_ERR_SCRATCH = 6     /* pgc_coeffs_to_q_static: the plan needs more than
+                               PGC_STATIC_SCRATCH_BYTES of scratch */
 } pgc_status;
 
 enum { PGC_MAP_LOG = 0, PGC_MAP_ALGEBRAIC = 1 };
@@ -190,6 +192,27 @@ pgc_status pgc_project(pgc_plan plan, const double* f_nodes_dev, void* coeffs_de
  * cosine transform, deconvolution and the final combination. */
 pgc_status pgc_coeffs_to_q(pgc_plan plan, const void* coeffs_dev, void* q_dev, void* qplus_dev,
                            void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as pgc_coeffs_to_q, with the same arguments, results and stream
+ * ordering, but every per-call buffer (nodal values, loss field, fine grid,
+ * transform buffers, partial sums: about 23 MB for the 3D 32-mode FP64
+ * workload) is carved from one static device array of
+ * PGC_STATIC_SCRATCH_BYTES held by the library on each device it runs on
+ * until the process ends.  The call allocates nothing; its first call on a
+ * device looks the array's address up once.  The plan's own tables (and its
+ * bin index) are still read.  Every call on a device shares that device's
+ * array, so calls that can overlap on one device -- on two streams, or from
+ * two threads -- race and must be serialised by the caller.  The array keeps
+ * the last call's contents; the call clears what must start at zero itself.
+ * Errors: INVALID_ARG (NULL arguments, or the current device is not the one
+ * the plan was created on), UNSUPPORTED (PGC_KERNEL_ANISO, as for
+ * pgc_coeffs_to_q), SCRATCH (the plan needs more than the array holds),
+ * DEVICE. */
+#define PGC_STATIC_SCRATCH_BYTES (32u * 1024u * 1024u)
+pgc_status pgc_coeffs_to_q_static(pgc_plan plan, const void* coeffs_dev, void* q_dev, void* qplus_dev,
+                                  void* stream);
 
 /* n_steps classical fourth-order Runge-Kutta steps of size dt on
  * d f_k/dt = Q_k (eq. spectral_ODE), in place on coeffs_dev (N^dim doubles,

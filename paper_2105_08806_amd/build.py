@@ -25,7 +25,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
-SOURCES = ["pgc_kernels.hip", "pgc_host.cpp", "pgc_batch.hip", "pgc_mlp.hip", "pgc_direct.hip"]
+SOURCES = ["pgc_kernels.hip", "pgc_host.cpp", "pgc_batch.hip", "pgc_mlp.hip", "pgc_direct.hip",
+           "pgc_static.hip"]
 
 
 def _compile(src: str) -> str:

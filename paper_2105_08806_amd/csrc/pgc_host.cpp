@@ -765,6 +765,7 @@ const char* pgc_status_string(pgc_status s)
     case PGC_ERR_OUT_OF_MEMORY: return "out of device memory";
     case PGC_ERR_DEVICE: return "device error";
     case PGC_ERR_NUMERIC: return "non-finite result";
+    case PGC_ERR_SCRATCH: return "the call needs more scratch memory than the static buffer holds";
     }
     return "unknown status";
 }
@@ -808,6 +809,7 @@ pgc_status pgc_plan_create(const pgc_plan_desc* desc, void* stream, pgc_plan* pl
     pgc_status st = PGC_OK;
     try {
         st = pgc::resolve(*desc, h->p);
+        if (st == PGC_OK) st = pgc::from_hip(hipGetDevice(&h->p.device));
         if (st == PGC_OK) {
             pgc::build_tables(h->p);
             st = pgc::from_hip(pgc::allocate(h->p, static_cast<hipStream_t>(stream)));
@@ -919,12 +921,12 @@ pgc_status pgc_coeffs_to_q(pgc_plan plan, const void* coeffs, void* q, void* qpl
         ++pr.used;
     }
     pgc::prof_mark(p, 0, s);
-    hipError_t e = pgc::launch_synthesis(p, coeffs, s);
+    hipError_t e = pgc::launch_synthesis(p, p.ws, coeffs, s);
     pgc::prof_mark(p, 1, s);
-    if (e == hipSuccess) e = pgc::launch_loss(p, s);
-    if (e == hipSuccess) e = pgc::launch_gain(p, s);
+    if (e == hipSuccess) e = pgc::launch_loss(p, p.ws, s);
+    if (e == hipSuccess) e = pgc::launch_gain(p, p.ws, s);
     pgc::prof_mark(p, 5, s);
-    if (e == hipSuccess) e = pgc::launch_combine(p, q, qplus, s);
+    if (e == hipSuccess) e = pgc::launch_combine(p, p.ws, q, qplus, s);
     pgc::prof_mark(p, 6, s);
     p.prof_set = -1;
     return pgc::from_hip(e);

@@ -135,6 +135,7 @@ struct Plan {
     Workspace ws;
     int64_t workspace_bytes = 0;
     std::vector<void*> allocations;
+    int device = -1;           // HIP device current when the plan was created
 };
 
 // Buffers of the dense (FP64) stages for nb cells, each nb times the size of
@@ -158,10 +159,12 @@ inline void prof_mark(const Plan& p, int stage, hipStream_t s)
 }
 
 // ----- launchers (pgc_kernels.hip); all enqueue on `s` and return the launch status
-hipError_t launch_synthesis(const Plan& p, const void* coeffs, hipStream_t s);
-hipError_t launch_loss(const Plan& p, hipStream_t s);
-hipError_t launch_gain(const Plan& p, hipStream_t s);
-hipError_t launch_combine(const Plan& p, void* q, void* qplus, hipStream_t s);
+// The four stages of one evaluation read and write the buffers of `ws`: the
+// plan's own Workspace, or one carved from the library's static scratch array.
+hipError_t launch_synthesis(const Plan& p, const Workspace& ws, const void* coeffs, hipStream_t s);
+hipError_t launch_loss(const Plan& p, const Workspace& ws, hipStream_t s);
+hipError_t launch_gain(const Plan& p, const Workspace& ws, hipStream_t s);
+hipError_t launch_combine(const Plan& p, const Workspace& ws, void* q, void* qplus, hipStream_t s);
 // the dense stages for nb cells of one plan's size (batches)
 hipError_t launch_dense_synthesis(const Plan& p, const double* c64, int nb, const DenseBufs& b,
                                   hipStream_t s);

@@ -1035,18 +1035,18 @@ __global__ void rk_finish_kernel(double* __restrict__ base, const T* __restrict_
 
 inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
-DenseBufs plan_bufs(const Plan& p)
+DenseBufs plan_bufs(const Workspace& ws)
 {
     DenseBufs b;
-    b.P = p.ws.P;
-    b.G = p.ws.G;
-    b.Gg = p.ws.Gg;
-    b.H = p.ws.H;
-    b.qminus = p.ws.qminus;
-    b.qplus = p.ws.qplus;
-    b.tmpA = p.ws.tmpA;
-    b.tmpB = p.ws.tmpB;
-    b.red = p.ws.red;
+    b.P = ws.P;
+    b.G = ws.G;
+    b.Gg = ws.Gg;
+    b.H = ws.H;
+    b.qminus = ws.qminus;
+    b.qplus = ws.qplus;
+    b.tmpA = ws.tmpA;
+    b.tmpB = ws.tmpB;
+    b.red = ws.red;
     return b;
 }
 
@@ -1067,15 +1067,15 @@ hipError_t dense_synthesis_t(const Plan& p, const double* c64, int nb, const Den
 }
 
 template <typename T>
-hipError_t synthesis_t(const Plan& p, const void* coeffs, hipStream_t s)
+hipError_t synthesis_t(const Plan& p, const Workspace& ws, const void* coeffs, hipStream_t s)
 {
     const double* c64 = static_cast<const double*>(coeffs);
     if (p.precision != PGC_PRECISION_FP64) {
         hipLaunchKernelGGL(widen<T>, dim3(blocks_for(p.Nd, 256)), dim3(256), 0, s,
-                           static_cast<const T*>(coeffs), p.ws.cin, p.Nd);
-        c64 = p.ws.cin;
+                           static_cast<const T*>(coeffs), ws.cin, p.Nd);
+        c64 = ws.cin;
     }
-    DenseBufs b = plan_bufs(p);
+    DenseBufs b = plan_bufs(ws);
     if (p.precision == PGC_PRECISION_FP64) b.Gg = nullptr;  // G itself is read by the gain
     return dense_synthesis_t<T>(p, c64, 1, b, s);
 }
@@ -1143,12 +1143,12 @@ hipError_t spread_dispatch(const Plan& p, const GainParams<T>& gp, hipStream_t s
 }
 
 template <typename T>
-GainParams<T> gain_params(const Plan& p)
+GainParams<T> gain_params(const Plan& p, const Workspace& ws)
 {
     GainParams<T> gp;
     gp.v1 = static_cast<const T*>(p.dt.v1);
-    gp.G = static_cast<const T*>(p.ws.Gg);
-    gp.sym = static_cast<const T*>(p.ws.sym);
+    gp.G = static_cast<const T*>(ws.Gg);
+    gp.sym = static_cast<const T*>(ws.sym);
     gp.pair_a = p.dt.pair_a;
     gp.pair_b = p.dt.pair_b;
     gp.pair_base = p.dt.pair_base;
@@ -1157,7 +1157,7 @@ GainParams<T> gain_params(const Plan& p)
     gp.poly = static_cast<const T*>(p.dt.poly);
     gp.slab_vlo = static_cast<const T*>(p.dt.slab_vlo);
     gp.slab_vhi = static_cast<const T*>(p.dt.slab_vhi);
-    gp.partial = static_cast<double*>(p.ws.partial);
+    gp.partial = static_cast<double*>(ws.partial);
     gp.S = (T)p.S;
     gp.inv_S = (T)(1.0 / p.S);
     gp.inv_S64 = 1.0 / p.S;
@@ -1239,7 +1239,7 @@ template <typename T>
 hipError_t bin_build_t(const Plan& p, unsigned int* count, unsigned long long* cursor,
                        unsigned long long* ids, int mode, hipStream_t s)
 {
-    const GainParams<T> gp = gain_params<T>(p);
+    const GainParams<T> gp = gain_params<T>(p, p.ws);
     BinGeo bg;
     bg.nb = p.bins.nb;
     bg.off = p.bins.off;
@@ -1263,7 +1263,7 @@ hipError_t bin_build_t(const Plan& p, unsigned int* count, unsigned long long* c
 }
 
 template <typename T>
-hipError_t gain_t(const Plan& p, hipStream_t s)
+hipError_t gain_t(const Plan& p, const Workspace& ws, hipStream_t s)
 {
     prof_mark(p, 2, s);
     const int64_t n_sym = p.dim == 2 ? (int64_t)p.np * p.np : (int64_t)p.np * p.np * p.np;
@@ -1271,25 +1271,25 @@ hipError_t gain_t(const Plan& p, hipStream_t s)
         // the binned scheme forms each orbit sum from G where it is used
     } else if (p.dim == 2)
         hipLaunchKernelGGL((pair_orbit_sums<T, 2>), dim3(blocks_for(n_sym, 256)), dim3(256), 0, s,
-                           static_cast<const T*>(p.ws.Gg), static_cast<T*>(p.ws.sym), p.dt.pair_a,
+                           static_cast<const T*>(ws.Gg), static_cast<T*>(ws.sym), p.dt.pair_a,
                            p.dt.pair_b, p.ni, p.np, n_sym);
     else
         hipLaunchKernelGGL((pair_orbit_sums<T, 3>), dim3(blocks_for(n_sym, 256)), dim3(256), 0, s,
-                           static_cast<const T*>(p.ws.Gg), static_cast<T*>(p.ws.sym), p.dt.pair_a,
+                           static_cast<const T*>(ws.Gg), static_cast<T*>(ws.sym), p.dt.pair_a,
                            p.dt.pair_b, p.ni, p.np, n_sym);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
 
-    const GainParams<T> gp = gain_params<T>(p);
+    const GainParams<T> gp = gain_params<T>(p, ws);
     prof_mark(p, 3, s);
     if (p.gain_mode == kGainBinned) {
-        hipLaunchKernelGGL(fill_zero, dim3(blocks_for(p.ngd, 256)), dim3(256), 0, s, p.ws.grid64, p.ngd);
+        hipLaunchKernelGGL(fill_zero, dim3(blocks_for(p.ngd, 256)), dim3(256), 0, s, ws.grid64, p.ngd);
         BinItems bi;
         bi.bin = p.bins.item_bin;
         bi.begin = p.bins.item_begin;
         bi.count = p.bins.item_count;
         bi.ids = p.bins.ids;
-        bi.grid = p.ws.grid64;
+        bi.grid = ws.grid64;
         bi.geo.nb = p.bins.nb;
         bi.geo.off = p.bins.off;
         bi.geo.W = p.W;
@@ -1302,25 +1302,25 @@ hipError_t gain_t(const Plan& p, hipStream_t s)
         }
         if (e != hipSuccess) return e;
         prof_mark(p, 4, s);
-        e = separable(p, p.ws.grid64, p.ws.qplus, p.dt.E, p.N, p.ng, 1, p.ws.tmpA, p.ws.tmpB, s);
+        e = separable(p, ws.grid64, ws.qplus, p.dt.E, p.N, p.ng, 1, ws.tmpA, ws.tmpB, s);
     } else {
         e = (p.dim == 2) ? spread_dispatch<T, 2>(p, gp, s) : spread_dispatch<T, 3>(p, gp, s);
         if (e != hipSuccess) return e;
         prof_mark(p, 4, s);
         hipLaunchKernelGGL(reduce_partials, dim3(blocks_for(p.ngd, 256)), dim3(256), 0, s,
-                           static_cast<const double*>(p.ws.partial), p.ws.grid, p.ngd, p.n_chunks);
+                           static_cast<const double*>(ws.partial), ws.grid, p.ngd, p.n_chunks);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = separable(p, p.ws.grid, p.ws.qplus, p.dt.E, p.N, p.ng, 1, p.ws.tmpA, p.ws.tmpB, s);
+        e = separable(p, ws.grid, ws.qplus, p.dt.E, p.N, p.ng, 1, ws.tmpA, ws.tmpB, s);
     }
     return e;
 }
 
 template <typename T>
-hipError_t combine_t(const Plan& p, void* q, void* qplus, hipStream_t s)
+hipError_t combine_t(const Plan& p, const Workspace& ws, void* q, void* qplus, hipStream_t s)
 {
-    hipLaunchKernelGGL(combine_kernel<T>, dim3(blocks_for(p.Nd, 256)), dim3(256), 0, s, p.ws.qplus,
-                       p.ws.qminus, static_cast<T*>(q), static_cast<T*>(qplus), p.Nd);
+    hipLaunchKernelGGL(combine_kernel<T>, dim3(blocks_for(p.Nd, 256)), dim3(256), 0, s, ws.qplus,
+                       ws.qminus, static_cast<T*>(q), static_cast<T*>(qplus), p.Nd);
     return hipGetLastError();
 }
 
@@ -1346,13 +1346,16 @@ hipError_t project_t(const Plan& p, const double* f, void* coeffs, hipStream_t s
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_synthesis(const Plan& p, const void* coeffs, hipStream_t s)
+hipError_t launch_synthesis(const Plan& p, const Workspace& ws, const void* coeffs, hipStream_t s)
 {
-    return p.precision == PGC_PRECISION_FP64 ? synthesis_t<double>(p, coeffs, s)
-                                             : synthesis_t<float>(p, coeffs, s);
+    return p.precision == PGC_PRECISION_FP64 ? synthesis_t<double>(p, ws, coeffs, s)
+                                             : synthesis_t<float>(p, ws, coeffs, s);
 }
 
-hipError_t launch_loss(const Plan& p, hipStream_t s) { return dense_loss(p, 1, plan_bufs(p), s); }
+hipError_t launch_loss(const Plan& p, const Workspace& ws, hipStream_t s)
+{
+    return dense_loss(p, 1, plan_bufs(ws), s);
+}
 
 hipError_t launch_dense_synthesis(const Plan& p, const double* c64, int nb, const DenseBufs& b,
                                   hipStream_t s)
@@ -1372,9 +1375,9 @@ hipError_t launch_dense_grid_to_modes(const Plan& p, const double* grid, int nb,
     return separable(p, grid, b.qplus, p.dt.E, p.N, p.ng, nb, b.tmpA, b.tmpB, s);
 }
 
-hipError_t launch_gain(const Plan& p, hipStream_t s)
+hipError_t launch_gain(const Plan& p, const Workspace& ws, hipStream_t s)
 {
-    return p.precision == PGC_PRECISION_FP64 ? gain_t<double>(p, s) : gain_t<float>(p, s);
+    return p.precision == PGC_PRECISION_FP64 ? gain_t<double>(p, ws, s) : gain_t<float>(p, ws, s);
 }
 
 hipError_t launch_bin_build(const Plan& p, unsigned int* count, unsigned long long* cursor,
@@ -1384,10 +1387,10 @@ hipError_t launch_bin_build(const Plan& p, unsigned int* count, unsigned long lo
                                              : bin_build_t<float>(p, count, cursor, ids, mode, s);
 }
 
-hipError_t launch_combine(const Plan& p, void* q, void* qplus, hipStream_t s)
+hipError_t launch_combine(const Plan& p, const Workspace& ws, void* q, void* qplus, hipStream_t s)
 {
-    return p.precision == PGC_PRECISION_FP64 ? combine_t<double>(p, q, qplus, s)
-                                             : combine_t<float>(p, q, qplus, s);
+    return p.precision == PGC_PRECISION_FP64 ? combine_t<double>(p, ws, q, qplus, s)
+                                             : combine_t<float>(p, ws, q, qplus, s);
 }
 
 hipError_t launch_project(const Plan& p, const double* f_nodes, void* coeffs, hipStream_t s)

@@ -23,7 +23,8 @@ FP64, FP32 = 0, 1
 GAIN_AUTO, GAIN_SLAB, GAIN_BINNED, GAIN_MFMA = 0, 1, 2, 3
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported configuration", 3: "out of device memory",
-          4: "device error", 5: "non-finite result"}
+          4: "device error", 5: "non-finite result",
+          6: "the call needs more scratch memory than the static buffer holds"}
 
 
 class PgcError(RuntimeError):
@@ -127,6 +128,7 @@ def lib():
         L.pgc_nodes.argtypes = [vp, dp, dp, dp]
         L.pgc_project.argtypes = [vp, vp, vp, vp]
         L.pgc_coeffs_to_q.argtypes = [vp, vp, vp, vp, vp]
+        L.pgc_coeffs_to_q_static.argtypes = [vp, vp, vp, vp, vp]
         L.pgc_rk4.argtypes = [vp, vp, dbl, i32, vp]
         L.pgc_moments.argtypes = [vp, vp, vp, vp]
         L.pgc_eval.argtypes = [vp, vp, vp, i64, vp, vp]
@@ -173,7 +175,8 @@ def lib():
                      "pgc_surrogate_set_params", "pgc_surrogate_save", "pgc_surrogate_load", "pgc_gemm_bf16"):
             getattr(L, name).restype = ctypes.c_int
         for name in ("pgc_desc_init", "pgc_nufft_params", "pgc_plan_create", "pgc_plan_destroy",
-                     "pgc_plan_query", "pgc_nodes", "pgc_project", "pgc_coeffs_to_q", "pgc_rk4",
+                     "pgc_plan_query", "pgc_nodes", "pgc_project", "pgc_coeffs_to_q",
+                     "pgc_coeffs_to_q_static", "pgc_rk4",
                      "pgc_moments", "pgc_eval", "pgc_set_profiling", "pgc_stage_times",
                      "pgc_batch_create", "pgc_batch_destroy", "pgc_batch_query", "pgc_batch_offsets",
                      "pgc_batch_set_tile", "pgc_batch_set_order", "pgc_batch_autotune", "pgc_batch_coeffs_to_q",
@@ -307,6 +310,20 @@ class Plan:
             qplus = torch.empty_like(c)
         _check(lib().pgc_coeffs_to_q(self._h, _ptr(c), _ptr(q), _ptr(qplus) if qplus is not None else None,
                                      _stream()), "pgc_coeffs_to_q")
+        return (q, qplus) if want_qplus else q
+
+    def coeffs_to_q_static(self, coeffs, q=None, qplus=None, want_qplus=False):
+        """pgc_coeffs_to_q_static: the same evaluation with the library's static
+        scratch array in place of the plan's per-call buffers."""
+        torch = self._torch
+        c = self._coeffs(coeffs)
+        if q is None:
+            q = torch.empty_like(c)
+        if want_qplus and qplus is None:
+            qplus = torch.empty_like(c)
+        _check(lib().pgc_coeffs_to_q_static(self._h, _ptr(c), _ptr(q),
+                                            _ptr(qplus) if qplus is not None else None, _stream()),
+               "pgc_coeffs_to_q_static")
         return (q, qplus) if want_qplus else q
 
     def rk4(self, coeffs, dt, n_steps):

@@ -61,6 +61,8 @@ def test_null_plan_is_rejected_without_a_device():
     assert L.pgc_plan_destroy(None) == 0
     assert L.pgc_plan_query(None, None) == 1
     assert L.pgc_coeffs_to_q(None, None, None, None, None) == 1
+    assert L.pgc_coeffs_to_q_static(None, None, None, None, None) == 1
+    assert L.pgc_status_string(6).startswith(b"the call needs more scratch")
     assert L.pgc_rk4(None, None, 0.1, 1, None) == 1
     out = ctypes.c_void_p()
     assert L.pgc_plan_create(None, None, ctypes.byref(out)) == 1
