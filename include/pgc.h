@@ -463,15 +463,17 @@ pgc_status pgc_direct_destroy(pgc_direct d);
 pgc_status pgc_direct_query(pgc_direct d, pgc_direct_info* info);
 /* q_dev[c][k] = Q_k of the coefficients coeffs_dev[c][k] (FP64, row-major
  * k_d fastest, n_cells x N^d each), max_cells at a time; stream-ordered.
- * The library allocates nothing here; the product runs through rocBLAS on
- * `stream`, which keeps its own workspace on the object's handle and may grow
- * it the first time a product of a new shape runs. */
+ * The library allocates nothing here: the product is the library's own FP64
+ * matrix-core kernel, whose split-K partial tiles live in the object's
+ * workspace (sized at creation for every chunk up to max_cells); its
+ * summation order is fixed, so a result repeats bit for bit. */
 pgc_status pgc_direct_coeffs_to_q(pgc_direct d, const double* coeffs_dev, int64_t n_cells, double* q_dev,
                                   void* stream);
 /* Record pgc_direct_coeffs_to_q for these pointers and n_cells into a HIP
  * graph owned by the object (replacing any earlier one).  One eager
- * evaluation runs first on `stream` (it writes q_dev and lets rocBLAS size its
- * workspace for these shapes), then the capture, on a private stream.
+ * evaluation runs first on `stream` (it writes q_dev), then the capture, on a
+ * private stream.  Eager calls of any size may run between replays: the graph
+ * and they share only the object's fixed workspace, used in stream order.
  * pgc_direct_graph_launch replays it on `stream` (INVALID_ARG without a
  * graph).  The graph reads the captured pointers: refill the same input
  * buffer between replays. */

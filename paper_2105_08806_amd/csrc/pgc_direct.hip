@@ -22,11 +22,15 @@
 // and Q_k = sum_p G_a G_b K[p][k], which is the quadrature of eqs. Qplus and
 // Qminus on the CGL nodes with the sphere rule, the same discrete sum the fast
 // algorithm approximates, without its transform tolerance.
+//
+// The product Q[c][k] = sum_p X[c][p] K[p][k] (X the pair products of the
+// cells) is a plain FP64 GEMM; it runs on a hand-written matrix-core kernel
+// (dgemm_tile below) with a fixed summation order, so results repeat bit for
+// bit.
 #include "pgc.h"
 #include "pgc_internal.h"
 
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -205,6 +209,205 @@ __global__ void __launch_bounds__(256)
         }
 }
 
+// ----------------------------------------------------------------- FP64 GEMM
+//
+// C[m][n] = sum_k A[m][k] B[k][n] for row-major A (M x K, row stride lda),
+// B (K x N, ldb) and C (M x N, ldc) on v_mfma_f64_16x16x4f64.  A workgroup of
+// four waves owns a 128 x 128 tile of C (each wave a 64 x 64 quarter, 4 x 4
+// instruction tiles of 16 x 16 held in 16 accumulators) and walks its share of
+// K in chunks of 16: the chunk's 128 x 16 slice of A and 16 x 128 slice of B
+// are staged in LDS (A transposed, so both operand fragments are 16
+// consecutive doubles per k row), double buffered, the next chunk's global
+// loads in flight while the matrix cores work on the current one.  Long K is
+// split over `splits` workgroups per tile when the tiles alone do not fill the
+// chip; each split writes its own partial tile and dgemm_reduce adds them in
+// split order, so the sum order is fixed.  Workgroups are numbered so that the
+// ones on one XCD (consecutive ids go round-robin over the 8 XCDs) share A row
+// blocks, which then come from that XCD's L2.
+constexpr int kGT = 128;          // tile rows and columns
+constexpr int kGK = 16;           // K chunk
+constexpr int kGS = kGT + 16;     // LDS row stride in doubles (shifts the four k rows of a fragment by 128 B)
+constexpr int kGThreads = 256;
+
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+struct GemmArgs {
+    const double* A;
+    const double* B;
+    double* C;        // splits == 1: the output; otherwise the partial tiles [split][M][N]
+    int64_t lda, ldb, ldc;
+    int M, N;
+    int64_t K;
+    int mt, nt, splits;
+    int64_t kspan;    // K per split, a multiple of kGK
+};
+
+__device__ __forceinline__ void gemm_load(const GemmArgs& g, int m0, int n0, int64_t k0, int64_t k1, double ra[8],
+                                          double rb[8])
+{
+    const int t = threadIdx.x;
+    // A: row t/2 of the tile, 8 consecutive k
+    {
+        const int m = m0 + (t >> 1);
+        const int64_t kb = k0 + (t & 1) * 8;
+        const double* src = g.A + (int64_t)m * g.lda + kb;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) ra[j] = (m < g.M && kb + j < k1) ? src[j] : 0.0;
+    }
+    // B: k row t/16 of the chunk, 8 consecutive columns
+    {
+        const int64_t k = k0 + (t >> 4);
+        const int n = n0 + (t & 15) * 8;
+        const double* src = g.B + k * g.ldb + n;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) rb[j] = (k < k1 && n + j < g.N) ? src[j] : 0.0;
+    }
+}
+
+__device__ __forceinline__ void gemm_stage(double* As, double* Bs, const double ra[8], const double rb[8])
+{
+    const int t = threadIdx.x;
+    const int m = t >> 1, kb = (t & 1) * 8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) As[(kb + j) * kGS + m] = ra[j];
+    const int k = t >> 4, n = (t & 15) * 8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Bs[k * kGS + n + j] = rb[j];
+}
+
+__global__ void __launch_bounds__(kGThreads, 2) dgemm_tile(GemmArgs g)
+{
+    __shared__ __align__(16) double As[2][kGK * kGS];
+    __shared__ __align__(16) double Bs[2][kGK * kGS];
+
+    // logical tile order: split, then tile row, then tile column (fastest);
+    // XCD x takes the x-th contiguous eighth of it when the count allows
+    const int total = g.mt * g.nt * g.splits;
+    int L = blockIdx.x;
+    if ((total & 7) == 0) L = (blockIdx.x & 7) * (total >> 3) + (blockIdx.x >> 3);
+    const int ni = L % g.nt;
+    const int mi = (L / g.nt) % g.mt;
+    const int sp = L / (g.nt * g.mt);
+    const int m0 = mi * kGT, n0 = ni * kGT;
+    const int64_t kbeg = (int64_t)sp * g.kspan;
+    const int64_t kend = min(g.K, kbeg + g.kspan);
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int i16 = lane & 15, k4 = lane >> 4;
+
+    dvec4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = dvec4{0.0, 0.0, 0.0, 0.0};
+
+    double ra[8], rb[8];
+    int cur = 0;
+    if (kbeg < kend) {
+        gemm_load(g, m0, n0, kbeg, kend, ra, rb);
+        gemm_stage(As[0], Bs[0], ra, rb);
+    }
+    __syncthreads();
+    for (int64_t k0 = kbeg; k0 < kend; k0 += kGK) {
+        const bool more = k0 + kGK < kend;
+        if (more) gemm_load(g, m0, n0, k0 + kGK, kend, ra, rb);
+        const double* as = As[cur];
+        const double* bs = Bs[cur];
+#pragma unroll
+        for (int ks = 0; ks < kGK / 4; ++ks) {
+            const int kr = (4 * ks + k4) * kGS;
+            double af[4], bf[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) af[i] = as[kr + wm + 16 * i + i16];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bf[j] = bs[kr + wn + 16 * j + i16];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        if (more) gemm_stage(As[cur ^ 1], Bs[cur ^ 1], ra, rb);
+        __syncthreads();
+        cur ^= 1;
+    }
+
+    // lane l holds rows l/16 + 4 r of column l % 16 of each 16 x 16 tile
+    double* out = g.C + (g.splits > 1 ? (int64_t)sp * g.M * (int64_t)g.N : 0);
+    const int64_t ldo = g.splits > 1 ? (int64_t)g.N : g.ldc;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = n0 + wn + 16 * j + i16;
+            if (n >= g.N) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + 16 * i + k4 + 4 * r;
+                if (m < g.M) out[(int64_t)m * ldo + n] = acc[i][j][r];
+            }
+        }
+}
+
+// C[m][n] = sum over splits, in split order, of the partial tiles
+__global__ void dgemm_reduce(const double* __restrict__ part, int splits, int M, int N, double* __restrict__ C,
+                             int64_t ldc)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t mn = (int64_t)M * N;
+    if (i >= mn) return;
+    double s = 0.0;
+    for (int p = 0; p < splits; ++p) s += part[(int64_t)p * mn + i];
+    C[(i / N) * ldc + i % N] = s;
+}
+
+// How many K splits a product of this shape takes: enough workgroups for two
+// per CU on the 256 CUs, each split at least 16 chunks long.
+int gemm_splits(int M, int N, int64_t K)
+{
+    const int64_t tiles = (int64_t)((M + kGT - 1) / kGT) * ((N + kGT - 1) / kGT);
+    const int64_t chunks = (K + kGK - 1) / kGK;
+    int64_t s = (512 + tiles - 1) / tiles;
+    s = std::min<int64_t>(s, std::max<int64_t>(1, chunks / 16));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
+}
+
+// Elements of the partial-tile buffer a product of this shape needs (0 when unsplit).
+int64_t gemm_partial_elems(int M, int N, int64_t K)
+{
+    const int s = gemm_splits(M, N, K);
+    return s > 1 ? (int64_t)s * M * N : 0;
+}
+
+hipError_t gemm_launch(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc, int M,
+                       int N, int64_t K, double* partial, hipStream_t s)
+{
+    if (M <= 0 || N <= 0) return hipSuccess;
+    GemmArgs g;
+    g.A = A;
+    g.B = B;
+    g.lda = lda;
+    g.ldb = ldb;
+    g.ldc = ldc;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.mt = (M + kGT - 1) / kGT;
+    g.nt = (N + kGT - 1) / kGT;
+    g.splits = gemm_splits(M, N, K);
+    const int64_t chunks = (K + kGK - 1) / kGK;
+    g.kspan = (chunks + g.splits - 1) / g.splits * kGK;
+    g.C = g.splits > 1 ? partial : C;
+    const int64_t blocks = (int64_t)g.mt * g.nt * g.splits;
+    hipLaunchKernelGGL(dgemm_tile, dim3((unsigned)blocks), dim3(kGThreads), 0, s, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || g.splits == 1) return e;
+    const int64_t mn = (int64_t)M * N;
+    hipLaunchKernelGGL(dgemm_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, partial, g.splits, M, N,
+                       C, ldc);
+    return hipGetLastError();
+}
+
 // RK4 stages over the cells of one chunk: y = base + a k, and the final update
 __global__ void rk_axpy(const double* __restrict__ base, const double* __restrict__ k, double a,
                         double* __restrict__ y, int64_t n)
@@ -235,7 +438,7 @@ struct pgc_direct_s {
     pgc::DenseBufs bufs;      // synthesis of max_cells cells
     double* rk_y = nullptr;   // RK4 stage state and slopes, max_cells x N^d each
     double* rk_k[4] = {nullptr, nullptr, nullptr, nullptr};
-    rocblas_handle blas = nullptr;
+    double* partial = nullptr;        // split-K partial tiles of the product
     hipGraph_t graph = nullptr;       // a captured evaluation (pgc_direct_capture)
     hipGraphExec_t exec = nullptr;
     double setup_ms = 0.0;
@@ -288,13 +491,8 @@ pgc_status direct_chunk(pgc_direct_s& d, const double* c, int nc, double* q, hip
                                                 (unsigned)((nc + pgc::kPairCells - 1) / pgc::kPairCells)),
                        dim3(256), 0, s, d.bufs.G, d.pa, d.pb, d.n_pairs, d.ldx, d.nid, nc, d.X);
     if ((e = hipGetLastError()) != hipSuccess) return pgc::status_of(e);
-    // column major: Q^T (N^d x nc) = K^T (N^d x n_pairs) X^T (n_pairs x nc, leading dimension ldx)
-    const double one = 1.0, zero = 0.0;
-    if (rocblas_dgemm(d.blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)d.Nd, nc,
-                      (rocblas_int)d.n_pairs, &one, d.K, (rocblas_int)d.Nd, d.X, (rocblas_int)d.ldx, &zero, q,
-                      (rocblas_int)d.Nd) != rocblas_status_success)
-        return PGC_ERR_DEVICE;
-    return PGC_OK;
+    // Q (nc x N^d) = X (nc x n_pairs, row stride ldx) K (n_pairs x N^d)
+    return pgc::status_of(pgc::gemm_launch(d.X, d.ldx, d.K, d.Nd, q, d.Nd, nc, (int)d.Nd, d.n_pairs, d.partial, s));
 }
 
 void d_free(pgc_direct_s* d)
@@ -303,7 +501,6 @@ void d_free(pgc_direct_s* d)
     (void)hipDeviceSynchronize();
     if (d->exec) (void)hipGraphExecDestroy(d->exec);
     if (d->graph) (void)hipGraphDestroy(d->graph);
-    if (d->blas) (void)rocblas_destroy_handle(d->blas);
     for (void* p : d->allocations) (void)hipFree(p);
     delete d;
 }
@@ -390,7 +587,13 @@ pgc_status pgc_direct_create(pgc_plan plan, int32_t max_cells, void* stream, pgc
                 if (e1) (void)hipEventDestroy(e1);
             }
         }
-        if (e == hipSuccess && rocblas_create_handle(&d->blas) != rocblas_status_success) st = PGC_ERR_DEVICE;
+        if (e == hipSuccess) {
+            // split-K partial tiles: the largest any chunk size up to max_cells needs
+            int64_t part = 0;
+            for (int nc = 1; nc <= max_cells; ++nc)
+                part = std::max(part, pgc::gemm_partial_elems(nc, (int)Nd, n_pairs));
+            if (part > 0) e = d_alloc_n(*d, &d->partial, part);
+        }
     } catch (...) {
         st = PGC_ERR_OUT_OF_MEMORY;
     }
@@ -428,7 +631,6 @@ pgc_status pgc_direct_coeffs_to_q(pgc_direct d, const double* coeffs_dev, int64_
 {
     if (!d || n_cells < 0 || (n_cells > 0 && (!coeffs_dev || !q_dev))) return PGC_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (n_cells > 0 && rocblas_set_stream(d->blas, s) != rocblas_status_success) return PGC_ERR_DEVICE;
     for (int64_t c0 = 0; c0 < n_cells; c0 += d->max_cells) {
         const int nc = (int)std::min<int64_t>(d->max_cells, n_cells - c0);
         const pgc_status st = direct_chunk(*d, coeffs_dev + c0 * d->Nd, nc, q_dev + c0 * d->Nd, s);
@@ -444,8 +646,7 @@ pgc_status pgc_direct_capture(pgc_direct d, const double* coeffs_dev, int64_t n_
     if (d->graph) (void)hipGraphDestroy(d->graph);
     d->exec = nullptr;
     d->graph = nullptr;
-    // one eager evaluation first: rocBLAS sizes its workspace for these shapes
-    // outside the capture
+    // one eager evaluation first (it also writes q_dev)
     pgc_status st = pgc_direct_coeffs_to_q(d, coeffs_dev, n_cells, q_dev, stream);
     if (st != PGC_OK) return st;
     hipStream_t user = static_cast<hipStream_t>(stream);
@@ -482,7 +683,6 @@ pgc_status pgc_direct_rk4(pgc_direct d, double* coeffs_dev, int64_t n_cells, dou
     if (!d || n_cells < 0 || n_steps < 0 || !std::isfinite(dt) || (n_cells > 0 && !coeffs_dev))
         return PGC_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (n_cells > 0 && rocblas_set_stream(d->blas, s) != rocblas_status_success) return PGC_ERR_DEVICE;
     const double a[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
     // cells are independent: each chunk takes all its steps in turn
     for (int64_t c0 = 0; c0 < n_cells; c0 += d->max_cells) {

@@ -342,3 +342,51 @@ def test_direct_graph_replays(torch_cuda):
         assert diff <= 1e-14
     d.close()
     plan.close()
+
+
+@pytest.mark.parametrize("N,n_cells,max_cells", [(20, 37, 37), (8, 300, 300), (8, 300, 128)])
+def test_direct_product_ragged_tiles(torch_cuda, N, n_cells, max_cells):
+    """The library's FP64 matrix-core product at shapes that leave partial
+    tiles everywhere: N^2 = 400 columns (three full 128-column tiles and 16),
+    37 or 300 rows (one or three row tiles, the last partial), n_pairs = 65341
+    or 1225 (K not a multiple of the 16-long chunks), and the split-K partial
+    sums the small products use.  Sampled cells against the oracle."""
+    torch = torch_cuda
+    ora, plan = make_pair(2, N, 3.0, 0, "vhs", 1.0, n_sigma=8)
+    cells = [I.random_coeffs((N, N), seed=900 + c) for c in range(n_cells)]
+    say("case: direct product N=%d, %d cells in products of %d" % (N, n_cells, max_cells))
+    q, info = direct_q(torch, plan, cells, max_cells=max_cells)
+    worst = 0.0
+    for c in sorted({0, 1, n_cells // 2, 127 % n_cells, 128 % n_cells, n_cells - 1}):
+        q_ref, _, _ = ora.collision(cells[c])
+        r = rel_l2(q[c].reshape(N, N), q_ref)
+        worst = max(worst, r)
+        assert r <= FP64_TOL, (c, r)
+    say("  worst sampled cell rel-L2 vs oracle %.3e" % worst)
+    plan.close()
+
+
+def test_direct_graph_survives_eager_calls_of_other_sizes(torch_cuda):
+    """A graph captured for 200 cells (two products: one full 128-row tile
+    pair and a ragged one) is replayed after eager calls of 3 and 150 cells on
+    the same object: the replay still equals its own eager result bit for bit
+    (the product's workspace is sized at creation and never regrown)."""
+    torch = torch_cuda
+    from paper_2105_08806_amd import pgc
+    _, plan = make_pair(2, 8, 3.0, 0, "maxwell", n_sigma=8)
+    d = pgc.Direct(plan, max_cells=160)
+    c = torch.tensor(np.stack([I.random_coeffs((8, 8), seed=1100 + i) for i in range(200)]), device="cuda")
+    q = torch.empty_like(c)
+    say("case: direct graph, then eager calls of other sizes")
+    d.capture(c, q)
+    ref = d.coeffs_to_q(c.clone()).clone()
+    for n in (3, 150):
+        other = torch.tensor(np.stack([I.random_coeffs((8, 8), seed=1400 + i) for i in range(n)]), device="cuda")
+        d.coeffs_to_q(other)
+    q.zero_()
+    torch.cuda.synchronize()
+    d.graph_launch()
+    torch.cuda.synchronize()
+    assert torch.equal(q, ref)
+    d.close()
+    plan.close()
