@@ -1,18 +1,22 @@
 """GPU checks at the full sizes of the benchmark configurations.
 
-The oracle cannot afford full evaluations here (2D N=64 VHS costs 2e12
-multiply-adds, 3D N=32 about 2e15), so these tests compare sampled outputs the
-oracle computes one by one, use a direction subset of the full 3D geometry, and
-check properties that hold at any size.  Bars: FP64 1e-11, FP32 1e-5 (relative
+Full oracle evaluations at these sizes take the CPU minutes to hours (2D N=64
+VHS costs 2e12 multiply-adds, 3D N=32 about 2e15), so they are stored once
+under tests/golden/ by tests/golden/make_golden.py, which calls only the
+oracle; the tests also compare sampled outputs the oracle computes one by one
+on a direction subset of the full 3D geometry, and check properties that hold
+at any size.  Bars: FP64 1e-11, FP32 1e-5 (relative
 L2 over the sampled coefficients).
 """
+import hashlib
+import os
 import sys
 
 import numpy as np
 import pytest
 
 import oracle as O
-from closed_forms import c_k
+from closed_forms import GOLDEN, c_k
 from paper_2105_08806_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -42,10 +46,33 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def load_c2_golden():
+    """The stored oracle values of the 2D VHS workload (tests/golden/c2_vhs2d_n64.txt,
+    written by tests/golden/make_golden.py from the oracle alone): per
+    coefficient (k1, k2), Q and Q+ for the FP64 input and for the input
+    rounded to FP32, and the input digests."""
+    path = os.path.join(GOLDEN, "c2_vhs2d_n64.txt")
+    digests = None
+    for line in open(path):
+        if line.startswith("# input sha256"):
+            parts = line.split()
+            digests = (parts[4], parts[6])
+            break
+    rows = np.loadtxt(path, comments="#")
+    N = 64
+    cols = [rows[:, 2 + j].reshape(N, N) for j in range(4)]
+    return digests, cols
+
+
+def digest(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=np.float64).tobytes()).hexdigest()[:16]
+
+
 @pytest.mark.parametrize("prec", [0, 1])
-def test_2d_n64_vhs_sampled(torch_cuda, prec):
-    """The 2D VHS workload: 64 modes, S=6, VHS gamma=1, 32 directions, two
-    Maxwellians at +-(1.5, 0) with seeded temperatures."""
+def test_2d_n64_vhs_all_coefficients(torch_cuda, prec):
+    """The 2D VHS workload (64 modes, S=6, VHS gamma=1, 32 directions, two
+    Maxwellians at +-(1.5, 0) with seeded temperatures): all 4096 coefficients
+    of Q and Q+ against the stored oracle values, element by element."""
     torch = torch_cuda
     from paper_2105_08806_amd import pgc
     N, S, M = 64, 6.0, 32
@@ -53,19 +80,22 @@ def test_2d_n64_vhs_sampled(torch_cuda, prec):
     sg, sw = O.circle_rule(M)
     ora = O.Problem(2, N, S, 0, kernel="vhs", b0=b0, gamma=1.0, sphere=sg, sphere_w=sw)
     c = ora.project(I.mixture(ora.interior_velocities(), I.two_maxwellians_2d()))
+    cin = c.astype(np.float32).astype(np.float64) if prec else c
+    digests, cols = load_c2_golden()
+    q_ref, qp_ref = cols[2 * prec], cols[2 * prec + 1]
+    if digest(cin) != digests[prec]:
+        # a different libm can move the projected input by an ulp; the
+        # comparison below still holds to far below the bar
+        say("  note: input digest %s differs from the stored %s" % (digest(cin), digests[prec]))
     plan = pgc.Plan(dim=2, n_modes=N, scale=S, kernel=pgc.KERNEL_VHS, kernel_b0=b0, kernel_gamma=1.0,
                     n_sigma=M, precision=prec)
     say("2D N=64 VHS prec=%d: W=%d points=%d" % (prec, plan.info.kernel_width, plan.info.n_points))
-    cin = c.astype(np.float32).astype(np.float64) if prec else c
     q, qp = plan.coeffs_to_q(torch.tensor(cin, dtype=plan.dtype, device="cuda"), want_qplus=True)
     torch.cuda.synchronize()
     q, qp = q.double().cpu().numpy(), qp.double().cpu().numpy()
-    kidx = sample_indices(2, N, 3, 8)[::3]
-    ap, am = ora.collision_at(cin, kidx)
-    got_q = q[kidx[:, 0], kidx[:, 1]]
-    got_qp = qp[kidx[:, 0], kidx[:, 1]]
-    r_q, r_qp = rel(got_q, ap - am), rel(got_qp, ap)
-    say("  sampled rel-L2 Q = %.3e, Q+ = %.3e" % (r_q, r_qp))
+    r_q, r_qp = rel(q, q_ref), rel(qp, qp_ref)
+    elem = float(np.max(np.abs(q - q_ref)) / np.max(np.abs(q_ref)))
+    say("  all 4096 coefficients: rel-L2 Q = %.3e, Q+ = %.3e; max |dQ| / max |Q| = %.3e" % (r_q, r_qp, elem))
     bar = 1e-11 if prec == 0 else 1e-5
     assert r_q <= bar and r_qp <= bar
     # the data are even in v_2: odd k_2 coefficients vanish at any size, up to
