@@ -42,9 +42,10 @@
  *    work on a plan (pgc_project, pgc_coeffs_to_q, pgc_rk4, pgc_moments,
  *    pgc_eval) allocate nothing.
  *  - A plan must not be used by two calls that can run concurrently.
- *  - The fast path's gain accumulates with FP64 atomics whose order varies,
- *    so repeated evaluations agree to rounding, not bit for bit; the direct
- *    algorithm (pgc_direct_*) repeats bit for bit.
+ *  - By default the fast path's gain accumulates with FP64 atomics whose
+ *    order varies, so repeated evaluations agree to rounding, not bit for bit;
+ *    a plan created with deterministic = 1, and the direct algorithm
+ *    (pgc_direct_*), repeat bit for bit.
  *  - Every call returns a pgc_status.  On an error return the outputs are
  *    untouched (for argument errors) or unspecified (device errors).  No C++
  *    exception crosses this interface.  PGC_ERR_NUMERIC needs a result on the
@@ -91,8 +92,12 @@ typedef struct pgc_plan_desc {
     double scale;         /* > 0 */
     int32_t kernel;       /* PGC_KERNEL_MAXWELL (B = b0), PGC_KERNEL_VHS (B = b0 |u|^gamma) or
                              PGC_KERNEL_ANISO (B = b0 |u|^gamma (1 + kernel_aniso cos^2 theta),
-                             cos theta = u.sigma/|u|: an angle-dependent rate, evaluated by the
-                             direct algorithm only; the fast path returns UNSUPPORTED for it) */
+                             cos theta = u.sigma/|u|: an angle-dependent rate, the general
+                             B(|u|, cos theta) of Sec. 4.2).  ANISO runs on the binned fast path
+                             (gain_mode 0 or 2: each merged point weighs its orbit's triples by their
+                             own angle; the loss's inner integral over sigma is a quadratic form in u)
+                             and on the direct algorithm; gain_mode 1 and 3, and batches, return
+                             UNSUPPORTED for it */
     double kernel_b0;     /* kernel constant; 0 = 1/|S^{d-1}| (so that int B dsigma = 1 for Maxwell) */
     double kernel_gamma;  /* exponent of |u| in [0, 1] (VHS and ANISO) */
     int32_t sphere;       /* PGC_SPHERE_UNIFORM_2D (theta_s = 2 pi s/n_sigma, W_s = 2 pi/n_sigma),
@@ -122,6 +127,15 @@ typedef struct pgc_plan_desc {
     double kernel_aniso;  /* ANISO: beta in [-1, 10] (B >= 0); Q(f, f) sees only the part of B
                              even in cos theta, so an even polynomial is the general smooth
                              low-order angular law */
+    int32_t deterministic;/* 0: the binned gain adds each bin run's footprint tile into the fine
+                             grid with FP64 atomics (fastest; repeated evaluations agree to
+                             rounding).  1: every run writes its tile to plan workspace
+                             (n_bin_items x W^d doubles) and a gather adds the tiles of every grid
+                             cell in a fixed order, so repeated evaluations of the plan are
+                             bit-identical (another plan of the same descriptor agrees to rounding:
+                             the order of the points within a bin is set by the plan-time scatter).
+                             Needs the binned vector gain (gain_mode 0 or 2; UNSUPPORTED with 1
+                             or 3) */
 } pgc_plan_desc;
 
 typedef struct pgc_plan_s* pgc_plan;
@@ -145,6 +159,8 @@ typedef struct pgc_plan_info {
     double offset_fit_err;  /* largest deviation, over every grid cell, of the stored per-cell
                                polynomial that gives a point's kernel offset from w (binned
                                gain) from the exact offset, in units of the offset's range [-1, 1] */
+    int32_t deterministic;  /* 1: fixed-order tile gather (bit-identical repeats) */
+    int64_t tile_bytes;     /* deterministic plans: workspace of the per-run footprint tiles */
 } pgc_plan_info;
 
 /* Human-readable text of a status code (static storage, never NULL). */
@@ -207,9 +223,8 @@ pgc_status pgc_coeffs_to_q(pgc_plan plan, const void* coeffs_dev, void* q_dev, v
  * two threads -- race and must be serialised by the caller.  The array keeps
  * the last call's contents; the call clears what must start at zero itself.
  * Errors: INVALID_ARG (NULL arguments, or the current device is not the one
- * the plan was created on), UNSUPPORTED (PGC_KERNEL_ANISO, as for
- * pgc_coeffs_to_q), SCRATCH (the plan needs more than the array holds),
- * DEVICE. */
+ * the plan was created on), SCRATCH (the plan needs more than the array
+ * holds), DEVICE. */
 #define PGC_STATIC_SCRATCH_BYTES (32u * 1024u * 1024u)
 pgc_status pgc_coeffs_to_q_static(pgc_plan plan, const void* coeffs_dev, void* q_dev, void* qplus_dev,
                                   void* stream);
@@ -341,9 +356,12 @@ pgc_status pgc_batch_graph_launch(pgc_batch batch, void* stream);
  * raw network output, or the RMS z-score of the normalised input, exceeds
  * gate_raw_factor times the largest one seen on the training set (an input
  * unlike the training data; 0 disables).  Every
- * judge_stride-th sample of a call is also evaluated by the plan; if any of
- * them differs from the network by more than judge_tol (relative L2), every
- * sample of the call comes from the plan (0 disables the judge).
+ * judge_stride-th sample of a call is also evaluated by the plan and returns
+ * the plan's value; if the network's output for it differs from the plan's by
+ * more than judge_tol (relative L2), the judge_stride - 1 samples that follow
+ * it (its window, within the batch_max rows of one pass) fall back as well
+ * (0 disables the judge).  Fallback flags: 0 network, 1 plan (a gate or the
+ * judge's window), 2 judged (the plan's value, computed for the judge).
  *
  * Arrays: f and q are n_samples x N^d float rows (device).  The plan must
  * outlive the surrogate and must not be used concurrently with it.
@@ -403,9 +421,11 @@ pgc_status pgc_surrogate_train(pgc_surrogate s, const float* f_dev, const float*
                                int32_t epochs, int32_t batch, double lr, uint64_t seed, double* loss_host,
                                void* stream);
 /* Q of n_samples rows: q_dev receives the surrogate's Q, or the plan's for
- * the samples that fall back.  fallback_host (may be NULL) receives one flag
- * per sample, n_fallback the count, judge_err the largest relative error the
- * judge saw.  Synchronises `stream`. */
+ * the samples that fall back or are judged.  fallback_host (may be NULL)
+ * receives one flag per sample (0, 1 or 2 as above), n_fallback the count of
+ * flag-1 samples, judge_err the largest relative error the judge saw.  The
+ * gates are read on the host: the call synchronises `stream` once per pass of
+ * batch_max rows, then enqueues the fallbacks' plan evaluations. */
 pgc_status pgc_surrogate_coeffs_to_q(pgc_surrogate s, const float* f_dev, int64_t n_samples, float* q_dev,
                                      int32_t* fallback_host, int64_t* n_fallback, double* judge_err, void* stream);
 /* Loss and gradient (all parameters, in the get_params order without the
@@ -485,6 +505,50 @@ pgc_status pgc_direct_graph_launch(pgc_direct d, void* stream);
  * object.  Stream-ordered, like pgc_direct_coeffs_to_q. */
 pgc_status pgc_direct_rk4(pgc_direct d, double* coeffs_dev, int64_t n_cells, double dt, int32_t n_steps,
                           void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Spatial transport and the split step (Sec. 1: the full equation adds the
+ * free-streaming term v . grad_x f, and splitting treats transport and
+ * collisions separately).  One periodic space dimension x along the first
+ * velocity component, n_x (odd) equispaced cells on [0, length), every cell
+ * holding the N^d coefficients of one plan (FP64, cell-major:
+ * coeffs_dev[c * N^d + k]).  Testing f_t + v_1 f_x = 0 against T^_k gives
+ * d/dt f_k + sum_l V_kl d/dx f_l = 0 on the first coefficient index, with
+ * V_kl = (v_1 T~_l, T^_k), finite for the logarithmic map only: for the
+ * closed form and the method see the comment of pgc_transport.hip.  Each
+ * step moves the characteristic variables of V exactly over dt on the
+ * trigonometric interpolant of the cells.
+ * ------------------------------------------------------------------------- */
+typedef struct pgc_transport_s* pgc_transport;
+
+typedef struct pgc_transport_info {
+    int32_t n_x, dim, n_modes;
+    double length, dt;
+    double max_speed;         /* largest |eigenvalue| of V (the fastest characteristic) */
+    int64_t workspace_bytes;
+} pgc_transport_info;
+
+/* Build the transport over dt for the cells of `plan` (LOG map only:
+ * UNSUPPORTED otherwise); synchronises `stream`.  INVALID_ARG for n_x even or
+ * outside 1..4095, length <= 0, a non-finite dt.  The plan must outlive the
+ * object. */
+pgc_status pgc_transport_create(pgc_plan plan, int32_t n_x, double length, double dt, void* stream,
+                                pgc_transport* out);
+pgc_status pgc_transport_destroy(pgc_transport t);
+/* Resolved parameters; speeds_host (may be NULL) receives the N
+ * characteristic speeds (eigenvalues of V). */
+pgc_status pgc_transport_query(pgc_transport t, pgc_transport_info* info, double* speeds_host);
+/* One transport step over dt, in place on coeffs_dev (n_x x N^d FP64);
+ * stream-ordered, allocates nothing. */
+pgc_status pgc_transport_step(pgc_transport t, double* coeffs_dev, void* stream);
+/* n_steps Strang steps of the full equation: transport over dt/2, one
+ * classical RK4 step of d f/dt = Q(f) in every cell over dt, transport over
+ * dt/2, where `half` is a transport built with dt/2.  The collisions run
+ * through `direct` (all cells in one product per stage) when it is not NULL,
+ * else cell by cell through pgc_rk4 of `plan` (which must be half's plan).
+ * Stream-ordered; INVALID_ARG for mismatched objects. */
+pgc_status pgc_split_step(pgc_transport half, pgc_plan plan, pgc_direct direct, double* coeffs_dev,
+                          int32_t n_steps, void* stream);
 
 #ifdef __cplusplus
 }

@@ -37,8 +37,9 @@ struct GainParams {
     const T* slab_vhi;
     double* partial;    // n_chunks x n_g^d
     T S, inv_S, h_inv, b0, gamma;
+    T aniso;            // beta of the angle-dependent rate b0 |u|^gamma (1 + beta cos^2 theta)
     double inv_S64, h_inv64;  // 1/S and 1/h in FP64
-    int map, vhs, ni, np, ng, nh, slab_planes, n_sigma;
+    int map, vhs, ni, np, ng, nh, slab_planes, n_sigma;  // vhs: the rate carries |u|^gamma
     int64_t ngd, n_units, units_per_chunk;
 };
 
@@ -331,6 +332,45 @@ __device__ __forceinline__ T orbit_sum(const GainParams<T>& P, int a1, int b1, i
     T acc = P.G[ix[0]] * P.G[iy[0]];
 #pragma unroll
     for (int t = 1; t < NT; ++t) acc = fma(P.G[ix[t]], P.G[iy[t]], acc);
+    return c * acc;
+}
+
+// The orbit sum of an angle-dependent rate B = R(|u|) (1 + beta cos^2 theta),
+// cos theta = u.sigma_s / |u|.  The triples of one orbit share |u| but not the
+// angle: exchanging i_l and j_l flips u_l.  Term t of orbit_terms takes node a
+// of the first dimension for i and flips the dimensions where it takes b, so
+// its cos theta is sum_l eps_l e_l / |u| with e_l = (v_{a_l} - v_{b_l}) sigma_l;
+// the mirror triple (i and j exchanged) flips every sign and keeps cos^2, which
+// is what the multiplicity 2 of each term counts.  u = 0 gives cos theta = 0.
+template <typename T, int DIM>
+__device__ __forceinline__ T orbit_sum_aniso(const GainParams<T>& P, int s, int a1, int b1, int p2, int p3)
+{
+    constexpr int NT = 1 << (DIM - 1);
+    int ix[NT], iy[NT];
+    const T c = orbit_terms<T, DIM>(P, a1, b1, p2, p3, ix, iy);
+    T e[DIM], u2;
+    {
+        const T d1 = P.v1[a1] - P.v1[b1];
+        const T d2 = P.v1[P.pair_a[p2]] - P.v1[P.pair_b[p2]];
+        u2 = d1 * d1 + d2 * d2;
+        e[0] = d1 * P.sigma[s * DIM];
+        e[1] = d2 * P.sigma[s * DIM + 1];
+        if constexpr (DIM == 3) {
+            const T d3 = P.v1[P.pair_a[p3]] - P.v1[P.pair_b[p3]];
+            u2 += d3 * d3;
+            e[2] = d3 * P.sigma[s * DIM + 2];
+        }
+    }
+    const T k = u2 > (T)0 ? P.aniso / u2 : (T)0;
+    T acc = (T)0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        // 2D: t = 0 (+, +), 1 (+, -); 3D: t = 0 (+, +, +), 1 (+, +, -), 2 (+, -, +), 3 (+, -, -)
+        T proj = e[0];
+        if constexpr (DIM == 2) proj += (t & 1) ? -e[1] : e[1];
+        else proj += ((t & 2) ? -e[1] : e[1]) + ((t & 1) ? -e[2] : e[2]);
+        acc = fma(P.G[ix[t]] * P.G[iy[t]], fma(k * proj, proj, (T)1), acc);
+    }
     return c * acc;
 }
 

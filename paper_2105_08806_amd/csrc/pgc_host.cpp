@@ -157,6 +157,7 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
         d.block_threads != 1024)
         return PGC_ERR_INVALID_ARG;
     if (d.gain_mode < 0 || d.gain_mode > 3) return PGC_ERR_INVALID_ARG;
+    if (d.deterministic != 0 && d.deterministic != 1) return PGC_ERR_INVALID_ARG;
 
     p.dim = d.dim;
     p.N = d.n_modes;
@@ -253,9 +254,17 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
         p.gain_mode = kGainSlab;
     }
     // the matrix-core binned gain: FP64 3D plans with W <= 12
+    // an angle-dependent rate needs the per-direction orbit weights that only
+    // the binned vector kernel forms (the slab scheme reads direction-free
+    // orbit sums, the matrix-core variant has no such path)
+    if (p.kernel == PGC_KERNEL_ANISO && (p.gain_mode != kGainBinned || d.gain_mode == 3))
+        return PGC_ERR_UNSUPPORTED;
     p.mfma = d.gain_mode == 3;
     if (p.mfma && (p.precision != PGC_PRECISION_FP64 || p.dim != 3 || p.W < 4 || p.W > 12))
         return PGC_ERR_UNSUPPORTED;
+    // the fixed-order gather reads the tiles of the binned vector kernel
+    p.deterministic = d.deterministic == 1;
+    if (p.deterministic && (p.gain_mode != kGainBinned || p.mfma)) return PGC_ERR_UNSUPPORTED;
     p.auto_gain = d.gain_mode == 0;
     p.terms = poly_terms(p.W);
     p.beta = beta_for(p.W, p.upsample);
@@ -592,6 +601,15 @@ hipError_t build_bins(Plan& p, hipStream_t s)
     for (int64_t b = 0; b < nbins; ++b)
         for (unsigned int o = 0; o < hc[b]; o += kBinChunk)
             items.push_back({(int)b, (long long)(begin[b] + o), (int)std::min<unsigned int>(kBinChunk, hc[b] - o)});
+    std::vector<int> orig_bin, orig_count;  // the unsorted order (deterministic plans)
+    if (p.deterministic) {
+        orig_bin.resize(items.size());
+        orig_count.resize(items.size());
+        for (size_t k = 0; k < items.size(); ++k) {
+            orig_bin[k] = items[k].bin;
+            orig_count[k] = items[k].count;
+        }
+    }
     // full runs first: the long items start early and the short ones fill the tail
     std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.count > y.count; });
     B.n_items = (int64_t)items.size();
@@ -615,6 +633,40 @@ hipError_t build_bins(Plan& p, hipStream_t s)
         if ((e = hipMemcpyAsync(B.item_bin, ib.data(), ib.size() * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
         if ((e = hipMemcpyAsync(B.item_begin, ibeg.data(), ibeg.size() * sizeof(long long), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
         if ((e = hipMemcpyAsync(B.item_count, ic.data(), ic.size() * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+    }
+    if (p.deterministic) {
+        // runs of every bin in run order: before the sort the items are grouped
+        // by bin and ordered by run, so the sorted position of each original
+        // item, taken in original order, is the CSR list
+        std::vector<int> bptr(nbins + 1, 0), blist(items.size());
+        std::vector<int> pos(items.size());
+        {
+            std::vector<int> idx(items.size());
+            for (size_t k = 0; k < idx.size(); ++k) idx[k] = (int)k;
+            // the same stable order as the sort above, on the original indices
+            std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return orig_count[x] > orig_count[y]; });
+            for (size_t k = 0; k < idx.size(); ++k) pos[idx[k]] = (int)k;
+        }
+        for (size_t k = 0; k < orig_bin.size(); ++k) {
+            bptr[orig_bin[k] + 1] += 1;
+            blist[k] = pos[k];
+        }
+        for (int64_t b = 0; b < nbins; ++b) bptr[b + 1] += bptr[b];
+        int64_t cells = 1;
+        for (int l = 0; l < p.dim; ++l) cells *= p.W;
+        B.tile_bytes = (int64_t)items.size() * cells * (int64_t)sizeof(double);
+        if ((e = dev_alloc(p, &d, bptr.size() * sizeof(int))) != hipSuccess) return e;
+        B.bin_ptr = static_cast<int*>(d);
+        if ((e = dev_alloc(p, &d, std::max<size_t>(1, blist.size()) * sizeof(int))) != hipSuccess) return e;
+        B.bin_items = static_cast<int*>(d);
+        if ((e = dev_alloc(p, &d, std::max<int64_t>(8, B.tile_bytes))) != hipSuccess) return e;
+        B.tiles = static_cast<double*>(d);
+        if ((e = hipMemcpyAsync(B.bin_ptr, bptr.data(), bptr.size() * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess)
+            return e;
+        if (!blist.empty() &&
+            (e = hipMemcpyAsync(B.bin_items, blist.data(), blist.size() * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess)
+            return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;  // the host vectors go out of scope
     }
     if ((e = hipMalloc(&cursor, nbins * sizeof(unsigned long long))) != hipSuccess) return e;
     e = hipMemcpyAsync(cursor, begin.data(), nbins * sizeof(unsigned long long), hipMemcpyHostToDevice, s);
@@ -729,7 +781,7 @@ hipError_t allocate(Plan& p, hipStream_t s)
         PGC_TRY(dev_alloc(p, &g64, p.ngd * sizeof(double)));
         p.ws.grid64 = static_cast<double*>(g64);
         e = build_bins(p, s);
-        if (e == hipErrorOutOfMemory && p.auto_gain) {
+        if (e == hipErrorOutOfMemory && p.auto_gain && p.kernel != PGC_KERNEL_ANISO && !p.deterministic) {
             // the bin index does not fit: fall back to LDS slabs
             (void)hipGetLastError();
             p.gain_mode = kGainSlab;
@@ -863,6 +915,8 @@ pgc_status pgc_plan_query(pgc_plan plan, pgc_plan_info* info)
     info->gain_mode = p.mfma && p.gain_mode == pgc::kGainBinned ? 3 : p.gain_mode;
     info->n_bin_items = p.bins.n_items;
     info->offset_fit_err = p.cellfit_err;
+    info->deterministic = p.deterministic ? 1 : 0;
+    info->tile_bytes = p.bins.tile_bytes;
     info->workspace_bytes = p.workspace_bytes;
     return PGC_OK;
 }
@@ -906,8 +960,6 @@ pgc_status pgc_coeffs_to_q(pgc_plan plan, const void* coeffs, void* q, void* qpl
 {
     if (!plan || !coeffs || !q) return PGC_ERR_INVALID_ARG;
     Plan& p = plan->p;
-    // the merged point weights and the loss field assume a rate of |u| alone
-    if (p.kernel == PGC_KERNEL_ANISO) return PGC_ERR_UNSUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (p.prof) {
         pgc::Profiler& pr = *p.prof;
@@ -985,7 +1037,6 @@ pgc_status pgc_rk4(pgc_plan plan, double* coeffs, double dt, int32_t n_steps, vo
 {
     if (!plan || !coeffs || n_steps < 0 || !std::isfinite(dt)) return PGC_ERR_INVALID_ARG;
     const Plan& p = plan->p;
-    if (p.kernel == PGC_KERNEL_ANISO) return PGC_ERR_UNSUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const double a[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
     for (int st = 0; st < n_steps; ++st) {

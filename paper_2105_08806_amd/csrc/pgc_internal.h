@@ -63,6 +63,12 @@ struct BinIndex {
     long long* item_begin = nullptr;
     int* item_count = nullptr;
     unsigned long long* ids = nullptr;  // n_points packed point ids, grouped by bin
+    // deterministic plans: the runs of every bin in run order (CSR), and one
+    // W^d footprint tile per run
+    int* bin_ptr = nullptr;     // nbins + 1
+    int* bin_items = nullptr;   // n_items
+    double* tiles = nullptr;    // n_items x W^d
+    int64_t tile_bytes = 0;
 };
 constexpr int kBinChunk = 8192;
 constexpr int kMaxBinnedNodes = 256;        // n_i: 8-bit node fields of a point id
@@ -127,6 +133,7 @@ struct Plan {
     size_t elt = 8;
     int gain_mode = kGainBinned;
     bool mfma = false;         // binned gain on the FP64 matrix cores (FP64 3D plans)
+    bool deterministic = false;  // fixed-order tile gather instead of grid atomics
     bool auto_gain = true;
     Profiler* prof = nullptr;  // stage timing, off unless requested
     int prof_set = -1;         // event set of the call being recorded

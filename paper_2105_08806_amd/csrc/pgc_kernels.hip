@@ -154,8 +154,20 @@ __global__ void loss_h_maxwell(const double* __restrict__ P, double* __restrict_
     H[f] = w * (scale * red[f / nid]) * P[f];
 }
 
+// The angular factor of an angle-dependent rate in the loss.  With
+// B = b0 |u|^gamma (1 + beta cos^2 theta) the inner integral over the sphere
+// is sum_s W_s (1 + beta (u.sigma_s)^2 / |u|^2) = W (1 + u^T M u / |u|^2)
+// with W = sum_s W_s and M = (beta / W) sum_s W_s sigma_s sigma_s^T (a d x d
+// form, upper triangle m[0..5] = M11 M12 M13 M22 M23 M33; M22 = m[3] in 2D as
+// well), so the loss stays one sum over node pairs.  on = 0: no factor.
+struct AngleForm {
+    double m[6];
+    int on;
+};
+
 // VHS: A_i = (sum_s W_s) b0 sum_j G_j |v_i - v_j|^gamma, one thread per node i
-// of cell blockIdx.y, the j sweep staged through LDS in tiles.
+// of cell blockIdx.y, the j sweep staged through LDS in tiles (times the
+// angular factor for an angle-dependent rate).
 template <int DIM>
 __global__ void __launch_bounds__(256) loss_h_vhs(const double* __restrict__ P,
                                                   const double* __restrict__ G,
@@ -163,7 +175,7 @@ __global__ void __launch_bounds__(256) loss_h_vhs(const double* __restrict__ P,
                                                   const double* __restrict__ v1,
                                                   const double* __restrict__ w1,
                                                   const double* __restrict__ mu21, double scale,
-                                                  double gamma, int ni, int64_t nid)
+                                                  double gamma, int ni, int64_t nid, AngleForm af)
 {
     constexpr int kTile = 256;
     __shared__ double sv[kTile][DIM];
@@ -199,15 +211,24 @@ __global__ void __launch_bounds__(256) loss_h_vhs(const double* __restrict__ P,
         __syncthreads();
         const int cnt = (int)((nid - j0) < kTile ? (nid - j0) : kTile);
         for (int t = 0; t < cnt; ++t) {
-            double u2 = 0;
+            double u2 = 0, d[DIM];
             for (int l = 0; l < DIM; ++l) {
-                const double d = vi[l] - sv[t][l];
-                u2 += d * d;
+                d[l] = vi[l] - sv[t][l];
+                u2 += d[l] * d[l];
             }
             double b;
             if (gamma == 1.0) b = sqrt(u2);
             else if (gamma == 0.0) b = 1;
             else b = u2 > 0 ? pow(u2, 0.5 * gamma) : 0.0;
+            if (af.on && u2 > 0) {
+                double quad;
+                if constexpr (DIM == 2)
+                    quad = af.m[0] * d[0] * d[0] + 2.0 * af.m[1] * d[0] * d[1] + af.m[3] * d[1] * d[1];
+                else
+                    quad = af.m[0] * d[0] * d[0] + af.m[3] * d[1] * d[1] + af.m[5] * d[2] * d[2] +
+                           2.0 * (af.m[1] * d[0] * d[1] + af.m[2] * d[0] * d[2] + af.m[4] * d[1] * d[2]);
+                b *= 1.0 + quad / u2;
+            }
             acc = fma(sg[t], b, acc);
         }
     }
@@ -547,6 +568,7 @@ struct BinItems {
     const int* count;            // ids in the item (<= 64 * batches)
     const unsigned long long* ids;
     double* grid;                // n_g^d FP64 accumulation grid
+    double* tiles;               // deterministic plans: one W^d tile per item (else nullptr)
     BinGeo geo;
 };
 
@@ -584,7 +606,7 @@ struct BinLayout {
 // (map_w), the kernel offset from the fit of the bin's cell (cell_offset) and
 // the W kernel values from the even and odd parts of the cells; the staged
 // vectors are k_1, q k_2 (q the full weight with the orbit sum) and, in 3D, k_3.
-template <typename T, int DIM, int W>
+template <typename T, int DIM, int W, bool ANISO>
 __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
 {
     using L = BinLayout<T, DIM, W>;
@@ -644,7 +666,8 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
                 const int p2 = (int)((id >> 26) & 0xffffull), p3 = (int)((id >> 42) & 0xffffull);
                 T q, vp[DIM];
                 point_velocity<T, DIM>(P, s, a1, b1, p2, p3, q, vp);
-                q *= orbit_sum<T, DIM>(P, a1, b1, p2, p3);
+                if constexpr (ANISO) q *= orbit_sum_aniso<T, DIM>(P, s, a1, b1, p2, p3);
+                else q *= orbit_sum<T, DIM>(P, a1, b1, p2, p3);
                 double sv[DIM];
 #pragma unroll
                 for (int l = 0; l < DIM; ++l) {
@@ -737,6 +760,18 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
         }
     }
     if (g != 0) return;
+    if (BI.tiles) {
+        // deterministic plans: the whole tile, [a][column], zeros included
+        double* tile = BI.tiles + (int64_t)item * (W * CELLS);
+#pragma unroll
+        for (int r = 0; r < NPASS; ++r) {
+            const int e = e0 + LP * r;
+            if (e >= CELLS) continue;
+#pragma unroll
+            for (int a = 0; a < W; ++a) tile[a * CELLS + e] = tot[r][a];
+        }
+        return;
+    }
 #pragma unroll
     for (int r = 0; r < NPASS; ++r) {
         const int e = e0 + LP * r;
@@ -857,6 +892,84 @@ __global__ void __launch_bounds__(64) gain_binned_mfma(GainParams<double> P, Bin
                                        __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+}
+
+// Deterministic plans: grid[m] = the sum of every tile value that lands on the
+// folded cell m, in a fixed order.  Cell m of one dimension receives the
+// unfolded indices u = m, -m (m > 0) and 2 nh - m (m < nh); u lies in the
+// footprint of the bins t0 = u - W + 1 .. u (offset u - t0), and each bin's
+// runs are taken in run order.
+template <int DIM>
+__global__ void __launch_bounds__(256)
+    gather_tiles(const double* __restrict__ tiles, const int* __restrict__ bin_ptr, const int* __restrict__ bin_items,
+                 int nb, int off, int W, int nh, int ng, int64_t ngd, double* __restrict__ grid)
+{
+    const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (f >= ngd) return;
+    int m[DIM];
+    {
+        int64_t r = f;
+#pragma unroll
+        for (int l = DIM - 1; l >= 0; --l) {
+            m[l] = (int)(r % ng);
+            r /= ng;
+        }
+    }
+    int cand[DIM][3], nc[DIM];
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) {
+        nc[l] = 0;
+        cand[l][nc[l]++] = m[l];
+        if (m[l] > 0) cand[l][nc[l]++] = -m[l];
+        if (m[l] < nh) cand[l][nc[l]++] = 2 * nh - m[l];
+    }
+    const int cells = (DIM == 2) ? W : W * W;  // columns of a tile
+    const int64_t tile = (int64_t)W * cells;
+    const int tlo = -off, thi = nb - 1 - off;
+    double acc = 0.0;
+    // one pass per combination of candidates, dimension 1 outermost
+    int combos = 1;
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) combos *= nc[l];
+    for (int cb = 0; cb < combos; ++cb) {
+        int u[DIM];
+        {
+            int r = cb;
+#pragma unroll
+            for (int l = DIM - 1; l >= 0; --l) {
+                u[l] = cand[l][r % nc[l]];
+                r /= nc[l];
+            }
+        }
+        int lo[DIM], hi[DIM];
+        bool empty = false;
+#pragma unroll
+        for (int l = 0; l < DIM; ++l) {
+            lo[l] = max(u[l] - W + 1, tlo);
+            hi[l] = min(u[l], thi);
+            empty |= lo[l] > hi[l];
+        }
+        if (empty) continue;
+        for (int t1 = lo[0]; t1 <= hi[0]; ++t1) {
+            const int a = u[0] - t1;
+            for (int t2 = lo[1]; t2 <= hi[1]; ++t2) {
+                if constexpr (DIM == 2) {
+                    const int bin = (t1 + off) * nb + (t2 + off);
+                    const int idx = a * cells + (u[1] - t2);
+                    for (int k = bin_ptr[bin]; k < bin_ptr[bin + 1]; ++k)
+                        acc += tiles[(int64_t)bin_items[k] * tile + idx];
+                } else {
+                    for (int t3 = lo[2]; t3 <= hi[2]; ++t3) {
+                        const int bin = ((t1 + off) * nb + (t2 + off)) * nb + (t3 + off);
+                        const int idx = a * cells + (u[1] - t2) * W + (u[2] - t3);
+                        for (int k = bin_ptr[bin]; k < bin_ptr[bin + 1]; ++k)
+                            acc += tiles[(int64_t)bin_items[k] * tile + idx];
+                    }
+                }
+            }
+        }
+    }
+    grid[f] = acc;
 }
 
 __global__ void fill_zero(double* __restrict__ x, int64_t n)
@@ -1089,12 +1202,24 @@ hipError_t dense_loss(const Plan& p, int nb, const DenseBufs& b, hipStream_t s)
         hipLaunchKernelGGL(sum_kernel, dim3(nb), dim3(kRedThreads), 0, s, b.G, p.nid, b.red);
         hipLaunchKernelGGL(loss_h_maxwell, dim3(blocks_for(n, 256)), dim3(256), 0, s, b.P, b.H,
                            p.dt.w1, p.dt.mu21, b.red, scale, p.dim, p.ni, p.nid, n);
-    } else if (p.dim == 2) {
-        hipLaunchKernelGGL(loss_h_vhs<2>, dim3(blocks_for(p.nid, 256), nb), dim3(256), 0, s, b.P, b.G,
-                           b.H, p.dt.v1d, p.dt.w1, p.dt.mu21, scale, p.gamma, p.ni, p.nid);
     } else {
-        hipLaunchKernelGGL(loss_h_vhs<3>, dim3(blocks_for(p.nid, 256), nb), dim3(256), 0, s, b.P, b.G,
-                           b.H, p.dt.v1d, p.dt.w1, p.dt.mu21, scale, p.gamma, p.ni, p.nid);
+        AngleForm af{};
+        if (p.kernel == PGC_KERNEL_ANISO) {
+            af.on = 1;
+            const int D = p.dim;
+            const int idx[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+            for (int s2 = 0; s2 < p.n_sigma; ++s2)
+                for (int a = 0; a < D; ++a)
+                    for (int c = a; c < D; ++c)
+                        af.m[idx[a][c]] += p.sigma_w[s2] * p.sigma[(size_t)s2 * D + a] * p.sigma[(size_t)s2 * D + c];
+            for (double& x : af.m) x *= p.aniso / p.wsum;
+        }
+        if (p.dim == 2)
+            hipLaunchKernelGGL(loss_h_vhs<2>, dim3(blocks_for(p.nid, 256), nb), dim3(256), 0, s, b.P, b.G,
+                               b.H, p.dt.v1d, p.dt.w1, p.dt.mu21, scale, p.gamma, p.ni, p.nid, af);
+        else
+            hipLaunchKernelGGL(loss_h_vhs<3>, dim3(blocks_for(p.nid, 256), nb), dim3(256), 0, s, b.P, b.G,
+                               b.H, p.dt.v1d, p.dt.w1, p.dt.mu21, scale, p.gamma, p.ni, p.nid, af);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1168,8 +1293,9 @@ GainParams<T> gain_params(const Plan& p, const Workspace& ws)
     gp.cellfit = p.dt.cellfit;
     gp.b0 = (T)p.b0;
     gp.gamma = (T)p.gamma;
+    gp.aniso = (T)p.aniso;
     gp.map = p.map;
-    gp.vhs = p.kernel == PGC_KERNEL_VHS;
+    gp.vhs = p.kernel != PGC_KERNEL_MAXWELL;
     gp.ni = p.ni;
     gp.np = p.np;
     gp.ng = p.ng;
@@ -1186,7 +1312,10 @@ template <typename T, int DIM, int W>
 hipError_t binned_launch(const Plan& p, const GainParams<T>& gp, const BinItems& bi, hipStream_t s)
 {
     if (p.bins.n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL((gain_binned<T, DIM, W>), dim3((unsigned)p.bins.n_items), dim3(64), 0, s, gp, bi);
+    if (p.kernel == PGC_KERNEL_ANISO)
+        hipLaunchKernelGGL((gain_binned<T, DIM, W, true>), dim3((unsigned)p.bins.n_items), dim3(64), 0, s, gp, bi);
+    else
+        hipLaunchKernelGGL((gain_binned<T, DIM, W, false>), dim3((unsigned)p.bins.n_items), dim3(64), 0, s, gp, bi);
     return hipGetLastError();
 }
 
@@ -1283,13 +1412,15 @@ hipError_t gain_t(const Plan& p, const Workspace& ws, hipStream_t s)
     const GainParams<T> gp = gain_params<T>(p, ws);
     prof_mark(p, 3, s);
     if (p.gain_mode == kGainBinned) {
-        hipLaunchKernelGGL(fill_zero, dim3(blocks_for(p.ngd, 256)), dim3(256), 0, s, ws.grid64, p.ngd);
+        if (!p.deterministic)
+            hipLaunchKernelGGL(fill_zero, dim3(blocks_for(p.ngd, 256)), dim3(256), 0, s, ws.grid64, p.ngd);
         BinItems bi;
         bi.bin = p.bins.item_bin;
         bi.begin = p.bins.item_begin;
         bi.count = p.bins.item_count;
         bi.ids = p.bins.ids;
         bi.grid = ws.grid64;
+        bi.tiles = p.deterministic ? p.bins.tiles : nullptr;
         bi.geo.nb = p.bins.nb;
         bi.geo.off = p.bins.off;
         bi.geo.W = p.W;
@@ -1301,6 +1432,16 @@ hipError_t gain_t(const Plan& p, const Workspace& ws, hipStream_t s)
             e = (p.dim == 2) ? binned_dispatch<T, 2>(p, gp, bi, s) : binned_dispatch<T, 3>(p, gp, bi, s);
         }
         if (e != hipSuccess) return e;
+        if (p.deterministic) {
+            const dim3 g(blocks_for(p.ngd, 256));
+            if (p.dim == 2)
+                hipLaunchKernelGGL(gather_tiles<2>, g, dim3(256), 0, s, p.bins.tiles, p.bins.bin_ptr, p.bins.bin_items,
+                                   p.bins.nb, p.bins.off, p.W, p.nh, p.ng, p.ngd, ws.grid64);
+            else
+                hipLaunchKernelGGL(gather_tiles<3>, g, dim3(256), 0, s, p.bins.tiles, p.bins.bin_ptr, p.bins.bin_items,
+                                   p.bins.nb, p.bins.off, p.W, p.nh, p.ng, p.ngd, ws.grid64);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
         prof_mark(p, 4, s);
         e = separable(p, ws.grid64, ws.qplus, p.dt.E, p.N, p.ng, 1, ws.tmpA, ws.tmpB, s);
     } else {

@@ -875,7 +875,7 @@ pgc_status pgc_surrogate_create(pgc_plan plan, const pgc_surrogate_desc* d, void
     *out = nullptr;
     const pgc::Plan& p = plan->p;
     // the plan's fast path is the fallback and the judge: FP32, rates of |u| alone
-    if (p.precision != PGC_PRECISION_FP32 || p.kernel == PGC_KERNEL_ANISO) return PGC_ERR_UNSUPPORTED;
+    if (p.precision != PGC_PRECISION_FP32) return PGC_ERR_UNSUPPORTED;
     if (d->width < 16 || d->width > 8192 || d->n_layers < 2 || d->n_layers > 16 || d->batch_max < 1 ||
         d->batch_max > 65536 || d->gate_residual < 0 || d->judge_stride < 0 || d->gate_raw_factor < 0 ||
         !(d->norm_floor_in > 0 && d->norm_floor_in <= 1) || !(d->norm_floor_out > 0 && d->norm_floor_out <= 1) ||
@@ -1123,17 +1123,18 @@ pgc_status pgc_surrogate_coeffs_to_q(pgc_surrogate s, const float* f_dev, int64_
     hipError_t e = hipSuccess;
     int64_t nfb = 0;
     double worst_judge = 0.0;
-    bool judge_failed = false;
     std::vector<double> rr, ro, er, zz;
-    std::vector<int> fb;
+    std::vector<int> fb, jrow;
     try {
         for (auto* v : {&rr, &ro, &er, &zz}) v->resize((size_t)s->bmax);
         fb.resize((size_t)s->bmax);
+        jrow.resize((size_t)s->bmax);
     } catch (...) {
         return PGC_ERR_OUT_OF_MEMORY;
     }
     const bool ood_on = s->gate_raw_factor > 0 && s->raw_calib > 0;
     const double raw_gate = s->gate_raw_factor * s->raw_calib, z_gate = s->gate_raw_factor * s->z_calib;
+    const int64_t stride = s->judge_stride;
     for (int64_t b0 = 0; b0 < n_samples && e == hipSuccess; b0 += s->bmax) {
         const int rows = (int)std::min<int64_t>(s->bmax, n_samples - b0);
         float* qo = q_dev + (size_t)b0 * n;
@@ -1148,55 +1149,51 @@ pgc_status pgc_surrogate_coeffs_to_q(pgc_surrogate s, const float* f_dev, int64_
             hipLaunchKernelGGL(pgc::row_zscore, dim3(rows), dim3(256), 0, st, f_dev, b0, n, s->mu_in, s->sd_in, s->zs);
             e = hipGetLastError();
         }
-        if (e == hipSuccess) e = hipMemcpyAsync(rr.data(), s->res_raw, rows * sizeof(double), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(ro.data(), s->res_out, rows * sizeof(double), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess && ood_on)
-            e = hipMemcpyAsync(zz.data(), s->zs, rows * sizeof(double), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) break;
-        // the judge: the plain evaluation of every judge_stride-th sample
-        if (s->judge_stride > 0 && !judge_failed) {
-            int nj = 0;
+        // the judge: the plain evaluation of every judge_stride-th sample, compared
+        // with the network's output; the sample then returns the plain value
+        int nj = 0;
+        if (e == hipSuccess && stride > 0) {
             for (int r = 0; r < rows; ++r) {
-                if ((b0 + r) % s->judge_stride != 0) continue;
+                if ((b0 + r) % stride != 0) continue;
                 pgc_status ps = pgc_coeffs_to_q(s->plan, f_dev + (size_t)(b0 + r) * n, s->qtmp + (size_t)nj * n,
                                                 nullptr, stream);
                 if (ps != PGC_OK) return ps;
                 hipLaunchKernelGGL(pgc::row_rel_err, dim3(1), dim3(256), 0, st, qo + (size_t)r * n,
                                    s->qtmp + (size_t)nj * n, n, s->err + nj);
-                ++nj;
-            }
-            if (nj > 0) {
-                e = hipMemcpyAsync(er.data(), s->err, nj * sizeof(double), hipMemcpyDeviceToHost, st);
-                if (e == hipSuccess) e = hipStreamSynchronize(st);
-                for (int j = 0; j < nj; ++j) {
-                    worst_judge = std::max(worst_judge, er[j]);
-                    if (!(er[j] <= s->judge_tol)) judge_failed = true;
-                }
+                e = hipMemcpyAsync(qo + (size_t)r * n, s->qtmp + (size_t)nj * n, (size_t)n * sizeof(float),
+                                   hipMemcpyDeviceToDevice, st);
+                if (e != hipSuccess) break;
+                jrow[nj++] = r;
             }
         }
+        if (e == hipSuccess) e = hipMemcpyAsync(rr.data(), s->res_raw, rows * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(ro.data(), s->res_out, rows * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && ood_on)
+            e = hipMemcpyAsync(zz.data(), s->zs, rows * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && nj > 0) e = hipMemcpyAsync(er.data(), s->err, nj * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) break;
         for (int r = 0; r < rows; ++r) {
             const bool bad = !(ro[r] <= s->gate_residual) ||
                              (ood_on && (!(rr[r] <= raw_gate) || !(zz[r] <= z_gate)));
             fb[r] = bad ? 1 : 0;
         }
+        // a judged sample stands for the stride of samples that start with it:
+        // when the network missed it, they fall back too
+        for (int j = 0; j < nj; ++j) {
+            worst_judge = std::max(worst_judge, er[j]);
+            const int r0 = jrow[j];
+            fb[r0] = 2;
+            if (!(er[j] <= s->judge_tol))
+                for (int r = r0 + 1; r < rows && r < r0 + stride; ++r) fb[r] = fb[r] ? fb[r] : 1;
+        }
         for (int r = 0; r < rows && e == hipSuccess; ++r) {
-            if (!fb[r]) continue;
+            if (fb[r] != 1) continue;
             pgc_status ps = pgc_coeffs_to_q(s->plan, f_dev + (size_t)(b0 + r) * n, qo + (size_t)r * n, nullptr, stream);
             if (ps != PGC_OK) return ps;
             ++nfb;
         }
         if (fallback_host) std::copy(fb.begin(), fb.begin() + rows, fallback_host + b0);
-    }
-    if (e == hipSuccess && judge_failed) {
-        // the judge rejected the network for these inputs: every sample from the plain path
-        nfb = 0;
-        for (int64_t r = 0; r < n_samples; ++r) {
-            pgc_status ps = pgc_coeffs_to_q(s->plan, f_dev + (size_t)r * n, q_dev + (size_t)r * n, nullptr, stream);
-            if (ps != PGC_OK) return ps;
-            if (fallback_host) fallback_host[r] = 1;
-            ++nfb;
-        }
     }
     if (n_fallback) *n_fallback = nfb;
     if (judge_err) *judge_err = worst_judge;

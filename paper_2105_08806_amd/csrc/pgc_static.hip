@@ -84,7 +84,6 @@ extern "C" pgc_status pgc_coeffs_to_q_static(pgc_plan plan, const void* coeffs, 
 {
     if (!plan || !coeffs || !q) return PGC_ERR_INVALID_ARG;
     const pgc::Plan& p = plan->p;
-    if (p.kernel == PGC_KERNEL_ANISO) return PGC_ERR_UNSUPPORTED;
     if (pgc::carve(p, nullptr, nullptr) > (size_t)PGC_STATIC_SCRATCH_BYTES) return PGC_ERR_SCRATCH;
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);

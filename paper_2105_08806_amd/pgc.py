@@ -47,6 +47,7 @@ class PlanDesc(ctypes.Structure):
         ("n_chunks", ctypes.c_int32), ("block_threads", ctypes.c_int32),
         ("gain_mode", ctypes.c_int32),
         ("kernel_aniso", ctypes.c_double),
+        ("deterministic", ctypes.c_int32),
     ]
 
 
@@ -61,7 +62,8 @@ class PlanInfo(ctypes.Structure):
         ("block_threads", ctypes.c_int32), ("n_triples", ctypes.c_int64),
         ("n_points", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
         ("gain_mode", ctypes.c_int32), ("n_bin_items", ctypes.c_int64),
-        ("offset_fit_err", ctypes.c_double),
+        ("offset_fit_err", ctypes.c_double), ("deterministic", ctypes.c_int32),
+        ("tile_bytes", ctypes.c_int64),
     ]
 
 
@@ -83,6 +85,14 @@ class DirectInfo(ctypes.Structure):
         ("n_pairs", ctypes.c_int64), ("n_modes_total", ctypes.c_int64), ("max_cells", ctypes.c_int32),
         ("tensor_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64), ("setup_ms", ctypes.c_double),
         ("flops_per_cell", ctypes.c_double),
+    ]
+
+
+class TransportInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_x", ctypes.c_int32), ("dim", ctypes.c_int32), ("n_modes", ctypes.c_int32),
+        ("length", ctypes.c_double), ("dt", ctypes.c_double), ("max_speed", ctypes.c_double),
+        ("workspace_bytes", ctypes.c_int64),
     ]
 
 
@@ -166,6 +176,14 @@ def lib():
         L.pgc_direct_rk4.argtypes = [vp, vp, i64, dbl, i32, vp]
         L.pgc_direct_capture.argtypes = [vp, vp, i64, vp, vp]
         L.pgc_direct_graph_launch.argtypes = [vp, vp]
+        L.pgc_transport_create.argtypes = [vp, i32, dbl, dbl, vp, ctypes.POINTER(vp)]
+        L.pgc_transport_destroy.argtypes = [vp]
+        L.pgc_transport_query.argtypes = [vp, ctypes.POINTER(TransportInfo), dp]
+        L.pgc_transport_step.argtypes = [vp, vp, vp]
+        L.pgc_split_step.argtypes = [vp, vp, vp, vp, i32, vp]
+        for name in ("pgc_transport_create", "pgc_transport_destroy", "pgc_transport_query",
+                     "pgc_transport_step", "pgc_split_step"):
+            getattr(L, name).restype = ctypes.c_int
         for name in ("pgc_direct_create", "pgc_direct_destroy", "pgc_direct_query", "pgc_direct_coeffs_to_q",
                      "pgc_direct_rk4", "pgc_direct_capture", "pgc_direct_graph_launch"):
             getattr(L, name).restype = ctypes.c_int
@@ -547,6 +565,61 @@ class Direct:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().pgc_direct_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Transport:
+    """Free streaming along x over dt for n_x (odd) periodic cells of one
+    plan's coefficients (pgc_transport_*), and the Strang split step."""
+
+    def __init__(self, plan, n_x, length, dt):
+        import torch
+        self._torch = torch
+        self.plan = plan
+        h = ctypes.c_void_p()
+        _check(lib().pgc_transport_create(plan._h, int(n_x), float(length), float(dt), _stream(), ctypes.byref(h)),
+               "pgc_transport_create")
+        self._h = h
+        self.info = TransportInfo()
+        _check(lib().pgc_transport_query(self._h, ctypes.byref(self.info), None), "pgc_transport_query")
+
+    def speeds(self):
+        out = np.zeros(self.info.n_modes)
+        _check(lib().pgc_transport_query(self._h, None, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "pgc_transport_query")
+        return out
+
+    def _state(self, coeffs):
+        torch = self._torch
+        if not (coeffs.is_cuda and coeffs.dtype == torch.float64 and coeffs.is_contiguous()):
+            raise ValueError("the state must be a contiguous float64 CUDA tensor")
+        if coeffs.numel() != self.info.n_x * self.info.n_modes ** self.info.dim:
+            raise ValueError("the state must hold n_x cells of N^d coefficients")
+
+    def step(self, coeffs):
+        """One transport step, in place."""
+        self._state(coeffs)
+        _check(lib().pgc_transport_step(self._h, _ptr(coeffs), _stream()), "pgc_transport_step")
+        return coeffs
+
+    def split_step(self, coeffs, n_steps=1, direct=None):
+        """Strang steps over 2 dt (this object is the half-step transport):
+        collisions cell by cell through the plan, or through ``direct``."""
+        self._state(coeffs)
+        _check(lib().pgc_split_step(self._h, None if direct is not None else self.plan._h,
+                                    direct._h if direct is not None else None, _ptr(coeffs), int(n_steps),
+                                    _stream()), "pgc_split_step")
+        return coeffs
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pgc_transport_destroy(self._h)
             self._h = None
 
     def __del__(self):

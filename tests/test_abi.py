@@ -128,6 +128,7 @@ def test_plan_descriptor_rejections_without_a_device():
            dict(kernel=pgc.KERNEL_ANISO, kernel_gamma=2.0), dict(kernel=3), dict(nufft_tol=-1e-6), dict(upsample=1.2),
            dict(upsample=5.0), dict(kernel_width=3), dict(kernel_width=99), dict(slab_planes=-1),
            dict(n_chunks=-2), dict(block_threads=300), dict(gain_mode=4), dict(gain_mode=-1),
+           dict(deterministic=2), dict(deterministic=-1),
            dict(n_sigma=7),                                  # a circle rule needs antipodal pairs
            dict(n_sigma=0), dict(sphere=9),
            dict(dim=3),                                      # the circle rule is a 2D rule
@@ -152,6 +153,12 @@ def test_plan_descriptor_rejections_without_a_device():
     # beyond the binned scheme's node limit is refused rather than replaced
     assert _create_status(pgc, L, gain_mode=3) == 2
     assert _create_status(pgc, L, gain_mode=2, n_modes=300) == 2
+    # the fixed-order tile gather and an angle-dependent rate need the binned
+    # vector gain: refused with the slab and matrix-core schemes
+    assert _create_status(pgc, L, deterministic=1, gain_mode=1) == 2
+    assert _create_status(pgc, L, deterministic=1, gain_mode=3, dim=3, sphere=pgc.SPHERE_PRODUCT_3D,
+                          n_theta=2, n_phi=4) == 2
+    assert _create_status(pgc, L, kernel=pgc.KERNEL_ANISO, kernel_aniso=0.5, gain_mode=1) == 2
 
 
 def test_gemm_argument_errors_without_a_device():
