@@ -240,12 +240,28 @@ struct GemmArgs {
     int64_t K;
     int mt, nt, splits;
     int64_t kspan;    // K per split, a multiple of kGK
+    int vec;          // rows of A and B 16-byte aligned: interior chunks load pairs of doubles
 };
 
 __device__ __forceinline__ void gemm_load(const GemmArgs& g, int m0, int n0, int64_t k0, int64_t k1, double ra[8],
                                           double rb[8])
 {
     const int t = threadIdx.x;
+    // interior chunks (the usual case) load without per-element guards, in
+    // 16-byte pairs, so the loads carry no branches and schedule freely
+    if (g.vec && m0 + kGT <= g.M && n0 + kGT <= g.N && k0 + kGK <= k1) {
+        const double2* a = reinterpret_cast<const double2*>(g.A + (int64_t)(m0 + (t >> 1)) * g.lda + k0 + (t & 1) * 8);
+        const double2* b = reinterpret_cast<const double2*>(g.B + (k0 + (t >> 4)) * g.ldb + n0 + (t & 15) * 8);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double2 x = a[j], y = b[j];
+            ra[2 * j] = x.x;
+            ra[2 * j + 1] = x.y;
+            rb[2 * j] = y.x;
+            rb[2 * j + 1] = y.y;
+        }
+        return;
+    }
     // A: row t/2 of the tile, 8 consecutive k
     {
         const int m = m0 + (t >> 1);
@@ -398,6 +414,10 @@ hipError_t gemm_launch(const double* A, int64_t lda, const double* B, int64_t ld
     const int64_t chunks = (K + kGK - 1) / kGK;
     g.kspan = (chunks + g.splits - 1) / g.splits * kGK;
     g.C = g.splits > 1 ? partial : C;
+    g.vec = (lda % 2 == 0 && ldb % 2 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
+             (reinterpret_cast<uintptr_t>(B) & 15) == 0)
+                ? 1
+                : 0;
     const int64_t blocks = (int64_t)g.mt * g.nt * g.splits;
     hipLaunchKernelGGL(dgemm_tile, dim3((unsigned)blocks), dim3(kGThreads), 0, s, g);
     hipError_t e = hipGetLastError();
