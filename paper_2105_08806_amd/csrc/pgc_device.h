@@ -86,9 +86,13 @@ __device__ __forceinline__ double map_w(T v, const GainParams<T>& P, T& m2)
 {
     const double t = (double)v * P.inv_S64;
     if (P.map == 0) {
+        // one reciprocal for both: with R = 1 / (e (1 + e)), 1/e = (1 + e) R and
+        // 1/(1 + e) = e R
         const double e = exp(-t);
-        m2 = (T)(0.5 * (e + rcp64(e)));
-        return (1.0 - e) * rcp64(1.0 + e);
+        const double ep = 1.0 + e;
+        const double R = rcp64(e * ep);
+        m2 = (T)(0.5 * fma(ep, R, e));
+        return (1.0 - e) * (e * R);
     }
     const double r = fma(t, t, 1.0);
     m2 = (T)r;

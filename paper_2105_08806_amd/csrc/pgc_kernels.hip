@@ -654,13 +654,17 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
             if constexpr (TWO_LEVEL) acc64[r][a] = 0.0;
         }
 
+    // the id of this lane's point in the next batch is loaded one batch ahead,
+    // so its latency hides under the current batch's spreading
+    unsigned long long id_next = lane < n ? BI.ids[first + lane] : 0ull;
     for (int base = 0; base < n; base += 64) {
         const int nv = min(64, n - base);
+        const unsigned long long id = id_next;
+        if (base + 64 + lane < n) id_next = BI.ids[first + base + 64 + lane];
         // regenerate one point per lane and stage its kernel vectors
         {
             T* st = stage + lane * STRIDE;
             if (lane < nv) {
-                const unsigned long long id = BI.ids[first + base + lane];
                 const int b1 = (int)(id & 0xffull), a1 = (int)((id >> 8) & 0xffull);
                 const int s = (int)((id >> 16) & 0x3ffull);
                 const int p2 = (int)((id >> 26) & 0xffffull), p3 = (int)((id >> 42) & 0xffffull);
