@@ -27,7 +27,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Q(f,f) evals/s, 3D N=32^3: FP64 plain vs FP32/batched/surrogate at stated rel-L2"
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}  # MI355X vector peaks, FLOP/s
-LOOSE_JUDGE = 0.15  # second judge tolerance reported for the surrogate: about its worst held-out error
 N, S, T0, DT = 32, 5.0, 6.5, 0.1
 N_THETA, N_PHI = 8, 8
 CSRC = os.path.join(ROOT, "paper_2105_08806_amd", "csrc")
@@ -39,8 +38,8 @@ KERNEL_SOURCES = {
     "gemm_bf16": ("pgc_mlp.hip",),
 }
 TRAFFIC_KERNELS = {  # record tag -> (kernel name prefix, source set)
-    "gain_binned_fp64_3d_n32": ("void pgc::(anonymous namespace)::gain_binned<double, 3, 11>", "gain_binned"),
-    "gain_binned_fp32_3d_n32": ("void pgc::(anonymous namespace)::gain_binned<float, 3, 5>", "gain_binned"),
+    "gain_binned_fp64_3d_n32": ("void pgc::(anonymous namespace)::gain_binned<double, 3, 11, false>", "gain_binned"),
+    "gain_binned_fp32_3d_n32": ("void pgc::(anonymous namespace)::gain_binned<float, 3, 5, false>", "gain_binned"),
     "gain_batched_lanes_2d_4096": ("void pgc::(anonymous namespace)::gain_batched_lanes<7, 64>",
                                    "gain_batched_lanes"),
 }
@@ -100,6 +99,32 @@ def time_variant(torch, pgc, inputs, precision, steps, warmup):
 
 
 TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")
+C3_GOLDEN = os.path.join(ROOT, "tests", "golden", "c3_bkw3d_n32_pairs.txt")
+
+
+def c3_rel_vs_oracle(q, np):
+    """rel-L2 of a full-rule Q of the 3D workload against the stored oracle
+    values (tests/golden/c3_bkw3d_n32_pairs.txt, written by
+    tests/golden/make_golden.py from the CPU oracle alone) at their 256
+    coefficients, summed over the 32 antipodal direction pairs; None while the
+    file holds fewer pairs."""
+    try:
+        lines = open(C3_GOLDEN).read().splitlines()
+    except OSError:
+        return None
+    kidx, ref, pairs = None, None, 0
+    for i, line in enumerate(lines):
+        if line.startswith("kidx "):
+            kidx = np.array([[int(x) for x in t.split(",")] for t in line.split()[1:]])
+        elif line.startswith("pair "):
+            qp = np.array([float(x) for x in lines[i + 1].split()[1:]])
+            qm = np.array([float(x) for x in lines[i + 2].split()[1:]])
+            ref = (qp - qm) if ref is None else ref + (qp - qm)
+            pairs += 1
+    if kidx is None or pairs != 32:
+        return None
+    got = q[tuple(kidx.T)]
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
 
 def traffic_for(kernel_tag, path=TRAFFIC_PATH):
@@ -157,17 +182,42 @@ def write_traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv, path=TRAFFIC_PAT
     return rec
 
 
-def cpu_baseline(inputs, budget_s=15.0):
+def cpu_baseline(inputs, budget_s=15.0, n_ranges=16):
     """The CPU oracle (FP64, all host cores) on a bounded sample of the same
-    workload: the gain of the first k collision units (s, i), scaled to
-    evaluations per second of the full operator."""
+    workload: the gain over n_ranges runs of collision units (s, i) spread
+    evenly over the whole unit range (every direction band and node range is
+    represented), scaled to evaluations per second of the full operator."""
     import numpy as np
     import oracle as O
     sg, sw = O.sphere_product_rule(N_THETA, N_PHI)
     p = O.Problem(3, N, S, 0, sphere=sg, sphere_w=sw)
     c = p.project(inputs.bkw_f(T0, p.interior_velocities()))
     n_units = len(sw) * (N - 1) ** 3
-    k = 16
+    starts = [int(r * n_units / n_ranges) for r in range(n_ranges)]
+
+    def run(per_range):
+        t = time.time()
+        for u in starts:
+            p.gain_units(c, u, min(n_units, u + per_range))
+        return time.time() - t
+
+    per = 1
+    dt = run(per)
+    if dt < budget_s / 4:
+        per = int(max(per, per * budget_s / max(dt, 1e-3) * 0.8))
+        dt = run(per)
+    k = per * n_ranges
+    per_eval = dt * n_units / k
+    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": "gain of %d of %d collision units (s, i) of the same 3D N=32 workload, in %d runs "
+                      "spread evenly over the unit range, %.1f s, scaled to one full evaluation (%.0f s)"
+                      % (k, n_units, n_ranges, dt, per_eval)}
+
+
+def oracle_gain_sample(p, c, n_units, budget_s):
+    """Time the oracle's gain over the first k collision units (s, i), k grown
+    until the sample takes about budget_s/4 or more; returns (k, seconds)."""
+    k = 4
     t = time.time()
     p.gain_units(c, 0, k)
     dt = time.time() - t
@@ -176,10 +226,180 @@ def cpu_baseline(inputs, budget_s=15.0):
         t = time.time()
         p.gain_units(c, 0, k)
         dt = time.time() - t
+    return k, dt
+
+
+def config1_leg(torch, pgc, inputs, np, reps=20):
+    """2D BKW (Sec. 5.1.1) at the first workload's size: 16 modes, S = 4,
+    Maxwell B = 1/(2 pi), 16 circle directions, t0 = 0.  One Q evaluation
+    (FP64) timed over `reps` calls, then RK4 to t = 1 (dt = 0.05) against the
+    projection of the exact BKW solution."""
+    N, S, M = 16, 4.0, 16
+    plan = pgc.Plan(dim=2, n_modes=N, scale=S, n_sigma=M, precision=pgc.FP64)
+    V = plan.interior_velocities()
+    c = plan.project(inputs.bkw_f(0.0, V))
+    q = plan.coeffs_to_q(c)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        plan.coeffs_to_q(c, q=q)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    st = c.clone()
+    start.record()
+    plan.rk4(st, 0.05, 20)
+    stop.record()
+    torch.cuda.synchronize()
+    rk_ms = start.elapsed_time(stop)
+    exact = plan.project(inputs.bkw_f(1.0, V))
+    err = float(torch.linalg.norm(st - exact) / torch.linalg.norm(exact))
+    out = {"value": 1e3 / ms, "unit": "evals/s", "ms_per_eval": ms, "dtype": "f64",
+           "workload": "2D BKW t0=0, N=16, S=4, Maxwell 1/(2pi), 16 directions",
+           "rk4_to_t1_ms": rk_ms, "rk4_t1_rel_l2_vs_exact_bkw": err,
+           "paper_table4_context": "fast gain of the paper's N=16 row (17 modes): 2.04 s per evaluation, "
+                                   "one i7-6700 thread (Test 04)"}
+    return out, plan, c.cpu().numpy(), q.cpu().numpy()
+
+
+def config2_leg(torch, pgc, inputs, np, reps=5):
+    """2D VHS workload: 64 modes, S = 6, B = |u|/(2 pi), 32 directions, two
+    Maxwellians; FP64 plain against FP32, each against the stored oracle values
+    of all 4096 coefficients (tests/golden/c2_vhs2d_n64.txt, written by
+    tests/golden/make_golden.py from the CPU oracle)."""
+    N, S, M = 64, 6.0, 32
+    b0 = 1.0 / (2 * np.pi)
+    path = os.path.join(ROOT, "tests", "golden", "c2_vhs2d_n64.txt")
+    gold = np.loadtxt(path, comments="#")
+    out = {"workload": "2D VHS gamma=1, N=64, S=6, 32 directions, two Maxwellians (seed 2105)"}
+    for prec, name in ((pgc.FP64, "fp64"), (pgc.FP32, "fp32")):
+        plan = pgc.Plan(dim=2, n_modes=N, scale=S, kernel=pgc.KERNEL_VHS, kernel_b0=b0, kernel_gamma=1.0,
+                        n_sigma=M, precision=prec)
+        c = plan.project(inputs.mixture(plan.interior_velocities(), inputs.two_maxwellians_2d()))
+        if prec == pgc.FP32:
+            c = c.float()
+        q = plan.coeffs_to_q(c)
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(reps):
+            plan.coeffs_to_q(c, q=q)
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / reps
+        col = 2 if prec == pgc.FP64 else 4
+        ref = gold[:, col].reshape(N, N)
+        rel = float(np.linalg.norm(q.double().cpu().numpy() - ref) / np.linalg.norm(ref))
+        out[name] = {"value": 1e3 / ms, "unit": "evals/s", "ms_per_eval": ms,
+                     "rel_l2_vs_oracle_all_coefficients": rel, "kernel_width": plan.info.kernel_width,
+                     "points_per_s": plan.info.n_points * 1e3 / ms}
+        plan.close()
+    out["fp32_speedup"] = out["fp32"]["value"] / out["fp64"]["value"]
+    out["paper_table4_context"] = ("fast gain of the paper's N=64 row (65 modes, 64 directions): 494 s per "
+                                   "evaluation, one i7-6700 thread (Test 04)")
+    return out
+
+
+def config_cpu_legs(inputs, np, c1_coeffs, c1_q, budget_s=10.0):
+    """cpu_baseline of the smaller workloads: the CPU oracle timed on the host
+    cores, the 2D BKW evaluation in full (and the GPU result's rel-L2 against
+    it), the 2D VHS workload on a bounded sample of its collision units."""
+    import oracle as O
+    sg, sw = O.circle_rule(16)
+    p = O.Problem(2, 16, 4.0, 0, sphere=sg, sphere_w=sw)
+    t = time.time()
+    q_ora, _, _ = p.collision(c1_coeffs)
+    t1 = time.time() - t
+    c1 = {"value": 1.0 / t1, "unit": "evals/s", "cores": O.num_threads(), "kind": "oracle",
+          "sample": "one full evaluation of the 2D BKW workload (%.2f s)" % t1,
+          "gpu_rel_l2_vs_oracle": float(np.linalg.norm(c1_q - q_ora) / np.linalg.norm(q_ora))}
+    sg, sw = O.circle_rule(32)
+    p2 = O.Problem(2, 64, 6.0, 0, kernel="vhs", b0=1.0 / (2 * np.pi), gamma=1.0, sphere=sg, sphere_w=sw)
+    c2 = p2.project(inputs.mixture(p2.interior_velocities(), inputs.two_maxwellians_2d()))
+    n_units = 32 * 63 ** 2
+    k, dt = oracle_gain_sample(p2, c2, n_units, budget_s)
     per_eval = dt * n_units / k
-    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": "gain of %d of %d collision units (s, i) of the same 3D N=32 workload, "
-                      "%.1f s, scaled to one full evaluation (%.0f s)" % (k, n_units, dt, per_eval)}
+    c2l = {"value": 1.0 / per_eval, "unit": "evals/s", "cores": O.num_threads(), "kind": "oracle",
+           "sample": "gain of %d of %d collision units (s, i) of the 2D VHS workload, %.1f s, scaled "
+                     "to one full evaluation (%.0f s)" % (k, n_units, dt, per_eval)}
+    return c1, c2l
+
+
+def fast_path_options(torch, pgc, inputs, np, reps=2):
+    """The 3D workload's plan with the two options of the fast path:
+    deterministic = 1 (tile gather instead of grid atomics; repeats compared
+    bit for bit) and an angle-dependent rate B = b0 (1 + cos^2 theta) in place
+    of Maxwell's constant (its extra cost per evaluation)."""
+    out = {}
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ref = None
+    for name, extra in (("atomic", {}), ("deterministic", {"deterministic": 1}),
+                        ("angle_dependent", {"kernel": pgc.KERNEL_ANISO, "kernel_aniso": 1.0})):
+        plan = pgc.Plan(dim=3, n_modes=N, scale=S, map=pgc.MAP_LOG, sphere=pgc.SPHERE_PRODUCT_3D,
+                        n_theta=N_THETA, n_phi=N_PHI, precision=pgc.FP64, **extra)
+        c = plan.project(inputs.bkw_f(T0, plan.interior_velocities()))
+        a = plan.coeffs_to_q(c).clone()
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(reps):
+            b = plan.coeffs_to_q(c)
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / reps
+        row = {"ms_per_eval": ms, "evals_per_s": 1e3 / ms}
+        if name == "atomic":
+            ref = a
+        elif name == "deterministic":
+            row["repeat_bit_identical"] = bool(torch.equal(a, b))
+            row["rel_l2_vs_atomic_flush"] = float(torch.linalg.norm(a - ref) / torch.linalg.norm(ref))
+            row["tile_bytes"] = plan.info.tile_bytes
+        out[name] = row
+        plan.close()
+    log("fast path options: %s" % {k: round(v["ms_per_eval"], 1) for k, v in out.items()})
+    return out
+
+
+def split_step_variant(torch, pgc, inputs, np, n_x=127, steps=4):
+    """The spatially inhomogeneous equation on n_x periodic cells in x (2D
+    velocity, 32 modes, S = 6, Maxwell, 32 directions): Strang steps of
+    dt = 0.05 with the collisions of all cells through the direct algorithm.
+    Initial data: a Maxwellian with a density and bulk-velocity wave in x."""
+    Nm, S_, dt, L = 32, 6.0, 0.05, 2 * np.pi
+    plan = pgc.Plan(dim=2, n_modes=Nm, scale=S_, n_sigma=32, precision=pgc.FP64)
+    V = plan.interior_velocities()
+    rows = []
+    for cidx in range(n_x):
+        x = L * cidx / n_x
+        rows.append(plan.project(inputs.maxwellian(V, 1.0 + 0.2 * np.cos(x), (0.3 * np.sin(x), 0.0), 1.0))
+                    .reshape(-1))
+    st = torch.stack(rows).contiguous()
+    half = pgc.Transport(plan, n_x, L, dt / 2)
+    d = pgc.Direct(plan, max_cells=n_x)
+    def total_mass():
+        return sum(float(plan.moments(st[cidx].view(Nm, Nm))[0]) for cidx in range(n_x))
+
+    m0 = total_mass()
+    half.split_step(st, n_steps=1, direct=d)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    half.split_step(st, n_steps=steps, direct=d)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    out = {"ms_per_step": ms, "cell_steps_per_s": n_x / (ms / 1e3), "n_x": n_x,
+           "max_speed": half.info.max_speed, "cfl_dt_over_dx": half.info.max_speed * dt / (L / n_x),
+           "workload": "1D periodic x (%d cells) x 2D velocity, N=32, S=6, Maxwell, 32 directions; "
+                       "Strang: exact transport dt/2, RK4 collisions (direct algorithm), transport dt/2"
+                       % n_x,
+           "total_mass_relative_change": abs(total_mass() - m0) / abs(m0),
+           "mass_note": "transport keeps every coefficient's sum over cells; the r=0 collisions keep mass "
+                        "to the discretisation's accuracy"}
+    half.close()
+    d.close()
+    plan.close()
+    return out
 
 
 def batched_variant(torch, pgc, inputs, np, n_cells, reps):
@@ -503,30 +723,47 @@ def surrogate_variant(torch, pgc, inputs, np, n_pairs, epochs):
         p64.coeffs_to_q(c64)
     torch.cuda.synchronize()
     t_fp64 = (time.time() - t) / 2
-    # the same network with a judge tolerance at its measured worst error: what
-    # the surrogate gains where that accuracy is acceptable
-    loose = pgc.Surrogate(plan, width=1024, n_layers=4, batch_max=256, seed=3, judge_tol=LOOSE_JUDGE)
+    # accuracy of what the deployed call returned: the samples the network
+    # served (flag 0), the judged ones (flag 2, the plan's value) and the
+    # fallbacks (flag 1)
+    err_dep = np.array([float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in
+                        zip(q_dep.double().cpu().numpy(), q_te.double().cpu().numpy())])
+    served = flags == 0
+    # the same network with the judge tolerance set at its worst measured
+    # held-out error: what the surrogate gains where that accuracy is acceptable
+    loose_tol = float(np.ceil(max(err) * 100.0) / 100.0)
+    loose = pgc.Surrogate(plan, width=1024, n_layers=4, batch_max=256, seed=3, judge_tol=loose_tol)
     with tempfile.TemporaryDirectory() as d:  # parameters and gate calibration
         s.save(os.path.join(d, "net.bin"))
         loose.load(os.path.join(d, "net.bin"))
     loose.coeffs_to_q(f_te)
     torch.cuda.synchronize()
     t = time.time()
-    q_l, _, nfb_l, jerr_l = loose.coeffs_to_q(f_te)
+    q_l, flags_l, nfb_l, jerr_l = loose.coeffs_to_q(f_te)
     torch.cuda.synchronize()
     t_loose = time.time() - t
     err_l = [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in
              zip(q_l.double().cpu().numpy(), q_te.double().cpu().numpy())]
-    out = {"value": f_te.shape[0] / t_dep, "unit": "Q-evals/s (gates and judge on, judge tol 5e-2)",
-           "network_only_evals_per_s": f_te.shape[0] / t_net,
+    n_te = int(f_te.shape[0])
+    out = {"value": n_te / t_dep, "unit": "Q-evals/s (gates and judge on, judge tol 5e-2)",
+           "network_only_evals_per_s": n_te / t_net,
            "plain_fp32_evals_per_s": 1.0 / t_plain, "plain_fp64_evals_per_s": 1.0 / t_fp64,
-           "speedup_vs_plain_fp64": (f_te.shape[0] / t_dep) * t_fp64,
+           "speedup_vs_plain_fp32": (n_te / t_dep) * t_plain,
+           "speedup_vs_plain_fp64": (n_te / t_dep) * t_fp64,
            "network_rel_l2_vs_plain_median": float(np.median(err)), "network_rel_l2_vs_plain_max": max(err),
-           "fallbacks": nfb, "of": int(f_te.shape[0]), "judge_max_rel_err": jerr,
-           "judge_tol_%g" % LOOSE_JUDGE: {"evals_per_s": f_te.shape[0] / t_loose, "fallbacks": nfb_l,
-                             "speedup_vs_plain_fp64": (f_te.shape[0] / t_loose) * t_fp64,
-                             "rel_l2_vs_plain_median": float(np.median(err_l)),
-                             "rel_l2_vs_plain_max": max(err_l)},
+           "returned": {"served_by_network": int(served.sum()), "judged_plan_value": int((flags == 2).sum()),
+                        "fallbacks": nfb, "fallback_rate": nfb / n_te,
+                        "rel_l2_vs_plain_max_all": float(err_dep.max()),
+                        "rel_l2_vs_plain_max_served": float(err_dep[served].max()) if served.any() else None,
+                        "rel_l2_vs_plain_median_served": float(np.median(err_dep[served])) if served.any() else None},
+           "of": n_te, "judge_max_rel_err": jerr,
+           "judge_tol_at_max_error": {"judge_tol": loose_tol, "evals_per_s": n_te / t_loose, "fallbacks": nfb_l,
+                                      "fallback_rate": nfb_l / n_te,
+                                      "served_by_network": int((flags_l == 0).sum()),
+                                      "speedup_vs_plain_fp32": (n_te / t_loose) * t_plain,
+                                      "speedup_vs_plain_fp64": (n_te / t_loose) * t_fp64,
+                                      "rel_l2_vs_plain_median": float(np.median(err_l)),
+                                      "rel_l2_vs_plain_max": max(err_l)},
            "training_pairs": n_pairs, "symmetric_images": 16, "epochs": epochs,
            "loss_first_last": [float(losses[0]), float(losses[-1])],
            "pair_generation_s": t_gen, "training_s": t_train,
@@ -580,6 +817,10 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-bkw", action="store_true", help="skip the 20-step RK4 BKW error curve")
     ap.add_argument("--no-direct", action="store_true", help="skip the direct-algorithm leg")
+    ap.add_argument("--no-options", action="store_true",
+                    help="skip the deterministic / angle-dependent fast-path options and the split-step leg")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 2D BKW (16 modes) and 2D VHS (64 modes) workload legs")
     ap.add_argument("--direct-cells", type=int, default=4096)
     ap.add_argument("--direct-reps", type=int, default=3)
     ap.add_argument("--batch-cells", type=int, default=4096)
@@ -681,6 +922,7 @@ def main():
     evals64 = 4 * args.steps / (r64["ms"] / 1e3)
     evals32 = 4 * args.fp32_steps / (r32["ms"] / 1e3)
     rel32 = float(np.linalg.norm(r32["q0"] - r64["q0"]) / np.linalg.norm(r64["q0"]))
+    ora64, ora32 = c3_rel_vs_oracle(r64["q0"], np), c3_rel_vs_oracle(r32["q0"], np)
 
     info = r64["info"]
     W = info.kernel_width
@@ -710,16 +952,32 @@ def main():
                    "kernel_width": W, "upsample": info.upsample, "n_points": info.n_points,
                    "n_triples": info.n_triples},
         "roofline": roofline,
+        "rel_l2_vs_oracle": ora64,
+        "rel_l2_vs_oracle_note": "Q at t0 over the 256 stored oracle coefficients (all 64 directions), "
+                                 "tests/golden/c3_bkw3d_n32_pairs.txt",
         "triples_per_s": info.n_triples * evals64,
         "points_per_s": info.n_points * evals64,
         "stage_ms_per_eval_fp64": {k: v / max(1, r64["calls"]) for k, v in r64["stages"].items()},
         "variants": {
             "fp32": {"value": evals32, "unit": "evals/s", "ms_per_step": r32["ms"] / args.fp32_steps,
-                     "rel_l2_vs_fp64_path": rel32, "kernel_width": r32["info"].kernel_width,
+                     "rel_l2_vs_fp64_path": rel32, "rel_l2_vs_oracle": ora32,
+                     "kernel_width": r32["info"].kernel_width,
                      "stage_ms_per_eval": {k: v / max(1, r32["calls"]) for k, v in r32["stages"].items()}},
         },
         "moments_fp64_final": r64["moments"],
     }
+    if not args.no_configs:
+        c1, c1_plan, c1_c, c1_q = config1_leg(torch, pgc, inputs, np)
+        line["variants"]["config_2d_bkw_n16"] = c1
+        line["variants"]["config_2d_vhs_n64"] = config2_leg(torch, pgc, inputs, np)
+        c1_plan.close()
+        if not args.no_cpu_baseline:
+            cb1, cb2 = config_cpu_legs(inputs, np, c1_c, c1_q)
+            c1["cpu_baseline"] = cb1
+            line["variants"]["config_2d_vhs_n64"]["cpu_baseline"] = cb2
+    if not args.no_options:
+        line["variants"]["fast_path_options_3d_n32"] = fast_path_options(torch, pgc, inputs, np)
+        line["variants"]["split_step_2d_n32"] = split_step_variant(torch, pgc, inputs, np)
     if not args.no_batched:
         line["variants"]["batched"] = batched_variant(torch, pgc, inputs, np, args.batch_cells, args.batch_reps)
     if not args.no_direct:
