@@ -232,3 +232,26 @@ def test_batch_workload_sizes_vs_fp64_plans(torch_cuda):
     b.close()
     for p in plans.values():
         p.close()
+
+
+def test_batch_workload_n32_cells_vs_oracle(torch_cuda):
+    """Cells of the batched workload itself (4096 cells drawn with its seed, S =
+    6, 32 directions, Maxwell) at N = 32, taken from a 256-cell batch of mixed
+    N: three of them against the oracle's full evaluation."""
+    torch = torch_cuda
+    from paper_2105_08806_amd import pgc
+    S, M = 6.0, 32
+    cells = I.cell_maxwellians_2d(256, seed=8806)
+    coeffs, probs = cell_coeffs(cells, S, M)
+    c32 = [x.astype(np.float32).astype(np.float64) for x in coeffs]
+    b = pgc.Batch([c["N"] for c in cells], scale=S, n_sigma=M, nufft_tol=TOL)
+    say("workload batch of 256 cells against the oracle at N = 32")
+    q = b.unpack(b.coeffs_to_q(b.pack(c32)))
+    torch.cuda.synchronize()
+    picks = [i for i, c in enumerate(cells) if c["N"] == 32][:3]
+    for i in picks:
+        ref, _, _ = probs[32].collision(c32[i])
+        r = rel(q[i], ref)
+        say("  cell %d (N=32) rel-L2 vs oracle %.3e" % (i, r))
+        assert r <= FP32_TOL
+    b.close()
