@@ -135,7 +135,19 @@ typedef struct pgc_plan_desc {
                              bit-identical (another plan of the same descriptor agrees to rounding:
                              the order of the points within a bin is set by the plan-time scatter).
                              Needs the binned vector gain (gain_mode 0 or 2; UNSUPPORTED with 1
-                             or 3) */
+                             or 3) and the whole point index (UNSUPPORTED when index_bytes
+                             streams it) */
+    int64_t index_bytes;  /* device memory for the point ids of the binned gain (the sort of the
+                             merged points by footprint corner that Sec. 4.3's on-the-fly evaluation
+                             leaves to each evaluation).  0: the plan builds the whole index once
+                             (8 bytes per merged point) when the device has room for it, and
+                             streams it within a quarter of the free memory otherwise.  > 0: when
+                             the whole index needs more than index_bytes, the directions are split
+                             into chunks whose ids fit in index_bytes (at least one direction per
+                             chunk) and every evaluation sorts each chunk's points into bins again
+                             (one more pass that regenerates every point) before spreading them.
+                             The plan keeps per chunk only the point count of every bin.  Negative:
+                             PGC_ERR_INVALID_ARG */
 } pgc_plan_desc;
 
 typedef struct pgc_plan_s* pgc_plan;
@@ -161,6 +173,9 @@ typedef struct pgc_plan_info {
                                gain) from the exact offset, in units of the offset's range [-1, 1] */
     int32_t deterministic;  /* 1: fixed-order tile gather (bit-identical repeats) */
     int64_t tile_bytes;     /* deterministic plans: workspace of the per-run footprint tiles */
+    int32_t index_chunks;   /* binned gain: 1 = the whole point index, built at plan time; > 1 =
+                               direction chunks sorted again at every evaluation */
+    int64_t index_bytes;    /* binned gain: bytes of the point-id buffer (the largest chunk) */
 } pgc_plan_info;
 
 /* Human-readable text of a status code (static storage, never NULL). */

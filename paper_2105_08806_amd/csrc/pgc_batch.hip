@@ -838,11 +838,14 @@ pgc_status pgc_batch_create(const pgc_plan_desc* base, int32_t n_cells, const in
             d.n_modes = g.N;
             d.m_v = 0;
             d.gain_mode = pgc::kGainBinned;
+            d.index_bytes = 0;
             st = pgc_plan_create(&d, stream, &g.plan);
             if (st != PGC_OK) break;
             const Plan& p = g.plan->p;
             if (b->W == 0) b->W = p.W;
-            if (p.W != b->W || !pgc::tile_supported(p.W, 1) || p.gain_mode != pgc::kGainBinned) {
+            // the lane kernel walks every cell group over the whole point index
+            if (p.W != b->W || !pgc::tile_supported(p.W, 1) || p.gain_mode != pgc::kGainBinned ||
+                p.bins.n_chunks != 1) {
                 st = PGC_ERR_UNSUPPORTED;
                 break;
             }

@@ -383,6 +383,8 @@ struct BinGeo {
     int off;     // bin index = t0 + off
     int W;
     int64_t n_items;  // (s, a_1, pencil) generation items
+    int s0, ns;       // directions [s0, s0 + ns) of the generation items
+    unsigned long long id_cap;  // scatter: ids the buffer holds (no write at or past it)
 };
 
 template <int DIM>

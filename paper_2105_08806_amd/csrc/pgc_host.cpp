@@ -82,6 +82,19 @@ double beta_for(int W, double upsample)
     return 0.98 * kPi * W * (1.0 - 0.5 / upsample);
 }
 
+// Directions per chunk of a streamed point index: as many as the budget holds
+// (at least one), spread evenly over the chunks, each chunk under 2^32 ids so
+// that 32-bit cursors address it; -1 when one direction alone exceeds that.
+int stream_dirs(const Plan& p, int64_t budget)
+{
+    const int64_t per_dir = p.n_points / p.n_sigma;
+    const int64_t max32 = 0xffffffffll / per_dir;
+    if (max32 < 1) return -1;
+    const int64_t dpc = std::min(max32, std::max<int64_t>(1, budget / (8 * per_dir)));
+    const int64_t chunks = (p.n_sigma + dpc - 1) / dpc;
+    return (int)((p.n_sigma + chunks - 1) / chunks);
+}
+
 int width_for(double tol, double upsample)
 {
     for (int W = 4; W <= kMaxWidth; ++W)
@@ -158,6 +171,7 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
         return PGC_ERR_INVALID_ARG;
     if (d.gain_mode < 0 || d.gain_mode > 3) return PGC_ERR_INVALID_ARG;
     if (d.deterministic != 0 && d.deterministic != 1) return PGC_ERR_INVALID_ARG;
+    if (d.index_bytes < 0) return PGC_ERR_INVALID_ARG;
 
     p.dim = d.dim;
     p.N = d.n_modes;
@@ -287,6 +301,14 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
     p.np = p.ni * (p.ni + 1) / 2;
     p.n_triples = (int64_t)p.n_sigma * p.nid * p.nid;
     p.n_points = (int64_t)p.n_sigma * ipow(p.np, p.dim);
+    // a budget below the whole index streams it in direction chunks (the
+    // deterministic gather needs the whole index)
+    p.index_budget = d.index_bytes;
+    if (p.gain_mode == kGainBinned && p.index_budget > 0 && p.n_points * 8 > p.index_budget) {
+        if (p.deterministic) return PGC_ERR_UNSUPPORTED;
+        p.bins.dirs_per_chunk = stream_dirs(p, p.index_budget);
+        if (p.bins.dirs_per_chunk < 0) return PGC_ERR_UNSUPPORTED;
+    }
     // a unit is (a_1, s): the smaller first-dimension node of a pair and a direction
     p.n_units = (int64_t)p.n_sigma * p.ni;
 
@@ -565,6 +587,8 @@ pgc_status from_hip(hipError_t e) { return status_of(e); }
 // Sort the merged points by the base cell of their footprint: count per bin on
 // the device, prefix sums and the work-item list on the host, then scatter the
 // point ids.  Temporaries are freed before returning.
+hipError_t build_stream(Plan& p, hipStream_t s);
+
 hipError_t build_bins(Plan& p, hipStream_t s)
 {
     BinIndex& B = p.bins;
@@ -572,13 +596,15 @@ hipError_t build_bins(Plan& p, hipStream_t s)
     B.off = p.W / 2;
     int64_t nbins = 1;
     for (int l = 0; l < p.dim; ++l) nbins *= B.nb;
+    B.nbins = nbins;
+    if (B.dirs_per_chunk > 0) return build_stream(p, s);
     unsigned int* count = nullptr;
     unsigned long long* cursor = nullptr;
     std::vector<unsigned int> hc(nbins);  // before the temporary, which nothing below may leak
     hipError_t e = hipMalloc(&count, nbins * sizeof(unsigned int));
     if (e != hipSuccess) return e;
     e = hipMemsetAsync(count, 0, nbins * sizeof(unsigned int), s);
-    if (e == hipSuccess) e = launch_bin_build(p, count, nullptr, nullptr, 0, s);
+    if (e == hipSuccess) e = launch_bin_build(p, count, nullptr, nullptr, nullptr, 0, 0, p.n_sigma, s);
     if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), count, nbins * sizeof(unsigned int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(count);
@@ -621,7 +647,8 @@ hipError_t build_bins(Plan& p, hipStream_t s)
         ic[k] = items[k].count;
     }
     void* d = nullptr;
-    if ((e = dev_alloc(p, &d, std::max<size_t>(1, total) * sizeof(unsigned long long))) != hipSuccess) return e;
+    B.id_bytes = (int64_t)std::max<unsigned long long>(1, total) * 8;
+    if ((e = dev_alloc(p, &d, (size_t)B.id_bytes)) != hipSuccess) return e;
     B.ids = static_cast<unsigned long long*>(d);
     if ((e = dev_alloc(p, &d, std::max<size_t>(1, ib.size()) * sizeof(int))) != hipSuccess) return e;
     B.item_bin = static_cast<int*>(d);
@@ -670,10 +697,104 @@ hipError_t build_bins(Plan& p, hipStream_t s)
     }
     if ((e = hipMalloc(&cursor, nbins * sizeof(unsigned long long))) != hipSuccess) return e;
     e = hipMemcpyAsync(cursor, begin.data(), nbins * sizeof(unsigned long long), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_bin_build(p, nullptr, cursor, B.ids, 1, s);
+    if (e == hipSuccess) e = launch_bin_build(p, nullptr, cursor, nullptr, B.ids, 1, 0, p.n_sigma, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(cursor);
+    B.n_chunks = 1;
+    B.chunk_s0 = {0, p.n_sigma};
+    B.chunk_item0 = {0, B.n_items};
     return e;
+}
+
+// The streamed index.  The point positions depend on the plan only, so the
+// plan counts the points of every chunk per bin once and keeps each chunk's
+// bin offsets and run list (runs of at most kBinChunk ids, the long ones
+// first); an evaluation scatters one chunk's ids into the shared buffer and
+// spreads them before the next chunk overwrites it.
+hipError_t build_stream(Plan& p, hipStream_t s)
+{
+    BinIndex& B = p.bins;
+    const int64_t nbins = B.nbins;
+    const int dpc = B.dirs_per_chunk;
+    const int D = (p.n_sigma + dpc - 1) / dpc;
+    const int64_t per_dir = p.n_points / p.n_sigma;
+    B.n_chunks = D;
+    B.chunk_s0.assign(D + 1, p.n_sigma);
+    for (int c = 0; c < D; ++c) B.chunk_s0[c] = c * dpc;
+
+    std::vector<unsigned int> hc((size_t)D * nbins);  // before the temporary, which nothing below may leak
+    unsigned int* count = nullptr;
+    hipError_t e = hipMalloc(&count, hc.size() * sizeof(unsigned int));
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(count, 0, hc.size() * sizeof(unsigned int), s);
+    for (int c = 0; c < D && e == hipSuccess; ++c)
+        e = launch_bin_build(p, count + (size_t)c * nbins, nullptr, nullptr, nullptr, 0, B.chunk_s0[c],
+                             B.chunk_s0[c + 1] - B.chunk_s0[c], s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hc.data(), count, hc.size() * sizeof(unsigned int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(count);
+    if (e != hipSuccess) return e;
+
+    // per chunk: bin offsets in place of the counts, then the runs
+    std::vector<int> ib;
+    std::vector<long long> ibeg;
+    std::vector<int> ic;
+    B.chunk_item0.assign(D + 1, 0);
+    int64_t max_ids = 1;
+    struct Item {
+        int bin;
+        long long begin;
+        int count;
+    };
+    std::vector<Item> items;
+    for (int c = 0; c < D; ++c) {
+        unsigned int* h = hc.data() + (size_t)c * nbins;
+        items.clear();
+        unsigned long long total = 0;
+        for (int64_t b = 0; b < nbins; ++b) {
+            const unsigned int n = h[b];
+            for (unsigned int o = 0; o < n; o += kBinChunk)
+                items.push_back({(int)b, (long long)(total + o), (int)std::min<unsigned int>(kBinChunk, n - o)});
+            h[b] = (unsigned int)total;
+            total += n;
+        }
+        if ((int64_t)total != per_dir * (B.chunk_s0[c + 1] - B.chunk_s0[c])) return hipErrorUnknown;
+        max_ids = std::max<int64_t>(max_ids, (int64_t)total);
+        std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.count > y.count; });
+        B.chunk_item0[c] = (int64_t)ib.size();
+        for (const Item& it : items) {
+            ib.push_back(it.bin);
+            ibeg.push_back(it.begin);
+            ic.push_back(it.count);
+        }
+    }
+    B.chunk_item0[D] = (int64_t)ib.size();
+    B.n_items = (int64_t)ib.size();
+    B.id_bytes = max_ids * 8;
+
+    void* d = nullptr;
+    if ((e = dev_alloc(p, &d, (size_t)B.id_bytes)) != hipSuccess) return e;
+    B.ids = static_cast<unsigned long long*>(d);
+    if ((e = dev_alloc(p, &d, hc.size() * sizeof(unsigned int))) != hipSuccess) return e;
+    B.chunk_begin = static_cast<unsigned int*>(d);
+    if ((e = dev_alloc(p, &d, nbins * sizeof(unsigned int))) != hipSuccess) return e;
+    B.cursor = static_cast<unsigned int*>(d);
+    if ((e = dev_alloc(p, &d, std::max<size_t>(1, ib.size()) * sizeof(int))) != hipSuccess) return e;
+    B.item_bin = static_cast<int*>(d);
+    if ((e = dev_alloc(p, &d, std::max<size_t>(1, ibeg.size()) * sizeof(long long))) != hipSuccess) return e;
+    B.item_begin = static_cast<long long*>(d);
+    if ((e = dev_alloc(p, &d, std::max<size_t>(1, ic.size()) * sizeof(int))) != hipSuccess) return e;
+    B.item_count = static_cast<int*>(d);
+    if ((e = hipMemcpyAsync(B.chunk_begin, hc.data(), hc.size() * sizeof(unsigned int), hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
+        return e;
+    if (!ib.empty()) {
+        if ((e = hipMemcpyAsync(B.item_bin, ib.data(), ib.size() * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(B.item_begin, ibeg.data(), ibeg.size() * sizeof(long long), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(B.item_count, ic.data(), ic.size() * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+    }
+    return hipStreamSynchronize(s);  // the host vectors go out of scope
 }
 
 hipError_t allocate(Plan& p, hipStream_t s)
@@ -780,6 +901,17 @@ hipError_t allocate(Plan& p, hipStream_t s)
         void* g64 = nullptr;
         PGC_TRY(dev_alloc(p, &g64, p.ngd * sizeof(double)));
         p.ws.grid64 = static_cast<double*>(g64);
+        if (p.index_budget == 0 && !p.deterministic) {
+            // no budget given: the whole index when the device has room for it
+            // (and its run list), else streamed within a quarter of the free memory
+            size_t free_b = 0, total_b = 0;
+            PGC_TRY(hipMemGetInfo(&free_b, &total_b));
+            const int64_t whole = p.n_points * 8;
+            if (whole + whole / 64 + (int64_t(1) << 30) > (int64_t)free_b) {
+                const int dpc = stream_dirs(p, (int64_t)free_b / 4);
+                if (dpc > 0) p.bins.dirs_per_chunk = dpc;
+            }
+        }
         e = build_bins(p, s);
         if (e == hipErrorOutOfMemory && p.auto_gain && p.kernel != PGC_KERNEL_ANISO && !p.deterministic) {
             // the bin index does not fit: fall back to LDS slabs
@@ -917,6 +1049,10 @@ pgc_status pgc_plan_query(pgc_plan plan, pgc_plan_info* info)
     info->offset_fit_err = p.cellfit_err;
     info->deterministic = p.deterministic ? 1 : 0;
     info->tile_bytes = p.bins.tile_bytes;
+    if (p.gain_mode == pgc::kGainBinned) {
+        info->index_chunks = p.bins.n_chunks;
+        info->index_bytes = p.bins.id_bytes;
+    }
     info->workspace_bytes = p.workspace_bytes;
     return PGC_OK;
 }

@@ -69,6 +69,17 @@ struct BinIndex {
     int* bin_items = nullptr;   // n_items
     double* tiles = nullptr;    // n_items x W^d
     int64_t tile_bytes = 0;
+    // streamed index: direction chunks [chunk_s0[c], chunk_s0[c + 1]) whose ids
+    // are sorted into `ids` again at every evaluation; the chunk's runs are the
+    // items [chunk_item0[c], chunk_item0[c + 1]) (begin relative to the chunk)
+    int n_chunks = 1;
+    int dirs_per_chunk = 0;      // 0: the whole index
+    std::vector<int> chunk_s0;
+    std::vector<int64_t> chunk_item0;
+    unsigned int* chunk_begin = nullptr;  // n_chunks x nbins  first slot of every bin in its chunk
+    unsigned int* cursor = nullptr;       // nbins  scatter cursors of the chunk being sorted
+    int64_t nbins = 0;
+    int64_t id_bytes = 0;        // bytes of `ids`
 };
 constexpr int kBinChunk = 8192;
 constexpr int kMaxBinnedNodes = 256;        // n_i: 8-bit node fields of a point id
@@ -122,6 +133,7 @@ struct Plan {
     int np = 0;  // unordered node pairs per dimension, n_i (n_i + 1) / 2
     int64_t nid = 0, Nd = 0, ngd = 0, n_units = 0, units_per_chunk = 0, n_triples = 0;
     int64_t n_points = 0;  // merged points per evaluation, n_sigma * np^d
+    int64_t index_budget = 0;  // bytes for the binned gain's point ids (0: whole index if it fits)
     int64_t tmp_elems = 0;
 
     // host tables (FP64)
@@ -178,10 +190,12 @@ hipError_t launch_dense_synthesis(const Plan& p, const double* c64, int nb, cons
 hipError_t launch_dense_loss(const Plan& p, int nb, const DenseBufs& b, hipStream_t s);
 hipError_t launch_dense_grid_to_modes(const Plan& p, const double* grid, int nb, const DenseBufs& b,
                                       hipStream_t s);
-// plan time: mode 0 counts points per bin into `count`, mode 1 scatters ids
-// through the per-bin cursors
+// mode 0 counts the points of directions [s0, s0 + ns) per bin into `count`;
+// mode 1 scatters their ids through 64-bit per-bin cursors (the whole index,
+// plan time), mode 2 through 32-bit ones (a chunk of a streamed index)
 hipError_t launch_bin_build(const Plan& p, unsigned int* count, unsigned long long* cursor,
-                            unsigned long long* ids, int mode, hipStream_t s);
+                            unsigned int* cursor32, unsigned long long* ids, int mode, int s0, int ns,
+                            hipStream_t s);
 hipError_t launch_project(const Plan& p, const double* f_nodes, void* coeffs, hipStream_t s);
 hipError_t launch_moments(const Plan& p, const void* coeffs, double* out, hipStream_t s);
 hipError_t launch_eval(const Plan& p, const void* coeffs, const double* v, int64_t n, double* out,

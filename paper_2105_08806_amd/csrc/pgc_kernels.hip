@@ -528,11 +528,15 @@ __global__ void __launch_bounds__(spread_max_threads<T>()) gain_spread(GainParam
 // vectors in LDS and accumulates the bin's W^d footprint in registers, one
 // lane per footprint column, before a single flush of W^d global FP64 atomics.
 
-// plan time: MODE 0 counts the points of every bin, MODE 1 scatters their ids
+// Over the points of directions [s0, s0 + ns): MODE 0 counts the points of
+// every bin, MODE 1 scatters their ids through 64-bit cursors (the whole
+// index, plan time), MODE 2 through 32-bit ones (one chunk of a streamed index,
+// every evaluation).
 template <typename T, int DIM, int MODE>
 __global__ void __launch_bounds__(256) bin_points(GainParams<T> P, BinGeo B,
                                                   unsigned int* __restrict__ count,
                                                   unsigned long long* __restrict__ cursor,
+                                                  unsigned int* __restrict__ cursor32,
                                                   unsigned long long* __restrict__ ids)
 {
     const int np = P.np;
@@ -542,8 +546,8 @@ __global__ void __launch_bounds__(256) bin_points(GainParams<T> P, BinGeo B,
          item += (int64_t)gridDim.x * blockDim.x) {
         const int pencil = (int)(item % npencil);
         const int64_t us = item / npencil;
-        const int s = (int)(us % P.n_sigma);
-        const int a1 = (int)(us / P.n_sigma);
+        const int s = B.s0 + (int)(us % B.ns);
+        const int a1 = (int)(us / B.ns);
         const int p2 = (DIM == 2) ? pencil : pencil / np;
         const int p3 = (DIM == 2) ? 0 : pencil % np;
         for (int b1 = a1; b1 < P.ni; ++b1) {
@@ -554,15 +558,19 @@ __global__ void __launch_bounds__(256) bin_points(GainParams<T> P, BinGeo B,
             const int64_t bin = point_bin<DIM>(xs, B);
             if constexpr (MODE == 0) {
                 atomicAdd(count + bin, 1u);
-            } else {
+            } else if constexpr (MODE == 1) {
                 const unsigned long long slot = atomicAdd(cursor + bin, 1ull);
-                ids[slot] = pack_id(s, a1, b1, p2, p3);
+                if (slot < B.id_cap) ids[slot] = pack_id(s, a1, b1, p2, p3);
+            } else {
+                const unsigned int slot = atomicAdd(cursor32 + bin, 1u);
+                if (slot < B.id_cap) ids[slot] = pack_id(s, a1, b1, p2, p3);
             }
         }
     }
 }
 
 struct BinItems {
+    int64_t n_items;             // work items of this launch
     const int* bin;              // bin of each work item
     const long long* begin;      // first id of the item
     const int* count;            // ids in the item (<= 64 * batches)
@@ -982,6 +990,12 @@ __global__ void fill_zero(double* __restrict__ x, int64_t n)
     if (i < n) x[i] = 0.0;
 }
 
+__global__ void copy_u32(const unsigned int* __restrict__ src, unsigned int* __restrict__ dst, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
 // grid[m] = sum_c partial[c][m], FP64 accumulation in chunk order
 __global__ void reduce_partials(const double* __restrict__ partial, double* __restrict__ grid,
                                 int64_t ngd, int n_chunks)
@@ -1315,18 +1329,18 @@ GainParams<T> gain_params(const Plan& p, const Workspace& ws)
 template <typename T, int DIM, int W>
 hipError_t binned_launch(const Plan& p, const GainParams<T>& gp, const BinItems& bi, hipStream_t s)
 {
-    if (p.bins.n_items == 0) return hipSuccess;
+    if (bi.n_items == 0) return hipSuccess;
     if (p.kernel == PGC_KERNEL_ANISO)
-        hipLaunchKernelGGL((gain_binned<T, DIM, W, true>), dim3((unsigned)p.bins.n_items), dim3(64), 0, s, gp, bi);
+        hipLaunchKernelGGL((gain_binned<T, DIM, W, true>), dim3((unsigned)bi.n_items), dim3(64), 0, s, gp, bi);
     else
-        hipLaunchKernelGGL((gain_binned<T, DIM, W, false>), dim3((unsigned)p.bins.n_items), dim3(64), 0, s, gp, bi);
+        hipLaunchKernelGGL((gain_binned<T, DIM, W, false>), dim3((unsigned)bi.n_items), dim3(64), 0, s, gp, bi);
     return hipGetLastError();
 }
 
 hipError_t mfma_dispatch(const Plan& p, const GainParams<double>& gp, const BinItems& bi, hipStream_t s)
 {
-    if (p.bins.n_items == 0) return hipSuccess;
-    const dim3 grid((unsigned)p.bins.n_items);
+    if (bi.n_items == 0) return hipSuccess;
+    const dim3 grid((unsigned)bi.n_items);
     switch (p.W) {
 #define PGC_M_CASE(w) \
     case w: hipLaunchKernelGGL(gain_binned_mfma<w>, grid, dim3(64), 0, s, gp, bi); break;
@@ -1367,31 +1381,37 @@ hipError_t binned_dispatch(const Plan& p, const GainParams<T>& gp, const BinItem
     }
 }
 
-// plan time: count and scatter the merged points into their bins
+// count or scatter the merged points of directions [s0, s0 + ns) into their bins
 template <typename T>
-hipError_t bin_build_t(const Plan& p, unsigned int* count, unsigned long long* cursor,
-                       unsigned long long* ids, int mode, hipStream_t s)
+hipError_t bin_build_t(const Plan& p, unsigned int* count, unsigned long long* cursor, unsigned int* cursor32,
+                       unsigned long long* ids, int mode, int s0, int ns, hipStream_t s)
 {
+    if (s0 < 0 || ns < 1 || s0 + ns > p.n_sigma || mode < 0 || mode > 2) return hipErrorInvalidValue;
     const GainParams<T> gp = gain_params<T>(p, p.ws);
     BinGeo bg;
     bg.nb = p.bins.nb;
     bg.off = p.bins.off;
     bg.W = p.W;
+    bg.s0 = s0;
+    bg.ns = ns;
+    bg.id_cap = (unsigned long long)(p.bins.id_bytes / 8);
     const int64_t npencil = p.dim == 2 ? p.np : (int64_t)p.np * p.np;
-    bg.n_items = (int64_t)p.n_sigma * p.ni * npencil;
+    bg.n_items = (int64_t)ns * p.ni * npencil;
     const int64_t want = (bg.n_items + 255) / 256;
     const unsigned blocks = (unsigned)std::min<int64_t>(want, 65536);
+#define PGC_BIN_LAUNCH(dim_, mode_)                                                                        \
+    hipLaunchKernelGGL((bin_points<T, dim_, mode_>), dim3(blocks), dim3(256), 0, s, gp, bg, count, cursor, \
+                       cursor32, ids)
     if (p.dim == 2) {
-        if (mode == 0)
-            hipLaunchKernelGGL((bin_points<T, 2, 0>), dim3(blocks), dim3(256), 0, s, gp, bg, count, cursor, ids);
-        else
-            hipLaunchKernelGGL((bin_points<T, 2, 1>), dim3(blocks), dim3(256), 0, s, gp, bg, count, cursor, ids);
+        if (mode == 0) PGC_BIN_LAUNCH(2, 0);
+        else if (mode == 1) PGC_BIN_LAUNCH(2, 1);
+        else PGC_BIN_LAUNCH(2, 2);
     } else {
-        if (mode == 0)
-            hipLaunchKernelGGL((bin_points<T, 3, 0>), dim3(blocks), dim3(256), 0, s, gp, bg, count, cursor, ids);
-        else
-            hipLaunchKernelGGL((bin_points<T, 3, 1>), dim3(blocks), dim3(256), 0, s, gp, bg, count, cursor, ids);
+        if (mode == 0) PGC_BIN_LAUNCH(3, 0);
+        else if (mode == 1) PGC_BIN_LAUNCH(3, 1);
+        else PGC_BIN_LAUNCH(3, 2);
     }
+#undef PGC_BIN_LAUNCH
     return hipGetLastError();
 }
 
@@ -1418,24 +1438,40 @@ hipError_t gain_t(const Plan& p, const Workspace& ws, hipStream_t s)
     if (p.gain_mode == kGainBinned) {
         if (!p.deterministic)
             hipLaunchKernelGGL(fill_zero, dim3(blocks_for(p.ngd, 256)), dim3(256), 0, s, ws.grid64, p.ngd);
-        BinItems bi;
-        bi.bin = p.bins.item_bin;
-        bi.begin = p.bins.item_begin;
-        bi.count = p.bins.item_count;
-        bi.ids = p.bins.ids;
-        bi.grid = ws.grid64;
-        bi.tiles = p.deterministic ? p.bins.tiles : nullptr;
-        bi.geo.nb = p.bins.nb;
-        bi.geo.off = p.bins.off;
-        bi.geo.W = p.W;
-        bi.geo.n_items = 0;
-        if constexpr (sizeof(T) == sizeof(double)) {
-            if (p.mfma) e = mfma_dispatch(p, gp, bi, s);
-            else e = (p.dim == 2) ? binned_dispatch<T, 2>(p, gp, bi, s) : binned_dispatch<T, 3>(p, gp, bi, s);
-        } else {
-            e = (p.dim == 2) ? binned_dispatch<T, 2>(p, gp, bi, s) : binned_dispatch<T, 3>(p, gp, bi, s);
+        const BinIndex& B = p.bins;
+        for (int c = 0; c < B.n_chunks; ++c) {
+            if (B.dirs_per_chunk > 0) {
+                // streamed index: sort this chunk's points into the id buffer
+                hipLaunchKernelGGL(copy_u32, dim3(blocks_for(B.nbins, 256)), dim3(256), 0, s,
+                                   B.chunk_begin + (int64_t)c * B.nbins, B.cursor, B.nbins);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+                e = launch_bin_build(p, nullptr, nullptr, B.cursor, B.ids, 2, B.chunk_s0[c],
+                                     B.chunk_s0[c + 1] - B.chunk_s0[c], s);
+                if (e != hipSuccess) return e;
+            }
+            const int64_t i0 = B.chunk_item0[c];
+            BinItems bi;
+            bi.n_items = B.chunk_item0[c + 1] - i0;
+            bi.bin = B.item_bin + i0;
+            bi.begin = B.item_begin + i0;
+            bi.count = B.item_count + i0;
+            bi.ids = B.ids;
+            bi.grid = ws.grid64;
+            bi.tiles = p.deterministic ? B.tiles : nullptr;
+            bi.geo.nb = B.nb;
+            bi.geo.off = B.off;
+            bi.geo.W = p.W;
+            bi.geo.n_items = 0;
+            bi.geo.s0 = B.chunk_s0[c];
+            bi.geo.ns = B.chunk_s0[c + 1] - B.chunk_s0[c];
+            if constexpr (sizeof(T) == sizeof(double)) {
+                if (p.mfma) e = mfma_dispatch(p, gp, bi, s);
+                else e = (p.dim == 2) ? binned_dispatch<T, 2>(p, gp, bi, s) : binned_dispatch<T, 3>(p, gp, bi, s);
+            } else {
+                e = (p.dim == 2) ? binned_dispatch<T, 2>(p, gp, bi, s) : binned_dispatch<T, 3>(p, gp, bi, s);
+            }
+            if (e != hipSuccess) return e;
         }
-        if (e != hipSuccess) return e;
         if (p.deterministic) {
             const dim3 g(blocks_for(p.ngd, 256));
             if (p.dim == 2)
@@ -1526,10 +1562,12 @@ hipError_t launch_gain(const Plan& p, const Workspace& ws, hipStream_t s)
 }
 
 hipError_t launch_bin_build(const Plan& p, unsigned int* count, unsigned long long* cursor,
-                            unsigned long long* ids, int mode, hipStream_t s)
+                            unsigned int* cursor32, unsigned long long* ids, int mode, int s0, int ns,
+                            hipStream_t s)
 {
-    return p.precision == PGC_PRECISION_FP64 ? bin_build_t<double>(p, count, cursor, ids, mode, s)
-                                             : bin_build_t<float>(p, count, cursor, ids, mode, s);
+    return p.precision == PGC_PRECISION_FP64
+               ? bin_build_t<double>(p, count, cursor, cursor32, ids, mode, s0, ns, s)
+               : bin_build_t<float>(p, count, cursor, cursor32, ids, mode, s0, ns, s);
 }
 
 hipError_t launch_combine(const Plan& p, const Workspace& ws, void* q, void* qplus, hipStream_t s)

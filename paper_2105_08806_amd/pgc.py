@@ -48,6 +48,7 @@ class PlanDesc(ctypes.Structure):
         ("gain_mode", ctypes.c_int32),
         ("kernel_aniso", ctypes.c_double),
         ("deterministic", ctypes.c_int32),
+        ("index_bytes", ctypes.c_int64),
     ]
 
 
@@ -64,6 +65,7 @@ class PlanInfo(ctypes.Structure):
         ("gain_mode", ctypes.c_int32), ("n_bin_items", ctypes.c_int64),
         ("offset_fit_err", ctypes.c_double), ("deterministic", ctypes.c_int32),
         ("tile_bytes", ctypes.c_int64),
+        ("index_chunks", ctypes.c_int32), ("index_bytes", ctypes.c_int64),
     ]
 
 

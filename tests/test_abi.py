@@ -128,7 +128,7 @@ def test_plan_descriptor_rejections_without_a_device():
            dict(kernel=pgc.KERNEL_ANISO, kernel_gamma=2.0), dict(kernel=3), dict(nufft_tol=-1e-6), dict(upsample=1.2),
            dict(upsample=5.0), dict(kernel_width=3), dict(kernel_width=99), dict(slab_planes=-1),
            dict(n_chunks=-2), dict(block_threads=300), dict(gain_mode=4), dict(gain_mode=-1),
-           dict(deterministic=2), dict(deterministic=-1),
+           dict(deterministic=2), dict(deterministic=-1), dict(index_bytes=-1),
            dict(n_sigma=7),                                  # a circle rule needs antipodal pairs
            dict(n_sigma=0), dict(sphere=9),
            dict(dim=3),                                      # the circle rule is a 2D rule
@@ -159,6 +159,8 @@ def test_plan_descriptor_rejections_without_a_device():
     assert _create_status(pgc, L, deterministic=1, gain_mode=3, dim=3, sphere=pgc.SPHERE_PRODUCT_3D,
                           n_theta=2, n_phi=4) == 2
     assert _create_status(pgc, L, kernel=pgc.KERNEL_ANISO, kernel_aniso=0.5, gain_mode=1) == 2
+    # the fixed-order gather needs the whole point index, not a streamed one
+    assert _create_status(pgc, L, deterministic=1, index_bytes=1) == 2
 
 
 def test_gemm_argument_errors_without_a_device():
