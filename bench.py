@@ -56,10 +56,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_plan(pgc, precision):
+def make_plan(pgc, precision, **extra):
     return pgc.Plan(dim=3, n_modes=N, scale=S, map=pgc.MAP_LOG, kernel=pgc.KERNEL_MAXWELL,
                     sphere=pgc.SPHERE_PRODUCT_3D, n_theta=N_THETA, n_phi=N_PHI,
-                    precision=precision)
+                    precision=precision, **extra)
 
 
 def time_variant(torch, pgc, inputs, precision, steps, warmup):
@@ -898,6 +898,14 @@ def main():
             log("profiled %s: W=%d points=%d" % ("fp64" if prec == pgc.FP64 else "fp32",
                                                  plan.info.kernel_width, plan.info.n_points))
             plan.close()
+        # the FP64 plan with its point index streamed within 8 GB (8 chunks)
+        plan = make_plan(pgc, pgc.FP64, index_bytes=8 * 10 ** 9)
+        c = plan.project(inputs.bkw_f(T0, plan.interior_velocities()))
+        for _ in range(2):
+            plan.coeffs_to_q(c)
+        torch.cuda.synchronize()
+        log("profiled fp64 streamed: %d chunks" % plan.info.index_chunks)
+        plan.close()
         # the batched workload in the lane-per-cell scheme (64 cells per wave)
         cells = inputs.cell_maxwellians_2d(4096, seed=8806)
         rng = np.random.default_rng(8806)
