@@ -44,8 +44,8 @@
  *  - A plan must not be used by two calls that can run concurrently.
  *  - By default the fast path's gain accumulates with FP64 atomics whose
  *    order varies, so repeated evaluations agree to rounding, not bit for bit;
- *    a plan created with deterministic = 1, and the direct algorithm
- *    (pgc_direct_*), repeat bit for bit.
+ *    a plan created with deterministic = 1, a batch created from such a
+ *    descriptor, and the direct algorithm (pgc_direct_*), repeat bit for bit.
  *  - Every call returns a pgc_status.  On an error return the outputs are
  *    untouched (for argument errors) or unspecified (device errors).  No C++
  *    exception crosses this interface.  PGC_ERR_NUMERIC needs a result on the
@@ -131,9 +131,9 @@ typedef struct pgc_plan_desc {
                              grid with FP64 atomics (fastest; repeated evaluations agree to
                              rounding).  1: every run writes its tile to plan workspace
                              (n_bin_items x W^d doubles) and a gather adds the tiles of every grid
-                             cell in a fixed order, so repeated evaluations of the plan are
-                             bit-identical (another plan of the same descriptor agrees to rounding:
-                             the order of the points within a bin is set by the plan-time scatter).
+                             cell in a fixed order, and the plan sorts the point ids inside every
+                             bin once after building the index, so the evaluations of every plan
+                             of the same descriptor are bit-identical (on one device type).
                              Needs the binned vector gain (gain_mode 0 or 2; UNSUPPORTED with 1
                              or 3) and the whole point index (UNSUPPORTED when index_bytes
                              streams it) */
@@ -312,6 +312,7 @@ typedef struct pgc_batch_info {
     int32_t group_major;        /* 1: work units run through all bin runs of one cell group before the
                                    next group (the G rows in use stay in L2); 0: bin-run major */
     double major_ms[2];         /* autotuner: gain time at the chosen C and order, bin-run / cell-group major */
+    int32_t deterministic;      /* 1: every cell through its group's deterministic plan */
 } pgc_batch_info;
 
 /* Build a batch of n_cells cells; n_modes_host[c] is the N of cell c.
@@ -320,6 +321,13 @@ typedef struct pgc_batch_info {
  * best so far) and keeps the fastest, then times the other bin-run order and
  * the other unit order at that C and keeps each only when it is over 3%
  * faster; otherwise C = 1, raster order, bin-run major.  `stream` orders the set-up work, which the call synchronises.
+ * With base->deterministic = 1 the batch evaluates every cell through its
+ * group's plan (created with deterministic = 1) instead of the batched gain:
+ * each cell's Q is then bit-identical to pgc_coeffs_to_q on a plan created
+ * from the same descriptor with that cell's N (gain_mode 0 or 2), at the
+ * speed of one plan evaluation per cell.  Such a batch takes no offsets_dev
+ * (UNSUPPORTED) and cannot be captured (UNSUPPORTED); the tile and order
+ * settings have no effect on it.
  * Errors: INVALID_ARG, UNSUPPORTED (dim != 2, precision != FP32, more than 8
  * distinct N, a kernel width outside 4..8), OUT_OF_MEMORY, DEVICE. */
 pgc_status pgc_batch_create(const pgc_plan_desc* base, int32_t n_cells, const int32_t* n_modes_host,

@@ -26,7 +26,7 @@ FLAGS = [
     "-Wno-unused-command-line-argument",
 ]
 SOURCES = ["pgc_kernels.hip", "pgc_host.cpp", "pgc_batch.hip", "pgc_mlp.hip", "pgc_direct.hip",
-           "pgc_static.hip", "pgc_transport.hip"]
+           "pgc_static.hip", "pgc_transport.hip", "pgc_sort.hip"]
 
 
 def _compile(src: str) -> str:

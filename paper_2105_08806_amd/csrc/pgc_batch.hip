@@ -555,6 +555,7 @@ struct pgc_batch_s {
     hipGraphExec_t exec = nullptr;
     std::vector<void*> allocations;
     int64_t workspace_bytes = 0;
+    bool deterministic = false;  // every cell through its group's deterministic plan
 };
 
 namespace {
@@ -694,6 +695,20 @@ hipError_t enqueue_all(const pgc_batch_s& b, const float* packed, const int64_t*
     return hipSuccess;
 }
 
+// Deterministic batches: every cell through its group's plan (created with
+// deterministic = 1), whose gain adds footprint tiles in a fixed order and
+// whose bins hold their ids sorted, so each cell's Q equals an unbatched
+// evaluation by a plan of the same descriptor bit for bit.
+pgc_status enqueue_cells(const pgc_batch_s& b, const float* packed, float* packed_q, hipStream_t s)
+{
+    for (const BatchGroup& G : b.groups)
+        for (int c : G.cells) {
+            const pgc_status st = pgc_coeffs_to_q(G.plan, packed + b.offsets[c], packed_q + b.offsets[c], nullptr, s);
+            if (st != PGC_OK) return st;
+        }
+    return PGC_OK;
+}
+
 // the lane-per-cell scheme indexes the cell-minor G with 32-bit offsets
 bool lanes_fit(const pgc_batch_s& b)
 {
@@ -803,6 +818,7 @@ pgc_status pgc_batch_create(const pgc_plan_desc* base, int32_t n_cells, const in
     try {
         b = new pgc_batch_s();
         b->n_cells = n_cells;
+        b->deterministic = base->deterministic == 1;
         b->cell_modes.assign(n_modes_host, n_modes_host + n_cells);
         std::map<int, std::vector<int>, std::greater<int>> by_n;  // largest N first
         for (int c = 0; c < n_cells; ++c) {
@@ -893,7 +909,8 @@ pgc_status pgc_batch_create(const pgc_plan_desc* base, int32_t n_cells, const in
                                     hipMemcpyHostToDevice, s)) == hipSuccess &&
                 (e = batch_alloc_n(*b, &b->groups_dev, (int64_t)b->groups.size())) == hipSuccess &&
                 (e = batch_alloc_n(*b, &b->counter, 1)) == hipSuccess) {
-                e = autotune_on ? autotune(*b, s) : set_units(*b, 1, s);
+                // a deterministic batch never runs the batched gain: nothing to tune
+                e = autotune_on && !b->deterministic ? autotune(*b, s) : set_units(*b, 1, s);
                 if (e == hipSuccess) e = hipStreamSynchronize(s);
             }
         }
@@ -942,6 +959,7 @@ pgc_status pgc_batch_query(pgc_batch b, pgc_batch_info* info)
     info->major_ms[0] = b->major_ms[0];
     info->major_ms[1] = b->major_ms[1];
     info->has_graph = b->exec != nullptr;
+    info->deterministic = b->deterministic ? 1 : 0;
     return PGC_OK;
 }
 
@@ -983,6 +1001,11 @@ pgc_status pgc_batch_coeffs_to_q(pgc_batch b, const void* packed_coeffs_dev, con
                                  void* packed_q_dev, void* stream)
 {
     if (!b || !packed_coeffs_dev || !packed_q_dev) return PGC_ERR_INVALID_ARG;
+    if (b->deterministic) {
+        if (offsets_dev) return PGC_ERR_UNSUPPORTED;  // the cells are enqueued from host offsets
+        return enqueue_cells(*b, static_cast<const float*>(packed_coeffs_dev), static_cast<float*>(packed_q_dev),
+                             static_cast<hipStream_t>(stream));
+    }
     const int64_t* off = offsets_dev ? offsets_dev : b->offsets_dev;
     return pgc::status_of(enqueue_all(*b, static_cast<const float*>(packed_coeffs_dev), off,
                                       static_cast<float*>(packed_q_dev), static_cast<hipStream_t>(stream)));
@@ -992,6 +1015,7 @@ pgc_status pgc_batch_capture(pgc_batch b, const void* packed_coeffs_dev, const i
                              void* packed_q_dev, void* stream)
 {
     if (!b || !packed_coeffs_dev || !packed_q_dev) return PGC_ERR_INVALID_ARG;
+    if (b->deterministic) return PGC_ERR_UNSUPPORTED;
     const int64_t* off = offsets_dev ? offsets_dev : b->offsets_dev;
     drop_graph(*b);
     hipStream_t user = static_cast<hipStream_t>(stream);

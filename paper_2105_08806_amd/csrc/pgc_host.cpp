@@ -700,6 +700,12 @@ hipError_t build_bins(Plan& p, hipStream_t s)
     if (e == hipSuccess) e = launch_bin_build(p, nullptr, cursor, nullptr, B.ids, 1, 0, p.n_sigma, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(cursor);
+    if (e == hipSuccess && p.deterministic) {
+        // the scatter's order inside a bin varies between builds: sort it away
+        // (58 id bits: b1 8, a1 8, s 10, p2 16, p3 16)
+        begin.push_back(total);
+        e = sort_bin_ids(B.ids, begin, 58, s);
+    }
     B.n_chunks = 1;
     B.chunk_s0 = {0, p.n_sigma};
     B.chunk_item0 = {0, B.n_items};

@@ -196,6 +196,10 @@ hipError_t launch_dense_grid_to_modes(const Plan& p, const double* grid, int nb,
 hipError_t launch_bin_build(const Plan& p, unsigned int* count, unsigned long long* cursor,
                             unsigned int* cursor32, unsigned long long* ids, int mode, int s0, int ns,
                             hipStream_t s);
+// deterministic plans: sort the point ids inside every bin by value (begin:
+// nbins + 1 offsets into ids; the ids use bits [0, end_bit))
+hipError_t sort_bin_ids(unsigned long long* ids, const std::vector<unsigned long long>& begin, int end_bit,
+                        hipStream_t s);
 hipError_t launch_project(const Plan& p, const double* f_nodes, void* coeffs, hipStream_t s);
 hipError_t launch_moments(const Plan& p, const void* coeffs, double* out, hipStream_t s);
 hipError_t launch_eval(const Plan& p, const void* coeffs, const double* v, int64_t n, double* out,

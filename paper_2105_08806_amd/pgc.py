@@ -79,6 +79,7 @@ class BatchInfo(ctypes.Structure):
         ("tuned_ms", ctypes.c_double * 7), ("has_graph", ctypes.c_int32), ("scheme", ctypes.c_int32),
         ("spatial_order", ctypes.c_int32), ("order_ms", ctypes.c_double * 2),
         ("group_major", ctypes.c_int32), ("major_ms", ctypes.c_double * 2),
+        ("deterministic", ctypes.c_int32),
     ]
 
 
