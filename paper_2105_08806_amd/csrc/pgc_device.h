@@ -385,18 +385,40 @@ struct BinGeo {
     int64_t n_items;  // (s, a_1, pencil) generation items
     int s0, ns;       // directions [s0, s0 + ns) of the generation items
     unsigned long long id_cap;  // scatter: ids the buffer holds (no write at or past it)
+    const double* vthr;         // nb + 2 velocity thresholds V_k, k = -off - 1 ..
+    float h_inv, half_w;        // 1/h and W/2 for the FP32 estimate
 };
 
-template <int DIM>
-__device__ __forceinline__ int64_t point_bin(const double* xs, const BinGeo& B)
+// Bin coordinate of one velocity component: the smallest k with v >= V_k
+// (V decreasing), then k + off clamped to the bins.  An FP32 evaluation of the
+// transform angle places k to within one of the answer, and two FP64
+// comparisons with the table settle it.  A velocity within 1e-9 S of the
+// deciding threshold (symmetric node pairs put many points exactly on a cell
+// boundary) takes ceil(z/h - W/2) of the FP64 angle instead, as the slab
+// scheme does: at a boundary both footprints are valid and differ by the
+// kernel's edge value, so every scheme must pick the same one.
+template <typename T>
+__device__ __forceinline__ int bin_coord(double v, const GainParams<T>& P, const BinGeo& B)
 {
-    int64_t bin = 0;
-    for (int l = 0; l < DIM; ++l) {
-        int t = (int)ceil(xs[l]) + B.off;
-        t = t < 0 ? 0 : (t >= B.nb ? B.nb - 1 : t);
-        bin = bin * B.nb + t;
+    const float t = (float)(v * P.inv_S64);
+    const float z = P.map == 0 ? 2.0f * atanf(expf(-t)) : atan2f(1.0f, t);
+    int k = (int)ceilf(z * B.h_inv - B.half_w);
+    const int kmin = -B.off - 1, kmax = B.nb - B.off;  // the table's k range
+    k = k < kmin + 1 ? kmin + 1 : (k > kmax - 1 ? kmax - 1 : k);
+    const double* V = B.vthr - kmin;
+    const double lo = V[k - 1], hi = V[k];
+    const bool above_lo = v >= lo, above_hi = v >= hi;
+    const double near = above_lo ? v - lo : (above_hi ? fmin(v - hi, lo - v) : hi - v);
+    if (near <= 1e-9 / P.inv_S64) {
+        double zz;
+        T m2;
+        map_point((T)v, P, zz, m2);
+        k = (int)ceil(zz * P.h_inv64 - 0.5 * B.W);
+    } else {
+        k = above_lo ? k - 1 : (above_hi ? k : k + 1);
     }
-    return bin;
+    const int c = k + B.off;
+    return c < 0 ? 0 : (c >= B.nb ? B.nb - 1 : c);
 }
 
 }  // namespace

@@ -338,6 +338,35 @@ pgc_status resolve(const pgc_plan_desc& d, Plan& p)
 
 // ---------------------------------------------------------------- tables
 
+// The footprint corner of a point in one dimension is ceil(z/h - W/2), the
+// smallest k with z <= (k + W/2) h.  The transform angle z decreases with the
+// velocity (r = 0: z = 2 atan(exp(-v/S)); r = 1: z = atan2(1, v/S)), so that
+// is the smallest k with v >= V_k, V_k = -S ln tan(Z_k/2) (r = 0) or
+// S cot Z_k (r = 1), Z_k = (k + W/2) h; +inf where Z_k <= 0, -inf where
+// Z_k >= pi.  The table holds V_k for k = -off - 1 .. n_h + 2 - off (the bin
+// coordinate k + off runs over -1 .. n_h + 2 before the clamp to the bins), in
+// long double rounded once, so that binning needs no transcendental per point.
+void build_bin_thresholds(Plan& p)
+{
+    const int nb = p.nh + 2, off = p.W / 2;
+    const long double pi = acosl(-1.0L), h = pi / p.nh, hw = 0.5L * p.W;
+    p.bin_vthr.assign((size_t)nb + 2, 0.0);
+    for (int j = 0; j < nb + 2; ++j) {
+        const int k = j - off - 1;
+        const long double Z = (k + hw) * h;
+        double V;
+        if (Z <= 0.0L)
+            V = HUGE_VAL;
+        else if (Z >= pi)
+            V = -HUGE_VAL;
+        else if (p.map == PGC_MAP_LOG)
+            V = (double)(-(long double)p.S * logl(tanl(0.5L * Z)));
+        else
+            V = (double)((long double)p.S * cosl(Z) / sinl(Z));
+        p.bin_vthr[j] = V;
+    }
+}
+
 // For every bin coordinate c of one dimension (footprint corner t0 = c - W/2,
 // int division) the points of the cell have z in ((t0 - 1 + W/2) h, (t0 + W/2) h]
 // and kernel offset s = 2 t0 + W - 1 - 2 z / h.  With z = pi/2 - 2 atan(w) the
@@ -453,6 +482,7 @@ void build_tables(Plan& p)
                 p.kpoly_eo[(size_t)NE * H + (size_t)j * HP + a] = p.poly[(size_t)(2 * j + 1) * W + a];
     }
     build_cell_fits(p);
+    build_bin_thresholds(p);
 
     // Fourier transform of the kernel in z units, psi^(k) = int psi(x/alpha) cos(k x) dx,
     // alpha = W h / 2, by a 256-point Gauss-Legendre rule in x/alpha
@@ -830,6 +860,7 @@ hipError_t allocate(Plan& p, hipStream_t s)
         PGC_TRY(upload64(p, &p.dt.poly64, p.poly, s));
     PGC_TRY(upload64(p, &p.dt.kpoly_eo, p.kpoly_eo, s));
     PGC_TRY(upload64(p, &p.dt.cellfit, p.cellfit, s));
+    PGC_TRY(upload64(p, &p.dt.bin_vthr, p.bin_vthr, s));
     PGC_TRY(upload(p, &p.dt.sigma, p.sigma, s));
     {
         // W_s b0 S^d: the constant factors of every point's weight, one rounding in FP32

@@ -42,6 +42,7 @@ struct DeviceTables {
     double* poly64 = nullptr; // the same in FP64 (aliases poly for FP64 plans)
     double* kpoly_eo = nullptr;  // even/odd parts of the cells a < W/2 (FP64)
     double* cellfit = nullptr;   // (n_h + 2) x (deg + 3) kernel-offset fits per grid cell (FP64)
+    double* bin_vthr = nullptr;  // n_h + 4 velocity thresholds of the footprint corners (FP64)
     void* sigma = nullptr;    // n_sigma x dim
     void* wfac = nullptr;     // n_sigma  W_s b0 S^d (direction weight, kernel constant, map scale)
     void* slab_vlo = nullptr; // n_slabs  v'_1 window of each slab
@@ -139,7 +140,7 @@ struct Plan {
     // host tables (FP64)
     std::vector<double> xi_all, v_all, w_all;
     std::vector<double> v1, w1, mu21, C, CT, E, poly, slab_vlo, slab_vhi, mom;
-    std::vector<double> kpoly_eo, cellfit;
+    std::vector<double> kpoly_eo, cellfit, bin_vthr;
     double cellfit_err = 0.0;  // largest deviation of a cell fit from the exact offset
 
     size_t elt = 8;

@@ -541,7 +541,6 @@ __global__ void __launch_bounds__(256) bin_points(GainParams<T> P, BinGeo B,
 {
     const int np = P.np;
     const int npencil = (DIM == 2) ? np : np * np;
-    const double halfW = 0.5 * B.W;
     for (int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; item < B.n_items;
          item += (int64_t)gridDim.x * blockDim.x) {
         const int pencil = (int)(item % npencil);
@@ -551,11 +550,11 @@ __global__ void __launch_bounds__(256) bin_points(GainParams<T> P, BinGeo B,
         const int p2 = (DIM == 2) ? pencil : pencil / np;
         const int p3 = (DIM == 2) ? 0 : pencil % np;
         for (int b1 = a1; b1 < P.ni; ++b1) {
-            T q;
-            double xs[DIM];
-            int64_t si;
-            point_geometry<T, DIM>(P, s, a1, b1, p2, p3, halfW, q, xs, si);
-            const int64_t bin = point_bin<DIM>(xs, B);
+            T q, vp[DIM];
+            point_velocity<T, DIM>(P, s, a1, b1, p2, p3, q, vp);
+            int64_t bin = 0;
+#pragma unroll
+            for (int l = 0; l < DIM; ++l) bin = bin * B.nb + bin_coord<T>((double)vp[l], P, B);
             if constexpr (MODE == 0) {
                 atomicAdd(count + bin, 1u);
             } else if constexpr (MODE == 1) {
@@ -1395,6 +1394,9 @@ hipError_t bin_build_t(const Plan& p, unsigned int* count, unsigned long long* c
     bg.s0 = s0;
     bg.ns = ns;
     bg.id_cap = (unsigned long long)(p.bins.id_bytes / 8);
+    bg.vthr = p.dt.bin_vthr;
+    bg.h_inv = (float)(1.0 / p.h);
+    bg.half_w = 0.5f * (float)p.W;
     const int64_t npencil = p.dim == 2 ? p.np : (int64_t)p.np * p.np;
     bg.n_items = (int64_t)ns * p.ni * npencil;
     const int64_t want = (bg.n_items + 255) / 256;
