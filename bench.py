@@ -144,17 +144,23 @@ def traffic_for(kernel_tag, path=TRAFFIC_PATH):
 
 def counter_per_dispatch(csv_path, counter):
     """Mean value of `counter` per dispatch, by kernel name, from a rocprofv3
-    counter-collection CSV."""
+    counter-collection CSV, over the dispatches of the largest grid of each
+    kernel (the profile run's whole-index plans; the chunks of its streamed
+    plan launch the same kernel on smaller grids)."""
     import csv
-    tot, cnt = {}, {}
+    rows = {}
     with open(csv_path) as fp:
         for row in csv.DictReader(fp):
             if row["Counter_Name"] != counter:
                 continue
-            k = row["Kernel_Name"]
-            tot[k] = tot.get(k, 0.0) + float(row["Counter_Value"])
-            cnt[k] = cnt.get(k, 0) + 1
-    return {k: tot[k] / cnt[k] for k in tot}
+            grid = int(float(row.get("Grid_Size") or 0))
+            rows.setdefault(row["Kernel_Name"], []).append((grid, float(row["Counter_Value"])))
+    out = {}
+    for k, v in rows.items():
+        big = max(g for g, _ in v)
+        vals = [x for g, x in v if g == big]
+        out[k] = sum(vals) / len(vals)
+    return out
 
 
 def write_traffic(fetch_csv, write_csv, cfetch_csv, cwrite_csv, path=TRAFFIC_PATH):

@@ -25,10 +25,12 @@ def test_more_than_one_gpu_is_refused():
 
 def _counter_csv(path, counter, rows):
     with open(path, "w", newline="") as fp:
-        w = csv.DictWriter(fp, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w = csv.DictWriter(fp, fieldnames=["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
         w.writeheader()
-        for name, value in rows:
-            w.writerow({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": value})
+        for row in rows:
+            name, value = row[:2]
+            grid = row[2] if len(row) > 2 else 64
+            w.writerow({"Kernel_Name": name, "Grid_Size": grid, "Counter_Name": counter, "Counter_Value": value})
 
 
 def test_traffic_bytes_from_counters(tmp_path):
@@ -52,6 +54,16 @@ def test_traffic_bytes_from_counters(tmp_path):
     assert json.load(open(out)) == rec
     assert bench.traffic_for("gain_binned_fp64_3d_n32", path=out) == e["bytes_per_launch"]
     assert bench.traffic_for("gain_batched_lanes_2d_4096", path=out) is None
+
+
+def test_traffic_counts_the_largest_grid_of_a_kernel(tmp_path):
+    """The profile run also launches the gain per chunk of a streamed index,
+    on smaller grids: only the dispatches of the largest grid are averaged."""
+    fp64 = bench.TRAFFIC_KERNELS["gain_binned_fp64_3d_n32"][0] + "(pgc::GainParams<double>, pgc::BinItems)"
+    path = os.path.join(str(tmp_path), "f.csv")
+    _counter_csv(path, "FETCH_SIZE", [(fp64, 1000.0, 9000), (fp64, 3000.0, 9000), (fp64, 10.0, 5000),
+                                      (fp64, 12.0, 4000)])
+    assert bench.counter_per_dispatch(path, "FETCH_SIZE") == {fp64: 2000.0}
 
 
 def test_traffic_of_other_sources_is_not_reported(tmp_path):
