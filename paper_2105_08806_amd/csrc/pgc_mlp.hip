@@ -51,6 +51,13 @@ __device__ __forceinline__ float from_bf16(bf16 b) { return __uint_as_float((uns
 
 constexpr int kBM = 64, kBN = 64, kBK = 64, kPad = 8;
 
+// Column of element (r, k) of a staged 64 x 64 tile: the eight 8-element
+// groups of a row are permuted by row bits 3..5 (an XOR swizzle).  Rows 16 B
+// apart that sit eight apart map to the same LDS banks; the transposed stores
+// write eight such rows at one k, which the swizzle spreads over eight banks.
+// Every 8-element group stays contiguous, so the 16-byte accesses stay whole.
+__device__ __forceinline__ int swz(int r, int k) { return k ^ (((r >> 3) & 7) << 3); }
+
 // C[M x N] = op(A) op(B) (+ bias[n]), or C += ... when `accumulate`; A and B
 // BF16, C FP32, all row-major:
 //   op(A)[m][k] = TA ? A[k lda + m] : A[m lda + k]
@@ -61,8 +68,8 @@ constexpr int kBM = 64, kBN = 64, kBK = 64, kPad = 8;
 // zeros or the values to accumulate onto).  Each 64-deep K slice is two
 // v_mfma_f32_16x16x32_bf16 per 16 x 16 tile: lane l supplies row (column)
 // l % 16 at k = 32 s + 8 (l / 16) .. + 7 and holds rows 4 (l / 16) + r, column
-// l % 16 of the result.  With `vec` (16-byte aligned rows) the next slice's
-// global loads are issued before the current slice's products.
+// l % 16 of the result.  With `vec` (16-byte aligned rows) the global loads
+// of the slice after next are issued before the current slice's products.
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
                                                  const bf16* __restrict__ A, int lda,
@@ -92,13 +99,15 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
             const int kq = kk + 8 * (lane >> 4);
             bf16x8m a[2], b[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                a[i] = __builtin_bit_cast(bf16x8m,
-                                          *reinterpret_cast<const u16x8*>(&sA[wm + i * 16 + (lane & 15)][kq]));
+            for (int i = 0; i < 2; ++i) {
+                const int r = wm + i * 16 + (lane & 15);
+                a[i] = __builtin_bit_cast(bf16x8m, *reinterpret_cast<const u16x8*>(&sA[r][swz(r, kq)]));
+            }
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                b[j] = __builtin_bit_cast(bf16x8m,
-                                          *reinterpret_cast<const u16x8*>(&sB[wn + j * 16 + (lane & 15)][kq]));
+            for (int j = 0; j < 2; ++j) {
+                const int r = wn + j * 16 + (lane & 15);
+                b[j] = __builtin_bit_cast(bf16x8m, *reinterpret_cast<const u16x8*>(&sB[r][swz(r, kq)]));
+            }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -156,32 +165,70 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
                 }
             }
         };
+        // a slice inside the matrix on every side: unconditional 16-byte loads,
+        // with no branch whose own waits would drain the loads in flight
+        const bool inside_mn = m0 + kBM <= M && n0 + kBN <= N;
+        auto gload_full = [&](int k0, u16x8* va, u16x8* vb) {
+#pragma unroll
+            for (int h = 0; h < CH; ++h) {
+                const int c = tid + 256 * h;
+                va[h] = !TA ? *reinterpret_cast<const u16x8*>(A + (size_t)(m0 + (c >> 3)) * lda + k0 + (c & 7) * 8)
+                            : *reinterpret_cast<const u16x8*>(A + (size_t)(k0 + (c >> 3)) * lda + m0 + (c & 7) * 8);
+                vb[h] = TB ? *reinterpret_cast<const u16x8*>(B + (size_t)(n0 + (c >> 3)) * ldb + k0 + (c & 7) * 8)
+                           : *reinterpret_cast<const u16x8*>(B + (size_t)(k0 + (c >> 3)) * ldb + n0 + (c & 7) * 8);
+            }
+        };
         auto sstore = [&](const u16x8* va, const u16x8* vb) {
 #pragma unroll
             for (int h = 0; h < CH; ++h) {
                 const int c = tid + 256 * h;
                 if (!TA) {
-                    *reinterpret_cast<u16x8*>(&sA[c >> 3][(c & 7) * 8]) = va[h];
+                    *reinterpret_cast<u16x8*>(&sA[c >> 3][swz(c >> 3, (c & 7) * 8)]) = va[h];
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) sA[(c & 7) * 8 + q][c >> 3] = va[h][q];
+                    for (int q = 0; q < 8; ++q) sA[(c & 7) * 8 + q][swz((c & 7) * 8 + q, c >> 3)] = va[h][q];
                 }
                 if (TB) {
-                    *reinterpret_cast<u16x8*>(&sB[c >> 3][(c & 7) * 8]) = vb[h];
+                    *reinterpret_cast<u16x8*>(&sB[c >> 3][swz(c >> 3, (c & 7) * 8)]) = vb[h];
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) sB[(c & 7) * 8 + q][c >> 3] = vb[h][q];
+                    for (int q = 0; q < 8; ++q) sB[(c & 7) * 8 + q][swz((c & 7) * 8 + q, c >> 3)] = vb[h][q];
                 }
             }
         };
-        u16x8 va[CH], vb[CH];
-        gload(kbeg, va, vb);
-        for (int k0 = kbeg; k0 < kend; k0 += kBK) {
-            sstore(va, vb);
-            __syncthreads();
-            if (k0 + kBK < kend) gload(k0 + kBK, va, vb);
-            compute();
-            __syncthreads();
+        const int nsl = (kend - kbeg) / kBK;
+        if (inside_mn && nsl > 0 && kbeg + nsl * kBK == kend) {
+            // whole slices inside the matrix: two register stages, so a slice's
+            // loads are issued two slices before it is staged.  The loop body has
+            // no branch around a load (the loads past the last slice reload it),
+            // so the compiler waits for each stage's own loads only.
+            const int klast = kend - kBK;
+            u16x8 va0[CH], vb0[CH], va1[CH], vb1[CH];
+            gload_full(kbeg, va0, vb0);
+            gload_full(min(kbeg + kBK, klast), va1, vb1);
+            for (int i = 0; i < nsl; i += 2) {
+                const int k0 = kbeg + i * kBK;
+                sstore(va0, vb0);
+                __syncthreads();
+                gload_full(min(k0 + 2 * kBK, klast), va0, vb0);
+                compute();
+                __syncthreads();
+                sstore(va1, vb1);
+                __syncthreads();
+                gload_full(min(k0 + 3 * kBK, klast), va1, vb1);
+                if (i + 1 < nsl) compute();  // uniform over the workgroup
+                __syncthreads();
+            }
+        } else {
+            u16x8 va[CH], vb[CH];
+            gload(kbeg, va, vb);
+            for (int k0 = kbeg; k0 < kend; k0 += kBK) {
+                sstore(va, vb);
+                __syncthreads();
+                if (k0 + kBK < kend) gload(k0 + kBK, va, vb);
+                compute();
+                __syncthreads();
+            }
         }
     } else {
         for (int k0 = kbeg; k0 < kend; k0 += kBK) {
@@ -197,7 +244,7 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
                 const int gm = m0 + m, gk = k0 + k;
                 bf16 v = 0;
                 if (gm < M && gk < kend) v = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
-                sA[m][k] = v;
+                sA[m][swz(m, k)] = v;
             }
             for (int e = tid; e < kBN * kBK; e += 256) {
                 int n, k;
@@ -211,7 +258,7 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
                 const int gn = n0 + n, gk = k0 + k;
                 bf16 v = 0;
                 if (gn < N && gk < kend) v = TB ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
-                sB[n][k] = v;
+                sB[n][swz(n, k)] = v;
             }
             __syncthreads();
             compute();
@@ -653,9 +700,14 @@ hipError_t gemm(int M, int N, int K, const bf16* A, int lda, bool ta, const bf16
         return hipGetLastError();
     }
     const int tiles = ((M + pgc::kBM - 1) / pgc::kBM) * ((N + pgc::kBN - 1) / pgc::kBN);
-    // split K until the tiles cover the device about four times over
+    // split K until the tiles cover the device twice over, while the atomic
+    // traffic of the partial tiles (split x the bytes of C) stays below the
+    // bytes of the operands: a product whose output is large next to its
+    // operands (the 13824-wide layers) is bound by writing C, not by the
+    // matrix cores, and runs unsplit
     int split = 1;
-    while (tiles * split < 1024 && K / (split * 2) >= 256) split *= 2;
+    const double operand_bytes = 2.0 * ((double)M * K + (double)N * K), c_bytes = 4.0 * (double)M * N;
+    while (tiles * split < 512 && K / (split * 2) >= 256 && c_bytes * split * 2 <= operand_bytes) split *= 2;
     const int kc = ((K + split - 1) / split + pgc::kBK - 1) / pgc::kBK * pgc::kBK;
     split = (K + kc - 1) / kc;
     if (split > 1 && !accumulate)
