@@ -138,6 +138,80 @@ def test_3d_n32_direction_subset_sampled(torch_cuda, prec):
     plan.close()
 
 
+def load_c3_golden():
+    """Stored oracle values of the 3D BKW workload (tests/golden/c3_bkw3d_n32_pairs.txt,
+    written by tests/golden/make_golden.py from the oracle alone): the 256
+    sampled multi-indices and, per antipodal direction pair (a, b) of the 8 x 8
+    product rule, Q+ and Q- at them."""
+    lines = open(os.path.join(GOLDEN, "c3_bkw3d_n32_pairs.txt")).read().splitlines()
+    kidx = None
+    pairs = []
+    for i, line in enumerate(lines):
+        if line.startswith("kidx "):
+            kidx = np.array([[int(x) for x in t.split(",")] for t in line.split()[1:]], dtype=np.int64)
+        elif line.startswith("pair "):
+            _, _, a, b = line.split()
+            qp = np.array([float(x) for x in lines[i + 1].split()[1:]])
+            qm = np.array([float(x) for x in lines[i + 2].split()[1:]])
+            pairs.append(((int(a), int(b)), qp, qm))
+    return kidx, pairs
+
+
+def c3_against_golden(torch, prec, pairs_used):
+    """GPU Q and Q+ of the 3D BKW workload over the directions of `pairs_used`
+    (a list of (pair, Q+, Q-)) against the sum of their stored oracle values."""
+    from paper_2105_08806_amd import pgc
+    N, S = 32, 5.0
+    sg, sw = O.sphere_product_rule(8, 8)
+    idx = [x for (ab, _, _) in pairs_used for x in ab]
+    if len(idx) == 64:
+        plan = pgc.Plan(dim=3, n_modes=N, scale=S, sphere=pgc.SPHERE_PRODUCT_3D, n_theta=8, n_phi=8,
+                        precision=prec)
+    else:
+        plan = pgc.Plan(dim=3, n_modes=N, scale=S, precision=prec, sigma=sg[idx], sigma_w=sw[idx])
+    ora = O.Problem(3, N, S, 0, sphere=sg, sphere_w=sw)
+    c = ora.project(I.bkw_f(6.5, ora.interior_velocities()))
+    cin = c.astype(np.float32).astype(np.float64) if prec else c
+    q, qp = plan.coeffs_to_q(torch.tensor(cin, dtype=plan.dtype, device="cuda"), want_qplus=True)
+    torch.cuda.synchronize()
+    plan.close()
+    return q.double().cpu().numpy(), qp.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_3d_n32_vs_stored_oracle(torch_cuda, prec):
+    """The 3D BKW workload against the stored oracle values at 256
+    coefficients (the product set {0, 1, 4, 15, 30, 31}^3 and 40 random
+    multi-indices): with the full 64-direction rule, and with the first four
+    antipodal pairs alone (the gain is linear in the direction rule).
+
+    FP64: Q and Q+ within 1e-11.  FP32 (the plan reads the input rounded to
+    FP32; the stored values are the FP64 input's): Q+ within 1e-5, and the
+    error of Q within 1e-5 of the norm of Q+.  The FP32 spreading is accurate
+    relative to the gain it sums (1e-6 of sum |q| by default); at t = 6.5 the
+    BKW state is near equilibrium, Q is a difference of gain and loss about
+    two orders of magnitude below them at these samples, which weight the
+    high modes, and relative to Q alone the same error reads 3.5e-5.  Over all
+    32768 coefficients the FP32 Q is 4.3e-6 from the FP64 path
+    (test_3d_n32_full_rule_properties), which is itself within 1e-11 of the oracle
+    here."""
+    kidx, pairs = load_c3_golden()
+    assert len(kidx) == 256 and len(pairs) == 32
+    for used in (pairs, pairs[:4]):
+        q, qp = c3_against_golden(torch_cuda, prec, used)
+        ref_p = sum(p for _, p, _ in used)
+        ref_q = ref_p - sum(m for _, _, m in used)
+        got_q, got_p = q[tuple(kidx.T)], qp[tuple(kidx.T)]
+        r_q, r_p = rel(got_q, ref_q), rel(got_p, ref_p)
+        r_q_gain = float(np.linalg.norm(got_q - ref_q) / np.linalg.norm(ref_p))
+        say("3D N=32 prec=%d, %d directions, 256 coefficients: rel-L2 Q = %.3e (over |Q+| %.3e), Q+ = %.3e"
+            % (prec, 2 * len(used), r_q, r_q_gain, r_p))
+        if prec == 0:
+            assert r_q <= 1e-11 and r_p <= 1e-11
+        else:
+            assert r_p <= 1e-5 and r_q_gain <= 1e-5
+
+
 def test_3d_n32_full_rule_properties(torch_cuda):
     """The full 64-direction workload: the product rule is invariant under
     v_l -> -v_l and v_1 <-> v_2 and the BKW data are isotropic, so odd-index
