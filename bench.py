@@ -484,10 +484,30 @@ def batched_variant(torch, pgc, inputs, np, n_cells, reps):
            "plain_fp64_est_s_per_batch": fp64_s, "speedup_vs_plain_fp64": fp64_s / (ms / 1e3),
            "cells_per_wave": b.info.cells_per_wave, "group_major": b.info.group_major,
            "points_per_s": b.info.n_points / (ms / 1e3)}
+    # two N = 32 cells (their FP32 input and batched Q) for the oracle leg
+    sample = [(coeffs[i].float().double().cpu().numpy(), qs[i])
+              for i in [i for i, c in enumerate(cells) if c["N"] == 32][:2]]
     b.close()
     for p in plans.values():
         p.close()
-    return out
+    return out, sample
+
+
+def batched_cpu_leg(np, sample):
+    """cpu_baseline of the batched workload: the CPU oracle's full evaluation
+    of two of its N = 32 cells (S = 6, Maxwell, 32 directions) on the host
+    cores, and the batched FP32 result's rel-L2 against it."""
+    import oracle as O
+    sg, sw = O.circle_rule(32)
+    p = O.Problem(2, 32, 6.0, 0, sphere=sg, sphere_w=sw)
+    errs, t = [], time.time()
+    for c, q in sample:
+        q_ora, _, _ = p.collision(c)
+        errs.append(float(np.linalg.norm(q - q_ora) / np.linalg.norm(q_ora)))
+    dt = time.time() - t
+    return {"value": len(sample) / dt, "unit": "cell Q-evals/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": "full evaluations of %d of the batch's N=32 cells (%.1f s)" % (len(sample), dt),
+            "gpu_rel_l2_vs_oracle_max": max(errs)}
 
 
 def direct_variant(torch, pgc, inputs, np, n_cells, reps):
@@ -1021,7 +1041,10 @@ def main():
         line["variants"]["fast_path_options_3d_n32"] = fast_path_options(torch, pgc, inputs, np)
         line["variants"]["split_step_2d_n32"] = split_step_variant(torch, pgc, inputs, np)
     if not args.no_batched:
-        line["variants"]["batched"] = batched_variant(torch, pgc, inputs, np, args.batch_cells, args.batch_reps)
+        bat, bat_sample = batched_variant(torch, pgc, inputs, np, args.batch_cells, args.batch_reps)
+        if not args.no_cpu_baseline:
+            bat["cpu_baseline"] = batched_cpu_leg(np, bat_sample)
+        line["variants"]["batched"] = bat
     if not args.no_direct:
         line["variants"]["direct"] = direct_variant(torch, pgc, inputs, np, args.direct_cells, args.direct_reps)
     if not args.no_surrogate:
