@@ -6,6 +6,7 @@ library.  It is run once, on the CPU; the GPU parity tests read the files.
 
     python tests/golden/make_golden.py c2     # 2D N=64 VHS, all 4096 coefficients
     python tests/golden/make_golden.py c3     # 3D N=32 BKW, 256 coefficients, all 64 directions
+    python tests/golden/make_golden.py a3     # 3D N=32, angle-dependent rate, one direction pair
 
 c2: the 2D variable-hard-sphere workload (64 modes, S = 6, B = |u|/(2 pi),
     32 circle directions, two Maxwellians of mass 1/2 at +-(1.5, 0) with
@@ -35,6 +36,7 @@ from paper_2105_08806_amd import inputs as I  # noqa: E402
 
 C2_FILE = os.path.join(HERE, "c2_vhs2d_n64.txt")
 C3_FILE = os.path.join(HERE, "c3_bkw3d_n32_pairs.txt")
+A3_FILE = os.path.join(HERE, "a3_aniso3d_n32_pair.txt")
 
 
 def digest(a):
@@ -113,6 +115,37 @@ def make_c3():
             f.write("qminus %s\n" % " ".join("%.17e" % x for x in qm))
 
 
+def a3_setup():
+    """3D, 32 modes, S = 5, the angle-dependent rate B = b0 |u| (1 + 2 cos^2 theta),
+    one antipodal pair of the 8 x 8 product rule off the axes (direction 13 and
+    its antipode), a two-Maxwellian input; 22 multi-indices."""
+    N, S = 32, 5.0
+    sg, sw = O.sphere_product_rule(8, 8)
+    s0 = 13
+    s1 = int(np.argmin(np.linalg.norm(sg + sg[s0], axis=1)))
+    ora = O.Problem(3, N, S, 0, kernel="aniso", aniso=2.0, gamma=1.0, sphere=sg[[s0, s1]], sphere_w=sw[[s0, s1]])
+    comps = [(0.6, (0.5, -0.3, 0.1), 0.7), (0.4, (-0.8, 0.6, 0.2), 1.2)]
+    c = ora.project(I.mixture(ora.interior_velocities(), comps))
+    rnd = np.random.default_rng(3233).integers(0, N, size=(20, 3))
+    kidx = np.concatenate([[[0, 0, 0], [N - 1, N - 1, N - 1]], rnd]).astype(np.int32)
+    return ora, c, kidx, (s0, s1)
+
+
+def make_a3():
+    ora, c, kidx, (s0, s1) = a3_setup()
+    t = time.time()
+    qp, qm = ora.collision_at(c, kidx)
+    print("a3: %d coefficients in %.0f s" % (len(kidx), time.time() - t), flush=True)
+    with open(A3_FILE, "w") as f:
+        f.write("# 3D N=32, S=5, B = b0 |u| (1 + 2 cos^2 theta), directions %d and %d of the 8x8 product rule, "
+                "two Maxwellians\n" % (s0, s1))
+        f.write("# written by tests/golden/make_golden.py a3 from the FP64 CPU oracle (oracle/)\n")
+        f.write("# input sha256[:16] %s\n" % digest(c))
+        f.write("kidx %s\n" % " ".join("%d,%d,%d" % tuple(k) for k in kidx))
+        f.write("qplus %s\n" % " ".join("%.17e" % x for x in qp))
+        f.write("qminus %s\n" % " ".join("%.17e" % x for x in qm))
+
+
 if __name__ == "__main__":
-    for what in sys.argv[1:] or ["c2", "c3"]:
-        {"c2": make_c2, "c3": make_c3}[what]()
+    for what in sys.argv[1:] or ["c2", "c3", "a3"]:
+        {"c2": make_c2, "c3": make_c3, "a3": make_a3}[what]()

@@ -9,6 +9,8 @@ which scales with Q+ rather than with Q; near equilibrium Q is a few percent
 of Q+, so that comparison is normalised by |Q+| (the near-equilibrium
 reading of the parity metric), with the same 1e-11 bar.
 """
+import hashlib
+import os
 import sys
 
 import numpy as np
@@ -178,6 +180,45 @@ def test_fast_path_angle_dependent_rate_3d_n24_sampled(torch_cuda):
     got_q, got_qp = q[tuple(kidx.T)], qp[tuple(kidx.T)]
     r, rp = rel_l2(got_q, ap - am), rel_l2(got_qp, ap)
     say("  %d sampled coefficients: rel-L2 Q = %.3e, Q+ = %.3e" % (len(kidx), r, rp))
+    assert r <= FP64_TOL and rp <= FP64_TOL
+    plan.close()
+
+
+def test_fast_path_angle_dependent_rate_3d_n32_stored(torch_cuda):
+    """The fast path with an angle-dependent rate at 32 modes (S = 5, B = b0 |u|
+    (1 + 2 cos^2 theta), direction 13 of the 8 x 8 product rule and its
+    antipode, a two-Maxwellian input) against oracle values stored once by
+    tests/golden/make_golden.py a3 at 22 coefficients: the oracle needs
+    minutes for them at this size."""
+    torch = torch_cuda
+    import oracle as O
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "a3_aniso3d_n32_pair.txt")
+    rows = {}
+    for line in open(path).read().splitlines():
+        if line.startswith("# input sha256[:16] "):
+            rows["sha"] = line.split()[-1]
+        elif not line.startswith("#"):
+            key, *vals = line.split()
+            rows[key] = vals
+    kidx = np.array([[int(x) for x in t.split(",")] for t in rows["kidx"]], dtype=np.int64)
+    ref_p = np.array([float(x) for x in rows["qplus"]])
+    ref_m = np.array([float(x) for x in rows["qminus"]])
+    N, S = 32, 5.0
+    sg64, sw64 = O.sphere_product_rule(8, 8)
+    s0 = 13
+    s1 = int(np.argmin(np.linalg.norm(sg64 + sg64[s0], axis=1)))
+    ora, plan = make_aniso(3, N, S, 0, 2.0, 1.0, sigma=sg64[[s0, s1]], sigma_w=sw64[[s0, s1]])
+    comps = [(0.6, (0.5, -0.3, 0.1), 0.7), (0.4, (-0.8, 0.6, 0.2), 1.2)]
+    c = ora.project(I.mixture(ora.interior_velocities(), comps))
+    # the input the stored values were computed from
+    assert hashlib.sha256(np.ascontiguousarray(c, dtype=np.float64).tobytes()).hexdigest()[:16] == rows["sha"]
+    say("case: fast path, angle-dependent rate, 3D N=32 direction pair vs stored oracle values")
+    q, qp = plan.coeffs_to_q(torch.tensor(c, device="cuda"), want_qplus=True)
+    torch.cuda.synchronize()
+    q, qp = q.cpu().numpy(), qp.cpu().numpy()
+    got_q, got_qp = q[tuple(kidx.T)], qp[tuple(kidx.T)]
+    r, rp = rel_l2(got_q, ref_p - ref_m), rel_l2(got_qp, ref_p)
+    say("  %d stored coefficients: rel-L2 Q = %.3e, Q+ = %.3e" % (len(kidx), r, rp))
     assert r <= FP64_TOL and rp <= FP64_TOL
     plan.close()
 
