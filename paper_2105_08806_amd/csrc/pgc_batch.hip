@@ -180,9 +180,13 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
     constexpr int CELLS = W * W;
     constexpr int NS = 64 / CW;
     constexpr int PB = 8;  // points whose G rows are gathered together
-    __shared__ float sq[64];
-    __shared__ float sk[64][2 * W];
-    __shared__ int sx[64][4];
+    // the staged points of a batch, with PAD zero-weight entries past the last
+    // lane, so a gather of PB points past the batch's end reads weight 0
+    // (offsets 0: row 0 of G) and needs no clamp per point
+    constexpr int PAD = PB * NS;
+    __shared__ float sq[64 + PAD];
+    __shared__ float sk[64 + PAD][2 * W];
+    __shared__ unsigned int sx[64 + PAD][4];  // byte offsets of the four G rows of each point
     __shared__ double red[(NS > 1) ? (NS - 1) * CW * CELLS : 1];
     // the kernel cells depend on W and the upsampling only, the same for every
     // group: read from LDS they are not hoisted into registers
@@ -194,6 +198,11 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
     // compiler knows it
     const int cl = lane % CW, stream = (NS == 1) ? 0 : lane / CW;
     for (int i = lane; i < EO; i += 64) seo[i] = groups[0].gp.kpoly_eo[i];
+    for (int i = 64 + lane; i < 64 + PAD; i += 64) {
+        sq[i] = 0.f;
+        for (int m = 0; m < 4; ++m) sx[i][m] = 0u;
+        for (int a = 0; a < 2 * W; ++a) sk[i][a] = 0.f;
+    }
     __syncthreads();
 
     for (;;) {
@@ -253,10 +262,14 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
                     sk[lane][a] = k[0][a];
                     sk[lane][W + a] = k[1][a];
                 }
-                sx[lane][0] = ix[0] * ldg;
-                sx[lane][1] = iy[0] * ldg;
-                sx[lane][2] = ix[1] * ldg;
-                sx[lane][3] = iy[1] * ldg;
+                sx[lane][0] = (unsigned)(ix[0] * ldg) * 4u;
+                sx[lane][1] = (unsigned)(iy[0] * ldg) * 4u;
+                sx[lane][2] = (unsigned)(ix[1] * ldg) * 4u;
+                sx[lane][3] = (unsigned)(iy[1] * ldg) * 4u;
+            } else {
+                sq[lane] = 0.f;
+                for (int m = 0; m < 4; ++m) sx[lane][m] = 0u;
+                for (int a = 0; a < 2 * W; ++a) sk[lane][a] = 0.f;
             }
             __syncthreads();
             if (valid) {
@@ -265,21 +278,26 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
                 for (int e = 0; e < CELLS; ++e) ab[e] = 0.f;
                 // The G rows of PB points are gathered together (4 PB loads in
                 // flight) before their arithmetic, so the memory latency is
-                // paid once per PB points.  Points past the batch repeat the
-                // last one with weight 0.
+                // paid once per PB points.  Points past the batch are the
+                // zero-weight entries.
+                // 32-bit byte offsets from the uniform base: the loads take the
+                // scalar-base form, with no 64-bit address arithmetic per load
+                const unsigned c4 = (unsigned)c * 4u;
+                const __attribute__((address_space(1))) char* Gb =
+                    (const __attribute__((address_space(1))) char*)Gt;
                 for (int j0 = stream; j0 < nv; j0 += PB * NS) {
                     float gv[PB][4];
 #pragma unroll
                     for (int k = 0; k < PB; ++k) {
-                        const int j = min(j0 + k * NS, nv - 1);
+                        const int j = j0 + k * NS;
 #pragma unroll
-                        for (int m = 0; m < 4; ++m) gv[k][m] = Gt[sx[j][m] + c];
+                        for (int m = 0; m < 4; ++m)
+                            gv[k][m] = *(const __attribute__((address_space(1))) float*)(Gb + (sx[j][m] + c4));
                     }
 #pragma unroll
                     for (int k = 0; k < PB; ++k) {
-                        const int j = min(j0 + k * NS, nv - 1);
-                        const float live = (j0 + k * NS < nv) ? 1.f : 0.f;
-                        const float w = live * sq[j] * fmaf(gv[k][0], gv[k][1], gv[k][2] * gv[k][3]);
+                        const int j = j0 + k * NS;
+                        const float w = sq[j] * fmaf(gv[k][0], gv[k][1], gv[k][2] * gv[k][3]);
 #pragma unroll
                         for (int a = 0; a < W; ++a) {
                             const float t = w * sk[j][a];
@@ -709,11 +727,11 @@ pgc_status enqueue_cells(const pgc_batch_s& b, const float* packed, float* packe
     return PGC_OK;
 }
 
-// the lane-per-cell scheme indexes the cell-minor G with 32-bit offsets
+// the lane-per-cell scheme addresses the cell-minor G with 32-bit byte offsets
 bool lanes_fit(const pgc_batch_s& b)
 {
     for (const BatchGroup& G : b.groups)
-        if (G.plan->p.nid * (int64_t)G.ldg >= 2147483647ll) return false;
+        if (G.plan->p.nid * (int64_t)G.ldg * 4 >= 4294967295ll) return false;
     return true;
 }
 
