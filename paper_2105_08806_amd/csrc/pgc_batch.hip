@@ -115,18 +115,16 @@ __global__ void __launch_bounds__(64) gain_batched(const GroupDev* __restrict__ 
 
         for (int i = lane; i < n; i += 64) {
             const unsigned long long id = D.ids[first + i];
-            const int b1 = (int)(id & 0xffull), a1 = (int)((id >> 8) & 0xffull);
-            const int s = (int)((id >> 16) & 0x3ffull);
-            const int p2 = (int)((id >> 26) & 0xffffull);
+            int s;
+            const PairNodes<2> nd = unpack_id<2>(id, s);
             float q;
             double xs[2];
-            int64_t si;
-            point_geometry<float, 2>(D.gp, s, a1, b1, p2, 0, halfW, q, xs, si);
+            point_geometry<float, 2>(D.gp, s, nd, halfW, q, xs);
             float kx[W], ky[W];
             kernel_cells64<float, W, TERMS>(D.gp.poly64, 2.0 * ((double)t0x - xs[0]) - 1.0, kx);
             kernel_cells64<float, W, TERMS>(D.gp.poly64, 2.0 * ((double)t0y - xs[1]) - 1.0, ky);
             int ix[2], iy[2];
-            q *= orbit_terms<float, 2>(D.gp, a1, b1, p2, 0, ix, iy);
+            q *= orbit_terms<float, 2>(D.gp, nd, ix, iy);
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 float w = 0.f;
@@ -240,11 +238,10 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
                 // the regeneration of gain_binned: w per dimension, the offset
                 // from the cell fit, the mirrored kernel cells
                 const unsigned long long id = D.ids[first + base + lane];
-                const int b1 = (int)(id & 0xffull), a1 = (int)((id >> 8) & 0xffull);
-                const int s = (int)((id >> 16) & 0x3ffull);
-                const int p2 = (int)((id >> 26) & 0xffffull);
+                int s;
+                const PairNodes<2> nd = unpack_id<2>(id, s);
                 float q, vp[2];
-                point_velocity<float, 2>(D.gp, s, a1, b1, p2, 0, q, vp);
+                point_velocity<float, 2>(D.gp, s, nd, q, vp);
                 double sv[2];
 #pragma unroll
                 for (int l = 0; l < 2; ++l) {
@@ -256,7 +253,7 @@ __global__ void __launch_bounds__(64) gain_batched_lanes(const GroupDev* __restr
                 float k[2][W];
                 kernel_cells_eo_dims<float, W, TERMS, 2>(seo, sv, k);
                 int ix[2], iy[2];
-                sq[lane] = q * orbit_terms<float, 2>(D.gp, a1, b1, p2, 0, ix, iy);
+                sq[lane] = q * orbit_terms<float, 2>(D.gp, nd, ix, iy);
 #pragma unroll
                 for (int a = 0; a < W; ++a) {
                     sk[lane][a] = k[0][a];
@@ -521,6 +518,7 @@ GainParams<float> group_gain_params(const Plan& p)
     gp.poly64 = p.dt.poly64;
     gp.kpoly_eo = p.dt.kpoly_eo;
     gp.cellfit = p.dt.cellfit;
+    gp.cellfit_v = p.dt.cellfit_v;
     gp.b0 = (float)p.b0;
     gp.gamma = (float)p.gamma;
     gp.map = p.map;

@@ -33,6 +33,7 @@ struct GainParams {
     const double* poly64;  // terms x W  the same coefficients in FP64 (binned schemes)
     const double* kpoly_eo;  // even and odd parts of the cells a < W/2 (binned scheme)
     const double* cellfit;   // per bin coordinate: w_c, 1/delta and the offset polynomial
+    const double* cellfit_v; // per bin coordinate: t_c, 1/delta (0: none), offset and map-factor polynomials in v/S
     const T* slab_vlo;  // n_slabs
     const T* slab_vhi;
     double* partial;    // n_chunks x n_g^d
@@ -99,15 +100,37 @@ __device__ __forceinline__ double map_w(T v, const GainParams<T>& P, T& m2)
     return t * rcp64(1.0 + sqrt(r));
 }
 
+// sum_k c[k] x^k (k = 0 .. DEG) by Horner's rule, for coefficients that are
+// the same on every lane (scalar registers).  The sum is carried negated,
+// u <- u x - c[k]: each step is then one three-operand FMA with the scalar
+// coefficient negated in place, where the plain form makes the compiler copy
+// every coefficient into a vector register first to use the two-operand FMA.
+// Negation is exact, so the result equals the plain Horner sum bit for bit.
+template <int DEG>
+__device__ __forceinline__ double horner_uniform(const double* __restrict__ c, double x)
+{
+    double u = -c[DEG];
+#pragma unroll
+    for (int k = DEG - 1; k >= 0; --k) u = fma(u, x, -c[k]);
+    return -u;
+}
+
 // kernel offset s = 2 (t0 - z/h + W/2) - 1 of a point whose footprint corner
 // in this dimension is t0, from the fit of that cell
 __device__ __forceinline__ double cell_offset(const double* __restrict__ cf, double w)
 {
     const double x = (w - cf[0]) * cf[1];
-    double s = cf[2 + kCellFitDeg];
-#pragma unroll
-    for (int k = kCellFitDeg - 1; k >= 0; --k) s = fma(s, x, cf[2 + k]);
-    return s;
+    return horner_uniform<kCellFitDeg>(cf + 2, x);
+}
+
+// kernel offset and map factor m2 of a point from its cell's fit in the scaled
+// velocity t = v/S (a cell with a nonzero 1/delta in cv[1])
+template <typename T>
+__device__ __forceinline__ double cell_offset_v(const double* __restrict__ cv, T v, double inv_S64, T& m2)
+{
+    const double x = ((double)v * inv_S64 - cv[0]) * cv[1];
+    m2 = (T)horner_uniform<kCellFitDeg>(cv + 3 + kCellFitDeg, x);
+    return horner_uniform<kCellFitDeg>(cv + 2, x);
 }
 
 // values of the W kernel cells at offset s in [-1, 1): Horner in s
@@ -235,37 +258,81 @@ __device__ __forceinline__ void kernel_cells_eo_dims(const double* __restrict__ 
     kernel_cells_eo_each<T, W, TERMS, DIM>(eo, sv, [&](int l, int a, T v) { out[l][a] = v; });
 }
 
-// Merged point ids pack (b_1, a_1, s, p_2, p_3) as
-// b1 | a1 << 8 | s << 16 | p2 << 26 | p3 << 42.
-__device__ __forceinline__ unsigned long long pack_id(int s, int a1, int b1, int p2, int p3)
+// The node pair (a_l <= b_l) of every dimension of one merged point.
+template <int DIM>
+struct PairNodes {
+    int a[DIM], b[DIM];
+};
+
+// the node pairs of a merged point given by the pair indices p_2, p_3 of the
+// later dimensions (the pair tables list the unordered pairs)
+template <typename T, int DIM>
+__device__ __forceinline__ PairNodes<DIM> pair_nodes(const GainParams<T>& P, int a1, int b1, int p2, int p3)
 {
-    return (unsigned long long)b1 | ((unsigned long long)a1 << 8) | ((unsigned long long)s << 16) |
-           ((unsigned long long)p2 << 26) | ((unsigned long long)p3 << 42);
+    PairNodes<DIM> nd;
+    nd.a[0] = a1;
+    nd.b[0] = b1;
+    nd.a[1] = P.pair_a[p2];
+    nd.b[1] = P.pair_b[p2];
+    if constexpr (DIM == 3) {
+        nd.a[2] = P.pair_a[p3];
+        nd.b[2] = P.pair_b[p3];
+    }
+    return nd;
+}
+
+// Merged point ids pack the direction s and the nodes of every dimension as
+// b1 | a1 << 8 | s << 16 | a2 << 26 | b2 << 34 | a3 << 42 | b3 << 50 (58 bits;
+// 256 interior nodes per dimension and 1024 directions at most).  Carrying the
+// nodes, not the pair indices, lets the spreading kernels fetch the node
+// velocities and nodal values of a point in one round of loads.
+template <int DIM>
+__device__ __forceinline__ unsigned long long pack_id(int s, const PairNodes<DIM>& nd)
+{
+    unsigned long long id = (unsigned long long)nd.b[0] | ((unsigned long long)nd.a[0] << 8) |
+                            ((unsigned long long)s << 16) | ((unsigned long long)nd.a[1] << 26) |
+                            ((unsigned long long)nd.b[1] << 34);
+    if constexpr (DIM == 3) id |= ((unsigned long long)nd.a[2] << 42) | ((unsigned long long)nd.b[2] << 50);
+    return id;
+}
+
+template <int DIM>
+__device__ __forceinline__ PairNodes<DIM> unpack_id(unsigned long long id, int& s)
+{
+    PairNodes<DIM> nd;
+    nd.b[0] = (int)(id & 0xffull);
+    nd.a[0] = (int)((id >> 8) & 0xffull);
+    s = (int)((id >> 16) & 0x3ffull);
+    nd.a[1] = (int)((id >> 26) & 0xffull);
+    nd.b[1] = (int)((id >> 34) & 0xffull);
+    if constexpr (DIM == 3) {
+        nd.a[2] = (int)((id >> 42) & 0xffull);
+        nd.b[2] = (int)((id >> 50) & 0xffull);
+    }
+    return nd;
 }
 
 // post-collision velocity of one merged point and its weight without the map
 // factors and the orbit sum: q = W_s b0 S^d (times |u|^gamma for VHS)
 template <typename T, int DIM>
-__device__ __forceinline__ void point_velocity(const GainParams<T>& P, int s, int a1, int b1, int p2,
-                                               int p3, T& q, T* vp)
+__device__ __forceinline__ void point_velocity(const GainParams<T>& P, int s, const PairNodes<DIM>& nd, T& q,
+                                               T* vp)
 {
     const T half = (T)0.5;
-    const T va = P.v1[a1], vb = P.v1[b1];
-    const T d = va - vb;
-    T cen[DIM], r2;
-    {
-        const T x = P.v1[P.pair_a[p2]], y = P.v1[P.pair_b[p2]];
-        cen[1] = (x + y) * half;
-        r2 = (x - y) * (x - y);
-    }
-    if constexpr (DIM == 3) {
-        const T x = P.v1[P.pair_a[p3]], y = P.v1[P.pair_b[p3]];
-        cen[2] = (x + y) * half;
+    T r2 = (T)0;
+#pragma unroll
+    for (int l = 1; l < DIM; ++l) {
+        const T x = P.v1[nd.a[l]], y = P.v1[nd.b[l]];
+        vp[l] = (x + y) * half;
         r2 += (x - y) * (x - y);
     }
+    // |u|^2 summed as d_1^2 + (d_2^2 + d_3^2), as the slab scheme sums it
+    const T va = P.v1[nd.a[0]], vb = P.v1[nd.b[0]];
+    const T d = va - vb;
     const T un = sqrt(d * d + r2);
     vp[0] = (va + vb) * half + un * P.sigma[s * DIM] * half;
-    for (int l = 1; l < DIM; ++l) vp[l] = cen[l] + un * P.sigma[s * DIM + l] * half;
+#pragma unroll
+    for (int l = 1; l < DIM; ++l) vp[l] += un * P.sigma[s * DIM + l] * half;
     q = P.wfac[s];
     if (P.vhs) q *= (P.gamma == (T)1) ? un : (un > (T)0 ? pow(un, P.gamma) : (T)(P.gamma == (T)0));
 }
@@ -273,12 +340,11 @@ __device__ __forceinline__ void point_velocity(const GainParams<T>& P, int s, in
 // geometry of one merged point: weight without the orbit sum, and z/h - W/2
 // (in FP64 from z, so that bins and kernel offsets agree for both precisions)
 template <typename T, int DIM>
-__device__ __forceinline__ void point_geometry(const GainParams<T>& P, int s, int a1, int b1, int p2,
-                                               int p3, double halfW, T& q, double* xs,
-                                               int64_t& sym_idx)
+__device__ __forceinline__ void point_geometry(const GainParams<T>& P, int s, const PairNodes<DIM>& nd,
+                                               double halfW, T& q, double* xs)
 {
     T vp[DIM];
-    point_velocity<T, DIM>(P, s, a1, b1, p2, p3, q, vp);
+    point_velocity<T, DIM>(P, s, nd, q, vp);
 #pragma unroll
     for (int l = 0; l < DIM; ++l) {
         double z;
@@ -287,8 +353,6 @@ __device__ __forceinline__ void point_geometry(const GainParams<T>& P, int s, in
         q *= m2;
         xs[l] = z * P.h_inv64 - halfW;
     }
-    const int64_t p1 = P.pair_base[a1] + (b1 - a1);
-    sym_idx = (DIM == 2) ? (int64_t)p2 * P.np + p1 : ((int64_t)p2 * P.np + p3) * P.np + p1;
 }
 
 // The 2^(d-1) products G_x G_y of the orbit of one merged point: the 2^d
@@ -296,11 +360,10 @@ __device__ __forceinline__ void point_geometry(const GainParams<T>& P, int s, in
 // pair a_l = b_l halves the count.  Writes the flat node indices of the
 // products and returns the multiplicity c.
 template <typename T, int DIM>
-__device__ __forceinline__ T orbit_terms(const GainParams<T>& P, int a1, int b1, int p2, int p3,
-                                         int* ix, int* iy)
+__device__ __forceinline__ T orbit_terms(const GainParams<T>& P, const PairNodes<DIM>& nd, int* ix, int* iy)
 {
     const int ni = P.ni;
-    const int a2 = P.pair_a[p2], b2 = P.pair_b[p2];
+    const int a1 = nd.a[0], b1 = nd.b[0], a2 = nd.a[1], b2 = nd.b[1];
     T c = (T)2;
     if (a1 == b1) c *= (T)0.5;
     if (a2 == b2) c *= (T)0.5;
@@ -310,7 +373,7 @@ __device__ __forceinline__ T orbit_terms(const GainParams<T>& P, int a1, int b1,
         ix[1] = a1 * ni + b2;
         iy[1] = b1 * ni + a2;
     } else {
-        const int a3 = P.pair_a[p3], b3 = P.pair_b[p3];
+        const int a3 = nd.a[2], b3 = nd.b[2];
         if (a3 == b3) c *= (T)0.5;
         const int A1 = a1 * ni, B1 = b1 * ni;
         ix[0] = (A1 + a2) * ni + a3;
@@ -328,11 +391,11 @@ __device__ __forceinline__ T orbit_terms(const GainParams<T>& P, int a1, int b1,
 // Orbit sum of one merged point straight from the nodal table G (small enough
 // to stay in L2).
 template <typename T, int DIM>
-__device__ __forceinline__ T orbit_sum(const GainParams<T>& P, int a1, int b1, int p2, int p3)
+__device__ __forceinline__ T orbit_sum(const GainParams<T>& P, const PairNodes<DIM>& nd)
 {
     constexpr int NT = 1 << (DIM - 1);
     int ix[NT], iy[NT];
-    const T c = orbit_terms<T, DIM>(P, a1, b1, p2, p3, ix, iy);
+    const T c = orbit_terms<T, DIM>(P, nd, ix, iy);
     T acc = P.G[ix[0]] * P.G[iy[0]];
 #pragma unroll
     for (int t = 1; t < NT; ++t) acc = fma(P.G[ix[t]], P.G[iy[t]], acc);
@@ -347,23 +410,17 @@ __device__ __forceinline__ T orbit_sum(const GainParams<T>& P, int a1, int b1, i
 // the mirror triple (i and j exchanged) flips every sign and keeps cos^2, which
 // is what the multiplicity 2 of each term counts.  u = 0 gives cos theta = 0.
 template <typename T, int DIM>
-__device__ __forceinline__ T orbit_sum_aniso(const GainParams<T>& P, int s, int a1, int b1, int p2, int p3)
+__device__ __forceinline__ T orbit_sum_aniso(const GainParams<T>& P, int s, const PairNodes<DIM>& nd)
 {
     constexpr int NT = 1 << (DIM - 1);
     int ix[NT], iy[NT];
-    const T c = orbit_terms<T, DIM>(P, a1, b1, p2, p3, ix, iy);
-    T e[DIM], u2;
-    {
-        const T d1 = P.v1[a1] - P.v1[b1];
-        const T d2 = P.v1[P.pair_a[p2]] - P.v1[P.pair_b[p2]];
-        u2 = d1 * d1 + d2 * d2;
-        e[0] = d1 * P.sigma[s * DIM];
-        e[1] = d2 * P.sigma[s * DIM + 1];
-        if constexpr (DIM == 3) {
-            const T d3 = P.v1[P.pair_a[p3]] - P.v1[P.pair_b[p3]];
-            u2 += d3 * d3;
-            e[2] = d3 * P.sigma[s * DIM + 2];
-        }
+    const T c = orbit_terms<T, DIM>(P, nd, ix, iy);
+    T e[DIM], u2 = (T)0;
+#pragma unroll
+    for (int l = 0; l < DIM; ++l) {
+        const T dl = P.v1[nd.a[l]] - P.v1[nd.b[l]];
+        u2 += dl * dl;
+        e[l] = dl * P.sigma[s * DIM + l];
     }
     const T k = u2 > (T)0 ? P.aniso / u2 : (T)0;
     T acc = (T)0;

@@ -367,20 +367,74 @@ void build_bin_thresholds(Plan& p)
     }
 }
 
+// Monomial coefficients (in x) of the Chebyshev interpolant of degree
+// kCellFitDeg of f on [-1, 1], at the Chebyshev points of the first kind, in
+// long double; rounded to FP64 into out[0 .. kCellFitDeg].
+template <typename F>
+static void cheb_fit_monomials(const F& f, double* out)
+{
+    constexpr int n = kCellFitDeg + 1;
+    const long double pi = acosl(-1.0L);
+    long double fx[n], cc[n], tm[n], t[n], tn[n], mono[n];
+    for (int j = 0; j < n; ++j) fx[j] = f(cosl(pi * (j + 0.5L) / n));
+    for (int k = 0; k < n; ++k) {
+        long double acc = 0.0L;
+        for (int j = 0; j < n; ++j) acc += fx[j] * cosl(pi * k * (j + 0.5L) / n);
+        cc[k] = (k == 0 ? 1.0L : 2.0L) * acc / n;
+    }
+    // sum_k cc_k T_k(x) -> monomials with T_{k+1} = 2 x T_k - T_{k-1}
+    for (int e = 0; e < n; ++e) tm[e] = t[e] = mono[e] = 0.0L;
+    tm[0] = 1.0L;
+    t[1] = 1.0L;
+    mono[0] = cc[0];
+    mono[1] = cc[1];
+    for (int k = 2; k < n; ++k) {
+        for (int e = 0; e < n; ++e) tn[e] = -tm[e] + (e > 0 ? 2.0L * t[e - 1] : 0.0L);
+        for (int e = 0; e < n; ++e) mono[e] += cc[k] * tn[e];
+        for (int e = 0; e < n; ++e) {
+            tm[e] = t[e];
+            t[e] = tn[e];
+        }
+    }
+    for (int k = 0; k < n; ++k) out[k] = (double)mono[k];
+}
+
+// The stored (rounded) polynomial c[0 .. kCellFitDeg] at x, in long double
+static long double cheb_fit_eval(const double* c, long double x)
+{
+    long double v = c[kCellFitDeg];
+    for (int k = kCellFitDeg - 1; k >= 0; --k) v = v * x + c[k];
+    return v;
+}
+
 // For every bin coordinate c of one dimension (footprint corner t0 = c - W/2,
 // int division) the points of the cell have z in ((t0 - 1 + W/2) h, (t0 + W/2) h]
 // and kernel offset s = 2 t0 + W - 1 - 2 z / h.  With z = pi/2 - 2 atan(w) the
 // offset is a smooth function of w over the cell's w-interval [w_c - d, w_c + d];
 // it is interpolated at the Chebyshev points of x = (w - w_c)/d in long double
 // and stored as w_c, 1/d and the monomial coefficients in x.
+//
+// Every cell whose z-interval lies inside (0, pi) also gets a fit in the scaled
+// velocity t = v/S itself, over the cell's t-interval [t_c - d, t_c + d]: the
+// offset s(t) and the map factor m2(t) (cosh t for r = 0, 1 + t^2 for r = 1),
+// each a polynomial of the same degree in x = (t - t_c)/d.  The functions are
+// analytic within distance pi/2 (r = 0) or 1 (r = 1) of the real axis, so the
+// interpolants converge on every cell whose t-interval is narrow against that;
+// a cell keeps the velocity fit only where the stored polynomials are within
+// 5e-16 of s and within 5e-16 relative of m2 (every cell but the one or few
+// at each end of the grid), else 1/d = 0 marks it and its points take the map
+// to w.  The velocity fit saves the exponential and reciprocals of the map.
 void build_cell_fits(Plan& p)
 {
-    constexpr int K = kCellFitDeg, n = K + 1;
+    constexpr int K = kCellFitDeg;
+    constexpr long double kTol = 5e-16L;
     const int nb = p.nh + 2, off = p.W / 2;
     const long double pi = acosl(-1.0L), h = pi / p.nh, hw = 0.5L * p.W;
     p.cellfit.assign((size_t)nb * kCellFitStride, 0.0);
+    p.cellfit_v.assign((size_t)nb * kCellFitVStride, 0.0);
     p.cellfit_err = 0.0;
-    std::vector<long double> fx(n), cc(n), tm(n), t(n), tn(n), mono(n);
+    p.cellfit_v_cells = 0;
+    const bool log_map = p.map == PGC_MAP_LOG;
     for (int c = 0; c < nb; ++c) {
         const int t0 = c - off;
         const long double zlo = std::max(0.0L, (t0 - 1 + hw) * h);
@@ -393,36 +447,45 @@ void build_cell_fits(Plan& p)
             const long double z = 0.5L * pi - 2.0L * atanl(wc + d * x);
             return (long double)(2 * t0 + p.W - 1) - 2.0L * z / h;
         };
-        for (int j = 0; j < n; ++j) fx[j] = offset(cosl(pi * (j + 0.5L) / n));
-        for (int k = 0; k < n; ++k) {
-            long double acc = 0.0L;
-            for (int j = 0; j < n; ++j) acc += fx[j] * cosl(pi * k * (j + 0.5L) / n);
-            cc[k] = (k == 0 ? 1.0L : 2.0L) * acc / n;
-        }
-        // sum_k cc_k T_k(x) -> monomials with T_{k+1} = 2 x T_k - T_{k-1}
-        std::fill(mono.begin(), mono.end(), 0.0L);
-        std::fill(tm.begin(), tm.end(), 0.0L);
-        std::fill(t.begin(), t.end(), 0.0L);
-        tm[0] = 1.0L;
-        t[1] = 1.0L;
-        mono[0] = cc[0];
-        mono[1] = cc[1];
-        for (int k = 2; k < n; ++k) {
-            for (int e = 0; e < n; ++e) tn[e] = -tm[e] + (e > 0 ? 2.0L * t[e - 1] : 0.0L);
-            for (int e = 0; e < n; ++e) mono[e] += cc[k] * tn[e];
-            tm = t;
-            t = tn;
-        }
         out[0] = (double)wc;
         out[1] = (double)(1.0L / d);
-        for (int k = 0; k < n; ++k) out[2 + k] = (double)mono[k];
+        cheb_fit_monomials(offset, out + 2);
         // deviation of the stored (rounded) fit from the exact offset
         for (int i = 0; i <= 64; ++i) {
             const long double x = -1.0L + i / 32.0L;
-            long double v = out[2 + K];
-            for (int k = K - 1; k >= 0; --k) v = v * x + out[2 + k];
-            p.cellfit_err = std::max(p.cellfit_err, (double)fabsl(v - offset(x)));
+            p.cellfit_err = std::max(p.cellfit_err, (double)fabsl(cheb_fit_eval(out + 2, x) - offset(x)));
         }
+
+        // the fit in the velocity
+        if (!(zlo > 0.0L && zhi < pi)) continue;
+        auto t_of_z = [&](long double z) { return log_map ? -logl(tanl(0.5L * z)) : cosl(z) / sinl(z); };
+        const long double ta = t_of_z(zhi), tb = t_of_z(zlo);
+        if (!(std::isfinite((double)ta) && std::isfinite((double)tb) && tb > ta)) continue;
+        const long double tc = 0.5L * (ta + tb), dt = 0.5L * (tb - ta);
+        auto offset_t = [&](long double x) {
+            const long double t = tc + dt * x;
+            const long double z = log_map ? 2.0L * atanl(expl(-t)) : 0.5L * pi - atanl(t);
+            return (long double)(2 * t0 + p.W - 1) - 2.0L * z / h;
+        };
+        auto m2_t = [&](long double x) {
+            const long double t = tc + dt * x;
+            return log_map ? coshl(t) : 1.0L + t * t;
+        };
+        double fv[kCellFitVStride];
+        fv[0] = (double)tc;
+        fv[1] = (double)(1.0L / dt);
+        cheb_fit_monomials(offset_t, fv + 2);
+        cheb_fit_monomials(m2_t, fv + 3 + K);
+        bool good = true;
+        for (int i = 0; i <= 256 && good; ++i) {
+            const long double x = -1.0L + i / 128.0L;
+            const long double es = fabsl(cheb_fit_eval(fv + 2, x) - offset_t(x));
+            const long double em = fabsl(cheb_fit_eval(fv + 3 + K, x) / m2_t(x) - 1.0L);
+            good = es <= kTol && em <= kTol;  // false for NaN too
+        }
+        if (!good) continue;
+        std::copy(fv, fv + kCellFitVStride, p.cellfit_v.data() + (size_t)c * kCellFitVStride);
+        ++p.cellfit_v_cells;
     }
 }
 
@@ -860,6 +923,7 @@ hipError_t allocate(Plan& p, hipStream_t s)
         PGC_TRY(upload64(p, &p.dt.poly64, p.poly, s));
     PGC_TRY(upload64(p, &p.dt.kpoly_eo, p.kpoly_eo, s));
     PGC_TRY(upload64(p, &p.dt.cellfit, p.cellfit, s));
+    PGC_TRY(upload64(p, &p.dt.cellfit_v, p.cellfit_v, s));
     PGC_TRY(upload64(p, &p.dt.bin_vthr, p.bin_vthr, s));
     PGC_TRY(upload(p, &p.dt.sigma, p.sigma, s));
     {

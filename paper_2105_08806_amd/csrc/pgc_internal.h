@@ -23,6 +23,8 @@ constexpr int kMaxPolyTerms = 18;     // Horner terms per kernel cell (degree + 
 // exact offset on every grid with at least 8 cells per half period.
 constexpr int kCellFitDeg = 12;
 constexpr int kCellFitStride = kCellFitDeg + 3;  // w_c, 1/delta, c_0 .. c_12
+// t_c, 1/delta (0: no fit), offset c_0 .. c_12, map factor c_0 .. c_12
+constexpr int kCellFitVStride = 2 * kCellFitDeg + 4;
 constexpr int kMaxLdsBytes = 160 * 1024;
 constexpr int kLdsBudget = 155 * 1024;  // slab bytes per workgroup
 
@@ -42,6 +44,7 @@ struct DeviceTables {
     double* poly64 = nullptr; // the same in FP64 (aliases poly for FP64 plans)
     double* kpoly_eo = nullptr;  // even/odd parts of the cells a < W/2 (FP64)
     double* cellfit = nullptr;   // (n_h + 2) x (deg + 3) kernel-offset fits per grid cell (FP64)
+    double* cellfit_v = nullptr; // (n_h + 2) x (2 deg + 4) offset and map-factor fits in v/S (FP64)
     double* bin_vthr = nullptr;  // n_h + 4 velocity thresholds of the footprint corners (FP64)
     void* sigma = nullptr;    // n_sigma x dim
     void* wfac = nullptr;     // n_sigma  W_s b0 S^d (direction weight, kernel constant, map scale)
@@ -140,8 +143,9 @@ struct Plan {
     // host tables (FP64)
     std::vector<double> xi_all, v_all, w_all;
     std::vector<double> v1, w1, mu21, C, CT, E, poly, slab_vlo, slab_vhi, mom;
-    std::vector<double> kpoly_eo, cellfit, bin_vthr;
+    std::vector<double> kpoly_eo, cellfit, cellfit_v, bin_vthr;
     double cellfit_err = 0.0;  // largest deviation of a cell fit from the exact offset
+    int cellfit_v_cells = 0;   // cells with a fit in the velocity
 
     size_t elt = 8;
     int gain_mode = kGainBinned;

@@ -549,9 +549,11 @@ __global__ void __launch_bounds__(256) bin_points(GainParams<T> P, BinGeo B,
         const int a1 = (int)(us / B.ns);
         const int p2 = (DIM == 2) ? pencil : pencil / np;
         const int p3 = (DIM == 2) ? 0 : pencil % np;
+        PairNodes<DIM> nd = pair_nodes<T, DIM>(P, a1, a1, p2, p3);
         for (int b1 = a1; b1 < P.ni; ++b1) {
+            nd.b[0] = b1;
             T q, vp[DIM];
-            point_velocity<T, DIM>(P, s, a1, b1, p2, p3, q, vp);
+            point_velocity<T, DIM>(P, s, nd, q, vp);
             int64_t bin = 0;
 #pragma unroll
             for (int l = 0; l < DIM; ++l) bin = bin * B.nb + bin_coord<T>((double)vp[l], P, B);
@@ -559,10 +561,10 @@ __global__ void __launch_bounds__(256) bin_points(GainParams<T> P, BinGeo B,
                 atomicAdd(count + bin, 1u);
             } else if constexpr (MODE == 1) {
                 const unsigned long long slot = atomicAdd(cursor + bin, 1ull);
-                if (slot < B.id_cap) ids[slot] = pack_id(s, a1, b1, p2, p3);
+                if (slot < B.id_cap) ids[slot] = pack_id<DIM>(s, nd);
             } else {
                 const unsigned int slot = atomicAdd(cursor32 + bin, 1u);
-                if (slot < B.id_cap) ids[slot] = pack_id(s, a1, b1, p2, p3);
+                if (slot < B.id_cap) ids[slot] = pack_id<DIM>(s, nd);
             }
         }
     }
@@ -609,10 +611,12 @@ struct BinLayout {
 
 // One wave per work item (a run of ids of one bin), BinLayout lanes per point.
 //
-// Regeneration: a lane forms one point's velocity, its w in every dimension
-// (map_w), the kernel offset from the fit of the bin's cell (cell_offset) and
-// the W kernel values from the even and odd parts of the cells; the staged
-// vectors are k_1, q k_2 (q the full weight with the orbit sum) and, in 3D, k_3.
+// Regeneration: a lane forms one point's velocity, then in every dimension the
+// kernel offset and the map factor, from the fit of the bin's cell in v/S
+// (cell_offset_v) or, in the few cells at the ends of the grid that have none,
+// through w (map_w, cell_offset), and the W kernel values from the even and
+// odd parts of the cells; the staged vectors are k_1, q k_2 (q the full weight
+// with the orbit sum) and, in 3D, k_3.
 template <typename T, int DIM, int W, bool ANISO>
 __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
 {
@@ -635,12 +639,14 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
     // base cell of the bin and the offset fit of its cell in every dimension
     int t0[DIM];
     const double* fit[DIM];
+    const double* fitv[DIM];
     {
         int r = bin;
         for (int l = DIM - 1; l >= 0; --l) {
             const int c = r % BI.geo.nb;
             t0[l] = c - BI.geo.off;
             fit[l] = P.cellfit + (int64_t)c * kCellFitStride;
+            fitv[l] = P.cellfit_v + (int64_t)c * kCellFitVStride;
             r /= BI.geo.nb;
         }
     }
@@ -672,20 +678,24 @@ __global__ void __launch_bounds__(64) gain_binned(GainParams<T> P, BinItems BI)
         {
             T* st = stage + lane * STRIDE;
             if (lane < nv) {
-                const int b1 = (int)(id & 0xffull), a1 = (int)((id >> 8) & 0xffull);
-                const int s = (int)((id >> 16) & 0x3ffull);
-                const int p2 = (int)((id >> 26) & 0xffffull), p3 = (int)((id >> 42) & 0xffffull);
+                int s;
+                const PairNodes<DIM> nd = unpack_id<DIM>(id, s);
                 T q, vp[DIM];
-                point_velocity<T, DIM>(P, s, a1, b1, p2, p3, q, vp);
-                if constexpr (ANISO) q *= orbit_sum_aniso<T, DIM>(P, s, a1, b1, p2, p3);
-                else q *= orbit_sum<T, DIM>(P, a1, b1, p2, p3);
+                point_velocity<T, DIM>(P, s, nd, q, vp);
+                if constexpr (ANISO) q *= orbit_sum_aniso<T, DIM>(P, s, nd);
+                else q *= orbit_sum<T, DIM>(P, nd);
                 double sv[DIM];
 #pragma unroll
                 for (int l = 0; l < DIM; ++l) {
+                    // the bin's cell is the same on every lane: a uniform branch
                     T m2;
-                    const double w = map_w(vp[l], P, m2);
+                    if (fitv[l][1] != 0.0) {
+                        sv[l] = cell_offset_v(fitv[l], vp[l], P.inv_S64, m2);
+                    } else {
+                        const double w = map_w(vp[l], P, m2);
+                        sv[l] = cell_offset(fit[l], w);
+                    }
                     q *= m2;
-                    sv[l] = cell_offset(fit[l], w);
                 }
                 // each kernel value is staged as soon as it is formed
                 kernel_cells_eo_each<T, W, TERMS, DIM>(P.kpoly_eo, sv, [&](int l, int a, T v) {
@@ -846,12 +856,11 @@ __global__ void __launch_bounds__(64) gain_binned_mfma(GainParams<double> P, Bin
             double* st = stage + lane * STRIDE;
             if (lane < nv) {
                 const unsigned long long id = BI.ids[first + base + lane];
-                const int b1 = (int)(id & 0xffull), a1 = (int)((id >> 8) & 0xffull);
-                const int s = (int)((id >> 16) & 0x3ffull);
-                const int p2 = (int)((id >> 26) & 0xffffull), p3 = (int)((id >> 42) & 0xffffull);
+                int s;
+                const PairNodes<3> nd = unpack_id<3>(id, s);
                 double q, vp[3];
-                point_velocity<double, 3>(P, s, a1, b1, p2, p3, q, vp);
-                q *= orbit_sum<double, 3>(P, a1, b1, p2, p3);
+                point_velocity<double, 3>(P, s, nd, q, vp);
+                q *= orbit_sum<double, 3>(P, nd);
                 double sv[3];
 #pragma unroll
                 for (int l = 0; l < 3; ++l) {
@@ -1308,6 +1317,7 @@ GainParams<T> gain_params(const Plan& p, const Workspace& ws)
     gp.poly64 = p.dt.poly64;
     gp.kpoly_eo = p.dt.kpoly_eo;
     gp.cellfit = p.dt.cellfit;
+    gp.cellfit_v = p.dt.cellfit_v;
     gp.b0 = (T)p.b0;
     gp.gamma = (T)p.gamma;
     gp.aniso = (T)p.aniso;
