@@ -258,6 +258,15 @@ __device__ __forceinline__ void kernel_cells_eo_dims(const double* __restrict__ 
     kernel_cells_eo_each<T, W, TERMS, DIM>(eo, sv, [&](int l, int a, T v) { out[l][a] = v; });
 }
 
+// base[i] for a table of fewer than 2^32 bytes: a 32-bit byte offset from a
+// base that is the same on every lane, which the loads take in their
+// scalar-base form (no per-lane 64-bit address arithmetic)
+template <typename T>
+__device__ __forceinline__ T ld_u32(const T* __restrict__ base, unsigned i)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(T));
+}
+
 // The node pair (a_l <= b_l) of every dimension of one merged point.
 template <int DIM>
 struct PairNodes {
@@ -322,18 +331,18 @@ __device__ __forceinline__ void point_velocity(const GainParams<T>& P, int s, co
     T r2 = (T)0;
 #pragma unroll
     for (int l = 1; l < DIM; ++l) {
-        const T x = P.v1[nd.a[l]], y = P.v1[nd.b[l]];
+        const T x = ld_u32(P.v1, nd.a[l]), y = ld_u32(P.v1, nd.b[l]);
         vp[l] = (x + y) * half;
         r2 += (x - y) * (x - y);
     }
     // |u|^2 summed as d_1^2 + (d_2^2 + d_3^2), as the slab scheme sums it
-    const T va = P.v1[nd.a[0]], vb = P.v1[nd.b[0]];
+    const T va = ld_u32(P.v1, nd.a[0]), vb = ld_u32(P.v1, nd.b[0]);
     const T d = va - vb;
     const T un = sqrt(d * d + r2);
-    vp[0] = (va + vb) * half + un * P.sigma[s * DIM] * half;
+    vp[0] = (va + vb) * half + un * ld_u32(P.sigma, s * DIM) * half;
 #pragma unroll
-    for (int l = 1; l < DIM; ++l) vp[l] += un * P.sigma[s * DIM + l] * half;
-    q = P.wfac[s];
+    for (int l = 1; l < DIM; ++l) vp[l] += un * ld_u32(P.sigma, s * DIM + l) * half;
+    q = ld_u32(P.wfac, s);
     if (P.vhs) q *= (P.gamma == (T)1) ? un : (un > (T)0 ? pow(un, P.gamma) : (T)(P.gamma == (T)0));
 }
 
@@ -396,9 +405,9 @@ __device__ __forceinline__ T orbit_sum(const GainParams<T>& P, const PairNodes<D
     constexpr int NT = 1 << (DIM - 1);
     int ix[NT], iy[NT];
     const T c = orbit_terms<T, DIM>(P, nd, ix, iy);
-    T acc = P.G[ix[0]] * P.G[iy[0]];
+    T acc = ld_u32(P.G, ix[0]) * ld_u32(P.G, iy[0]);
 #pragma unroll
-    for (int t = 1; t < NT; ++t) acc = fma(P.G[ix[t]], P.G[iy[t]], acc);
+    for (int t = 1; t < NT; ++t) acc = fma(ld_u32(P.G, ix[t]), ld_u32(P.G, iy[t]), acc);
     return c * acc;
 }
 

@@ -597,7 +597,11 @@ struct BinLayout {
     static constexpr bool WIDE = CELLS > 64;
     static constexpr int ACC_MAX = sizeof(T) == 8 ? 48 : 96;
     static constexpr int VEC = 16 / (int)sizeof(T);
-    static constexpr int STRIDE = (DIM * W + VEC - 1) / VEC * VEC;  // staged values per point
+    // staged values per point, whole 16-byte vectors; a stride of a multiple
+    // of 64 bytes would put every fourth lane's staging stores in the same
+    // LDS banks, so such strides take one vector more
+    static constexpr int STRIDE0 = (DIM * W + VEC - 1) / VEC * VEC;
+    static constexpr int STRIDE = (STRIDE0 * (int)sizeof(T)) % 64 == 0 ? STRIDE0 + VEC : STRIDE0;
     static constexpr int STAGE_BYTES = 64 * STRIDE * (int)sizeof(T);
     // a wide layout with g groups fits when its accumulators do and one group's
     // FP64 partial tile fits in the stage buffer (groups are reduced one by one)
