@@ -176,6 +176,10 @@ typedef struct pgc_plan_info {
     int32_t index_chunks;   /* binned gain: 1 = the whole point index, built at plan time; > 1 =
                                direction chunks sorted again at every evaluation */
     int64_t index_bytes;    /* binned gain: bytes of the point-id buffer (the largest chunk) */
+    int32_t velocity_fit_cells; /* grid cells (of grid_folded + 1 bin coordinates) whose points take
+                               their kernel offset and map factor from a per-cell polynomial in
+                               v/S, within 5e-16 of the exact values; the points of the other cells
+                               (one or a few at each end of the grid) go through the map to w */
 } pgc_plan_info;
 
 /* Human-readable text of a status code (static storage, never NULL). */

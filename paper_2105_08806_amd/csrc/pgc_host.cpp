@@ -1148,6 +1148,7 @@ pgc_status pgc_plan_query(pgc_plan plan, pgc_plan_info* info)
     info->gain_mode = p.mfma && p.gain_mode == pgc::kGainBinned ? 3 : p.gain_mode;
     info->n_bin_items = p.bins.n_items;
     info->offset_fit_err = p.cellfit_err;
+    info->velocity_fit_cells = p.cellfit_v_cells;
     info->deterministic = p.deterministic ? 1 : 0;
     info->tile_bytes = p.bins.tile_bytes;
     if (p.gain_mode == pgc::kGainBinned) {

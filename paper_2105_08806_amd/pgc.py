@@ -66,6 +66,7 @@ class PlanInfo(ctypes.Structure):
         ("offset_fit_err", ctypes.c_double), ("deterministic", ctypes.c_int32),
         ("tile_bytes", ctypes.c_int64),
         ("index_chunks", ctypes.c_int32), ("index_bytes", ctypes.c_int64),
+        ("velocity_fit_cells", ctypes.c_int32),
     ]
 
 

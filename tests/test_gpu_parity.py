@@ -275,6 +275,38 @@ def test_binned_matches_slabs_every_width(torch_cuda, dim, prec):
         assert rp <= tol_qp and r <= tol_q, (W, r, rp)
 
 
+@pytest.mark.parametrize("map_", [0, 1])
+def test_velocity_fits_cover_the_grid(torch_cuda, map_):
+    """The binned gain takes a point's kernel offset and map factor from a
+    per-cell polynomial in v/S wherever the plan found one within 5e-16 (the
+    cell's velocity interval narrow against the distance of the map's
+    singularities from the real axis): all bin coordinates but the few at the
+    ends of the grid, 93 of the 97 of the N = 32 grid for the logarithmic map
+    and 87 for the algebraic one (computed for this grid in long double).  The
+    other cells go through the map to w.  Both kinds of cell carry points of
+    one plan, whose Q agrees with the slab scheme, which maps every point
+    through the exact arctangent, to rounding."""
+    from paper_2105_08806_amd import pgc
+    torch = torch_cuda
+    N = 32
+    c = I.random_coeffs((N, N), seed=41 + map_)
+    out = []
+    for mode in (pgc.GAIN_SLAB, pgc.GAIN_BINNED):
+        plan = pgc.Plan(dim=2, n_modes=N, scale=5.0, map=map_, kernel=pgc.KERNEL_MAXWELL, n_sigma=8,
+                        precision=pgc.FP64, gain_mode=mode)
+        info = plan.info
+        say("case: map=%d mode=%d grid_folded=%d velocity_fit_cells=%d" % (
+            map_, mode, info.grid_folded, info.velocity_fit_cells))
+        assert info.grid_folded == 97
+        assert info.velocity_fit_cells == (93 if map_ == 0 else 87)
+        out.append(gpu_q(torch, plan, c))
+        plan.close()
+    (q_s, qp_s), (q_b, qp_b) = out
+    r, rp = rel_l2(q_b, q_s), rel_l2(qp_b, qp_s)
+    say("  binned vs slabs: rel-L2 Q %.2e Q+ %.2e" % (r, rp))
+    assert rp <= 1e-13 and r <= 1e-12
+
+
 def test_binned_limits_at_the_largest_node_count(torch_cuda):
     """The binned scheme's point ids hold a first-dimension node in 8 bits: at
     the largest node count (2D, m_v = 258, 256 interior nodes) binned and slab
