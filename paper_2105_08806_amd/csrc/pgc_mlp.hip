@@ -49,7 +49,7 @@ __device__ __forceinline__ bf16 to_bf16(float f)
 
 __device__ __forceinline__ float from_bf16(bf16 b) { return __uint_as_float((unsigned int)b << 16); }
 
-constexpr int kBM = 64, kBN = 64, kBK = 64, kPad = 8;
+constexpr int kBK = 64, kPad = 8;
 
 // Column of element (r, k) of a staged 64 x 64 tile: the eight 8-element
 // groups of a row are permuted by row bits 3..5 (an XOR swizzle).  Rows 16 B
@@ -62,16 +62,17 @@ __device__ __forceinline__ int swz(int r, int k) { return k ^ (((r >> 3) & 7) <<
 // BF16, C FP32, all row-major:
 //   op(A)[m][k] = TA ? A[k lda + m] : A[m lda + k]
 //   op(B)[k][n] = TB ? B[n ldb + k] : B[k ldb + n]
-// A 256-thread workgroup owns a 64 x 64 tile of C (four waves of 32 x 32, each
-// 2 x 2 tiles of 16 x 16); blockIdx.z takes the K range [z kc, (z+1) kc)
+// A workgroup of NW waves owns a BT x BT tile of C (BT = 64: four waves of
+// 32 x 32; BT = 128: eight waves of 32 x 64), each wave a part of 16 x 16
+// tiles; blockIdx.z takes the K range [z kc, (z+1) kc)
 // and, when gridDim.z > 1, adds its partial tile into C atomically (C holds
 // zeros or the values to accumulate onto).  Each 64-deep K slice is two
 // v_mfma_f32_16x16x32_bf16 per 16 x 16 tile: lane l supplies row (column)
 // l % 16 at k = 32 s + 8 (l / 16) .. + 7 and holds rows 4 (l / 16) + r, column
 // l % 16 of the result.  With `vec` (16-byte aligned rows) the global loads
 // of the slice after next are issued before the current slice's products.
-template <bool TA, bool TB>
-__global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
+template <bool TA, bool TB, int BT, int NW>
+__global__ void __launch_bounds__(64 * NW) gemm_bf16(int M, int N, int K, int kc,
                                                  const bf16* __restrict__ A, int lda,
                                                  const bf16* __restrict__ B, int ldb,
                                                  float* __restrict__ C, int ldc,
@@ -79,39 +80,43 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
 {
     typedef __bf16 bf16x8m __attribute__((ext_vector_type(8)));
     typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
-    __shared__ __attribute__((aligned(16))) bf16 sA[kBM][kBK + kPad];
-    __shared__ __attribute__((aligned(16))) bf16 sB[kBN][kBK + kPad];
+    constexpr int NT = 64 * NW;                          // threads
+    constexpr int WMS = BT / (NW / 2), WNS = BT / 2;     // a wave's part: NW/2 x 2 waves
+    constexpr int NBM = WMS / 16, NBN = WNS / 16;        // its 16 x 16 tiles
+    static_assert(NW % 2 == 0 && WMS % 16 == 0 && WNS % 16 == 0, "wave layout");
+    __shared__ __attribute__((aligned(16))) bf16 sA[BT][kBK + kPad];
+    __shared__ __attribute__((aligned(16))) bf16 sB[BT][kBK + kPad];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    const int m0 = blockIdx.y * BT, n0 = blockIdx.x * BT;
     const int kbeg = blockIdx.z * kc;
     const int kend = min(K, kbeg + kc);
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    f32x4 acc[2][2];
+    const int wm = (wave >> 1) * WMS, wn = (wave & 1) * WNS;
+    f32x4 acc[NBM][NBN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NBM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < NBN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     // 16 x 16 x 32 products of the wave's tiles over the staged slice
     auto compute = [&]() {
 #pragma unroll
         for (int kk = 0; kk < kBK; kk += 32) {
             const int kq = kk + 8 * (lane >> 4);
-            bf16x8m a[2], b[2];
+            bf16x8m a[NBM], b[NBN];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < NBM; ++i) {
                 const int r = wm + i * 16 + (lane & 15);
                 a[i] = __builtin_bit_cast(bf16x8m, *reinterpret_cast<const u16x8*>(&sA[r][swz(r, kq)]));
             }
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+            for (int j = 0; j < NBN; ++j) {
                 const int r = wn + j * 16 + (lane & 15);
                 b[j] = __builtin_bit_cast(bf16x8m, *reinterpret_cast<const u16x8*>(&sB[r][swz(r, kq)]));
             }
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < NBM; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < NBN; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
     };
@@ -119,14 +124,15 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
     if (vec) {
         // every thread moves CH 16-byte runs of 8 elements of each operand along
         // its contiguous dimension (k, or m / n when the operand is transposed):
-        // run c = tid + 256 h covers, untransposed, row c / 8 at k = 8 (c % 8),
-        // transposed, k = c / 8 at rows 8 (c % 8) .. + 7
-        constexpr int CH = kBM * kBK / 8 / 256;
-        static_assert(kBM == kBN && kBM * kBK == 8 * 256 * CH && kBK == 64 && kBM == 64, "tile shape");
+        // run c = tid + NT h covers, untransposed, row c / 8 at k = 8 (c % 8),
+        // transposed, k = c / RM at rows 8 (c % RM) .. + 7
+        constexpr int CH = BT * kBK / 8 / NT;
+        constexpr int RM = BT / 8;  // 16-byte runs per k of an m- (n-) contiguous operand
+        static_assert(BT * kBK == 8 * NT * CH && kBK == 64, "tile shape");
         auto gload = [&](int k0, u16x8* va, u16x8* vb) {
 #pragma unroll
             for (int h = 0; h < CH; ++h) {
-                const int c = tid + 256 * h;
+                const int c = tid + NT * h;
                 va[h] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
                 vb[h] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
                 if (!TA) {
@@ -138,7 +144,7 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
                             if (gk + q < kend) va[h][q] = A[(size_t)gm * lda + gk + q];
                     }
                 } else {
-                    const int gk = k0 + (c >> 3), gm = m0 + (c & 7) * 8;
+                    const int gk = k0 + c / RM, gm = m0 + (c % RM) * 8;
                     if (gk < kend && gm + 8 <= M) {
                         va[h] = *reinterpret_cast<const u16x8*>(A + (size_t)gk * lda + gm);
                     } else if (gk < kend) {
@@ -155,7 +161,7 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
                             if (gk + q < kend) vb[h][q] = B[(size_t)gn * ldb + gk + q];
                     }
                 } else {
-                    const int gk = k0 + (c >> 3), gn = n0 + (c & 7) * 8;
+                    const int gk = k0 + c / RM, gn = n0 + (c % RM) * 8;
                     if (gk < kend && gn + 8 <= N) {
                         vb[h] = *reinterpret_cast<const u16x8*>(B + (size_t)gk * ldb + gn);
                     } else if (gk < kend) {
@@ -167,32 +173,32 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
         };
         // a slice inside the matrix on every side: unconditional 16-byte loads,
         // with no branch whose own waits would drain the loads in flight
-        const bool inside_mn = m0 + kBM <= M && n0 + kBN <= N;
+        const bool inside_mn = m0 + BT <= M && n0 + BT <= N;
         auto gload_full = [&](int k0, u16x8* va, u16x8* vb) {
 #pragma unroll
             for (int h = 0; h < CH; ++h) {
-                const int c = tid + 256 * h;
+                const int c = tid + NT * h;
                 va[h] = !TA ? *reinterpret_cast<const u16x8*>(A + (size_t)(m0 + (c >> 3)) * lda + k0 + (c & 7) * 8)
-                            : *reinterpret_cast<const u16x8*>(A + (size_t)(k0 + (c >> 3)) * lda + m0 + (c & 7) * 8);
+                            : *reinterpret_cast<const u16x8*>(A + (size_t)(k0 + c / RM) * lda + m0 + (c % RM) * 8);
                 vb[h] = TB ? *reinterpret_cast<const u16x8*>(B + (size_t)(n0 + (c >> 3)) * ldb + k0 + (c & 7) * 8)
-                           : *reinterpret_cast<const u16x8*>(B + (size_t)(k0 + (c >> 3)) * ldb + n0 + (c & 7) * 8);
+                           : *reinterpret_cast<const u16x8*>(B + (size_t)(k0 + c / RM) * ldb + n0 + (c % RM) * 8);
             }
         };
         auto sstore = [&](const u16x8* va, const u16x8* vb) {
 #pragma unroll
             for (int h = 0; h < CH; ++h) {
-                const int c = tid + 256 * h;
+                const int c = tid + NT * h;
                 if (!TA) {
                     *reinterpret_cast<u16x8*>(&sA[c >> 3][swz(c >> 3, (c & 7) * 8)]) = va[h];
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) sA[(c & 7) * 8 + q][swz((c & 7) * 8 + q, c >> 3)] = va[h][q];
+                    for (int q = 0; q < 8; ++q) sA[(c % RM) * 8 + q][swz((c % RM) * 8 + q, c / RM)] = va[h][q];
                 }
                 if (TB) {
                     *reinterpret_cast<u16x8*>(&sB[c >> 3][swz(c >> 3, (c & 7) * 8)]) = vb[h];
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) sB[(c & 7) * 8 + q][swz((c & 7) * 8 + q, c >> 3)] = vb[h][q];
+                    for (int q = 0; q < 8; ++q) sB[(c % RM) * 8 + q][swz((c % RM) * 8 + q, c / RM)] = vb[h][q];
                 }
             }
         };
@@ -232,11 +238,11 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
         }
     } else {
         for (int k0 = kbeg; k0 < kend; k0 += kBK) {
-            for (int e = tid; e < kBM * kBK; e += 256) {
+            for (int e = tid; e < BT * kBK; e += NT) {
                 int m, k;
                 if (TA) {
-                    m = e % kBM;
-                    k = e / kBM;
+                    m = e % BT;
+                    k = e / BT;
                 } else {
                     k = e % kBK;
                     m = e / kBK;
@@ -246,14 +252,14 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
                 if (gm < M && gk < kend) v = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
                 sA[m][swz(m, k)] = v;
             }
-            for (int e = tid; e < kBN * kBK; e += 256) {
+            for (int e = tid; e < BT * kBK; e += NT) {
                 int n, k;
                 if (TB) {
                     k = e % kBK;
                     n = e / kBK;
                 } else {
-                    n = e % kBN;
-                    k = e / kBN;
+                    n = e % BT;
+                    k = e / BT;
                 }
                 const int gn = n0 + n, gk = k0 + k;
                 bf16 v = 0;
@@ -267,9 +273,9 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, int kc,
     }
     const bool add = gridDim.z > 1;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NBM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NBN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 // lane l holds row 4 (l / 16) + r, column l % 16 of each 16 x 16 tile
@@ -699,20 +705,33 @@ hipError_t gemm(int M, int N, int K, const bf16* A, int lda, bool ta, const bf16
                            accumulate ? 1 : 0);
         return hipGetLastError();
     }
-    const int tiles = ((M + pgc::kBM - 1) / pgc::kBM) * ((N + pgc::kBN - 1) / pgc::kBN);
     // split K until the tiles cover the device twice over, while the atomic
     // traffic of the partial tiles (split x the bytes of C) stays below the
     // bytes of the operands: a product whose output is large next to its
     // operands (the 13824-wide layers) is bound by writing C, not by the
     // matrix cores, and runs unsplit
-    int split = 1;
     const double operand_bytes = 2.0 * ((double)M * K + (double)N * K), c_bytes = 4.0 * (double)M * N;
-    while (tiles * split < 512 && K / (split * 2) >= 256 && c_bytes * split * 2 <= operand_bytes) split *= 2;
-    const int kc = ((K + split - 1) / split + pgc::kBK - 1) / pgc::kBK * pgc::kBK;
-    split = (K + kc - 1) / kc;
+    auto plan_split = [&](int bt, int& split, int& kc) {
+        const int tiles = ((M + bt - 1) / bt) * ((N + bt - 1) / bt);
+        split = 1;
+        while (tiles * split < 512 && K / (split * 2) >= 256 && c_bytes * split * 2 <= operand_bytes) split *= 2;
+        kc = ((K + split - 1) / split + pgc::kBK - 1) / pgc::kBK * pgc::kBK;
+        split = (K + kc - 1) / kc;
+        return tiles * split;
+    };
+    // 128 x 128 tiles (eight waves of 32 x 64) read half the operand bytes per
+    // flop of 64 x 64 ones (four waves of 32 x 32).  Measured on the network's
+    // products they pay only with many tiles (the weight gradients, 864 tiles:
+    // 6-9% faster) and cost 40-80% on the 256-row products (216 or 256
+    // workgroups), so they are taken from 512 workgroups on
+    int split, kc, bt = 128;
+    if (M < 128 || N < 128 || plan_split(128, split, kc) < 512) {
+        bt = 64;
+        plan_split(64, split, kc);
+    }
     if (split > 1 && !accumulate)
         hipLaunchKernelGGL(pgc::zero_rows, dim3(pgc::nb((int64_t)M * N, 256)), dim3(256), 0, st, C, ldc, M, N);
-    dim3 grid((N + pgc::kBN - 1) / pgc::kBN, (M + pgc::kBM - 1) / pgc::kBM, split);
+    dim3 grid((N + bt - 1) / bt, (M + bt - 1) / bt, split);
     const int acc = accumulate ? 1 : 0;
     // 16-byte runs need 16-byte aligned rows: leading dimensions that are
     // multiples of 8 elements on 16-byte aligned bases (kc is a multiple of 32)
@@ -720,18 +739,24 @@ hipError_t gemm(int M, int N, int K, const bf16* A, int lda, bool ta, const bf16
                      (reinterpret_cast<uintptr_t>(B) & 15) == 0)
                         ? 1
                         : 0;
+#define PGC_GEMM_LAUNCH(TA_, TB_)                                                                                    \
+    do {                                                                                                             \
+        if (bt == 128)                                                                                               \
+            hipLaunchKernelGGL((pgc::gemm_bf16<TA_, TB_, 128, 8>), grid, dim3(512), 0, st, M, N, K, kc, A, lda, B,   \
+                               ldb, C, ldc, bias, acc, vec);                                                         \
+        else                                                                                                         \
+            hipLaunchKernelGGL((pgc::gemm_bf16<TA_, TB_, 64, 4>), grid, dim3(256), 0, st, M, N, K, kc, A, lda, B,    \
+                               ldb, C, ldc, bias, acc, vec);                                                         \
+    } while (0)
     if (!ta && !tb)
-        hipLaunchKernelGGL((pgc::gemm_bf16<false, false>), grid, dim3(256), 0, st, M, N, K, kc, A, lda, B, ldb, C, ldc,
-                           bias, acc, vec);
+        PGC_GEMM_LAUNCH(false, false);
     else if (!ta && tb)
-        hipLaunchKernelGGL((pgc::gemm_bf16<false, true>), grid, dim3(256), 0, st, M, N, K, kc, A, lda, B, ldb, C, ldc,
-                           bias, acc, vec);
+        PGC_GEMM_LAUNCH(false, true);
     else if (ta && !tb)
-        hipLaunchKernelGGL((pgc::gemm_bf16<true, false>), grid, dim3(256), 0, st, M, N, K, kc, A, lda, B, ldb, C, ldc,
-                           bias, acc, vec);
+        PGC_GEMM_LAUNCH(true, false);
     else
-        hipLaunchKernelGGL((pgc::gemm_bf16<true, true>), grid, dim3(256), 0, st, M, N, K, kc, A, lda, B, ldb, C, ldc,
-                           bias, acc, vec);
+        PGC_GEMM_LAUNCH(true, true);
+#undef PGC_GEMM_LAUNCH
     return hipGetLastError();
 }
 

@@ -36,8 +36,9 @@ def rel(a, b):
 @pytest.mark.parametrize("ta,tb", [(False, False), (False, True), (True, False), (True, True)])
 @pytest.mark.parametrize("M,N,K", [(70, 45, 83), (130, 200, 1500), (1, 17, 5), (96, 72, 1000), (200, 136, 264),
                                    (256, 300, 2100), (300, 257, 700),
-                                   # 128 x 128 tiles: ragged on every side, whole tiles and slices, split K
-                                   (2000, 1500, 264), (2048, 1280, 192), (256, 768, 13824)])
+                                   # split K over a long inner dimension; 128 x 128 tiles (from 512
+                                   # of them): whole tiles and slices, and ragged on every side
+                                   (256, 768, 13824), (4096, 2048, 128), (4000, 2100, 200)])
 def test_gemm_bf16_layouts(torch_cuda, ta, tb, M, N, K):
     torch = torch_cuda
     from paper_2105_08806_amd import pgc
