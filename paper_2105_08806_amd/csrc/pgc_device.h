@@ -124,13 +124,15 @@ __device__ __forceinline__ double cell_offset(const double* __restrict__ cf, dou
 }
 
 // kernel offset and map factor m2 of a point from its cell's fit in the scaled
-// velocity t = v/S (a cell with a nonzero 1/delta in cv[1])
+// velocity t = v/S (a cell with a nonzero 1/delta in cv[1]); FP32 plans hold
+// fits of a lower degree in the same slots
 template <typename T>
 __device__ __forceinline__ double cell_offset_v(const double* __restrict__ cv, T v, double inv_S64, T& m2)
 {
+    constexpr int DEG = sizeof(T) == sizeof(double) ? kCellFitDeg : kCellFitDegV32;
     const double x = ((double)v * inv_S64 - cv[0]) * cv[1];
-    m2 = (T)horner_uniform<kCellFitDeg>(cv + 3 + kCellFitDeg, x);
-    return horner_uniform<kCellFitDeg>(cv + 2, x);
+    m2 = (T)horner_uniform<DEG>(cv + 3 + kCellFitDeg, x);
+    return horner_uniform<DEG>(cv + 2, x);
 }
 
 // values of the W kernel cells at offset s in [-1, 1): Horner in s

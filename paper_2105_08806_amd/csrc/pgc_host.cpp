@@ -368,14 +368,15 @@ void build_bin_thresholds(Plan& p)
 }
 
 // Monomial coefficients (in x) of the Chebyshev interpolant of degree
-// kCellFitDeg of f on [-1, 1], at the Chebyshev points of the first kind, in
-// long double; rounded to FP64 into out[0 .. kCellFitDeg].
+// deg <= kCellFitDeg of f on [-1, 1], at the Chebyshev points of the first
+// kind, in long double; rounded to FP64 into out[0 .. deg].
 template <typename F>
-static void cheb_fit_monomials(const F& f, double* out)
+static void cheb_fit_monomials(const F& f, double* out, int deg = kCellFitDeg)
 {
-    constexpr int n = kCellFitDeg + 1;
+    const int n = deg + 1;
     const long double pi = acosl(-1.0L);
-    long double fx[n], cc[n], tm[n], t[n], tn[n], mono[n];
+    long double fx[kCellFitDeg + 1], cc[kCellFitDeg + 1], tm[kCellFitDeg + 1], t[kCellFitDeg + 1],
+        tn[kCellFitDeg + 1], mono[kCellFitDeg + 1];
     for (int j = 0; j < n; ++j) fx[j] = f(cosl(pi * (j + 0.5L) / n));
     for (int k = 0; k < n; ++k) {
         long double acc = 0.0L;
@@ -399,11 +400,11 @@ static void cheb_fit_monomials(const F& f, double* out)
     for (int k = 0; k < n; ++k) out[k] = (double)mono[k];
 }
 
-// The stored (rounded) polynomial c[0 .. kCellFitDeg] at x, in long double
-static long double cheb_fit_eval(const double* c, long double x)
+// The stored (rounded) polynomial c[0 .. deg] at x, in long double
+static long double cheb_fit_eval(const double* c, long double x, int deg = kCellFitDeg)
 {
-    long double v = c[kCellFitDeg];
-    for (int k = kCellFitDeg - 1; k >= 0; --k) v = v * x + c[k];
+    long double v = c[deg];
+    for (int k = deg - 1; k >= 0; --k) v = v * x + c[k];
     return v;
 }
 
@@ -424,10 +425,14 @@ static long double cheb_fit_eval(const double* c, long double x)
 // 5e-16 of s and within 5e-16 relative of m2 (every cell but the one or few
 // at each end of the grid), else 1/d = 0 marks it and its points take the map
 // to w.  The velocity fit saves the exponential and reciprocals of the map.
+// FP32 plans, whose kernel values are rounded to FP32, fit to degree 7 within
+// 2e-10, which covers as many cells.
 void build_cell_fits(Plan& p)
 {
     constexpr int K = kCellFitDeg;
-    constexpr long double kTol = 5e-16L;
+    const bool fp64 = p.precision == PGC_PRECISION_FP64;
+    const int kv = fp64 ? kCellFitDeg : kCellFitDegV32;
+    const long double kTol = fp64 ? 5e-16L : 2e-10L;
     const int nb = p.nh + 2, off = p.W / 2;
     const long double pi = acosl(-1.0L), h = pi / p.nh, hw = 0.5L * p.W;
     p.cellfit.assign((size_t)nb * kCellFitStride, 0.0);
@@ -471,16 +476,16 @@ void build_cell_fits(Plan& p)
             const long double t = tc + dt * x;
             return log_map ? coshl(t) : 1.0L + t * t;
         };
-        double fv[kCellFitVStride];
+        double fv[kCellFitVStride] = {};
         fv[0] = (double)tc;
         fv[1] = (double)(1.0L / dt);
-        cheb_fit_monomials(offset_t, fv + 2);
-        cheb_fit_monomials(m2_t, fv + 3 + K);
+        cheb_fit_monomials(offset_t, fv + 2, kv);
+        cheb_fit_monomials(m2_t, fv + 3 + K, kv);
         bool good = true;
         for (int i = 0; i <= 256 && good; ++i) {
             const long double x = -1.0L + i / 128.0L;
-            const long double es = fabsl(cheb_fit_eval(fv + 2, x) - offset_t(x));
-            const long double em = fabsl(cheb_fit_eval(fv + 3 + K, x) / m2_t(x) - 1.0L);
+            const long double es = fabsl(cheb_fit_eval(fv + 2, x, kv) - offset_t(x));
+            const long double em = fabsl(cheb_fit_eval(fv + 3 + K, x, kv) / m2_t(x) - 1.0L);
             good = es <= kTol && em <= kTol;  // false for NaN too
         }
         if (!good) continue;

@@ -25,6 +25,9 @@ constexpr int kCellFitDeg = 12;
 constexpr int kCellFitStride = kCellFitDeg + 3;  // w_c, 1/delta, c_0 .. c_12
 // t_c, 1/delta (0: no fit), offset c_0 .. c_12, map factor c_0 .. c_12
 constexpr int kCellFitVStride = 2 * kCellFitDeg + 4;
+// FP32 plans fit the offset and map factor in v/S to degree 7 (within 2e-10,
+// far below the FP32 rounding of the kernel values), in the same slots
+constexpr int kCellFitDegV32 = 7;
 constexpr int kMaxLdsBytes = 160 * 1024;
 constexpr int kLdsBudget = 155 * 1024;  // slab bytes per workgroup
 
