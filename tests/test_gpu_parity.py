@@ -305,6 +305,17 @@ def test_velocity_fits_cover_the_grid(torch_cuda, map_):
     r, rp = rel_l2(q_b, q_s), rel_l2(qp_b, qp_s)
     say("  binned vs slabs: rel-L2 Q %.2e Q+ %.2e" % (r, rp))
     assert rp <= 1e-13 and r <= 1e-12
+    # FP32 plans fit to degree 7 within 2e-10, which covers 93 (r = 0) and 85
+    # (r = 1) of the cells; their Q meets the FP32 bar against the FP64 plan's
+    plan = pgc.Plan(dim=2, n_modes=N, scale=5.0, map=map_, kernel=pgc.KERNEL_MAXWELL, n_sigma=8,
+                    precision=pgc.FP32, nufft_tol=1e-8)
+    say("case: FP32 map=%d velocity_fit_cells=%d" % (map_, plan.info.velocity_fit_cells))
+    assert plan.info.velocity_fit_cells == (93 if map_ == 0 else 85)
+    q32, qp32 = gpu_q(torch, plan, c)
+    plan.close()
+    r32 = rel_l2(qp32, qp_b)
+    say("  FP32 binned vs FP64 binned: rel-L2 Q+ %.2e" % r32)
+    assert r32 <= FP32_TOL
 
 
 def test_binned_limits_at_the_largest_node_count(torch_cuda):
