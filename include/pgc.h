@@ -253,6 +253,24 @@ pgc_status pgc_coeffs_to_q_static(pgc_plan plan, const void* coeffs_dev, void* q
  * whatever the plan precision; FP32 plans round each stage input to float). */
 pgc_status pgc_rk4(pgc_plan plan, double* coeffs_dev, double dt, int32_t n_steps, void* stream);
 
+/* HIP graphs of a plan's launch sequences, for callers that evaluate the same
+ * buffers many times (a small plan's evaluation is a dozen short launches;
+ * a replay issues them as one).  Each capture replaces the plan's earlier
+ * graph.  pgc_plan_capture records pgc_coeffs_to_q for these pointers: one
+ * eager evaluation runs first on `stream` (it writes q_dev and qplus_dev), then
+ * the capture, on a private stream.  pgc_plan_capture_rk4 records
+ * pgc_rk4(coeffs_dev, dt, n_steps) (n_steps >= 1), in place on coeffs_dev:
+ * `stream` is synchronised first and nothing runs.  pgc_plan_graph_launch
+ * replays the graph on `stream`.  A graph reads and writes the pointers it was
+ * captured with (refill the same input buffer between replays) and uses the
+ * plan's workspace, which eager calls share in stream order.  Errors:
+ * INVALID_ARG (NULL plan or buffers, n_steps < 1, non-finite dt, a launch
+ * with no graph), UNSUPPORTED (profiling is on: its events stay out of
+ * graphs), DEVICE. */
+pgc_status pgc_plan_capture(pgc_plan plan, const void* coeffs_dev, void* q_dev, void* qplus_dev, void* stream);
+pgc_status pgc_plan_capture_rk4(pgc_plan plan, double* coeffs_dev, double dt, int32_t n_steps, void* stream);
+pgc_status pgc_plan_graph_launch(pgc_plan plan, void* stream);
+
 /* Mass, momentum (dim values) and energy int |v|^2 f_N dv of the expansion
  * with coefficients coeffs_dev (plan precision), eq. (def_mom), computed in
  * FP64 from 1D moment functionals: out_dev receives dim + 2 doubles. */

@@ -1121,6 +1121,8 @@ pgc_status pgc_plan_destroy(pgc_plan plan)
     if (!plan) return PGC_OK;
     (void)pgc_set_profiling(plan, 0);
     (void)hipDeviceSynchronize();
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
     pgc::free_all(plan->p);
     delete plan;
     return PGC_OK;
@@ -1294,6 +1296,72 @@ pgc_status pgc_rk4(pgc_plan plan, double* coeffs, double dt, int32_t n_steps, vo
         if (e != hipSuccess) return pgc::from_hip(e);
     }
     return PGC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+void drop_graph(pgc_plan plan)
+{
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    plan->exec = nullptr;
+    plan->graph = nullptr;
+}
+
+// records `body(stream)` into the plan's graph on a private stream, after the
+// caller's stream has drained
+template <typename F>
+pgc_status capture_into(pgc_plan plan, hipStream_t user, F body)
+{
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamSynchronize(user);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return pgc::from_hip(e);
+    pgc_status st = PGC_OK;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = body(cs);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        plan->graph = g;
+    }
+    if (st == PGC_OK && e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (st == PGC_OK && e != hipSuccess) st = pgc::from_hip(e);
+    if (st != PGC_OK) drop_graph(plan);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+pgc_status pgc_plan_capture(pgc_plan plan, const void* coeffs, void* q, void* qplus, void* stream)
+{
+    if (!plan || !coeffs || !q) return PGC_ERR_INVALID_ARG;
+    if (plan->p.prof) return PGC_ERR_UNSUPPORTED;
+    drop_graph(plan);
+    pgc_status st = pgc_coeffs_to_q(plan, coeffs, q, qplus, stream);
+    if (st != PGC_OK) return st;
+    return capture_into(plan, static_cast<hipStream_t>(stream),
+                        [&](hipStream_t cs) { return pgc_coeffs_to_q(plan, coeffs, q, qplus, cs); });
+}
+
+pgc_status pgc_plan_capture_rk4(pgc_plan plan, double* coeffs, double dt, int32_t n_steps, void* stream)
+{
+    if (!plan || !coeffs || n_steps < 1 || !std::isfinite(dt)) return PGC_ERR_INVALID_ARG;
+    if (plan->p.prof) return PGC_ERR_UNSUPPORTED;
+    drop_graph(plan);
+    return capture_into(plan, static_cast<hipStream_t>(stream),
+                        [&](hipStream_t cs) { return pgc_rk4(plan, coeffs, dt, n_steps, cs); });
+}
+
+pgc_status pgc_plan_graph_launch(pgc_plan plan, void* stream)
+{
+    if (!plan || !plan->exec) return PGC_ERR_INVALID_ARG;
+    return pgc::from_hip(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)));
 }
 
 pgc_status pgc_moments(pgc_plan plan, const void* coeffs, double* out, void* stream)

@@ -232,4 +232,6 @@ inline pgc_status status_of(hipError_t e)
 // the opaque plan handle of the C ABI
 struct pgc_plan_s {
     pgc::Plan p;
+    hipGraph_t graph = nullptr;  // a captured evaluation or RK4 run (pgc_plan_capture*)
+    hipGraphExec_t exec = nullptr;
 };

@@ -144,6 +144,9 @@ def lib():
         L.pgc_coeffs_to_q.argtypes = [vp, vp, vp, vp, vp]
         L.pgc_coeffs_to_q_static.argtypes = [vp, vp, vp, vp, vp]
         L.pgc_rk4.argtypes = [vp, vp, dbl, i32, vp]
+        L.pgc_plan_capture.argtypes = [vp, vp, vp, vp, vp]
+        L.pgc_plan_capture_rk4.argtypes = [vp, vp, dbl, i32, vp]
+        L.pgc_plan_graph_launch.argtypes = [vp, vp]
         L.pgc_moments.argtypes = [vp, vp, vp, vp]
         L.pgc_eval.argtypes = [vp, vp, vp, i64, vp, vp]
         L.pgc_set_profiling.argtypes = [vp, i32]
@@ -355,6 +358,34 @@ class Plan:
             raise ValueError("rk4 state must be a contiguous float64 CUDA tensor")
         _check(lib().pgc_rk4(self._h, _ptr(coeffs), float(dt), int(n_steps), _stream()), "pgc_rk4")
         return coeffs
+
+    def capture(self, coeffs, q=None, qplus=None, want_qplus=False):
+        """pgc_plan_capture: one evaluation of these buffers, then its HIP graph,
+        which graph_launch replays.  The graph reads coeffs and writes q (and
+        qplus) in place: refill coeffs between replays."""
+        torch = self._torch
+        c = self._coeffs(coeffs)
+        if q is None:
+            q = torch.empty_like(c)
+        if want_qplus and qplus is None:
+            qplus = torch.empty_like(c)
+        _check(lib().pgc_plan_capture(self._h, _ptr(c), _ptr(q), _ptr(qplus) if qplus is not None else None,
+                                      _stream()), "pgc_plan_capture")
+        self._graph_io = (c, q, qplus)  # the graph reads and writes these buffers
+        return (q, qplus) if want_qplus else q
+
+    def capture_rk4(self, coeffs, dt, n_steps):
+        """pgc_plan_capture_rk4: the graph of n_steps RK4 steps in place on a
+        float64 CUDA tensor of shape N^dim (nothing runs until graph_launch)."""
+        torch = self._torch
+        if not (coeffs.is_cuda and coeffs.dtype == torch.float64 and coeffs.is_contiguous()):
+            raise ValueError("rk4 state must be a contiguous float64 CUDA tensor")
+        _check(lib().pgc_plan_capture_rk4(self._h, _ptr(coeffs), float(dt), int(n_steps), _stream()),
+               "pgc_plan_capture_rk4")
+        self._graph_io = (coeffs,)
+
+    def graph_launch(self):
+        _check(lib().pgc_plan_graph_launch(self._h, _stream()), "pgc_plan_graph_launch")
 
     def moments(self, coeffs):
         torch = self._torch

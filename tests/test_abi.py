@@ -64,6 +64,9 @@ def test_null_plan_is_rejected_without_a_device():
     assert L.pgc_coeffs_to_q_static(None, None, None, None, None) == 1
     assert L.pgc_status_string(6).startswith(b"the call needs more scratch")
     assert L.pgc_rk4(None, None, 0.1, 1, None) == 1
+    assert L.pgc_plan_capture(None, None, None, None, None) == 1
+    assert L.pgc_plan_capture_rk4(None, None, 0.1, 1, None) == 1
+    assert L.pgc_plan_graph_launch(None, None) == 1
     out = ctypes.c_void_p()
     assert L.pgc_plan_create(None, None, ctypes.byref(out)) == 1
 
