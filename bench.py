@@ -907,7 +907,7 @@ def main():
                          "accuracy: the 2D BKW accuracy tests (S sweeps, adaptive S, fixed S) on the GPU path")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d"
+        print("bench.py runs on one GPU only (the library has no multi-GPU path); got --gpus %d"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
 
