@@ -288,7 +288,8 @@ pgc_status pgc_eval(pgc_plan plan, const void* coeffs_dev, const double* v_dev, 
  * milliseconds (ms_out) and the number of timed calls (calls_out may be NULL),
  * then resets the accumulators.  Stages: 0 synthesis, 1 loss field and loss
  * projection, 2 pair-orbit sums, 3 spreading (the dominant kernel), 4 grid to
- * modes (conversion and cosine transform), 5 combination.  n_stages <= 8.
+ * modes (conversion, cosine transform and the combination Q = Q+ - Q-), 5
+ * empty (the combination, which stage 4 now ends with).  n_stages <= 8.
  * pgc_set_profiling(plan, 0) stops recording. */
 pgc_status pgc_set_profiling(pgc_plan plan, int32_t on);
 pgc_status pgc_stage_times(pgc_plan plan, double* ms_out, int32_t n_stages, int64_t* calls_out);

@@ -1221,10 +1221,9 @@ pgc_status pgc_coeffs_to_q(pgc_plan plan, const void* coeffs, void* q, void* qpl
     hipError_t e = pgc::launch_synthesis(p, p.ws, coeffs, s);
     pgc::prof_mark(p, 1, s);
     if (e == hipSuccess) e = pgc::launch_loss(p, p.ws, s);
-    if (e == hipSuccess) e = pgc::launch_gain(p, p.ws, s);
+    if (e == hipSuccess) e = pgc::launch_gain(p, p.ws, q, qplus, s);
     pgc::prof_mark(p, 5, s);
-    if (e == hipSuccess) e = pgc::launch_combine(p, p.ws, q, qplus, s);
-    pgc::prof_mark(p, 6, s);
+    pgc::prof_mark(p, 6, s);  // the combination runs in the grid-to-modes stage
     p.prof_set = -1;
     return pgc::from_hip(e);
 }

@@ -190,8 +190,9 @@ inline void prof_mark(const Plan& p, int stage, hipStream_t s)
 // plan's own Workspace, or one carved from the library's static scratch array.
 hipError_t launch_synthesis(const Plan& p, const Workspace& ws, const void* coeffs, hipStream_t s);
 hipError_t launch_loss(const Plan& p, const Workspace& ws, hipStream_t s);
-hipError_t launch_gain(const Plan& p, const Workspace& ws, hipStream_t s);
-hipError_t launch_combine(const Plan& p, const Workspace& ws, void* q, void* qplus, hipStream_t s);
+// the gain and its cosine transform, ending with Q = Q+ - Q- into q (and Q+
+// into qplus when it is given) in the plan precision
+hipError_t launch_gain(const Plan& p, const Workspace& ws, void* q, void* qplus, hipStream_t s);
 // the dense stages for nb cells of one plan's size (batches)
 hipError_t launch_dense_synthesis(const Plan& p, const double* c64, int nb, const DenseBufs& b,
                                   hipStream_t s);

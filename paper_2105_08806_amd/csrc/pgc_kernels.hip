@@ -26,6 +26,8 @@ namespace {
 
 constexpr int kRedThreads = 1024;
 
+inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
 // ------------------------------------------------------------------ transforms
 
 // out[a][k][b] = sum_l M[k][l] in[a][l][b]   (a < A, k < K, b < B)
@@ -46,32 +48,6 @@ __global__ void __launch_bounds__(256) sep_apply(const T* __restrict__ in, T* __
     T acc = 0;
     for (int l = 0; l < L; ++l) acc = fma(m[l], src[(int64_t)l * B], acc);
     out[idx] = acc;
-}
-
-// apply the K x L matrix M along every axis of nb consecutive dim-dimensional
-// L^dim tensors (FP64); tmpA and tmpB hold nb * max(K, L)^dim values each
-hipError_t separable(const Plan& p, const double* in, double* out, const double* M, int K, int L,
-                     int nb, double* tmpA, double* tmpB, hipStream_t s)
-{
-    int64_t dims[3] = {L, L, L};
-    const double* src = in;
-    double* bufs[2] = {tmpA, tmpB};
-    int pp = 0;
-    for (int ax = p.dim - 1; ax >= 0; --ax) {
-        double* dst = (ax == 0) ? out : bufs[pp];
-        pp ^= 1;
-        int64_t A = nb, B = 1;
-        for (int l = 0; l < ax; ++l) A *= dims[l];
-        for (int l = ax + 1; l < p.dim; ++l) B *= dims[l];
-        const int64_t total = A * K * B;
-        const int threads = 256;
-        const int64_t blocks = (total + threads - 1) / threads;
-        hipLaunchKernelGGL(sep_apply<double>, dim3((unsigned)blocks), dim3(threads), 0, s, src, dst, M,
-                           A, L, B, K);
-        dims[ax] = K;
-        src = dst;
-    }
-    return hipGetLastError();
 }
 
 // flat interior-node index -> product of per-dimension tables
@@ -124,21 +100,27 @@ __global__ void narrow(const double* __restrict__ x, T* __restrict__ y, int64_t 
 
 // red[c] = sum_j G_j of cell c = blockIdx.x (Maxwell molecules: the inner
 // integral of eq. Qminus is a single number; fixed order within one workgroup)
-__global__ void __launch_bounds__(kRedThreads) sum_kernel(const double* __restrict__ G, int64_t n,
-                                                          double* __restrict__ red)
+// the sum of g[0 .. n) over a workgroup of kRedThreads threads, in one fixed
+// order; thread 0 receives it
+__device__ __forceinline__ double block_sum(const double* __restrict__ g, int64_t n)
 {
     __shared__ double sh[kRedThreads / 64];
-    const double* g = G + blockIdx.x * n;
     double acc = 0.0;
-    for (int64_t f = threadIdx.x; f < n; f += blockDim.x) acc += g[f];
+    for (int64_t f = threadIdx.x; f < n; f += kRedThreads) acc += g[f];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
-        red[blockIdx.x] = t;
-    }
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kRedThreads / 64; ++w) t += sh[w];
+    return t;
+}
+
+__global__ void __launch_bounds__(kRedThreads) sum_kernel(const double* __restrict__ G, int64_t n,
+                                                          double* __restrict__ red)
+{
+    const double t = block_sum(G + blockIdx.x * n, n);
+    if (threadIdx.x == 0) red[blockIdx.x] = t;
 }
 
 // H_i = w_i A P_i with A = (sum_s W_s) b0 sum_j G_j, over n_cells * nid nodes
@@ -152,6 +134,219 @@ __global__ void loss_h_maxwell(const double* __restrict__ P, double* __restrict_
     double w, mu2;
     node_weights(f % nid, dim, ni, w1, mu21, w, mu2);
     H[f] = w * (scale * red[f / nid]) * P[f];
+}
+
+// Q = Q+ - Q- formed in FP64, rounded once to the output precision (and Q+
+// when qplus_out is given)
+template <typename T>
+__global__ void combine_kernel(const double* __restrict__ qp, const double* __restrict__ qm,
+                               T* __restrict__ q, T* __restrict__ qplus_out, int64_t n)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double a = qp[k];
+    q[k] = (T)(a - qm[k]);
+    if (qplus_out) qplus_out[k] = (T)a;
+}
+
+// What a transform reads before its first pass and writes after its last
+// besides its output, so that the elementwise stages around a small transform
+// run inside it.  Where the transform is not fused, separable() launches the
+// kernels of those stages around its passes instead; both forms compute the
+// same values in the same order.
+struct SepIO {
+    // input: 0 = the input tensor; 1 = the Maxwell loss field of eq. Qminus,
+    // H_i = w_i (scale sum_j G_j) P_i over the ni^dim interior nodes (the
+    // unfused form writes it to H, with the sum in red)
+    int pro = 0;
+    const double* P = nullptr;
+    const double* G = nullptr;
+    double scale = 0.0;
+    double* H = nullptr;
+    double* red = nullptr;
+    // after the last pass: 0 = nothing; 1 = G_i = w_i mu_i^2 out_i (Gout) and,
+    // when Gg is given, G rounded once to the plan precision (FP32 if gg_f32)
+    int epi = 0;
+    double* Gout = nullptr;
+    void* Gg = nullptr;
+    int gg_f32 = 0;
+    // 2 = Q = out - qm and Q+ = out rounded to the plan precision into q and,
+    // when given, qp (FP32 if q_f32), as combine_kernel forms them
+    const double* qm = nullptr;
+    void* q = nullptr;
+    void* qp = nullptr;
+    int q_f32 = 0;
+    // node tables of the prologue and epilogue (ni nodes per dimension)
+    const double* w1 = nullptr;
+    const double* mu21 = nullptr;
+    int ni = 0;
+};
+
+// Every pass of separable() for one tensor per workgroup (small plans, where a
+// pass is a few thousand outputs and passes launched one by one wait on one
+// another's latency).  The tensor and the matrix are first copied to LDS by
+// independent loads, then every pass reads and writes LDS only, except the
+// last, which writes the output.  Each output is the FMA chain of sep_apply in
+// the same order, so both forms agree bit for bit; the prologue's sum is
+// block_sum over the same number of threads as sum_kernel.
+constexpr int kSepFusedThreads = kRedThreads;
+constexpr int64_t kSepFusedMaxFma = int64_t(1) << 18;  // per tensor, over all passes
+constexpr int kSepFusedMaxLds = 64 * 1024;
+
+// LDS layout, in doubles: M (K L), the input tensor (L^dim), then the
+// intermediates of the passes before the last (two ping-pong buffers)
+__global__ void __launch_bounds__(kSepFusedThreads) sep_fused(const double* __restrict__ in,
+                                                              double* __restrict__ out,
+                                                              const double* __restrict__ M, int dim,
+                                                              int L, int K, int lds0, SepIO io)
+{
+    extern __shared__ double sep_lds[];
+    int Ld = 1, Kd = 1;
+    for (int l = 0; l < dim; ++l) {
+        Ld *= L;
+        Kd *= K;
+    }
+    double* sm = sep_lds;
+    double* sx = sm + K * L;
+    for (int i = threadIdx.x; i < K * L; i += kSepFusedThreads) sm[i] = M[i];
+    const int64_t cell = blockIdx.x;
+    if (io.pro == 1) {
+        const double t = block_sum(io.G + cell * Ld, Ld);
+        __shared__ double a_sh;
+        if (threadIdx.x == 0) a_sh = io.scale * t;
+        __syncthreads();
+        const double A = a_sh;
+        const double* P = io.P + cell * Ld;
+        for (int i = threadIdx.x; i < Ld; i += kSepFusedThreads) {
+            double w, mu2;
+            node_weights(i, dim, io.ni, io.w1, io.mu21, w, mu2);
+            sx[i] = w * A * P[i];
+        }
+    } else {
+        const double* g = in + cell * Ld;
+        for (int i = threadIdx.x; i < Ld; i += kSepFusedThreads) sx[i] = g[i];
+    }
+    __syncthreads();
+    double* bufs[2] = {sx + Ld, sx + Ld + lds0};
+    const double* src = sx;
+    int dims[3] = {L, L, L};
+    int pp = 0;
+    for (int ax = dim - 1; ax >= 0; --ax) {
+        const bool last = ax == 0;
+        double* dst = last ? out + cell * Kd : bufs[pp];
+        pp ^= 1;
+        int A = 1, B = 1;
+        for (int l = 0; l < ax; ++l) A *= dims[l];
+        for (int l = ax + 1; l < dim; ++l) B *= dims[l];
+        const int total = A * K * B;
+        for (int idx = threadIdx.x; idx < total; idx += kSepFusedThreads) {
+            const int b = idx % B;
+            const int t = idx / B;
+            const int k = t % K;
+            const int a = t / K;
+            const double* x = src + (a * L) * B + b;
+            const double* m = sm + k * L;
+            double acc = 0;
+            for (int l = 0; l < L; ++l) acc = fma(m[l], x[l * B], acc);
+            dst[idx] = acc;
+            if (last && io.epi == 1) {
+                double w, mu2;
+                node_weights(idx, dim, io.ni, io.w1, io.mu21, w, mu2);
+                const double g = w * mu2 * acc;
+                io.Gout[cell * Kd + idx] = g;
+                if (io.Gg) {
+                    if (io.gg_f32) static_cast<float*>(io.Gg)[cell * Kd + idx] = (float)g;
+                    else static_cast<double*>(io.Gg)[cell * Kd + idx] = g;
+                }
+            } else if (last && io.epi == 2) {
+                const int64_t o = cell * Kd + idx;
+                const double d = acc - io.qm[o];
+                if (io.q_f32) {
+                    static_cast<float*>(io.q)[o] = (float)d;
+                    if (io.qp) static_cast<float*>(io.qp)[o] = (float)acc;
+                } else {
+                    static_cast<double*>(io.q)[o] = d;
+                    if (io.qp) static_cast<double*>(io.qp)[o] = acc;
+                }
+            }
+        }
+        if (!last) __syncthreads();
+        dims[ax] = K;
+        src = dst;
+    }
+}
+
+// apply the K x L matrix M along every axis of nb consecutive dim-dimensional
+// L^dim tensors (FP64), with the input and output stages io; tmpA and tmpB
+// hold nb * max(K, L)^dim values each
+hipError_t separable(const Plan& p, const double* in, double* out, const double* M, int K, int L,
+                     int nb, double* tmpA, double* tmpB, hipStream_t s, const SepIO& io = SepIO{})
+{
+    {
+        // the fused form when every intermediate of one tensor fits in LDS and
+        // the work per tensor is small; the choice depends on the sizes only
+        int64_t fma_n = 0, lds[2] = {0, 0}, cur = 1;
+        for (int l = 0; l < p.dim; ++l) cur *= L;
+        const int64_t staged = (int64_t)K * L + cur;  // M and the input tensor
+        for (int ax = p.dim - 1, pp = 0; ax >= 0; --ax, pp ^= 1) {
+            cur = cur / L * K;
+            fma_n += cur * L;
+            if (ax > 0) lds[pp] = std::max(lds[pp], cur);
+        }
+        const int64_t lds_bytes = (staged + lds[0] + lds[1]) * (int64_t)sizeof(double);
+        if (p.dim >= 2 && fma_n <= kSepFusedMaxFma && lds_bytes <= kSepFusedMaxLds) {
+            hipLaunchKernelGGL(sep_fused, dim3(nb), dim3(kSepFusedThreads), (size_t)lds_bytes, s, in, out, M,
+                               p.dim, L, K, (int)lds[0], io);
+            return hipGetLastError();
+        }
+    }
+    int64_t Ld = 1;
+    for (int l = 0; l < p.dim; ++l) Ld *= L;
+    if (io.pro == 1) {
+        const int64_t n = (int64_t)nb * Ld;
+        hipLaunchKernelGGL(sum_kernel, dim3(nb), dim3(kRedThreads), 0, s, io.G, Ld, io.red);
+        hipLaunchKernelGGL(loss_h_maxwell, dim3(blocks_for(n, 256)), dim3(256), 0, s, io.P, io.H, io.w1,
+                           io.mu21, io.red, io.scale, p.dim, io.ni, Ld, n);
+        in = io.H;
+    }
+    int64_t dims[3] = {L, L, L};
+    const double* src = in;
+    double* bufs[2] = {tmpA, tmpB};
+    int pp = 0;
+    for (int ax = p.dim - 1; ax >= 0; --ax) {
+        double* dst = (ax == 0) ? out : bufs[pp];
+        pp ^= 1;
+        int64_t A = nb, B = 1;
+        for (int l = 0; l < ax; ++l) A *= dims[l];
+        for (int l = ax + 1; l < p.dim; ++l) B *= dims[l];
+        const int64_t total = A * K * B;
+        const int threads = 256;
+        const int64_t blocks = (total + threads - 1) / threads;
+        hipLaunchKernelGGL(sep_apply<double>, dim3((unsigned)blocks), dim3(threads), 0, s, src, dst, M,
+                           A, L, B, K);
+        dims[ax] = K;
+        src = dst;
+    }
+    int64_t Kd = 1;
+    for (int l = 0; l < p.dim; ++l) Kd *= K;
+    const int64_t n = (int64_t)nb * Kd;
+    if (io.epi == 2) {
+        if (io.q_f32)
+            hipLaunchKernelGGL(combine_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, out, io.qm,
+                               static_cast<float*>(io.q), static_cast<float*>(io.qp), n);
+        else
+            hipLaunchKernelGGL(combine_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, out, io.qm,
+                               static_cast<double*>(io.q), static_cast<double*>(io.qp), n);
+    }
+    if (io.epi == 1) {
+        if (io.gg_f32)
+            hipLaunchKernelGGL(make_weighted<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, out, io.Gout,
+                               static_cast<float*>(io.Gg), io.w1, io.mu21, p.dim, io.ni, Kd, n);
+        else
+            hipLaunchKernelGGL(make_weighted<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, out, io.Gout,
+                               static_cast<double*>(io.Gg), io.w1, io.mu21, p.dim, io.ni, Kd, n);
+    }
+    return hipGetLastError();
 }
 
 // The angular factor of an angle-dependent rate in the loss.  With
@@ -1019,17 +1214,6 @@ __global__ void reduce_partials(const double* __restrict__ partial, double* __re
     grid[m] = acc;
 }
 
-// Q = Q+ - Q- formed in FP64, rounded once to the output precision
-template <typename T>
-__global__ void combine_kernel(const double* __restrict__ qp, const double* __restrict__ qm,
-                               T* __restrict__ q, T* __restrict__ qplus_out, int64_t n)
-{
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const double a = qp[k];
-    q[k] = (T)(a - qm[k]);
-    if (qplus_out) qplus_out[k] = (T)a;
-}
 
 // ------------------------------------------------------------------ projection
 
@@ -1176,7 +1360,6 @@ __global__ void rk_finish_kernel(double* __restrict__ base, const T* __restrict_
                ((double)k1[i] + 2.0 * (double)k2[i] + 2.0 * (double)k3[i] + (double)k4[i]);
 }
 
-inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
 DenseBufs plan_bufs(const Workspace& ws)
 {
@@ -1201,12 +1384,15 @@ template <typename T>
 hipError_t dense_synthesis_t(const Plan& p, const double* c64, int nb, const DenseBufs& b,
                              hipStream_t s)
 {
-    hipError_t e = separable(p, c64, b.P, p.dt.C, p.ni, p.N, nb, b.tmpA, b.tmpB, s);
-    if (e != hipSuccess) return e;
-    const int64_t n = (int64_t)nb * p.nid;
-    hipLaunchKernelGGL(make_weighted<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, b.P, b.G,
-                       static_cast<T*>(b.Gg), p.dt.w1, p.dt.mu21, p.dim, p.ni, p.nid, n);
-    return hipGetLastError();
+    SepIO io;
+    io.epi = 1;
+    io.Gout = b.G;
+    io.Gg = b.Gg;
+    io.gg_f32 = sizeof(T) == sizeof(float);
+    io.w1 = p.dt.w1;
+    io.mu21 = p.dt.mu21;
+    io.ni = p.ni;
+    return separable(p, c64, b.P, p.dt.C, p.ni, p.N, nb, b.tmpA, b.tmpB, s, io);
 }
 
 template <typename T>
@@ -1228,10 +1414,17 @@ hipError_t dense_loss(const Plan& p, int nb, const DenseBufs& b, hipStream_t s)
 {
     const double scale = p.wsum * p.b0;
     if (p.kernel == PGC_KERNEL_MAXWELL) {
-        const int64_t n = (int64_t)nb * p.nid;
-        hipLaunchKernelGGL(sum_kernel, dim3(nb), dim3(kRedThreads), 0, s, b.G, p.nid, b.red);
-        hipLaunchKernelGGL(loss_h_maxwell, dim3(blocks_for(n, 256)), dim3(256), 0, s, b.P, b.H,
-                           p.dt.w1, p.dt.mu21, b.red, scale, p.dim, p.ni, p.nid, n);
+        SepIO io;
+        io.pro = 1;
+        io.P = b.P;
+        io.G = b.G;
+        io.scale = scale;
+        io.H = b.H;
+        io.red = b.red;
+        io.w1 = p.dt.w1;
+        io.mu21 = p.dt.mu21;
+        io.ni = p.ni;
+        return separable(p, nullptr, b.qminus, p.dt.CT, p.N, p.ni, nb, b.tmpA, b.tmpB, s, io);
     } else {
         AngleForm af{};
         if (p.kernel == PGC_KERNEL_ANISO) {
@@ -1432,8 +1625,15 @@ hipError_t bin_build_t(const Plan& p, unsigned int* count, unsigned long long* c
 }
 
 template <typename T>
-hipError_t gain_t(const Plan& p, const Workspace& ws, hipStream_t s)
+hipError_t gain_t(const Plan& p, const Workspace& ws, void* q, void* qplus, hipStream_t s)
 {
+    // the cosine transform of the grid ends with Q = Q+ - Q- into q (and Q+)
+    SepIO io;
+    io.epi = 2;
+    io.qm = ws.qminus;
+    io.q = q;
+    io.qp = qplus;
+    io.q_f32 = sizeof(T) == sizeof(float);
     prof_mark(p, 2, s);
     const int64_t n_sym = p.dim == 2 ? (int64_t)p.np * p.np : (int64_t)p.np * p.np * p.np;
     if (p.gain_mode == kGainBinned) {
@@ -1499,7 +1699,7 @@ hipError_t gain_t(const Plan& p, const Workspace& ws, hipStream_t s)
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         prof_mark(p, 4, s);
-        e = separable(p, ws.grid64, ws.qplus, p.dt.E, p.N, p.ng, 1, ws.tmpA, ws.tmpB, s);
+        e = separable(p, ws.grid64, ws.qplus, p.dt.E, p.N, p.ng, 1, ws.tmpA, ws.tmpB, s, io);
     } else {
         e = (p.dim == 2) ? spread_dispatch<T, 2>(p, gp, s) : spread_dispatch<T, 3>(p, gp, s);
         if (e != hipSuccess) return e;
@@ -1508,17 +1708,9 @@ hipError_t gain_t(const Plan& p, const Workspace& ws, hipStream_t s)
                            static_cast<const double*>(ws.partial), ws.grid, p.ngd, p.n_chunks);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = separable(p, ws.grid, ws.qplus, p.dt.E, p.N, p.ng, 1, ws.tmpA, ws.tmpB, s);
+        e = separable(p, ws.grid, ws.qplus, p.dt.E, p.N, p.ng, 1, ws.tmpA, ws.tmpB, s, io);
     }
     return e;
-}
-
-template <typename T>
-hipError_t combine_t(const Plan& p, const Workspace& ws, void* q, void* qplus, hipStream_t s)
-{
-    hipLaunchKernelGGL(combine_kernel<T>, dim3(blocks_for(p.Nd, 256)), dim3(256), 0, s, ws.qplus,
-                       ws.qminus, static_cast<T*>(q), static_cast<T*>(qplus), p.Nd);
-    return hipGetLastError();
 }
 
 // the projection in FP64; FP32 plans round the coefficients once at the end
@@ -1572,9 +1764,10 @@ hipError_t launch_dense_grid_to_modes(const Plan& p, const double* grid, int nb,
     return separable(p, grid, b.qplus, p.dt.E, p.N, p.ng, nb, b.tmpA, b.tmpB, s);
 }
 
-hipError_t launch_gain(const Plan& p, const Workspace& ws, hipStream_t s)
+hipError_t launch_gain(const Plan& p, const Workspace& ws, void* q, void* qplus, hipStream_t s)
 {
-    return p.precision == PGC_PRECISION_FP64 ? gain_t<double>(p, ws, s) : gain_t<float>(p, ws, s);
+    return p.precision == PGC_PRECISION_FP64 ? gain_t<double>(p, ws, q, qplus, s)
+                                             : gain_t<float>(p, ws, q, qplus, s);
 }
 
 hipError_t launch_bin_build(const Plan& p, unsigned int* count, unsigned long long* cursor,
@@ -1584,12 +1777,6 @@ hipError_t launch_bin_build(const Plan& p, unsigned int* count, unsigned long lo
     return p.precision == PGC_PRECISION_FP64
                ? bin_build_t<double>(p, count, cursor, cursor32, ids, mode, s0, ns, s)
                : bin_build_t<float>(p, count, cursor, cursor32, ids, mode, s0, ns, s);
-}
-
-hipError_t launch_combine(const Plan& p, const Workspace& ws, void* q, void* qplus, hipStream_t s)
-{
-    return p.precision == PGC_PRECISION_FP64 ? combine_t<double>(p, ws, q, qplus, s)
-                                             : combine_t<float>(p, ws, q, qplus, s);
 }
 
 hipError_t launch_project(const Plan& p, const double* f_nodes, void* coeffs, hipStream_t s)

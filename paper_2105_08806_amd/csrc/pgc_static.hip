@@ -97,7 +97,6 @@ extern "C" pgc_status pgc_coeffs_to_q_static(pgc_plan plan, const void* coeffs, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     e = pgc::launch_synthesis(p, ws, coeffs, s);
     if (e == hipSuccess) e = pgc::launch_loss(p, ws, s);
-    if (e == hipSuccess) e = pgc::launch_gain(p, ws, s);
-    if (e == hipSuccess) e = pgc::launch_combine(p, ws, q, qplus, s);
+    if (e == hipSuccess) e = pgc::launch_gain(p, ws, q, qplus, s);
     return pgc::status_of(e);
 }
