@@ -360,77 +360,87 @@ struct AngleForm {
     int on;
 };
 
-// VHS: A_i = (sum_s W_s) b0 sum_j G_j |v_i - v_j|^gamma, one thread per node i
-// of cell blockIdx.y, the j sweep staged through LDS in tiles (times the
-// angular factor for an angle-dependent rate).
+// VHS: A_i = (sum_s W_s) b0 sum_j G_j |v_i - v_j|^gamma (times the angular
+// factor for an angle-dependent rate) over the nodes of cell blockIdx.y.  A
+// workgroup takes kVhsI nodes i and splits the sweep over j into kVhsJ
+// contiguous slices, one lane per (i, slice), then adds the slices of each i
+// in slice order: one cell alone fills the chip, and the summation order
+// depends on the sizes only.  The per-dimension node table (ni values) is in
+// dynamic LDS.
+constexpr int kVhsI = 8, kVhsJ = 32;
+constexpr int kVhsMaxTableBytes = 60 * 1024;
 template <int DIM>
-__global__ void __launch_bounds__(256) loss_h_vhs(const double* __restrict__ P,
-                                                  const double* __restrict__ G,
-                                                  double* __restrict__ H,
-                                                  const double* __restrict__ v1,
-                                                  const double* __restrict__ w1,
-                                                  const double* __restrict__ mu21, double scale,
-                                                  double gamma, int ni, int64_t nid, AngleForm af)
+__global__ void __launch_bounds__(kVhsI * kVhsJ) loss_h_vhs(const double* __restrict__ P,
+                                                           const double* __restrict__ G,
+                                                           double* __restrict__ H,
+                                                           const double* __restrict__ v1,
+                                                           const double* __restrict__ w1,
+                                                           const double* __restrict__ mu21, double scale,
+                                                           double gamma, int ni, int64_t nid, AngleForm af)
 {
-    constexpr int kTile = 256;
-    __shared__ double sv[kTile][DIM];
-    __shared__ double sg[kTile];
+    extern __shared__ double sv[];
+    __shared__ double part[kVhsJ][kVhsI];
+    for (int a = threadIdx.x; a < ni; a += kVhsI * kVhsJ) sv[a] = v1[a];
     const int64_t cell = blockIdx.y;
     const double* Gc = G + cell * nid;
-    const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int ii = threadIdx.x % kVhsI, js = threadIdx.x / kVhsI;
+    const int64_t f = blockIdx.x * (int64_t)kVhsI + ii;
+    __syncthreads();
     double vi[DIM];
     {
         int64_t r = f < nid ? f : 0;
         for (int l = DIM - 1; l >= 0; --l) {
-            vi[l] = v1[r % ni];
+            vi[l] = sv[r % ni];
+            r /= ni;
+        }
+    }
+    // slice js: the nodes j in [j0, j1) of the flat order, walked by their
+    // per-dimension indices (last dimension fastest)
+    const int64_t span = (nid + kVhsJ - 1) / kVhsJ;
+    const int64_t j0 = js * span < nid ? js * span : nid;
+    const int64_t j1 = j0 + span < nid ? j0 + span : nid;
+    int jd[DIM];
+    {
+        int64_t r = j0;
+        for (int l = DIM - 1; l >= 0; --l) {
+            jd[l] = (int)(r % ni);
             r /= ni;
         }
     }
     double acc = 0;
-    for (int64_t j0 = 0; j0 < nid; j0 += kTile) {
-        __syncthreads();
-        const int64_t j = j0 + threadIdx.x;
-        if (threadIdx.x < kTile) {
-            if (j < nid) {
-                int64_t r = j;
-                for (int l = DIM - 1; l >= 0; --l) {
-                    sv[threadIdx.x][l] = v1[r % ni];
-                    r /= ni;
-                }
-                sg[threadIdx.x] = Gc[j];
-            } else {
-                for (int l = 0; l < DIM; ++l) sv[threadIdx.x][l] = 0;
-                sg[threadIdx.x] = 0;
-            }
+    for (int64_t j = j0; j < j1; ++j) {
+        double u2 = 0, d[DIM];
+        for (int l = 0; l < DIM; ++l) {
+            d[l] = vi[l] - sv[jd[l]];
+            u2 += d[l] * d[l];
         }
-        __syncthreads();
-        const int cnt = (int)((nid - j0) < kTile ? (nid - j0) : kTile);
-        for (int t = 0; t < cnt; ++t) {
-            double u2 = 0, d[DIM];
-            for (int l = 0; l < DIM; ++l) {
-                d[l] = vi[l] - sv[t][l];
-                u2 += d[l] * d[l];
-            }
-            double b;
-            if (gamma == 1.0) b = sqrt(u2);
-            else if (gamma == 0.0) b = 1;
-            else b = u2 > 0 ? pow(u2, 0.5 * gamma) : 0.0;
-            if (af.on && u2 > 0) {
-                double quad;
-                if constexpr (DIM == 2)
-                    quad = af.m[0] * d[0] * d[0] + 2.0 * af.m[1] * d[0] * d[1] + af.m[3] * d[1] * d[1];
-                else
-                    quad = af.m[0] * d[0] * d[0] + af.m[3] * d[1] * d[1] + af.m[5] * d[2] * d[2] +
-                           2.0 * (af.m[1] * d[0] * d[1] + af.m[2] * d[0] * d[2] + af.m[4] * d[1] * d[2]);
-                b *= 1.0 + quad / u2;
-            }
-            acc = fma(sg[t], b, acc);
+        double b;
+        if (gamma == 1.0) b = sqrt(u2);
+        else if (gamma == 0.0) b = 1;
+        else b = u2 > 0 ? pow(u2, 0.5 * gamma) : 0.0;
+        if (af.on && u2 > 0) {
+            double quad;
+            if constexpr (DIM == 2)
+                quad = af.m[0] * d[0] * d[0] + 2.0 * af.m[1] * d[0] * d[1] + af.m[3] * d[1] * d[1];
+            else
+                quad = af.m[0] * d[0] * d[0] + af.m[3] * d[1] * d[1] + af.m[5] * d[2] * d[2] +
+                       2.0 * (af.m[1] * d[0] * d[1] + af.m[2] * d[0] * d[2] + af.m[4] * d[1] * d[2]);
+            b *= 1.0 + quad / u2;
+        }
+        acc = fma(Gc[j], b, acc);
+        for (int l = DIM - 1; l >= 0; --l) {  // next j
+            if (++jd[l] < ni) break;
+            jd[l] = 0;
         }
     }
-    if (f >= nid) return;
+    part[js][ii] = acc;
+    __syncthreads();
+    if (js != 0 || f >= nid) return;
+    double sum = 0;
+    for (int k = 0; k < kVhsJ; ++k) sum += part[k][ii];
     double w, mu2;
     node_weights(f, DIM, ni, w1, mu21, w, mu2);
-    H[cell * nid + f] = w * scale * acc * P[cell * nid + f];
+    H[cell * nid + f] = w * scale * sum * P[cell * nid + f];
 }
 
 // ------------------------------------------------------------------ gain
@@ -1437,12 +1447,15 @@ hipError_t dense_loss(const Plan& p, int nb, const DenseBufs& b, hipStream_t s)
                         af.m[idx[a][c]] += p.sigma_w[s2] * p.sigma[(size_t)s2 * D + a] * p.sigma[(size_t)s2 * D + c];
             for (double& x : af.m) x *= p.aniso / p.wsum;
         }
+        const size_t table = (size_t)p.ni * sizeof(double);
+        if (table > (size_t)kVhsMaxTableBytes) return hipErrorInvalidValue;
+        const dim3 grid(blocks_for(p.nid, kVhsI), nb);
         if (p.dim == 2)
-            hipLaunchKernelGGL(loss_h_vhs<2>, dim3(blocks_for(p.nid, 256), nb), dim3(256), 0, s, b.P, b.G,
-                               b.H, p.dt.v1d, p.dt.w1, p.dt.mu21, scale, p.gamma, p.ni, p.nid, af);
+            hipLaunchKernelGGL(loss_h_vhs<2>, grid, dim3(kVhsI * kVhsJ), table, s, b.P, b.G, b.H, p.dt.v1d,
+                               p.dt.w1, p.dt.mu21, scale, p.gamma, p.ni, p.nid, af);
         else
-            hipLaunchKernelGGL(loss_h_vhs<3>, dim3(blocks_for(p.nid, 256), nb), dim3(256), 0, s, b.P, b.G,
-                               b.H, p.dt.v1d, p.dt.w1, p.dt.mu21, scale, p.gamma, p.ni, p.nid, af);
+            hipLaunchKernelGGL(loss_h_vhs<3>, grid, dim3(kVhsI * kVhsJ), table, s, b.P, b.G, b.H, p.dt.v1d,
+                               p.dt.w1, p.dt.mu21, scale, p.gamma, p.ni, p.nid, af);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
