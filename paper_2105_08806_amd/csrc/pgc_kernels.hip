@@ -50,6 +50,46 @@ __global__ void __launch_bounds__(256) sep_apply(const T* __restrict__ in, T* __
     out[idx] = acc;
 }
 
+// One pass of sep_apply for larger sizes: a workgroup computes 16 outputs k
+// by 16 columns (a, b) from the tile's rows of M and columns of the input,
+// staged in LDS, so the FMA chains read LDS instead of waiting on L2 at every
+// step.  Each output is sep_apply's FMA chain in the same order.
+constexpr int kSepTile = 16;
+constexpr int kSepTiledMaxL = 256;  // 2 x 16 x L doubles of LDS
+
+__global__ void __launch_bounds__(kSepTile * kSepTile) sep_tiled(const double* __restrict__ in,
+                                                                double* __restrict__ out,
+                                                                const double* __restrict__ M, int64_t A,
+                                                                int L, int64_t B, int K)
+{
+    extern __shared__ double sep_tile[];
+    double* sm = sep_tile;                  // sm[kk L + l]
+    double* sx = sep_tile + kSepTile * L;   // sx[l 16 + cc]
+    const int64_t c0 = blockIdx.x * (int64_t)kSepTile;
+    const int k0 = blockIdx.y * kSepTile;
+    const int64_t ncol = A * B;
+    for (int i = threadIdx.x; i < kSepTile * L; i += kSepTile * kSepTile) {
+        const int kk = i / L, l = i % L;
+        sm[i] = (k0 + kk < K) ? M[(int64_t)(k0 + kk) * L + l] : 0.0;
+    }
+    for (int i = threadIdx.x; i < kSepTile * L; i += kSepTile * kSepTile) {
+        const int l = i / kSepTile, cc = i % kSepTile;
+        const int64_t c = c0 + cc;
+        double v = 0.0;
+        if (c < ncol) v = in[((c / B) * L + l) * B + c % B];
+        sx[i] = v;
+    }
+    __syncthreads();
+    const int cc = threadIdx.x % kSepTile, kk = threadIdx.x / kSepTile;
+    const int64_t c = c0 + cc;
+    const int k = k0 + kk;
+    if (c >= ncol || k >= K) return;
+    const double* m = sm + kk * L;
+    double acc = 0;
+    for (int l = 0; l < L; ++l) acc = fma(m[l], sx[l * kSepTile + cc], acc);
+    out[((c / B) * K + k) * B + c % B] = acc;
+}
+
 // flat interior-node index -> product of per-dimension tables
 template <typename T>
 __device__ __forceinline__ void node_weights(int64_t f, int dim, int ni, const T* __restrict__ w1,
@@ -319,11 +359,17 @@ hipError_t separable(const Plan& p, const double* in, double* out, const double*
         int64_t A = nb, B = 1;
         for (int l = 0; l < ax; ++l) A *= dims[l];
         for (int l = ax + 1; l < p.dim; ++l) B *= dims[l];
-        const int64_t total = A * K * B;
-        const int threads = 256;
-        const int64_t blocks = (total + threads - 1) / threads;
-        hipLaunchKernelGGL(sep_apply<double>, dim3((unsigned)blocks), dim3(threads), 0, s, src, dst, M,
-                           A, L, B, K);
+        if (L <= kSepTiledMaxL) {
+            const dim3 grid(blocks_for(A * B, kSepTile), blocks_for(K, kSepTile));
+            const size_t lds = (size_t)2 * kSepTile * L * sizeof(double);
+            hipLaunchKernelGGL(sep_tiled, grid, dim3(kSepTile * kSepTile), lds, s, src, dst, M, A, L, B, K);
+        } else {
+            const int64_t total = A * K * B;
+            const int threads = 256;
+            const int64_t blocks = (total + threads - 1) / threads;
+            hipLaunchKernelGGL(sep_apply<double>, dim3((unsigned)blocks), dim3(threads), 0, s, src, dst, M,
+                               A, L, B, K);
+        }
         dims[ax] = K;
         src = dst;
     }
