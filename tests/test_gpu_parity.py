@@ -183,6 +183,28 @@ def test_project_moments_eval(torch_cuda):
         plan.close()
 
 
+@pytest.mark.parametrize("dim,N,m_v", [(2, 6, 258), (2, 6, 260), (3, 12, None), (3, 20, None)])
+def test_projection_transform_forms(torch_cuda, dim, N, m_v):
+    """The projection is one separable transform with the matrix C^T (N x n_i)
+    along every axis.  The library takes one of three forms by size: all
+    passes in one workgroup (3D N=12), pass by pass with the operands staged
+    in LDS (n_i = 256, its largest case, and 3D N=20, above the fused form's
+    work limit), or the plain pass for n_i > 256 (n_i = 258).  Each is
+    checked against the oracle's projection."""
+    import torch
+    ora, plan = make_pair(dim, N, 3.0, m_v=m_v, n_sigma=2, n_theta=2, n_phi=2)
+    assert plan.info.m_v == ora.m_v
+    V = ora.interior_velocities()
+    f = I.mixture(V, [(0.6, (0.4,) * dim, 0.8), (0.4, (-0.3,) * dim, 1.3)])
+    c_ref = ora.project(f)
+    c = plan.project(f)
+    torch.cuda.synchronize()
+    r = rel_l2(c.cpu().numpy(), c_ref)
+    say("case: projection %dD N=%d n_i=%d: rel-L2 %.2e" % (dim, N, ora.n_int, r))
+    assert r <= 1e-13
+    plan.close()
+
+
 def test_rk4_parity(torch_cuda):
     import torch
     ora, plan = make_pair(2, 12, 3.0, n_sigma=8)
