@@ -899,8 +899,10 @@ def main():
     ap.add_argument("--surrogate-pairs", type=int, default=4096)
     ap.add_argument("--surrogate-epochs", type=int, default=150)
     ap.add_argument("--pmc-dir", default="counters", help="folder holding the fetch/write/cfetch/cwrite counter passes")
-    ap.add_argument("--mode", choices=["bench", "profile", "copy", "bkw", "traffic", "accuracy"], default="bench",
+    ap.add_argument("--mode", choices=["bench", "profile", "profile2d", "copy", "bkw", "traffic", "accuracy"],
+                    default="bench",
                     help="profile: two evaluations per precision (for rocprofv3); "
+                         "profile2d: the same for the 2D VHS workload (64 modes) alone; "
                          "copy: a 1 GiB device copy (calibrates the HBM byte counters); "
                          "bkw: the 20-step RK4 BKW error curve in FP64 and FP32; "
                          "traffic: write profiles/traffic.json from the counter CSVs under --pmc-dir; "
@@ -937,6 +939,18 @@ def main():
         return
     if args.mode == "accuracy":
         print(json.dumps({"accuracy_2d_bkw_t2": accuracy_study(torch, pgc, inputs, np)}), flush=True)
+        return
+    if args.mode == "profile2d":
+        for prec in (pgc.FP64, pgc.FP32):
+            plan = pgc.Plan(dim=2, n_modes=64, scale=6.0, kernel=pgc.KERNEL_VHS, kernel_b0=1.0 / (2 * np.pi),
+                            kernel_gamma=1.0, n_sigma=32, precision=prec)
+            c = plan.project(inputs.mixture(plan.interior_velocities(), inputs.two_maxwellians_2d()))
+            for _ in range(2):
+                plan.coeffs_to_q(c)
+            torch.cuda.synchronize()
+            log("profiled 2D VHS %s: W=%d points=%d" % ("fp64" if prec == pgc.FP64 else "fp32",
+                                                        plan.info.kernel_width, plan.info.n_points))
+            plan.close()
         return
     if args.mode == "profile":
         for prec in (pgc.FP64, pgc.FP32):
